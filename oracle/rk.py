@@ -1,0 +1,111 @@
+"""SSP-RK3 with modified moments, time-step rule and stage restart -- oracle.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Stage structure (eq. (2.12); the 2D analogue in Sec. 3.1): every stage
+combines the cell averages with the *modified* first-order moments hat-v
+produced by the reconstruction of that stage's input, and the residual is
+evaluated on the stage input itself:
+
+    U1 = B(U^n)                    + dt F(U^n)
+    U2 = 3/4 B(U^n) + 1/4 (B(U1)   + dt F(U1))
+    U3 = 1/3 B(U^n) + 2/3 (B(U2)   + dt F(U2))
+
+where B(U) = (ubar, hat-v(U)).  Time step (Sec. 5 preamble):
+dt_trial = min(CFL h / alpha*, b Re h^2), alpha* from the stage-1 traces, the
+last step clipped to t_final.  A stage whose cell averages have nonpositive
+density or pressure rejects the step, which is redone from t^n with dt/2.
+"""
+
+import math
+
+import numpy as np
+
+from .common import pressure
+
+
+class InadmissibleError(RuntimeError):
+    """More restarts than ``Options.max_halvings`` were needed."""
+
+
+def admissible(U, gamma):
+    """All cell averages finite with rho > 0 and p > 0 (strictly)."""
+    Ub = np.real(U[0])
+    if not np.all(np.isfinite(np.real(U))):
+        return False
+    return bool(np.min(Ub[0]) > 0.0 and np.min(pressure(Ub, gamma)) > 0.0)
+
+
+def _base(U, Vhat):
+    return np.concatenate([U[0:1], Vhat], axis=0)
+
+
+def grid_h(scheme):
+    return min(scheme.dx, scheme.dy) if hasattr(scheme, 'dy') else scheme.dx
+
+
+def trial_dt(scheme, alpha, t, rule='paper'):
+    """dt_trial of the Sec. 5 preamble ('paper'), or CFL h^{5/3}/alpha ('h53')."""
+    op, ph = scheme.opts, scheme.phys
+    h = grid_h(scheme)
+    if rule == 'paper':
+        dt = op.cfl * h / alpha
+        if ph.mu_ref > 0.0:
+            dt = min(dt, op.b_visc * h * h / ph.mu_ref)
+    elif rule == 'h53':
+        dt = op.cfl * h ** (5.0 / 3.0) / alpha
+    else:
+        raise ValueError(rule)
+    if math.isfinite(op.t_final):
+        dt = min(dt, op.t_final - t)
+    return dt
+
+
+def rk3_step(scheme, U, t, dt=None, rule='paper', source=None):
+    """One SSP-RK3 step.  Returns (U_new, dt_used, info).
+
+    ``dt`` fixed, or None for the time-step rule.  ``source(t)`` returns the
+    source moments to add to the residual at time t (manufactured solutions).
+    """
+    g = scheme.phys.gamma
+    src = (lambda tt: None) if source is None else source
+    F0, V0, d0 = scheme.residual(U, src(t))
+    if dt is None:
+        dt = trial_dt(scheme, d0['alpha'], t, rule)
+    B0 = _base(U, V0)
+    info = dict(alpha=d0['alpha'], beta_max=d0['beta_max'], restarts=0, pp_cells=0)
+    while True:
+        pp = d0['pp_cells']
+        U1 = B0 + dt * F0
+        ok = admissible(U1, g)
+        if ok:
+            F1, V1, d1 = scheme.residual(U1, src(t + dt))
+            U2 = 0.75 * B0 + 0.25 * (_base(U1, V1) + dt * F1)
+            ok = admissible(U2, g)
+            pp += d1['pp_cells']
+        if ok:
+            F2, V2, d2 = scheme.residual(U2, src(t + 0.5 * dt))
+            U3 = (1.0 / 3.0) * B0 + (2.0 / 3.0) * (_base(U2, V2) + dt * F2)
+            ok = admissible(U3, g)
+            pp += d2['pp_cells']
+        if ok:
+            info['pp_cells'] = pp
+            return U3, dt, info
+        info['restarts'] += 1
+        if info['restarts'] > scheme.opts.max_halvings:
+            raise InadmissibleError('stage admissibility failed after %d halvings'
+                                    % scheme.opts.max_halvings)
+        dt = 0.5 * dt
+
+
+def run(scheme, U, t0, t1, rule='paper', source=None, dt=None, max_steps=10 ** 7):
+    """Advance from t0 to t1 (the last step clipped).  Returns (U, t, nsteps)."""
+    scheme.opts.t_final = t1
+    t = t0
+    n = 0
+    while t < t1 - 1e-14 * max(1.0, abs(t1)) and n < max_steps:
+        step_dt = None if dt is None else min(dt, t1 - t)
+        U, used, _ = rk3_step(scheme, U, t, step_dt, rule, source)
+        t += used
+        n += 1
+    return U, t, n

@@ -1,0 +1,609 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the pin it provides.  None of them re-types the oracle's
+formulas: they use values printed in the paper (tests/golden), exact
+polynomial calculus (sympy), invariants of the method and closed forms.
+"""
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import rk
+from oracle.common import (GAUSS3_NODES, GAUSS3_WEIGHTS, LGL_NODES, LGL_WEIGHTS,
+                           Options, Physics, beta_pp1d, beta_pp2d)
+from oracle.mms import MMS1D, MMS2D
+from oracle.recon import Hweno1D, Hweno2D, avg_integral, mom_integral
+from oracle.scheme1d import Scheme1D
+from oracle.scheme2d import Scheme2D, VOL, XFACE, YFACE
+
+GOLDEN = os.path.join(os.path.dirname(__file__), 'golden')
+
+
+def load_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith('#'):
+                rows.append([float(v) for v in line.split()])
+    return {int(r[0]): (r[1], r[2]) for r in rows}
+
+
+def load_constants():
+    out = {}
+    with open(os.path.join(GOLDEN, 'closed_forms.txt')) as f:
+        for line in f:
+            if line.strip() and not line.startswith('#'):
+                k, *v = line.split()
+                out[k] = [float(Fraction(x)) for x in v]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# P5: quadrature rules and constants printed in the paper
+# ---------------------------------------------------------------------------
+
+def test_quadrature_rules_exactness():
+    c = load_constants()
+    assert np.allclose(LGL_WEIGHTS, c['lgl_weights'], rtol=0, atol=1e-16)
+    assert np.allclose(GAUSS3_WEIGHTS, c['gauss3_weights'], rtol=0, atol=1e-16)
+    for n in range(8):
+        exact = 0.0 if n % 2 else 1.0 / ((n + 1) * 2 ** n)
+        lgl = np.sum(LGL_WEIGHTS * LGL_NODES ** n)
+        gau = np.sum(GAUSS3_WEIGHTS * GAUSS3_NODES ** n)
+        if n <= 5:
+            assert abs(lgl - exact) < 1e-16 and abs(gau - exact) < 1e-16
+        if n == 6:   # both rules are exact to degree 5 and no further
+            assert abs(lgl - exact) > 1e-6 and abs(gau - exact) > 1e-6
+    op = Options()
+    assert op.gamma1d == tuple(c['gamma_1d']) and op.gamma2d == tuple(c['gamma_2d'])
+    assert op.eps_weno == c['eps_weno'][0] and op.eps_pp == c['eps_pp'][0]
+    assert op.cfl == c['cfl'][0] and op.b_visc == c['b_visc'][0]
+
+
+# ---------------------------------------------------------------------------
+# P2: the interface error constant 241/95760 of the quartic p0 (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def test_interface_error_constant():
+    c = load_constants()['interface_error_constant'][0]
+    rec = Hweno1D()
+    # data of w = x^5 (dx = 1, x_i = 0): w^(5) = 120
+    data = np.array([avg_integral(5, -1), avg_integral(5, 0), avg_integral(5, 1),
+                     mom_integral(5, -1), mom_integral(5, 1)])
+    coef = rec.Q[0] @ data
+    right = sum(coef[k] * 0.5 ** k for k in range(5)) - 0.5 ** 5
+    left = sum(coef[k] * (-0.5) ** k for k in range(5)) - (-0.5) ** 5
+    # p0^- at x_{i+1/2} (right end of cell i) and p0^+ at x_{i-1/2} (left end):
+    # opposite signs, so the arithmetic average of two traces cancels them.
+    assert abs(right - (-c * 120.0)) < 1e-13
+    assert abs(left - (c * 120.0)) < 1e-13
+
+
+def test_p0_1d_exact_rationals():
+    """Brute force in exact rationals: the quartic fixed by eq. (A.1)."""
+    xi = sp.symbols('xi')
+    a = sp.symbols('a0:5')
+    p = sum(a[k] * xi ** k for k in range(5))
+    h = sp.Rational(1, 2)
+    eqs = []
+    data = sp.symbols('um uc up vm vp')
+    for d, val in zip((-1, 0, 1), data[:3]):
+        eqs.append(sp.integrate(p, (xi, d - h, d + h)) - val)
+    for d, val in zip((-1, 1), data[3:]):
+        eqs.append(sp.integrate(p * (xi - d), (xi, d - h, d + h)) - val)
+    sol = sp.solve(eqs, a)
+    face = sp.expand(p.subs(sol).subs(xi, h))
+    row = [float(face.coeff(s)) for s in data]
+    rec = Hweno1D()
+    orow = np.array([0.5 ** k for k in range(5)]) @ rec.Q[0]
+    assert np.allclose(orow, row, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# P1 / P4: polynomial reproduction and weights on linear data
+# ---------------------------------------------------------------------------
+
+def _moments_2d(coef, rec):
+    inp = np.zeros(17)
+    for k in range(1, 10):
+        inp[k - 1] = coef @ np.array(rec._row('avg', k))
+    for i, k in enumerate((2, 4, 6, 8)):
+        inp[9 + i] = coef @ np.array(rec._row('xi', k))
+        inp[13 + i] = coef @ np.array(rec._row('eta', k))
+    return inp
+
+
+def test_polynomial_reproduction_1d():
+    rec = Hweno1D()
+    rng = np.random.default_rng(11)
+    lin = Options(linear_weights=True)
+    nonlin = Options()
+    for _ in range(5):
+        coef = rng.standard_normal(5)
+        data = np.array([sum(coef[n] * avg_integral(n, d) for n in range(5)) for d in (-1, 0, 1)]
+                        + [sum(coef[n] * mom_integral(n, d) for n in range(5)) for d in (-1, 1)])
+        C = rec.combined(data[:, None], lin)[:, 0]
+        assert np.allclose(C, coef, rtol=0, atol=1e-13)
+        # P1 data: every candidate reproduces it, so any weights do; beta_m
+        # are all equal and omega = gamma exactly (P4)
+        c1 = coef.copy()
+        c1[2:] = 0.0
+        d1 = np.array([c1[0] + c1[1] * d for d in (-1, 0, 1)] + [c1[1] / 12.0] * 2)
+        C1 = rec.combined(d1[:, None], nonlin)[:, 0]
+        assert np.allclose(C1, c1, rtol=0, atol=1e-13)
+
+
+def test_polynomial_reproduction_2d():
+    rec = Hweno2D()
+    rng = np.random.default_rng(12)
+    lin = Options(linear_weights=True)
+    for _ in range(5):
+        coef = rng.standard_normal(15)
+        C = rec.combined(_moments_2d(coef, rec)[:, None], lin)[:, 0]
+        assert np.allclose(C, coef, rtol=0, atol=1e-12)
+        mx, my = rec.moments(C[:, None])
+        assert abs(mx[0] - coef @ np.array(rec._row('xi', 5))) < 1e-13
+        assert abs(my[0] - coef @ np.array(rec._row('eta', 5))) < 1e-13
+        c1 = np.zeros(15)
+        c1[:3] = coef[:3]
+        C1 = rec.combined(_moments_2d(c1, rec)[:, None], Options())[:, 0]
+        assert np.allclose(C1, c1, rtol=0, atol=1e-13)
+
+
+def test_weights_on_constant_and_linear_data():
+    """Linear data: all beta_m equal -> tau = 0 -> omega = gamma (eq. (A.6))."""
+    rec = Hweno2D()
+    c1 = np.zeros(15)
+    c1[:3] = [0.3, -1.2, 0.7]
+    inp = _moments_2d(c1, rec)
+    betas = [float(cm @ rec.G @ cm) for cm in (Q @ inp for Q in rec.Q)]
+    assert np.allclose(betas, betas[1], rtol=1e-13, atol=0)
+    assert abs(betas[1] - (1.2 ** 2 + 0.7 ** 2)) < 1e-13
+
+
+def test_linear_modified_moment_1d():
+    """With linear weights hat-v excludes the cell's own moment (Appendix A)."""
+    rec = Hweno1D()
+    C = rec.combined(np.eye(5), Options(linear_weights=True))
+    vh = rec.moment(C)
+    assert abs(vh[1]) < 1e-16           # no dependence on the own average
+    assert vh.shape == (5,)
+
+
+# ---------------------------------------------------------------------------
+# P6 / P7: free stream and conservation
+# ---------------------------------------------------------------------------
+
+PH = Physics(gamma=1.4, Pr=0.72, mu_ref=0.01)
+
+
+def _random_state_1d(n, seed):
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    U = np.zeros((2, 3, n))
+    U[0, 0] = 1.0 + 0.2 * np.sin(2 * np.pi * x) + 0.02 * rng.standard_normal(n)
+    U[0, 1] = 0.3 * U[0, 0] + 0.02 * rng.standard_normal(n)
+    U[0, 2] = 2.5 + 0.05 * rng.standard_normal(n)
+    U[1] = 0.003 * rng.standard_normal((3, n))
+    return U
+
+
+def _random_state_2d(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    U = np.zeros((3, 4, ny, nx))
+    U[0, 0] = 1.0 + 0.05 * rng.standard_normal((ny, nx))
+    U[0, 1] = 0.3 + 0.05 * rng.standard_normal((ny, nx))
+    U[0, 2] = -0.2 + 0.05 * rng.standard_normal((ny, nx))
+    U[0, 3] = 2.5 + 0.05 * rng.standard_normal((ny, nx))
+    U[1:] = 0.004 * rng.standard_normal((2, 4, ny, nx))
+    return U
+
+
+def test_free_stream():
+    s1 = Scheme1D(24, 0.0, 1.0, PH)
+    U = np.zeros((2, 3, 24))
+    U[0] = np.array([1.3, 0.4, 2.7])[:, None]
+    F, V, _ = s1.residual(U)
+    assert np.all(F[0] == 0.0)
+    assert np.abs(F[1]).max() < 1e-13 and np.abs(V).max() < 1e-15
+    s2 = Scheme2D(10, 9, 0.0, 1.0, 0.0, 1.0, PH)
+    U = np.zeros((3, 4, 9, 10))
+    U[0] = np.array([1.3, 0.4, -0.3, 2.7])[:, None, None]
+    F, V, _ = s2.residual(U)
+    assert np.all(F[0] == 0.0)
+    assert np.abs(F[1:]).max() < 1e-13 and np.abs(V).max() < 1e-15
+
+
+def test_discrete_conservation():
+    s1 = Scheme1D(32, 0.0, 1.0, PH)
+    F, _, _ = s1.residual(_random_state_1d(32, 3))
+    tot = F[0].sum(axis=-1) * s1.dx
+    assert np.abs(tot).max() < 1e-14 * np.abs(F[0]).max()
+    s2 = Scheme2D(12, 10, 0.0, 1.0, 0.0, 1.0, PH)
+    F, _, _ = s2.residual(_random_state_2d(12, 10, 4))
+    tot = F[0].sum(axis=(-1, -2)) * s2.dx * s2.dy
+    assert np.abs(tot).max() < 1e-14 * np.abs(F[0]).max()
+
+
+# ---------------------------------------------------------------------------
+# P8 / P9: exact residual and gradients on polynomial states (linear mode)
+# ---------------------------------------------------------------------------
+
+def _cell_moments_1d(expr, x, n, x0, x1):
+    dx = (x1 - x0) / n
+    F0 = sp.lambdify(x, sp.integrate(expr, x))
+    F1 = sp.lambdify(x, sp.integrate(expr * x, x))
+    xl = x0 + np.arange(n) * dx
+    xr = xl + dx
+    xc = xl + 0.5 * dx
+    I0 = F0(xr) - F0(xl)
+    I1 = F1(xr) - F1(xl) - xc * I0
+    return np.broadcast_to(I0 / dx, (n,)), np.broadcast_to(I1 / dx ** 2, (n,))
+
+
+def _cell_moments_2d(expr, x, y, n, x0, x1):
+    d = (x1 - x0) / n
+    lo = x0 + np.arange(n) * d
+    hi = lo + d
+    c = lo + 0.5 * d
+
+    def box(e):
+        P = sp.lambdify((x, y), sp.integrate(sp.integrate(e, x), y))
+        XH, YH = np.meshgrid(hi, hi)
+        XL, YL = np.meshgrid(lo, lo)
+        return np.broadcast_to(P(XH, YH) - P(XL, YH) - P(XH, YL) + P(XL, YL), (n, n))
+
+    I0 = box(expr)
+    XC, YC = np.meshgrid(c, c)
+    Ix = box(expr * x) - XC * I0
+    Iy = box(expr * y) - YC * I0
+    return I0 / d ** 2, Ix / d ** 3, Iy / d ** 3
+
+
+def _poly_state_1d(deg_u, deg_e):
+    x = sp.symbols('x', real=True)
+    rho = sp.Rational(13, 10)
+    u = sp.Rational(3, 10) - sp.Rational(1, 5) * x + (sp.Rational(1, 4) * x ** 2 if deg_u > 1 else 0)
+    e = 2 + sp.Rational(1, 2) * x - sp.Rational(3, 10) * x ** 2 + sp.Rational(1, 5) * x ** 3
+    if deg_e > 3:
+        e += sp.Rational(1, 10) * x ** 4
+    return x, rho, u, e
+
+
+def test_exact_residual_polynomial_1d():
+    ph = PH
+    x, rho, u, e = _poly_state_1d(1, 3)
+    g = sp.nsimplify(ph.gamma)
+    p = (g - 1) * rho * e
+    E = rho * (e + u * u / 2)
+    mu = sp.nsimplify(ph.mu_ref)
+    tau = sp.Rational(4, 3) * mu * sp.diff(u, x)
+    q = -g * mu * sp.diff(e, x) / sp.nsimplify(ph.Pr)
+    cons = [rho + 0 * x, rho * u, E]
+    flux = [rho * u, rho * u * u + p - tau, (E + p) * u - (tau * u - q)]
+    n = 14
+    s = Scheme1D(n, -1.0, 1.0, ph, Options(linear_weights=True), bc=('outflow', 'outflow'))
+    U = np.stack([np.stack(_cell_moments_1d(cf, x, n, -1.0, 1.0)) for cf in cons], axis=1)
+    F, _, _ = s.residual(U)
+    ex = np.stack([np.stack(_cell_moments_1d(-sp.diff(fl, x), x, n, -1.0, 1.0)) for fl in flux],
+                  axis=1)
+    sl = slice(4, n - 4)
+    scale = np.abs(ex[..., sl]).max()
+    assert np.abs(F[..., sl] - ex[..., sl]).max() < 1e-12 * max(scale, 1.0)
+
+
+def test_exact_gradients_polynomial_1d():
+    x, rho, u, e = _poly_state_1d(2, 4)
+    n = 14
+    s = Scheme1D(n, -1.0, 1.0, PH, Options(linear_weights=True), bc=('outflow', 'outflow'))
+    g = sp.nsimplify(PH.gamma)
+    E = rho * (e + u * u / 2)
+    cons = [rho + 0 * x, rho * u, E]
+    U = np.stack([np.stack(_cell_moments_1d(cf, x, n, -1.0, 1.0)) for cf in cons], axis=1)
+    s.residual(U)
+    grads = s.last['grads']                         # (4 pts, 2, n)
+    xc = -1.0 + (np.arange(n) + 0.5) * s.dx
+    pts = xc[None, :] + LGL_NODES[:, None] * s.dx
+    ux = sp.lambdify(x, sp.diff(u, x))(pts)
+    ex = sp.lambdify(x, sp.diff(e, x))(pts)
+    sl = slice(4, n - 4)
+    assert np.abs(grads[:, 0, sl] - ux[:, sl]).max() < 1e-11
+    assert np.abs(grads[:, 1, sl] - ex[:, sl]).max() < 1e-11
+    del g
+
+
+def _poly_state_2d(quad):
+    x, y = sp.symbols('x y', real=True)
+    rho = sp.Rational(6, 5)
+    u = sp.Rational(3, 10) + sp.Rational(1, 5) * x - sp.Rational(1, 10) * y
+    v = -sp.Rational(1, 5) + sp.Rational(1, 10) * x + sp.Rational(1, 4) * y
+    e = (2 + sp.Rational(1, 5) * x - sp.Rational(1, 10) * y + sp.Rational(1, 10) * x * y
+         + sp.Rational(1, 20) * x ** 3 - sp.Rational(1, 25) * y ** 3 + sp.Rational(1, 30) * x * y * y)
+    if quad:
+        u += sp.Rational(1, 10) * x * y - sp.Rational(1, 20) * x * x
+        v += sp.Rational(1, 12) * y * y
+        e += sp.Rational(1, 40) * x ** 2 * y ** 2 - sp.Rational(1, 50) * x ** 4
+    return x, y, rho, u, v, e
+
+
+def _cons_2d(rho, u, v, e):
+    E = rho * (e + (u * u + v * v) / 2)
+    return [rho, rho * u, rho * v, E]
+
+
+def test_exact_residual_polynomial_2d():
+    ph = PH
+    x, y, rho, u, v, e = _poly_state_2d(False)
+    g = sp.nsimplify(ph.gamma)
+    Pr = sp.nsimplify(ph.Pr)
+    mu = sp.nsimplify(ph.mu_ref)
+    cons = _cons_2d(rho, u, v, e)
+    E = cons[3]
+    p = (g - 1) * rho * e
+    ux, uy, vx, vy = sp.diff(u, x), sp.diff(u, y), sp.diff(v, x), sp.diff(v, y)
+    txx = mu * (sp.Rational(4, 3) * ux - sp.Rational(2, 3) * vy)
+    txy = mu * (uy + vx)
+    tyy = mu * (sp.Rational(4, 3) * vy - sp.Rational(2, 3) * ux)
+    f = [rho * u, rho * u * u + p - txx, rho * u * v - txy,
+         (E + p) * u - (txx * u + txy * v + g * mu * sp.diff(e, x) / Pr)]
+    gg = [rho * v, rho * u * v - txy, rho * v * v + p - tyy,
+          (E + p) * v - (txy * u + tyy * v + g * mu * sp.diff(e, y) / Pr)]
+    n = 12
+    s = Scheme2D(n, n, -1.0, 1.0, -1.0, 1.0, ph, Options(linear_weights=True),
+                 bc=('outflow',) * 4)
+    U = np.stack([np.stack(_cell_moments_2d(cf + 0 * x, x, y, n, -1.0, 1.0)) for cf in cons],
+                 axis=1)
+    F, _, _ = s.residual(U)
+    ex = np.stack([np.stack(_cell_moments_2d(-(sp.diff(f[c], x) + sp.diff(gg[c], y)),
+                                             x, y, n, -1.0, 1.0)) for c in range(4)], axis=1)
+    sl = (Ellipsis, slice(4, n - 4), slice(4, n - 4))
+    err = np.abs(F[sl] - ex[sl]).max()
+    assert err < 1e-12 * max(np.abs(ex[sl]).max(), 1.0)
+
+
+def test_exact_gradients_polynomial_2d():
+    x, y, rho, u, v, e = _poly_state_2d(True)
+    cons = _cons_2d(rho, u, v, e)
+    n = 12
+    s = Scheme2D(n, n, -1.0, 1.0, -1.0, 1.0, PH, Options(linear_weights=True),
+                 bc=('outflow',) * 4)
+    U = np.stack([np.stack(_cell_moments_2d(cf + 0 * x, x, y, n, -1.0, 1.0)) for cf in cons],
+                 axis=1)
+    s.residual(U)
+    grads = s.last['grads']                          # (21, 6, n, n)
+    d = s.dx
+    c = -1.0 + (np.arange(n) + 0.5) * d
+    XC, YC = np.meshgrid(c, c)
+    exprs = [sp.diff(w, z) for w in (u, v, e) for z in (x, y)]
+    fns = [sp.lambdify((x, y), ex_) for ex_ in exprs]
+    for k, (px, py) in enumerate(XFACE + YFACE + VOL):
+        X = XC + px * d
+        Y = YC + py * d
+        for q in range(6):
+            want = np.broadcast_to(fns[q](X, Y), X.shape)
+            got = grads[k, q]
+            assert np.abs(got[4:-4, 4:-4] - want[4:-4, 4:-4]).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# P10: convergence against Tables 5.1 / 5.2
+# ---------------------------------------------------------------------------
+
+def _rate(e0, e1, n0, n1):
+    return math.log(e0 / e1) / math.log(n1 / n0)
+
+
+def test_mms_1d_convergence_table_5_1():
+    tab = load_table('table_5_1_gr.txt')
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=0.01)
+    res = {}
+    for n in (80, 160):
+        s = Scheme1D(n, 0.0, 1.0, ph, Options(cfl=0.6))
+        m = MMS1D(s)
+        U, t, _ = rk.run(s, m.exact(0.0), 0.0, 0.1, rule='h53', source=m.source)
+        err = U[0, 0] - m.exact(t)[0, 0]
+        res[n] = (np.abs(err).max(), np.abs(err).mean())
+    for n in res:
+        for k in range(2):
+            assert tab[n][k] / 3.0 < res[n][k] < tab[n][k] * 3.0, (n, k, res[n], tab[n])
+    for k in range(2):
+        assert _rate(res[80][k], res[160][k], 80, 160) > 4.8
+
+
+def test_mms_2d_spatial_convergence():
+    """Residual truncation error: exact moments fed in, exact d/dt compared."""
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=0.01)
+    errs = {}
+    for lin in (True, False):
+        for n in (40, 80):
+            s = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, ph, Options(linear_weights=lin))
+            m = MMS2D(s)
+            F, _, _ = s.residual(m.exact(0.0), m.source(0.0))
+            E = F - m.exact_dt(0.0)
+            errs[lin, n] = [np.abs(E[k]).max() for k in range(3)]
+    assert _rate(errs[True, 40][0], errs[True, 80][0], 40, 80) > 4.8
+    for k in (1, 2):
+        assert _rate(errs[True, 40][k], errs[True, 80][k], 40, 80) > 3.8
+    # the nonlinear weights approach the linear ones on refined smooth meshes
+    assert errs[False, 80][0] < 3.0 * errs[True, 80][0]
+
+
+def test_mms_2d_run_convergence():
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=0.01)
+    res = {}
+    for n in (10, 20):
+        s = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, ph, Options(cfl=0.6))
+        m = MMS2D(s)
+        U, t, _ = rk.run(s, m.exact(0.0), 0.0, 0.1, rule='h53', source=m.source)
+        err = U[0, 0] - m.exact(t)[0, 0]
+        res[n] = (np.abs(err).max(), np.abs(err).mean())
+    for k in range(2):
+        assert _rate(res[10][k], res[20][k], 10, 20) > 4.5
+    # magnitudes: on the way to the 40x40 row of Table 5.2
+    tab = load_table('table_5_2_gr.txt')
+    assert res[20][0] > tab[40][0] and res[20][1] > tab[40][1]
+
+
+# ---------------------------------------------------------------------------
+# P13: equivariance under reflection and (2D) exchange of x and y
+# ---------------------------------------------------------------------------
+
+def test_reflection_equivariance_1d():
+    s = Scheme1D(20, 0.0, 1.0, PH)
+    U = _random_state_1d(20, 5)
+    par = np.array([1.0, -1.0, 1.0])
+    Um = np.stack([par[:, None] * U[0, :, ::-1], -par[:, None] * U[1, :, ::-1]])
+    F, V, _ = s.residual(U)
+    Fm, Vm, _ = s.residual(Um)
+    want = np.stack([par[:, None] * F[0, :, ::-1], -par[:, None] * F[1, :, ::-1]])
+    assert np.abs(Fm - want).max() < 1e-11 * np.abs(F).max()
+    assert np.abs(Vm[0] + par[:, None] * V[0, :, ::-1]).max() < 1e-14
+
+
+def test_reflection_and_swap_equivariance_2d():
+    n = 10
+    s = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, PH)
+    U = _random_state_2d(n, n, 6)
+    F, V, _ = s.residual(U)
+    tol = 1e-11 * np.abs(F).max()
+    # x -> -x: u odd, the xi-moment flips
+    par = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None]
+    sg = np.array([1.0, -1.0, 1.0])
+    Um = np.stack([sg[m] * par * U[m][..., ::-1] for m in range(3)])
+    Fm, Vm, _ = s.residual(Um)
+    want = np.stack([sg[m] * par * F[m][..., ::-1] for m in range(3)])
+    assert np.abs(Fm - want).max() < tol
+    # x <-> y: exchange i and j, u and v, xi and eta moments
+    perm = [0, 2, 1, 3]
+    Us = np.stack([U[m][perm].swapaxes(-1, -2) for m in (0, 2, 1)])
+    Fs, Vs, _ = s.residual(Us)
+    want = np.stack([F[m][perm].swapaxes(-1, -2) for m in (0, 2, 1)])
+    assert np.abs(Fs - want).max() < tol
+    wantV = np.stack([V[m][perm].swapaxes(-1, -2) for m in (1, 0)])
+    assert np.abs(Vs - wantV).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P15: PP wave-speed bound in the Euler limit (eq. (2.3), eq. (3.3))
+# ---------------------------------------------------------------------------
+
+def test_beta_pp_euler_limit():
+    g = 1.4
+    ph = Physics(gamma=g, mu_ref=0.0)
+    rho, u, p = 0.8, -0.6, 1.7
+    E = p / (g - 1) + 0.5 * rho * u * u
+    c = math.sqrt(g * p / rho)
+    want = abs(u) + math.sqrt((g - 1) / (2 * g)) * c
+    b1 = beta_pp1d(np.array([rho, rho * u, E]), 3.0, -2.0, ph)
+    assert abs(b1 - want) < 1e-14
+    v = 0.25
+    E2 = p / (g - 1) + 0.5 * rho * (u * u + v * v)
+    U2 = np.array([rho, rho * u, rho * v, E2])
+    s = np.array([1.0, 2.0, -1.0, 0.5, 3.0, -4.0])
+    assert abs(beta_pp2d(U2, s, ph, 0) - want) < 1e-14
+    want_y = abs(v) + math.sqrt((g - 1) / (2 * g)) * c
+    assert abs(beta_pp2d(U2, s, ph, 1) - want_y) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P11 / P17: positivity on a low-density double rarefaction; stage restarts
+# ---------------------------------------------------------------------------
+
+def _riemann_1d(n, left, right, gamma):
+    x = (np.arange(n) + 0.5) / n
+    U = np.zeros((2, 3, n))
+    for side, (r, u, p) in ((x < 0.5, left), (x >= 0.5, right)):
+        U[0, 0, side] = r
+        U[0, 1, side] = r * u
+        U[0, 2, side] = p / (gamma - 1) + 0.5 * r * u * u
+    return U
+
+
+def test_positivity_double_rarefaction():
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    n = 200
+    s = Scheme1D(n, 0.0, 1.0, ph, Options(cfl=0.3, b_visc=math.inf), bc=('outflow', 'outflow'))
+    U = _riemann_1d(n, (1.0, -2.0, 0.4), (1.0, 2.0, 0.4), ph.gamma)
+    t, pp = 0.0, 0
+    s.opts.t_final = 0.15
+    while t < 0.15 - 1e-12:
+        U, dt, info = rk.rk3_step(s, U, t)
+        t += dt
+        pp += info['pp_cells']
+        assert rk.admissible(U, ph.gamma)
+    assert pp > 0                      # the limiter is active on this problem
+    assert U[0, 0].min() > 0.0
+
+
+def test_smooth_run_limiter_inactive():
+    s = Scheme1D(64, 0.0, 2 * np.pi, PH, Options(cfl=0.3))
+    x = (np.arange(64) + 0.5) * s.dx
+    U = np.zeros((2, 3, 64))
+    U[0, 0] = 1.0 + 0.2 * np.sin(x)
+    U[0, 1] = U[0, 0]
+    U[0, 2] = 1.0 / 0.4 + 0.5 * U[0, 0]
+    U[1, 0] = 0.2 * (np.sin(x + s.dx / 2) + np.sin(x - s.dx / 2) - 2 * np.sin(x)) / 4 + \
+        0.2 * np.cos(x) * s.dx / 12
+    U[1, 1] = U[1, 0]
+    U[1, 2] = 0.5 * U[1, 0]
+    for _ in range(3):
+        U, dt, info = rk.rk3_step(s, U, 0.0)
+        assert info['pp_cells'] == 0 and info['restarts'] == 0
+
+
+def test_stage_restart_matches_halved_step():
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    n = 100
+    s = Scheme1D(n, 0.0, 1.0, ph, Options(b_visc=math.inf), bc=('outflow', 'outflow'))
+    U0 = _riemann_1d(n, (1.0, -2.0, 0.4), (1.0, 2.0, 0.4), ph.gamma)
+    big = 0.05                            # far above the CFL limit
+    U1, used, info = rk.rk3_step(s, U0, 0.0, dt=big)
+    assert info['restarts'] > 0
+    assert used == big / 2 ** info['restarts']
+    U2, used2, info2 = rk.rk3_step(s, U0, 0.0, dt=used)
+    assert info2['restarts'] == 0 and np.array_equal(U1, U2)
+
+
+def test_restart_cap_raises():
+    ph = Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    s = Scheme1D(50, 0.0, 1.0, ph, Options(max_halvings=1), bc=('outflow', 'outflow'))
+    U0 = _riemann_1d(50, (1.0, -2.0, 0.4), (1.0, 2.0, 0.4), ph.gamma)
+    with pytest.raises(rk.InadmissibleError):
+        rk.rk3_step(s, U0, 0.0, dt=1.0)
+
+
+# ---------------------------------------------------------------------------
+# Ghost cells (Remark 4.1)
+# ---------------------------------------------------------------------------
+
+def test_wall_ghost_parity_2d():
+    s = Scheme2D(6, 5, 0.0, 1.0, 0.0, 1.0, PH, bc=('noslip', 'slip', 'outflow', 'slip'))
+    U = _random_state_2d(6, 5, 7)
+    Ug = s.ghost(U)
+    H = 4
+    # no-slip at x-low: u, v odd; rho, E even; xi-moment with opposite parity
+    for g in range(1, H + 1):
+        src = Ug[:, :, H:H + 5, H + g - 1]
+        dst = Ug[:, :, H:H + 5, H - g]
+        s_ = np.array([1, -1, -1, 1.0])[:, None]
+        assert np.array_equal(dst[0], s_ * src[0])
+        assert np.array_equal(dst[1], -s_ * src[1])
+        assert np.array_equal(dst[2], s_ * src[2])
+    # slip at y-high: v odd, eta-moment with opposite parity
+    for g in range(1, H + 1):
+        src = Ug[:, :, H + 5 - g, :]
+        dst = Ug[:, :, H + 4 + g, :]
+        s_ = np.array([1, 1, -1, 1.0])[:, None]
+        assert np.array_equal(dst[0], s_ * src[0])
+        assert np.array_equal(dst[1], s_ * src[1])
+        assert np.array_equal(dst[2], -s_ * src[2])
+    # a mirrored constant state at rest stays at rest: zero mass flux at walls
+    U = np.zeros((3, 4, 5, 6))
+    U[0] = np.array([1.0, 0.0, 0.0, 2.5])[:, None, None]
+    F, _, _ = s.residual(U)
+    assert np.abs(F[0]).max() < 1e-13
