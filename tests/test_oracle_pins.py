@@ -607,3 +607,42 @@ def test_wall_ghost_parity_2d():
     U[0] = np.array([1.0, 0.0, 0.0, 2.5])[:, None, None]
     F, _, _ = s.residual(U)
     assert np.abs(F[0]).max() < 1e-13
+
+
+def test_rk_stages_use_modified_moments():
+    """dt = 0 limit of one step (eq. (2.12)) in linear mode, exact rationals.
+
+    Every stage replaces the first-order moment by hat-v of the stage input.
+    With linear weights hat-v is a fixed linear stencil T(ubar, vbar) (the
+    characteristic projection cancels), derived here from the moment
+    conditions (A.1), so the step output is a closed form.
+    """
+    xi = sp.symbols('xi')
+    a = sp.symbols('a0:5')
+    p = sum(a[k] * xi ** k for k in range(5))
+    h = sp.Rational(1, 2)
+    data = sp.symbols('um uc up vm vp')
+    eqs = [sp.integrate(p, (xi, d - h, d + h)) - val for d, val in zip((-1, 0, 1), data[:3])]
+    eqs += [sp.integrate(p * (xi - d), (xi, d - h, d + h)) - val
+            for d, val in zip((-1, 1), data[3:])]
+    sol = sp.solve(eqs, a)
+    g = (sp.Rational(199, 200), sp.Rational(1, 400), sp.Rational(1, 400))
+    p1 = data[1] + (data[1] - data[0]) * xi
+    p2 = data[1] + (data[2] - data[1]) * xi
+    u = p.subs(sol) / g[0] * g[0] + 0 * p1 + 0 * p2      # linear weights: u = p0
+    vh = sp.expand(sp.integrate(u * xi, (xi, -h, h)))
+    coef = [float(vh.coeff(s)) for s in data]
+
+    def T(ub, vb):
+        return (coef[0] * np.roll(ub, 1, -1) + coef[1] * ub + coef[2] * np.roll(ub, -1, -1)
+                + coef[3] * np.roll(vb, 1, -1) + coef[4] * np.roll(vb, -1, -1))
+
+    s = Scheme1D(16, 0.0, 1.0, PH, Options(linear_weights=True))
+    U = _random_state_1d(16, 9)
+    Un, _, _ = rk.rk3_step(s, U, 0.0, dt=0.0)
+    ub, vb = U[0], U[1]
+    v1 = T(ub, vb)
+    v2 = 0.75 * v1 + 0.25 * T(ub, v1)
+    v3 = v1 / 3.0 + 2.0 / 3.0 * T(ub, v2)
+    assert np.abs(Un[0] - ub).max() < 4e-16 * np.abs(ub).max()
+    assert np.abs(Un[1] - v3).max() < 1e-14
