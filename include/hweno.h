@@ -1,0 +1,170 @@
+/*
+ * hweno.h -- C ABI of the MI355X FP64 HWENO-GR library (libhweno.so).
+ *
+ * The library evaluates the per-stage spatial residual of the fifth-order
+ * finite-volume HWENO scheme with gradient reconstruction for the
+ * compressible Navier-Stokes equations (arXiv 2608.10569) and advances it
+ * with the SSP-RK3 scheme with modified first-order moments, on one GPU.
+ *
+ * Problem statement (Sec. 2.1 and 3.1 of the paper): a uniform grid of
+ * nx (x ny) cells on [x0,x1] (x [y0,y1]); unknowns per cell are the cell
+ * average and the scaled first-order moments of the conserved variables
+ * u = (rho, rho*u, (rho*v,) E); ideal gas with ratio of specific heats
+ * gamma; viscous terms with the dynamic viscosity mu(T) (the paper's 1/Re)
+ * and the Prandtl number Pr; ghost-cell boundary conditions of Remark 4.1.
+ *
+ * State layout ("D1"): a contiguous FP64 array U[m][c][j][i] (2D) or
+ * U[m][c][i] (1D), x index fastest, interior cells only:
+ *   m = 0 cell average, 1 xi-moment (1/|I| int u (x-x_i)/dx), 2 eta-moment
+ *   (2D only); c = rho, rho*u, (rho*v,) E.
+ *   2D: 12 * nx * ny doubles;  1D: 6 * nx doubles.
+ *
+ * Conventions
+ *  - Every function returns hweno_status; nothing throws or aborts across
+ *    the ABI.  hweno_status_string() names a status.
+ *  - Array arguments documented as "device" are GPU pointers (HIP device
+ *    memory of the device current when the context was created).  The
+ *    caller owns every pointer it passes; the library keeps none after a
+ *    call returns, except the workspace given to hweno_set_workspace.
+ *  - The library allocates no device memory.  All scratch lives in a
+ *    caller-provided workspace of hweno_workspace_bytes() bytes.
+ *  - Calls are ordered on the HIP stream set with hweno_set_stream (default:
+ *    the null stream).  hweno_rk_step and hweno_residual with a non-NULL
+ *    diag synchronise that stream once; other calls are asynchronous.
+ *  - Device faults surface at the next synchronising call as
+ *    HWENO_E_DEVICE.  A context is not thread-safe; distinct contexts are
+ *    independent.
+ */
+#ifndef HWENO_H
+#define HWENO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HWENO_API __attribute__((visibility("default")))
+
+typedef struct hweno_ctx hweno_ctx;
+
+typedef enum hweno_status {
+    HWENO_OK = 0,
+    HWENO_E_INVAL = 1,          /* invalid argument (size, parameter, BC pairing, NULL) */
+    HWENO_E_DEVICE = 2,         /* HIP runtime or kernel error */
+    HWENO_E_WORKSPACE = 3,      /* no workspace set, or too small / misaligned */
+    HWENO_E_INADMISSIBLE = 4,   /* restart cap reached: a stage kept nonpositive rho or p */
+    HWENO_E_NONFINITE = 5,      /* input state with non-finite values or rho<=0 / p<=0 */
+    HWENO_E_STATE = 6           /* no state set yet */
+} hweno_status;
+
+/* Ghost-cell rules of Remark 4.1. */
+typedef enum hweno_bc_kind {
+    HWENO_BC_PERIODIC = 0,      /* must be set on both sides of a direction */
+    HWENO_BC_OUTFLOW = 1,       /* ghost cells copy the adjacent interior cell (average and moments) */
+    HWENO_BC_INFLOW = 2,        /* prescribed state (average), zero moments */
+    HWENO_BC_SLIP = 3,          /* reflective / slip wall / symmetry: normal velocity odd */
+    HWENO_BC_NOSLIP = 4         /* adiabatic no-slip wall: both velocity components odd */
+} hweno_bc_kind;
+
+typedef struct hweno_grid {
+    int dim;                    /* 1 or 2 */
+    int nx, ny;                 /* interior cells; each >= 4; ny ignored for dim = 1 */
+    double x0, x1, y0, y1;      /* domain; x1 > x0 (and y1 > y0 in 2D) */
+} hweno_grid;
+
+/* Eq. (2.1) / (3.1): the paper's 1/Re is mu(T) = mu_ref * (T/T_ref)^mu_exp
+ * with T = p/rho; mu_exp = 0 is the paper's constant viscosity. */
+typedef struct hweno_physics {
+    double gamma;               /* > 1 */
+    double Pr;                  /* > 0 */
+    double mu_ref;              /* >= 0 (0: Euler limit) */
+    double mu_exp;              /* exponent of the power law; 0 = constant */
+    double T_ref;               /* > 0 */
+} hweno_physics;
+
+typedef struct hweno_bcs {
+    int kind[4];                /* hweno_bc_kind for xlo, xhi, ylo, yhi (1D: first two) */
+    double inflow[4][4];        /* per side, primitive (rho, u, v, p) used with HWENO_BC_INFLOW;
+                                   1D uses (rho, u, p) in the first three slots */
+} hweno_bcs;
+
+/* Scheme constants (Sec. 5 preamble and Appendix A). */
+typedef struct hweno_options {
+    double cfl;                 /* CFL number of the time-step rule (paper: 0.6) */
+    double b_visc;              /* viscous time-step constant b (paper: 0.001); <= 0 disables */
+    double eps_pp;              /* positivity floor (paper: 1e-12) */
+    double eps_weno;            /* nonlinear-weight epsilon (paper: 1e-8) */
+    double t_final;             /* steps are clipped to end at t_final; <= 0: no clipping */
+    int linear_weights;         /* 1: omega = gamma (test mode); 0: nonlinear weights */
+    int max_halvings;           /* restarts with dt/2 allowed per step (>= 0) */
+} hweno_options;
+
+/* Diagnostics of the last call (Sec. 5 preamble; Table 5.3 PP activity). */
+typedef struct hweno_diag {
+    double t;                   /* time after the call */
+    double dt;                  /* step size used (rk_step) */
+    double alpha_star;          /* max over interior face traces of max(|u|,|v|) + c, stage 1 */
+    double beta_max;            /* max Lax-Friedrichs coefficient over faces (all stages) */
+    double min_rho, min_p;      /* min cell-average density / pressure of the last stage */
+    unsigned long long pp_cells;/* cell-stages where the positivity limiter acted */
+    int restarts;               /* dt halvings taken by this step */
+    int pad;
+} hweno_diag;
+
+/* Fills the paper's constants: cfl 0.6, b 0.001, eps_pp 1e-12, eps_weno 1e-8,
+ * no clipping, nonlinear weights, 40 halvings. */
+HWENO_API hweno_status hweno_default_options(hweno_options* opt);
+
+/* Validates the problem and creates a context (host memory only).
+ * Errors: HWENO_E_INVAL for a NULL argument, dim not 1/2, nx/ny < 4,
+ * empty domain, gamma <= 1, Pr <= 0, mu_ref < 0, T_ref <= 0, unknown BC
+ * kind, a periodic side paired with a non-periodic one, inflow density or
+ * pressure <= 0, cfl <= 0, eps_pp <= 0, eps_weno <= 0, max_halvings < 0. */
+HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
+                                    const hweno_bcs* bcs, const hweno_options* opt,
+                                    hweno_ctx** out);
+
+HWENO_API hweno_status hweno_destroy(hweno_ctx* ctx);
+
+/* Device bytes the caller must provide (256-byte aligned). */
+HWENO_API hweno_status hweno_workspace_bytes(const hweno_ctx* ctx, size_t* bytes);
+
+/* Hands the library a device buffer of at least hweno_workspace_bytes();
+ * it stays owned by the caller and must outlive the context's use. */
+HWENO_API hweno_status hweno_set_workspace(hweno_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Stream (hipStream_t) on which all later work of this context is ordered. */
+HWENO_API hweno_status hweno_set_stream(hweno_ctx* ctx, void* hip_stream);
+
+/* Copies a D1 state (device) in and sets the time.  Asynchronous. */
+HWENO_API hweno_status hweno_set_state(hweno_ctx* ctx, const double* U, double t);
+
+/* Copies the current state out (device, D1) and returns the time. */
+HWENO_API hweno_status hweno_get_state(hweno_ctx* ctx, double* U, double* t);
+
+/* Spatial residual of eq. (2.2) / (3.2) at the state U (device, D1):
+ * R (device, same layout as U) receives (F^1, F^2[, F^3]); Vhat (device)
+ * receives the modified moments of eq. (2.4) / (3.4): 1D Vhat[c][i]
+ * (3*nx), 2D Vhat[q][j][i] with q = hat-v of c = 0..3, then hat-w of
+ * c = 0..3 (8*nx*ny).  Uses the workspace; leaves the context state alone.
+ * diag may be NULL (no synchronisation). */
+HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R, double* Vhat,
+                                      hweno_diag* diag);
+
+/* One SSP-RK3 step of eq. (2.12) on the context state.  dt > 0: that step;
+ * dt <= 0: dt = min(cfl*h/alpha*, b*h^2/mu_ref, t_final - t) with alpha*
+ * from the stage-1 face traces (Sec. 5 preamble).  A stage with a cell of
+ * nonpositive density or pressure (or a non-finite value) rejects the step,
+ * which is redone from t^n with dt/2, at most max_halvings times; then
+ * HWENO_E_INADMISSIBLE with the state unchanged.  Synchronises once per
+ * attempt. */
+HWENO_API hweno_status hweno_rk_step(hweno_ctx* ctx, double dt, hweno_diag* diag);
+
+HWENO_API const char* hweno_status_string(hweno_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWENO_H */

@@ -157,10 +157,18 @@ class Scheme2D:
         Vhat[2, 4, ny, nx] = (hat-v, hat-w) and diag = dict(alpha, beta_max,
         pp_cells).  ``source`` (optional) is added to F.
         """
+        return self.residual_ghosted(self.ghost(U), source)
+
+    def residual_ghosted(self, Ug, source=None):
+        """The residual of the interior of an already ghosted array (halo 4).
+
+        Lets a window of a large grid be evaluated on its own: the interior of
+        ``Ug`` may be any sub-block, its halo the true neighbours.
+        """
         ph, op, rec = self.phys, self.opts, self.rec
         g = ph.gamma
-        dx, dy, nx, ny = self.dx, self.dy, self.nx, self.ny
-        Ug = self.ghost(U)
+        dx, dy = self.dx, self.dy
+        ny, nx = Ug.shape[2] - 2 * HALO, Ug.shape[3] - 2 * HALO
         r = self.reconstruct(Ug)             # region c: ghosted index - 1
 
         # 4. weak-derivative moments (eqs. (3.6)-(3.8)) on region c shrunk by 1

@@ -1,0 +1,695 @@
+// 2D HWENO-GR residual and SSP-RK3 stage update (Sec. 3 of arXiv 2608.10569)
+// as a pipeline of HIP kernels over a ghosted structure-of-arrays grid.
+//
+//   ghost_x, ghost_y : halo of width 4 (Remark 4.1)
+//   recon            : characteristic HWENO in the x- and y-bases (eq. (3.4)),
+//                      positivity limiter on the face values, wbar, hat-v/w,
+//                      CFL wave speed                 [cells of halo ring 3]
+//   rbar             : interface averages, face moments, weak-derivative
+//                      moments (eqs. (3.6)-(3.8))      [halo ring 2]
+//   grad             : gradient HWENO (eq. (3.9)) at 12 face + 9 volume points,
+//                      volume-flux quadratures         [halo ring 1]
+//   flux_x, flux_y   : PP Lax-Friedrichs fluxes at face Gauss points (eq. (3.3))
+//   update           : assembly of eq. (3.2) and the stage combination of the
+//                      SSP-RK3 scheme with modified moments (eq. (2.12))
+//
+// Every intermediate lives in HBM, laid out component-major over the ghosted
+// grid so that consecutive lanes touch consecutive cells.
+
+#include "hweno_kernels.h"
+
+namespace hw {
+
+namespace {
+
+constexpr int HALO = 4;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One atomic per wavefront for the reductions below (lane 0 issues it).
+__device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0 && v > -INFINITY) atomicMax(slot, dkey(v));
+}
+__device__ __forceinline__ void red_min(unsigned long long* slot, double v) {
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0 && v < INFINITY) atomicMin(slot, dkey(v));
+}
+__device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long long v) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(slot, v);
+}
+__device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
+    unsigned long long s = wave_sum((unsigned long long)v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(slot, (unsigned int)s);
+}
+
+// ---------------------------------------------------------------------------
+// Ghost cells (Remark 4.1).  x sweep on interior rows, then y sweep on every
+// column, so corner cells compose the two rules.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N, long long dst,
+                                         long long src) {
+    if (sd.kind == 2) {   // inflow: prescribed average, zero moments
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            S[c * N + dst] = sd.inflow[c];
+            S[(4 + c) * N + dst] = 0.0;
+            S[(8 + c) * N + dst] = 0.0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) S[q * N + dst] = sd.sign[q] * S[q * N + src];
+}
+
+__global__ void k_ghost2_x(Grid2 g, double* S) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.ny * 2 * HALO) return;
+    const int j = HALO + t / (2 * HALO);
+    const int gi = t % (2 * HALO);
+    const int right = gi >= HALO;
+    const int d = (gi % HALO) + 1;                      // distance from the boundary
+    const Side& sd = g.side[right];
+    int di, si;
+    if (!right) {
+        di = HALO - d;
+        si = sd.kind == 0 ? HALO + g.nx - d : (sd.kind == 1 ? HALO : HALO + d - 1);
+    } else {
+        di = HALO + g.nx - 1 + d;
+        si = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.nx - 1 : HALO + g.nx - d);
+    }
+    const long long row = (long long)j * g.NX;
+    fill_one(sd, S, g.ncell, row + di, row + si);
+}
+
+__global__ void k_ghost2_y(Grid2 g, double* S) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.NX * 2 * HALO) return;
+    const int i = t % g.NX;
+    const int gj = t / g.NX;
+    const int top = gj >= HALO;
+    const int d = (gj % HALO) + 1;
+    const Side& sd = g.side[2 + top];
+    int dj, sj;
+    if (!top) {
+        dj = HALO - d;
+        sj = sd.kind == 0 ? HALO + g.ny - d : (sd.kind == 1 ? HALO : HALO + d - 1);
+    } else {
+        dj = HALO + g.ny - 1 + d;
+        sj = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.ny - 1 : HALO + g.ny - d);
+    }
+    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i);
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic reconstruction + positivity limiter.
+// Block: 32 cells x 8 threads; thread (b, k) projects onto characteristic
+// field k of basis b (0: x-Jacobian, 1: y-Jacobian), reconstructs it, and
+// after an LDS exchange owns conservative component k of basis b.
+// ---------------------------------------------------------------------------
+constexpr int RC_CELLS = 32;
+
+__global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restrict__ S) {
+    __shared__ double sh[8 * 16 * RC_CELLS];
+    __shared__ double redA[8 * RC_CELLS];
+    __shared__ double redB[8 * RC_CELLS];
+    const Consts& K = g.K;
+    const int tid = threadIdx.x;
+    const int cl = tid & (RC_CELLS - 1);
+    const int bk = tid / RC_CELLS;
+    const int b = bk >> 2, k = bk & 3;
+    const int wc = g.NX - 2;
+    const long long nreg = (long long)wc * (g.NY - 2);
+    const long long cid = (long long)blockIdx.x * RC_CELLS + cl;
+    const bool valid = cid < nreg;
+    int j = 1, i = 1;
+    if (valid) {
+        j = 1 + (int)(cid / wc);
+        i = 1 + (int)(cid % wc);
+    }
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+
+    double ub[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ub[c] = S[c * N + cell];
+    double Lr[4], Rr[4];
+    eig2_rows(K, ub, b, k, Lr, Rr);
+
+    double a[17];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += Lr[c] * S[c * N + nb];
+        a[s] = acc;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int s = 2 * e + 1;   // cells 2, 4, 6, 8
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+        double ax = 0.0, ay = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ax += Lr[c] * S[(4 + c) * N + nb];
+            ay += Lr[c] * S[(8 + c) * N + nb];
+        }
+        a[9 + e] = ax;
+        a[13 + e] = ay;
+    }
+    double C[15];
+    hweno2d(a, K, C);
+    double out[16];
+    if (b == 0) eval_xface(C, out);
+    else eval_yface(C, out);
+    eval_vol(C, out + 6);
+    out[15] = b == 0 ? moment_xi(C) : moment_eta(C);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) sh[(bk * 16 + o) * RC_CELLS + cl] = out[o];
+    __syncthreads();
+    // back to conservative component k of basis b
+    double U[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        double acc = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc += Rr[f] * sh[((b * 4 + f) * 16 + o) * RC_CELLS + cl];
+        U[o] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 16; ++o) sh[(bk * 16 + o) * RC_CELLS + cl] = U[o];
+    __syncthreads();
+
+    // positivity limiter: theta over 6 face + 9 volume points of both bases
+    auto comp = [&](int bb, int c, int o) { return sh[((bb * 4 + c) * 16 + o) * RC_CELLS + cl]; };
+    double rmin = INFINITY;
+    for (int o = k; o < 15; o += 4) rmin = fmin(rmin, comp(b, 0, o));
+    redA[bk * RC_CELLS + cl] = rmin;
+    __syncthreads();
+    rmin = redA[cl];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) rmin = fmin(rmin, redA[q * RC_CELLS + cl]);
+    const double rbar = ub[0];
+    const double pbar = pressure2(K, ub[0], ub[1], ub[2], ub[3]);
+    const double eps = fmin(fmin(K.eps_pp, rbar), pbar);
+    const double th1 = rmin < eps ? (rbar - eps) / (rbar - rmin) : 1.0;
+    double tmin = 1.0;
+    for (int o = k; o < 15; o += 4) {
+        const double rt = rbar + th1 * (comp(b, 0, o) - rbar);
+        const double pt = pressure2(K, rt, comp(b, 1, o), comp(b, 2, o), comp(b, 3, o));
+        if (pt < eps) tmin = fmin(tmin, (pbar - eps) / (pbar - pt));
+    }
+    redB[bk * RC_CELLS + cl] = tmin;
+    __syncthreads();
+    double th2 = redB[cl];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) th2 = fmin(th2, redB[q * RC_CELLS + cl]);
+
+    const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
+    if (valid) {
+        double* F = b == 0 ? g.xf : g.yf;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            const double ut = k == 0 ? rbar + th1 * (U[o] - rbar) : U[o];
+            F[(o * 4 + k) * N + cell] = ub[k] + th2 * (ut - ub[k]);
+        }
+        if (k == 0) {
+            // wbar of (u, v, e) from this basis' unlimited volume values
+            double su = 0.0, sv = 0.0, se = 0.0;
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+#pragma unroll
+                for (int gg = 0; gg < 3; ++gg) {
+                    const int o = 6 + 3 * h + gg;
+                    const double w = (h == 1 ? GW1 : GW0) * (gg == 1 ? GW1 : GW0);
+                    const double r = comp(b, 0, o);
+                    const double u = comp(b, 1, o) / r, v = comp(b, 2, o) / r;
+                    const double e = comp(b, 3, o) / r - 0.5 * (u * u + v * v);
+                    su += w * u;
+                    sv += w * v;
+                    se += w * e;
+                }
+            }
+            g.wb[(b * 3 + 0) * N + cell] = su;
+            g.wb[(b * 3 + 1) * N + cell] = sv;
+            g.wb[(b * 3 + 2) * N + cell] = se;
+        }
+    }
+    if (inter) {
+        double* V = b == 0 ? g.xv : g.yv;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) V[(q * 4 + k) * N + cell] = U[6 + q];
+        g.vk[(b * 4 + k) * N + cell] = U[15];
+    }
+    // CFL wave speed over the limited face traces of interior cells
+    double amax = -INFINITY;
+    if (inter && k == 1) {
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            double Ul[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double x = comp(b, c, o);
+                const double ut = c == 0 ? rbar + th1 * (x - rbar) : x;
+                Ul[c] = ub[c] + th2 * (ut - ub[c]);
+            }
+            const double p = pressure2(K, Ul[0], Ul[1], Ul[2], Ul[3]);
+            const double cs = sqrt(K.gamma * p / Ul[0]);
+            const double sp = fmax(fabs(Ul[1] / Ul[0]), fabs(Ul[2] / Ul[0])) + cs;
+            amax = fmax(amax, sp);
+        }
+    }
+    red_max(&g.red->alpha_key, amax);
+    red_add(&g.red->pp_cells, (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// Weak-derivative moments (eqs. (3.6)-(3.8)) on cells of halo ring 2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void prim3(const double* F, long long N, long long cell, int p,
+                                      double* w) {
+    const double r = F[(p * 4 + 0) * N + cell];
+    const double u = F[(p * 4 + 1) * N + cell] / r;
+    const double v = F[(p * 4 + 2) * N + cell] / r;
+    w[0] = u;
+    w[1] = v;
+    w[2] = F[(p * 4 + 3) * N + cell] / r - 0.5 * (u * u + v * v);
+}
+
+__global__ __launch_bounds__(256) void k_rbar2(Grid2 g) {
+    const int wc = g.NX - 4;
+    const long long nreg = (long long)wc * (g.NY - 4);
+    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cid >= nreg) return;
+    const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    const long long L = cell - 1, Rt = cell + 1, B = cell - g.NX, T = cell + g.NX;
+    double hl[3][3], hr[3][3], hb[3][3], ht[3][3];   // [G][w]
+#pragma unroll
+    for (int G = 0; G < 3; ++G) {
+        double a[3], c[3];
+        prim3(g.xf, N, L, 3 + G, a);
+        prim3(g.xf, N, cell, G, c);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) hl[G][w] = 0.5 * (a[w] + c[w]);
+        prim3(g.xf, N, cell, 3 + G, a);
+        prim3(g.xf, N, Rt, G, c);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) hr[G][w] = 0.5 * (a[w] + c[w]);
+        prim3(g.yf, N, B, 3 + G, a);
+        prim3(g.yf, N, cell, G, c);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) hb[G][w] = 0.5 * (a[w] + c[w]);
+        prim3(g.yf, N, cell, 3 + G, a);
+        prim3(g.yf, N, T, G, c);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) ht[G][w] = 0.5 * (a[w] + c[w]);
+    }
+    const double idx = g.K.idx, idy = g.K.idy;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        const double Wl0 = GW0 * hl[0][w] + GW1 * hl[1][w] + GW0 * hl[2][w];
+        const double Wr0 = GW0 * hr[0][w] + GW1 * hr[1][w] + GW0 * hr[2][w];
+        const double Wl1 = GW0 * GS * (hl[2][w] - hl[0][w]);
+        const double Wr1 = GW0 * GS * (hr[2][w] - hr[0][w]);
+        const double Wb0 = GW0 * hb[0][w] + GW1 * hb[1][w] + GW0 * hb[2][w];
+        const double Wt0 = GW0 * ht[0][w] + GW1 * ht[1][w] + GW0 * ht[2][w];
+        const double Wb1 = GW0 * GS * (hb[2][w] - hb[0][w]);
+        const double Wt1 = GW0 * GS * (ht[2][w] - ht[0][w]);
+        const double wbx = g.wb[(0 * 3 + w) * N + cell];
+        const double wby = g.wb[(1 * 3 + w) * N + cell];
+        // l = 0 (x): moments 0, xi, eta
+        g.rb[((0 * 3 + w) * 3 + 0) * N + cell] = (Wr0 - Wl0) * idx;
+        g.rb[((0 * 3 + w) * 3 + 1) * N + cell] = (0.5 * (Wr0 + Wl0) - wbx) * idx;
+        g.rb[((0 * 3 + w) * 3 + 2) * N + cell] = (Wr1 - Wl1) * idx;
+        // l = 1 (y)
+        g.rb[((1 * 3 + w) * 3 + 0) * N + cell] = (Wt0 - Wb0) * idy;
+        g.rb[((1 * 3 + w) * 3 + 1) * N + cell] = (Wt1 - Wb1) * idy;
+        g.rb[((1 * 3 + w) * 3 + 2) * N + cell] = (0.5 * (Wt0 + Wb0) - wby) * idy;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient reconstruction (eq. (3.9)) on halo ring 1; block 32 cells x 6
+// (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also form
+// the volume-flux quadratures of eq. (3.2).
+// ---------------------------------------------------------------------------
+constexpr int GR_CELLS = 32;
+
+__global__ __launch_bounds__(192) void k_grad2(Grid2 g) {
+    __shared__ double shv[6 * 9 * GR_CELLS];
+    const Consts& K = g.K;
+    const int tid = threadIdx.x;
+    const int cl = tid % GR_CELLS;
+    const int s = tid / GR_CELLS;
+    const int w = s >> 1, l = s & 1;
+    const int wc = g.NX - 6;
+    const long long nreg = (long long)wc * (g.NY - 6);
+    const long long cid = (long long)blockIdx.x * GR_CELLS + cl;
+    const bool valid = cid < nreg;
+    int j = 3, i = 3;
+    if (valid) {
+        j = 3 + (int)(cid / wc);
+        i = 3 + (int)(cid % wc);
+    }
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    const double* R0 = g.rb + ((l * 3 + w) * 3 + 0) * N;
+    const double* R1 = g.rb + ((l * 3 + w) * 3 + 1) * N;
+    const double* R2 = g.rb + ((l * 3 + w) * 3 + 2) * N;
+    double a[17];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        a[q] = R0[cell + (long long)(q / 3 - 1) * g.NX + (q % 3 - 1)];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = 2 * e + 1;
+        const long long nb = cell + (long long)(q / 3 - 1) * g.NX + (q % 3 - 1);
+        a[9 + e] = R1[nb];
+        a[13 + e] = R2[nb];
+    }
+    double C[15];
+    hweno2d(a, K, C);
+    double fo[12], vo[9];
+    eval_xface(C, fo);
+    eval_yface(C, fo + 6);
+    eval_vol(C, vo);
+    if (valid) {
+#pragma unroll
+        for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
+    }
+    const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * GR_CELLS + cl] = vo[q];
+    __syncthreads();
+    if (inter && s < 2) {
+        const double* V = s == 0 ? g.xv : g.yv;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+#pragma unroll
+            for (int gg = 0; gg < 3; ++gg) {
+                const int q = 3 * h + gg;
+                const double wq = (h == 1 ? GW1 : GW0) * (gg == 1 ? GW1 : GW0);
+                double Uq[4], sq[6], f[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Uq[c] = V[(q * 4 + c) * N + cell];
+#pragma unroll
+                for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
+                if (s == 0) flux2<0>(K, Uq, sq, f);
+                else flux2<1>(K, Uq, sq, f);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g.vf[(s * 4 + c) * N + cell] = acc[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes (eq. (3.3)): x-faces (j, i+1/2) for interior rows, i from the
+// last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
+// max over the face's three Gauss points and both sides.
+// ---------------------------------------------------------------------------
+template <int d>
+__global__ __launch_bounds__(256) void k_flux2(Grid2 g) {
+    const Consts& K = g.K;
+    const int nfi = d == 0 ? g.nx + 1 : g.nx;
+    const int nfj = d == 0 ? g.ny : g.ny + 1;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double bmax = -INFINITY;
+    if (t < (long long)nfi * nfj) {
+        const int fj = (int)(t / nfi), fi = (int)(t % nfi);
+        const int j = d == 0 ? HALO + fj : HALO - 1 + fj;
+        const int i = d == 0 ? HALO - 1 + fi : HALO + fi;
+        const long long N = g.ncell;
+        const long long cm = (long long)j * g.NX + i;
+        const long long cp = d == 0 ? cm + 1 : cm + g.NX;
+        const double* F = d == 0 ? g.xf : g.yf;
+        const int pg = d == 0 ? 0 : 6;
+        double Um[3][4], Up[3][4], fm[3][4], fp[3][4];
+        double beta = -INFINITY;
+#pragma unroll
+        for (int G = 0; G < 3; ++G) {
+            double sm[6], sp[6];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                Um[G][c] = F[((3 + G) * 4 + c) * N + cm];
+                Up[G][c] = F[(G * 4 + c) * N + cp];
+            }
+#pragma unroll
+            for (int z = 0; z < 6; ++z) {
+                sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
+                sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
+            }
+            flux2<d>(K, Um[G], sm, fm[G]);
+            flux2<d>(K, Up[G], sp, fp[G]);
+            beta = fmax(beta, fmax(speed2<d>(K, Um[G], sm), speed2<d>(K, Up[G], sp)));
+        }
+        double* out = d == 0 ? g.fx : g.fy;
+#pragma unroll
+        for (int G = 0; G < 3; ++G) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                out[(G * 4 + c) * N + cm] =
+                    0.5 * (fm[G][c] + fp[G][c] - beta * (Up[G][c] - Um[G][c]));
+        }
+        bmax = beta;
+    }
+    red_max(&g.red->beta_key, bmax);
+}
+
+// ---------------------------------------------------------------------------
+// Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form).
+// stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3 stage.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_update2(Grid2 g, int stage, const double* __restrict__ S0,
+                          const double* __restrict__ Sin, double* __restrict__ Sout,
+                          double* __restrict__ Rout, double* __restrict__ Vout) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double rmin = INFINITY, pmin = INFINITY;
+    unsigned int bad = 0;
+    if (t < nint) {
+        const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
+        const long long N = g.ncell;
+        const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
+        const double idx = g.K.idx, idy = g.K.idy;
+        double Fm[3][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double dfx = 0.0, sfx = 0.0, dfxe = 0.0, dgy = 0.0, sgy = 0.0, dgyx = 0.0;
+#pragma unroll
+            for (int G = 0; G < 3; ++G) {
+                const double wg = G == 1 ? GW1 : GW0;
+                const double xg = G == 0 ? -GS : (G == 1 ? 0.0 : GS);
+                const double fr = g.fx[(G * 4 + c) * N + cell];
+                const double fl = g.fx[(G * 4 + c) * N + cell - 1];
+                const double gt = g.fy[(G * 4 + c) * N + cell];
+                const double gb = g.fy[(G * 4 + c) * N + cell - g.NX];
+                dfx += wg * (fr - fl);
+                sfx += wg * (fl + fr);
+                dfxe += wg * xg * (fr - fl);
+                dgy += wg * (gt - gb);
+                sgy += wg * (gb + gt);
+                dgyx += wg * xg * (gt - gb);
+            }
+            Fm[0][c] = -dfx * idx - dgy * idy;
+            Fm[1][c] = -sfx * (0.5 * idx) - dgyx * idy + g.vf[c * N + cell] * idx;
+            Fm[2][c] = -dfxe * idx - sgy * (0.5 * idy) + g.vf[(4 + c) * N + cell] * idy;
+        }
+        if (stage == 0) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Rout[(m * 4 + c) * nint + t] = Fm[m][c];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Vout[q * nint + t] = g.vk[q * N + cell];
+        } else {
+            const double dt = g.red->dt;
+            double nw[12];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double in0 = Sin[c * N + cell];
+                const double in1 = g.vk[c * N + cell];
+                const double in2 = g.vk[(4 + c) * N + cell];
+                if (stage == 1) {
+                    nw[c] = in0 + dt * Fm[0][c];
+                    nw[4 + c] = in1 + dt * Fm[1][c];
+                    nw[8 + c] = in2 + dt * Fm[2][c];
+                    g.vn[c * N + cell] = in1;
+                    g.vn[(4 + c) * N + cell] = in2;
+                } else {
+                    const double a = stage == 2 ? 0.75 : 1.0 / 3.0;
+                    const double bb = stage == 2 ? 0.25 : 2.0 / 3.0;
+                    nw[c] = a * S0[c * N + cell] + bb * (in0 + dt * Fm[0][c]);
+                    nw[4 + c] = a * g.vn[c * N + cell] + bb * (in1 + dt * Fm[1][c]);
+                    nw[8 + c] = a * g.vn[(4 + c) * N + cell] + bb * (in2 + dt * Fm[2][c]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 12; ++q) Sout[q * N + cell] = nw[q];
+            const double p = pressure2(g.K, nw[0], nw[1], nw[2], nw[3]);
+            rmin = nw[0];
+            pmin = p;
+            bool ok = nw[0] > 0.0 && p > 0.0;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) ok = ok && isfinite(nw[q]);
+            bad = ok ? 0u : 1u;
+        }
+    }
+    if (stage > 0) {
+        red_min(&g.red->min_rho_key, rmin);
+        red_min(&g.red->min_p_key, pmin);
+        red_add32(&g.red->bad[stage], bad);
+    }
+}
+
+__global__ void k_copy_in2(Grid2 g, const double* __restrict__ U, double* __restrict__ S) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nint * 12) return;
+    const int q = (int)(t / nint);
+    const long long r = t % nint;
+    const int jj = (int)(r / g.nx), ii = (int)(r % g.nx);
+    S[q * g.ncell + (long long)(jj + HALO) * g.NX + ii + HALO] = U[t];
+}
+
+__global__ void k_copy_out2(Grid2 g, const double* __restrict__ S, double* __restrict__ U) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nint * 12) return;
+    const int q = (int)(t / nint);
+    const long long r = t % nint;
+    const int jj = (int)(r / g.nx), ii = (int)(r % g.nx);
+    U[t] = S[q * g.ncell + (long long)(jj + HALO) * g.NX + ii + HALO];
+}
+
+// Input admissibility (finite values, positive density and pressure).
+__global__ void k_check2(Grid2 g, const double* __restrict__ S) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned int bad = 0;
+    if (t < nint) {
+        const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
+        const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
+        double q[12];
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            q[k] = S[k * g.ncell + cell];
+            ok = ok && isfinite(q[k]);
+        }
+        ok = ok && q[0] > 0.0 && pressure2(g.K, q[0], q[1], q[2], q[3]) > 0.0;
+        bad = ok ? 0u : 1u;
+    }
+    red_add32(&g.red->bad[0], bad);
+}
+
+__global__ void k_reset(Reduce* r) {
+    if (threadIdx.x == 0) {
+        r->alpha_key = dkey(-INFINITY);
+        r->beta_key = dkey(-INFINITY);
+        r->pp_cells = 0;
+        r->min_rho_key = dkey(INFINITY);
+        r->min_p_key = dkey(INFINITY);
+        r->bad[0] = r->bad[1] = r->bad[2] = r->bad[3] = 0;
+    }
+}
+
+__global__ void k_dt(Reduce* r, double cfl_h, double visc_dt, double t_left) {
+    if (threadIdx.x == 0) {
+        const double a = dkey_inv(r->alpha_key);
+        double dt = cfl_h / a;
+        dt = fmin(dt, visc_dt);
+        dt = fmin(dt, t_left);
+        r->dt = dt;
+    }
+}
+
+__global__ void k_set_dt(Reduce* r, double dt) {
+    if (threadIdx.x == 0) r->dt = dt;
+}
+
+inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_reset(Reduce* red, hipStream_t st) {
+    k_reset<<<1, 64, 0, st>>>(red);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(Reduce* red, double cfl_h, double visc_dt, double t_left, hipStream_t st) {
+    k_dt<<<1, 64, 0, st>>>(red, cfl_h, visc_dt, t_left);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(Reduce* red, double dt, hipStream_t st) {
+    k_set_dt<<<1, 64, 0, st>>>(red, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_check2(const Grid2& g, const double* S, hipStream_t st) {
+    const long long n = (long long)g.nx * g.ny;
+    k_check2<<<nblk(n, 256), 256, 0, st>>>(g, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream_t st) {
+    const long long n = (long long)g.nx * g.ny * 12;
+    k_copy_in2<<<nblk(n, 256), 256, 0, st>>>(g, U, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st) {
+    const long long n = (long long)g.nx * g.ny * 12;
+    k_copy_out2<<<nblk(n, 256), 256, 0, st>>>(g, S, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st) {
+    k_ghost2_x<<<nblk((long long)g.ny * 2 * HALO, 256), 256, 0, st>>>(g, S);
+    k_ghost2_y<<<nblk((long long)g.NX * 2 * HALO, 256), 256, 0, st>>>(g, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st) {
+    const long long nc = (long long)(g.NX - 2) * (g.NY - 2);
+    k_recon2<<<nblk(nc, RC_CELLS), 256, 0, st>>>(g, S);
+    const long long n2 = (long long)(g.NX - 4) * (g.NY - 4);
+    k_rbar2<<<nblk(n2, 256), 256, 0, st>>>(g);
+    const long long n1 = (long long)(g.NX - 6) * (g.NY - 6);
+    k_grad2<<<nblk(n1, GR_CELLS), 192, 0, st>>>(g);
+    k_flux2<0><<<nblk((long long)(g.nx + 1) * g.ny, 256), 256, 0, st>>>(g);
+    k_flux2<1><<<nblk((long long)g.nx * (g.ny + 1), 256), 256, 0, st>>>(g);
+    return hipGetLastError();
+}
+
+hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
+                          double* Sout, double* R, double* Vhat, hipStream_t st) {
+    const long long n = (long long)g.nx * g.ny;
+    k_update2<<<nblk(n, 256), 256, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat);
+    return hipGetLastError();
+}
+
+}  // namespace hw

@@ -1,0 +1,395 @@
+// Device math of the HWENO-GR scheme (arXiv 2608.10569): gas physics,
+// characteristic bases, the scalar unified-stencil HWENO reconstruction and
+// the positivity-preserving flux bound.  FP64 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hweno_gen.h"
+
+namespace hw {
+
+// ---------------------------------------------------------------------------
+// Quadrature (Sec. 2.1: 4-point Legendre-Gauss-Lobatto; Sec. 3.1: 3-point
+// Gauss per direction), scaled to the unit cell [-1/2, 1/2].
+// ---------------------------------------------------------------------------
+constexpr double LGL_T = 0.22360679774997896;   // sqrt(5)/10
+constexpr double LGL_W0 = 1.0 / 12.0;           // end points
+constexpr double LGL_W1 = 5.0 / 12.0;           // interior points
+constexpr double GS = 0.3872983346207417;       // sqrt(15)/10
+constexpr double GS2 = 0.15;                    // GS^2
+constexpr double GS3 = 0.05809475019311125;     // GS^3
+constexpr double GS4 = 0.0225;                  // GS^4
+constexpr double GW0 = 5.0 / 18.0;              // outer Gauss weight
+constexpr double GW1 = 4.0 / 9.0;               // centre Gauss weight
+
+// Linear weights of the nonlinear combination (eqs. (A.3), (A.6)).
+constexpr double G1D_0 = 199.0 / 200.0;
+constexpr double G1D_1 = 1.0 / 400.0;
+constexpr double G2D_0 = 99.0 / 100.0;
+constexpr double G2D_1 = 1.0 / 400.0;
+
+// Scheme constants shared by every kernel of one grid.
+struct Consts {
+    double gamma, gm1;          // ratio of specific heats, gamma - 1
+    double Pr;
+    double mu_ref, mu_exp, T_ref;   // mu(T) = mu_ref (T/T_ref)^mu_exp, T = p/rho
+    double eps_pp, eps_weno;
+    int linear;                 // 1: omega = gamma (test mode)
+    double dx, dy, idx, idy;    // cell sizes and inverses
+};
+
+__device__ __forceinline__ double dabs(double x) { return fabs(x); }
+
+__device__ __forceinline__ double viscosity(const Consts& K, double rho, double p) {
+    if (K.mu_exp == 0.0) return K.mu_ref;
+    return K.mu_ref * pow((p / rho) / K.T_ref, K.mu_exp);
+}
+
+// ---------------------------------------------------------------------------
+// Scalar HWENO, 1D (Appendix A.1).  Input a[5] = {abar0_{i-1}, abar0_i,
+// abar0_{i+1}, abar1_{i-1}, abar1_{i+1}}; output: coefficients C[5] (powers
+// of xi) of the nonlinear combination of eq. (2.4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void hweno1d(const double* __restrict__ a, const Consts& K,
+                                        double* __restrict__ C) {
+    double c0[5];
+    hweno_gen::p0_1d(a, c0);
+    const double s1 = a[1] - a[0];      // p1 slope on {i-1, i}
+    const double s2 = a[2] - a[1];      // p2 slope on {i, i+1}
+    double w0 = G1D_0, w1 = G1D_1, w2 = G1D_1;
+    if (!K.linear) {
+        const double b0 = hweno_gen::sobolev_1d(c0);
+        const double b1 = s1 * s1, b2 = s2 * s2;
+        double tau = 0.5 * (dabs(b0 - b1) + dabs(b0 - b2));
+        tau = tau * tau;
+        const double t0 = G1D_0 * (1.0 + tau / (b0 + K.eps_weno));
+        const double t1 = G1D_1 * (1.0 + tau / (b1 + K.eps_weno));
+        const double t2 = G1D_1 * (1.0 + tau / (b2 + K.eps_weno));
+        const double tot = t0 + t1 + t2;
+        w0 = t0 / tot;
+        w1 = t1 / tot;
+        w2 = t2 / tot;
+    }
+    const double r0 = w0 / G1D_0;
+    const double d1 = w1 - w0 * G1D_1 / G1D_0;
+    const double d2 = w2 - w0 * G1D_1 / G1D_0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) C[k] = r0 * c0[k];
+    C[0] += (d1 + d2) * a[1];
+    C[1] += d1 * s1 + d2 * s2;
+}
+
+// Values at the four LGL points (-1/2, -t, t, 1/2) and the scaled moment.
+__device__ __forceinline__ void eval1d(const double* __restrict__ C, double* __restrict__ v) {
+    const double eh = C[0] + C[2] * 0.25 + C[4] * 0.0625;
+    const double oh = C[1] * 0.5 + C[3] * 0.125;
+    const double t2 = LGL_T * LGL_T;
+    const double et = C[0] + t2 * (C[2] + t2 * C[4]);
+    const double ot = LGL_T * (C[1] + t2 * C[3]);
+    v[0] = eh - oh;
+    v[1] = et - ot;
+    v[2] = et + ot;
+    v[3] = eh + oh;
+}
+__device__ __forceinline__ double moment1d(const double* __restrict__ C) {
+    return C[1] * (1.0 / 12.0) + C[3] * (1.0 / 80.0);
+}
+
+// ---------------------------------------------------------------------------
+// Scalar HWENO, 2D (Appendix A.2).  Input a[17] (averages of cells 1..9,
+// xi-moments of 2,4,6,8, eta-moments of 2,4,6,8; cells row-major from
+// (i-1, j-1)); output coefficients C[15] of the combination of eq. (3.4).
+// Linear candidates (eq. (A.5)) on S1={2,4,5}, S2={2,5,6}, S3={4,5,8},
+// S4={5,6,8}: p_m = abar_5 + sx*xi + sy*eta.
+// ---------------------------------------------------------------------------
+// monomial index of xi^a eta^b
+#define MI(a, b) ((((a) + (b)) * ((a) + (b) + 1)) / 2 + (b))
+
+__device__ __forceinline__ void hweno2d(const double* __restrict__ a, const Consts& K,
+                                        double* __restrict__ C) {
+    double c0[15];
+    hweno_gen::p0_2d(a, c0);
+    const double a2 = a[1], a4 = a[3], a5 = a[4], a6 = a[5], a8 = a[7];
+    const double sxl = a5 - a4, sxr = a6 - a5, syb = a5 - a2, syt = a8 - a5;
+    double w0 = G2D_0, w1 = G2D_1, w2 = G2D_1, w3 = G2D_1, w4 = G2D_1;
+    if (!K.linear) {
+        const double b0 = hweno_gen::sobolev_2d(c0);
+        const double b1 = sxl * sxl + syb * syb;
+        const double b2 = sxr * sxr + syb * syb;
+        const double b3 = sxl * sxl + syt * syt;
+        const double b4 = sxr * sxr + syt * syt;
+        double tau = 0.25 * (dabs(b0 - b1) + dabs(b0 - b2) + dabs(b0 - b3) + dabs(b0 - b4));
+        tau = tau * tau;
+        const double e = K.eps_weno;
+        const double t0 = G2D_0 * (1.0 + tau / (b0 + e));
+        const double t1 = G2D_1 * (1.0 + tau / (b1 + e));
+        const double t2 = G2D_1 * (1.0 + tau / (b2 + e));
+        const double t3 = G2D_1 * (1.0 + tau / (b3 + e));
+        const double t4 = G2D_1 * (1.0 + tau / (b4 + e));
+        const double tot = t0 + t1 + t2 + t3 + t4;
+        w0 = t0 / tot;
+        w1 = t1 / tot;
+        w2 = t2 / tot;
+        w3 = t3 / tot;
+        w4 = t4 / tot;
+    }
+    const double r0 = w0 / G2D_0;
+    const double q = w0 * G2D_1 / G2D_0;
+    const double d1 = w1 - q, d2 = w2 - q, d3 = w3 - q, d4 = w4 - q;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) C[k] = r0 * c0[k];
+    C[0] += (d1 + d2 + d3 + d4) * a5;
+    C[1] += (d1 + d3) * sxl + (d2 + d4) * sxr;
+    C[2] += (d1 + d2) * syb + (d3 + d4) * syt;
+}
+
+// Values on the x-faces: out[0..2] at (-1/2, eta_G), out[3..5] at (1/2, eta_G),
+// eta_G = (-s, 0, s).
+__device__ __forceinline__ void eval_xface(const double* __restrict__ C, double* __restrict__ out) {
+    // E_b, O_b: even / odd parts in xi at |xi| = 1/2, for each power b of eta
+    const double E0 = C[MI(0, 0)] + 0.25 * C[MI(2, 0)] + 0.0625 * C[MI(4, 0)];
+    const double O0 = 0.5 * C[MI(1, 0)] + 0.125 * C[MI(3, 0)];
+    const double E1 = C[MI(0, 1)] + 0.25 * C[MI(2, 1)];
+    const double O1 = 0.5 * C[MI(1, 1)] + 0.125 * C[MI(3, 1)];
+    const double E2 = C[MI(0, 2)] + 0.25 * C[MI(2, 2)];
+    const double O2 = 0.5 * C[MI(1, 2)];
+    const double E3 = C[MI(0, 3)];
+    const double O3 = 0.5 * C[MI(1, 3)];
+    const double E4 = C[MI(0, 4)];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const double sg = side ? 1.0 : -1.0;
+        const double Q0 = E0 + sg * O0, Q1 = E1 + sg * O1, Q2 = E2 + sg * O2;
+        const double Q3 = E3 + sg * O3, Q4 = E4;
+        const double ev = Q0 + GS2 * Q2 + GS4 * Q4;
+        const double od = GS * Q1 + GS3 * Q3;
+        out[3 * side + 0] = ev - od;
+        out[3 * side + 1] = Q0;
+        out[3 * side + 2] = ev + od;
+    }
+}
+
+// Values on the y-faces: out[0..2] at (xi_G, -1/2), out[3..5] at (xi_G, 1/2).
+__device__ __forceinline__ void eval_yface(const double* __restrict__ C, double* __restrict__ out) {
+    const double E0 = C[MI(0, 0)] + 0.25 * C[MI(0, 2)] + 0.0625 * C[MI(0, 4)];
+    const double O0 = 0.5 * C[MI(0, 1)] + 0.125 * C[MI(0, 3)];
+    const double E1 = C[MI(1, 0)] + 0.25 * C[MI(1, 2)];
+    const double O1 = 0.5 * C[MI(1, 1)] + 0.125 * C[MI(1, 3)];
+    const double E2 = C[MI(2, 0)] + 0.25 * C[MI(2, 2)];
+    const double O2 = 0.5 * C[MI(2, 1)];
+    const double E3 = C[MI(3, 0)];
+    const double O3 = 0.5 * C[MI(3, 1)];
+    const double E4 = C[MI(4, 0)];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const double sg = side ? 1.0 : -1.0;
+        const double Q0 = E0 + sg * O0, Q1 = E1 + sg * O1, Q2 = E2 + sg * O2;
+        const double Q3 = E3 + sg * O3, Q4 = E4;
+        const double ev = Q0 + GS2 * Q2 + GS4 * Q4;
+        const double od = GS * Q1 + GS3 * Q3;
+        out[3 * side + 0] = ev - od;
+        out[3 * side + 1] = Q0;
+        out[3 * side + 2] = ev + od;
+    }
+}
+
+// Values at the 3x3 tensor Gauss points: out[3*h + g] at (xi_g, eta_h).
+__device__ __forceinline__ void eval_vol(const double* __restrict__ C, double* __restrict__ out) {
+    // r_a(eta): polynomial in xi with coefficients depending on eta
+    double rm[5], r0[5], rp[5];
+#pragma unroll
+    for (int a = 0; a <= 4; ++a) {
+        double ev = C[MI(a, 0)], od = 0.0;
+        if (a <= 3) od += GS * C[MI(a, 1)];
+        if (a <= 2) ev += GS2 * C[MI(a, 2)];
+        if (a <= 1) od += GS3 * C[MI(a, 3)];
+        if (a == 0) ev += GS4 * C[MI(0, 4)];
+        rm[a] = ev - od;
+        r0[a] = C[MI(a, 0)];
+        rp[a] = ev + od;
+    }
+    const double* rows[3] = {rm, r0, rp};
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        const double* r = rows[h];
+        const double ev = r[0] + GS2 * r[2] + GS4 * r[4];
+        const double od = GS * r[1] + GS3 * r[3];
+        out[3 * h + 0] = ev - od;
+        out[3 * h + 1] = r[0];
+        out[3 * h + 2] = ev + od;
+    }
+}
+
+// Scaled first moments over the own cell: int p xi, int p eta.
+__device__ __forceinline__ double moment_xi(const double* __restrict__ C) {
+    return C[MI(1, 0)] * (1.0 / 12.0) + C[MI(1, 2)] * (1.0 / 144.0) + C[MI(3, 0)] * (1.0 / 80.0);
+}
+__device__ __forceinline__ double moment_eta(const double* __restrict__ C) {
+    return C[MI(0, 1)] * (1.0 / 12.0) + C[MI(2, 1)] * (1.0 / 144.0) + C[MI(0, 3)] * (1.0 / 80.0);
+}
+
+// ---------------------------------------------------------------------------
+// Gas physics (eqs. (2.1), (3.1)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pressure1(const Consts& K, double r, double m, double E) {
+    return K.gm1 * (E - 0.5 * (m * m) / r);
+}
+__device__ __forceinline__ double pressure2(const Consts& K, double r, double m, double n,
+                                            double E) {
+    return K.gm1 * (E - 0.5 * (m * m + n * n) / r);
+}
+
+// 1D total flux f = f^a - f^d with tau = (4/3) mu u_x, q = -gamma mu e_x / Pr.
+__device__ __forceinline__ void flux1(const Consts& K, const double* U, double ux, double ex,
+                                      double* f) {
+    const double r = U[0], m = U[1], E = U[2];
+    const double u = m / r;
+    const double p = pressure1(K, r, m, E);
+    const double mu = viscosity(K, r, p);
+    const double tau = (4.0 / 3.0) * mu * ux;
+    const double q = -K.gamma * mu * ex / K.Pr;
+    f[0] = m;
+    f[1] = m * u + p - tau;
+    f[2] = (E + p) * u - (tau * u - q);
+}
+
+// PP wave-speed bound of eq. (2.3), taken no smaller than |u| + c.
+__device__ __forceinline__ double speed1(const Consts& K, const double* U, double ux, double ex) {
+    const double r = U[0], m = U[1], E = U[2];
+    const double u = m / r;
+    const double p = pressure1(K, r, m, E);
+    const double e = p / (K.gm1 * r);
+    const double mu = viscosity(K, r, p);
+    const double tau = (4.0 / 3.0) * mu * ux;
+    const double q = -K.gamma * mu * ex / K.Pr;
+    const double r2e = r * r * e;
+    const double root = sqrt(r * r * q * q + 2.0 * r2e * (tau - p) * (tau - p));
+    const double bpp = fabs(u) + (root + r * fabs(q)) / (2.0 * r2e);
+    const double ac = fabs(u) + sqrt(K.gamma * p / r);
+    return ac >= bpp ? ac : bpp;
+}
+
+// 2D stresses divided by Re (mu(T) in place of 1/Re).
+struct Stress { double xx, xy, yy; };
+__device__ __forceinline__ Stress stresses(double mu, const double* s) {
+    Stress t;
+    t.xx = mu * ((4.0 / 3.0) * s[0] - (2.0 / 3.0) * s[3]);
+    t.xy = mu * (s[1] + s[2]);
+    t.yy = mu * ((4.0 / 3.0) * s[3] - (2.0 / 3.0) * s[0]);
+    return t;
+}
+
+// 2D total flux in direction d (0: f, 1: g); s = (u_x,u_y,v_x,v_y,e_x,e_y).
+template <int d>
+__device__ __forceinline__ void flux2(const Consts& K, const double* U, const double* s,
+                                      double* f) {
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double u = m / r, v = n / r;
+    const double p = pressure2(K, r, m, n, E);
+    const double mu = viscosity(K, r, p);
+    const Stress t = stresses(mu, s);
+    const double kq = K.gamma * mu / K.Pr;
+    if (d == 0) {
+        f[0] = m;
+        f[1] = m * u + p - t.xx;
+        f[2] = n * u - t.xy;
+        f[3] = (E + p) * u - (t.xx * u + t.xy * v + kq * s[4]);
+    } else {
+        f[0] = n;
+        f[1] = m * v - t.xy;
+        f[2] = n * v + p - t.yy;
+        f[3] = (E + p) * v - (t.xy * u + t.yy * v + kq * s[5]);
+    }
+}
+
+// PP wave-speed bound of eq. (3.3) in direction d, no smaller than |u_d| + c.
+template <int d>
+__device__ __forceinline__ double speed2(const Consts& K, const double* U, const double* s) {
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double p = pressure2(K, r, m, n, E);
+    const double e = p / (K.gm1 * r);
+    const double mu = viscosity(K, r, p);
+    const Stress t = stresses(mu, s);
+    const double kq = K.gamma * mu / K.Pr;
+    const double un = (d == 0 ? m : n) / r;
+    const double q = kq * s[4 + d];
+    const double t2 = d == 0 ? (t.xx - p) * (t.xx - p) + t.xy * t.xy
+                             : t.xy * t.xy + (t.yy - p) * (t.yy - p);
+    const double r2e = r * r * e;
+    const double root = sqrt(r * r * q * q + 2.0 * r2e * t2);
+    const double bpp = fabs(un) + (root + r * fabs(q)) / (2.0 * r2e);
+    const double ac = fabs(un) + sqrt(K.gamma * p / r);
+    return ac >= bpp ? ac : bpp;
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic bases (Sec. 2.1 / 3.1): eigenvectors of the convective
+// Jacobian at a cell average.  Right eigenvectors as columns of R; L = R^-1.
+// ---------------------------------------------------------------------------
+struct Eig1 { double R[3][3], L[3][3]; };
+__device__ __forceinline__ void eig1(const Consts& K, const double* Ub, Eig1& e) {
+    const double r = Ub[0], u = Ub[1] / r;
+    const double p = pressure1(K, r, Ub[1], Ub[2]);
+    const double c = sqrt(K.gamma * p / r);
+    const double H = (Ub[2] + p) / r;
+    const double b1 = K.gm1 / (c * c), b2 = 0.5 * b1 * u * u, ic = 1.0 / c;
+    e.R[0][0] = 1.0;        e.R[0][1] = 1.0;         e.R[0][2] = 1.0;
+    e.R[1][0] = u - c;      e.R[1][1] = u;           e.R[1][2] = u + c;
+    e.R[2][0] = H - u * c;  e.R[2][1] = 0.5 * u * u; e.R[2][2] = H + u * c;
+    e.L[0][0] = 0.5 * (b2 + u * ic); e.L[0][1] = -0.5 * (b1 * u + ic); e.L[0][2] = 0.5 * b1;
+    e.L[1][0] = 1.0 - b2;            e.L[1][1] = b1 * u;               e.L[1][2] = -b1;
+    e.L[2][0] = 0.5 * (b2 - u * ic); e.L[2][1] = 0.5 * (ic - b1 * u);  e.L[2][2] = 0.5 * b1;
+}
+
+// Row k of L and row c of R of the x- (b = 0) or y-Jacobian (b = 1).
+__device__ __forceinline__ void eig2_rows(const Consts& K, const double* Ub, int b, int k,
+                                          double* Lrow, double* Rrow) {
+    const double r = Ub[0], u = Ub[1] / r, v = Ub[2] / r;
+    const double p = pressure2(K, r, Ub[1], Ub[2], Ub[3]);
+    const double c = sqrt(K.gamma * p / r);
+    const double H = (Ub[3] + p) / r;
+    const double q2 = u * u + v * v;
+    const double b1 = K.gm1 / (c * c), b2 = 0.5 * b1 * q2, ic = 1.0 / c;
+    const double un = b ? v : u;       // normal velocity
+    const double ut = b ? u : v;       // tangential velocity
+    // In (rho, m_n, m_t, E) ordering the two Jacobians have identical
+    // eigenvectors; map to (rho, m, n, E) by placing n/t slots.
+    const int in = b ? 2 : 1, it = b ? 1 : 2;
+    double Lr[4], Rr[4];
+    // L rows in normal/tangential ordering
+    switch (k) {
+        case 0: Lr[0] = 0.5 * (b2 + un * ic); Lr[in] = -0.5 * (b1 * un + ic);
+                Lr[it] = -0.5 * b1 * ut;      Lr[3] = 0.5 * b1; break;
+        case 1: Lr[0] = 1.0 - b2; Lr[in] = b1 * un; Lr[it] = b1 * ut; Lr[3] = -b1; break;
+        case 2: Lr[0] = -ut; Lr[in] = 0.0; Lr[it] = 1.0; Lr[3] = 0.0; break;
+        default: Lr[0] = 0.5 * (b2 - un * ic); Lr[in] = 0.5 * (ic - b1 * un);
+                 Lr[it] = -0.5 * b1 * ut;     Lr[3] = 0.5 * b1; break;
+    }
+    // R row for conserved component k (columns: fields 0..3)
+    // columns: (1, un-c, ut, H-un c), (1, un, ut, q2/2), (0, 0, 1, ut), (1, un+c, ut, H+un c)
+    if (k == 0) { Rr[0] = 1.0; Rr[1] = 1.0; Rr[2] = 0.0; Rr[3] = 1.0; }
+    else if (k == in) { Rr[0] = un - c; Rr[1] = un; Rr[2] = 0.0; Rr[3] = un + c; }
+    else if (k == it) { Rr[0] = ut; Rr[1] = ut; Rr[2] = 1.0; Rr[3] = ut; }
+    else { Rr[0] = H - un * c; Rr[1] = 0.5 * q2; Rr[2] = ut; Rr[3] = H + un * c; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { Lrow[i] = Lr[i]; Rrow[i] = Rr[i]; }
+}
+
+// ---------------------------------------------------------------------------
+// Order-preserving maps of doubles to unsigned 64-bit keys (for atomic
+// max / min of doubles of any sign).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dkey(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double dkey_inv(unsigned long long k) {
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double x;
+    __builtin_memcpy(&x, &b, 8);
+    return x;
+}
+
+}  // namespace hw

@@ -1,0 +1,86 @@
+// Kernel launch interface shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hweno_device.h"
+
+namespace hw {
+
+// Device-side reduction slots, one set per grid.  Doubles are stored as
+// order-preserving keys (dkey) so that atomicMax / atomicMin work for any sign.
+struct Reduce {
+    unsigned long long alpha_key;     // max |u_n| + c over interior face traces
+    unsigned long long beta_key;      // max LF coefficient over interior faces
+    unsigned long long pp_cells;      // cells where the limiter acted (any stage)
+    unsigned long long min_rho_key;   // min cell-average density (per call)
+    unsigned long long min_p_key;     // min cell-average pressure
+    unsigned int bad[4];              // inadmissible cells per stage (index 1..3)
+    double dt;                        // step size used by the update kernels
+    double pad[3];
+};
+
+// Ghost-fill description of one side (xlo, xhi, ylo, yhi).
+struct Side {
+    int kind;             // HWENO_BC_* value
+    double sign[12];      // multiplier per (moment, component) for walls
+    double inflow[4];     // conservative inflow state
+};
+
+// Pointers and sizes of one 2D grid's workspace (all arrays SoA over the
+// ghosted grid NX x NY, component-major: a[q * ncell + j * NX + i]).
+struct Grid2 {
+    int nx, ny, NX, NY;       // interior and ghosted sizes (halo 4)
+    long long ncell;          // NX * NY
+    Consts K;
+    Side side[4];
+    double* xf;   // 24: x-face traces (p*4 + c), p 0..2 left face, 3..5 right face
+    double* yf;   // 24: y-face traces, p 0..2 bottom face, 3..5 top face
+    double* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g
+    double* yv;   // 36: y-basis volume values
+    double* wb;   // 6:  wbar of (u, v, e) from x-basis, then from y-basis
+    double* vk;   // 8:  modified moments of the current input (hat-v 0..3, hat-w 4..7)
+    double* vn;   // 8:  modified moments of U^n (kept for stages 2 and 3)
+    double* rb;   // 18: weak moments ((l*3 + w)*3 + mom)
+    double* gf;   // 72: gradients at face points ((p*6 + s)), p 0..5 x-face, 6..11 y-face
+    double* vf;   // 8:  volume flux quadratures (sum f, sum g)
+    double* fx;   // 12: x-face fluxes at (j, i+1/2) (G*4 + c)
+    double* fy;   // 12: y-face fluxes at (j+1/2, i)
+    Reduce* red;
+};
+
+struct Grid1 {
+    int nx, NX;               // interior and ghosted (halo 4) sizes
+    Consts K;
+    Side side[2];
+    double* pts;  // 12: limited LGL point values (p*3 + c)
+    double* wb;   // 2: wbar of (u, e)
+    double* vk;   // 3: modified moment of the current input
+    double* vn;   // 3: modified moment of U^n
+    double* rb;   // 4: weak moments (w*2 + mom)
+    double* gr;   // 8: gradients at the LGL points (p*2 + w)
+    double* fh;   // 3: face flux at i+1/2
+    double* vf;   // 3: volume flux quadrature
+    Reduce* red;
+};
+
+// Launchers (stream-ordered, no synchronisation).  Return hipError_t.
+hipError_t launch_reset(Reduce* red, hipStream_t st);
+hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream_t st);
+hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st);
+hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st);
+hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st);
+// stage 0: write R (12) and Vhat (8) in interior layout; stage 1..3: RK update
+hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
+                          double* Sout, double* R, double* Vhat, hipStream_t st);
+hipError_t launch_dt(Reduce* red, double cfl_h, double visc_dt, double t_left, hipStream_t st);
+hipError_t launch_set_dt(Reduce* red, double dt, hipStream_t st);
+
+hipError_t launch_copy_in1(const Grid1& g, const double* U, double* S, hipStream_t st);
+hipError_t launch_copy_out1(const Grid1& g, const double* S, double* U, hipStream_t st);
+hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st);
+hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st);
+hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
+                          double* Sout, double* R, double* Vhat, hipStream_t st);
+
+}  // namespace hw

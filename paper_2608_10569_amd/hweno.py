@@ -1,0 +1,196 @@
+"""Thin ctypes binding of libhweno.so (include/hweno.h).
+
+Argument marshalling only: every step of the scheme runs in the library's
+HIP kernels.  PyTorch supplies device memory (the workspace and the state
+tensors) and the current HIP stream.  If the library is missing the calls
+raise; there is no fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libhweno.so')
+
+BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
+
+#: every symbol include/hweno.h declares
+EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
+           'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
+           'hweno_residual', 'hweno_rk_step', 'hweno_status_string')
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [('dim', ctypes.c_int), ('nx', ctypes.c_int), ('ny', ctypes.c_int),
+                ('x0', ctypes.c_double), ('x1', ctypes.c_double),
+                ('y0', ctypes.c_double), ('y1', ctypes.c_double)]
+
+
+class PhysicsC(ctypes.Structure):
+    _fields_ = [('gamma', ctypes.c_double), ('Pr', ctypes.c_double), ('mu_ref', ctypes.c_double),
+                ('mu_exp', ctypes.c_double), ('T_ref', ctypes.c_double)]
+
+
+class Bcs(ctypes.Structure):
+    _fields_ = [('kind', ctypes.c_int * 4), ('inflow', (ctypes.c_double * 4) * 4)]
+
+
+class OptionsC(ctypes.Structure):
+    _fields_ = [('cfl', ctypes.c_double), ('b_visc', ctypes.c_double),
+                ('eps_pp', ctypes.c_double), ('eps_weno', ctypes.c_double),
+                ('t_final', ctypes.c_double), ('linear_weights', ctypes.c_int),
+                ('max_halvings', ctypes.c_int)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [('t', ctypes.c_double), ('dt', ctypes.c_double), ('alpha_star', ctypes.c_double),
+                ('beta_max', ctypes.c_double), ('min_rho', ctypes.c_double),
+                ('min_p', ctypes.c_double), ('pp_cells', ctypes.c_ulonglong),
+                ('restarts', ctypes.c_int), ('pad', ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != 'pad'}
+
+
+class HwenoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__('%s (status %d)' % (msg, code))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libhweno.so from the package directory (raises if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError('libhweno.so not built: run paper_2608_10569_amd.build.build()')
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.hweno_default_options.argtypes = [ctypes.POINTER(OptionsC)]
+        L.hweno_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(PhysicsC),
+                                   ctypes.POINTER(Bcs), ctypes.POINTER(OptionsC),
+                                   ctypes.POINTER(vp)]
+        L.hweno_destroy.argtypes = [vp]
+        L.hweno_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.hweno_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+        L.hweno_set_stream.argtypes = [vp, vp]
+        L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
+        L.hweno_get_state.argtypes = [vp, vp, dp]
+        L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
+        L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
+        L.hweno_status_string.argtypes = [ctypes.c_int]
+        L.hweno_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != 'hweno_status_string':
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != 0:
+        raise HwenoError(code, lib().hweno_status_string(code).decode())
+
+
+def default_options(**kw):
+    o = OptionsC()
+    check(lib().hweno_default_options(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One grid on the current CUDA/HIP device.
+
+    ``bc`` = kinds for (xlo, xhi[, ylo, yhi]); ``inflow`` = {side: primitive
+    state (rho, u, [v,] p)}; ``options`` = keyword overrides of the paper's
+    defaults (cfl, b_visc, eps_pp, eps_weno, t_final, linear_weights,
+    max_halvings).
+    """
+
+    def __init__(self, nx, ny=None, extent=(0.0, 1.0, 0.0, 1.0), gamma=1.4, Pr=0.72,
+                 mu_ref=0.01, mu_exp=0.0, T_ref=1.0, bc=None, inflow=None, device='cuda',
+                 **options):
+        import torch
+        self.dim = 1 if ny is None else 2
+        self.nx, self.ny = nx, (ny or 1)
+        g = Grid(self.dim, nx, ny or 1, *[float(v) for v in
+                                          (list(extent) + [0.0, 1.0])[:4]])
+        ph = PhysicsC(gamma, Pr, mu_ref, mu_exp, T_ref)
+        b = Bcs()
+        kinds = bc or ['periodic'] * (2 * self.dim)
+        for s, k in enumerate(kinds):
+            b.kind[s] = BC[k] if isinstance(k, str) else int(k)
+        for s, st in (inflow or {}).items():
+            for q, v in enumerate(st):
+                b.inflow[s][q] = float(v)
+        o = default_options(**options)
+        h = ctypes.c_void_p()
+        check(lib().hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b),
+                                 ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        check(lib().hweno_workspace_bytes(h, ctypes.byref(nb)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        check(lib().hweno_set_workspace(h, _ptr(self.workspace), nb.value))
+        self.set_stream(torch.cuda.current_stream(self.device).cuda_stream)
+        self.state_shape = (3, 4, ny, nx) if self.dim == 2 else (2, 3, nx)
+        self.vhat_shape = (8, ny, nx) if self.dim == 2 else (3, nx)
+
+    def set_stream(self, stream):
+        check(lib().hweno_set_stream(self._h, ctypes.c_void_p(stream)))
+
+    def _dev(self, U):
+        import torch
+        if U.device != self.device or U.dtype != torch.float64 or not U.is_contiguous():
+            raise ValueError('expected a contiguous float64 tensor on %s' % self.device)
+        if tuple(U.shape) != self.state_shape:
+            raise ValueError('state shape %s, expected %s' % (tuple(U.shape), self.state_shape))
+        return U
+
+    def set_state(self, U, t=0.0):
+        check(lib().hweno_set_state(self._h, _ptr(self._dev(U)), float(t)))
+
+    def get_state(self):
+        import torch
+        U = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        t = ctypes.c_double()
+        check(lib().hweno_get_state(self._h, _ptr(U), ctypes.byref(t)))
+        return U, t.value
+
+    def residual(self, U, diag=True):
+        """(R, Vhat, diag dict or None) at the state U."""
+        import torch
+        self._dev(U)
+        R = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        V = torch.empty(self.vhat_shape, dtype=torch.float64, device=self.device)
+        d = Diag()
+        check(lib().hweno_residual(self._h, _ptr(U), _ptr(R), _ptr(V),
+                                   ctypes.byref(d) if diag else None))
+        return R, V, (d.as_dict() if diag else None)
+
+    def rk_step(self, dt=0.0):
+        """One SSP-RK3 step (dt <= 0: the paper's time-step rule); diag dict."""
+        d = Diag()
+        check(lib().hweno_rk_step(self._h, float(dt), ctypes.byref(d)))
+        return d.as_dict()
+
+    def close(self):
+        if getattr(self, '_h', None):
+            lib().hweno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,203 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+Only initial data lives here (the workloads' definitions): pointwise
+primitive fields are converted to conserved variables and projected onto the
+cell average and scaled first-order moments with a 6-point Gauss-Legendre
+rule per direction.  None of the scheme's arithmetic is in this module.
+
+Every generator returns numpy float64 arrays in the D1 layout of
+include/hweno.h: 1D U[m, c, i] (2, 3, nx); 2D U[m, c, j, i] (3, 4, ny, nx).
+Random draws use numpy's PCG64 with the base seed 2608.
+"""
+
+import math
+
+import numpy as np
+
+SEED = 2608
+
+
+def _gauss6():
+    x, w = np.polynomial.legendre.leggauss(6)
+    return 0.5 * x, 0.5 * w
+
+
+def _cons1(rho, u, p, gamma):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def _cons2(rho, u, v, p, gamma):
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def project1d(prim, nx, x0, x1, gamma):
+    """prim(x) -> (rho, u, p); returns U (2, 3, nx)."""
+    gx, gw = _gauss6()
+    dx = (x1 - x0) / nx
+    xc = x0 + (np.arange(nx) + 0.5) * dx
+    X = xc[None, :] + gx[:, None] * dx                       # (6, nx)
+    Q = _cons1(*[np.broadcast_to(a, X.shape) for a in prim(X)], gamma)   # (3, 6, nx)
+    avg = np.einsum('g,cgi->ci', gw, Q)
+    mom = np.einsum('g,cgi->ci', gw * gx, Q)
+    return np.ascontiguousarray(np.stack([avg, mom]))
+
+
+def project2d(prim, nx, ny, extent, gamma):
+    """prim(X, Y) -> (rho, u, v, p); returns U (3, 4, ny, nx)."""
+    x0, x1, y0, y1 = extent
+    gx, gw = _gauss6()
+    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+    xc = x0 + (np.arange(nx) + 0.5) * dx
+    yc = y0 + (np.arange(ny) + 0.5) * dy
+    out = np.zeros((3, 4, ny, nx))
+    for b in range(6):            # eta points
+        Y = (yc + gx[b] * dy)[:, None] + np.zeros((1, nx))
+        for a in range(6):        # xi points
+            X = (xc + gx[a] * dx)[None, :] + np.zeros((ny, 1))
+            Q = _cons2(*[np.broadcast_to(f, X.shape) for f in prim(X, Y)], gamma)
+            w = gw[a] * gw[b]
+            out[0] += w * Q
+            out[1] += w * gx[a] * Q
+            out[2] += w * gx[b] * Q
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 1D workloads
+# ---------------------------------------------------------------------------
+
+def smooth_wave_1d(nx=200, gamma=1.4, seed=None, amp=1e-3):
+    """Smooth density wave on [0, 2 pi) periodic: rho = 1 + 0.2 sin x, u = 1,
+    p = 1.  With ``seed``, a random Fourier perturbation of relative size
+    ``amp`` (modes 1..8) is added to rho, u and p."""
+    if seed is None:
+        def prim(x):
+            return 1.0 + 0.2 * np.sin(x), np.ones_like(x), np.ones_like(x)
+    else:
+        rng = np.random.default_rng([SEED, 1, seed])
+        k = np.arange(1, 9)
+        ph = rng.uniform(0, 2 * np.pi, (3, 8))
+        a = rng.standard_normal((3, 8)) * amp
+
+        def prim(x):
+            pert = [np.sum(a[q][:, None, None] * np.sin(k[:, None, None] * x[None] + ph[q][:, None, None]),
+                           axis=0) for q in range(3)]
+            return (1.0 + 0.2 * np.sin(x) + pert[0], 1.0 + pert[1], 1.0 + pert[2])
+    return project1d(prim, nx, 0.0, 2 * np.pi, gamma)
+
+
+def riemann_1d(left, right, nx=2000, x0=0.0, x1=1.0, xd=0.5, gamma=1.4):
+    """Piecewise-constant (rho, u, p) states with the diaphragm at xd."""
+    def prim(x):
+        L = x < xd
+        return tuple(np.where(L, left[q], right[q]) for q in range(3))
+    return project1d(prim, nx, x0, x1, gamma)
+
+
+def sod_1d(nx=2000, gamma=1.4):
+    return riemann_1d((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), nx, gamma=gamma)
+
+
+def double_rarefaction_1d(nx=2000, gamma=1.4):
+    """Low-density double rarefaction (1,-2,0.4) | (1,2,0.4)."""
+    return riemann_1d((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), nx, gamma=gamma)
+
+
+def random_smooth_1d(nx, seed, gamma=1.4):
+    """Smooth random periodic state on [0, 1] (modes 1..4) plus small
+    cell-level noise on the moments, for parity tests."""
+    rng = np.random.default_rng([SEED, 11, seed])
+    k = np.arange(1, 5)
+    a = rng.uniform(-1, 1, (3, 4)) * np.array([0.15, 0.3, 0.15])[:, None] / k
+    ph = rng.uniform(0, 2 * np.pi, (3, 4))
+
+    def prim(x):
+        f = [np.sum(a[q][:, None, None] * np.sin(2 * np.pi * k[:, None, None] * x[None]
+                                                + ph[q][:, None, None]), axis=0) for q in range(3)]
+        return 1.0 + f[0], 0.5 + f[1], 1.0 + f[2]
+    U = project1d(prim, nx, 0.0, 1.0, gamma)
+    U[1] += 1e-4 * rng.standard_normal(U[1].shape)
+    return U
+
+
+# ---------------------------------------------------------------------------
+# 2D workloads
+# ---------------------------------------------------------------------------
+
+def viscous_shock_tube_2d(nx=1000, ny=500, gamma=1.4):
+    """Viscous shock tube on [0,1] x [0,0.5]: (rho, p) = (120, 120/gamma) for
+    x < 0.5 and (1.2, 1.2/gamma) for x >= 0.5, at rest."""
+    def prim(X, Y):
+        L = X < 0.5
+        rho = np.where(L, 120.0, 1.2)
+        return rho, np.zeros_like(X), np.zeros_like(X), rho / gamma
+    return project2d(prim, nx, ny, (0.0, 1.0, 0.0, 0.5), gamma)
+
+
+def random_smooth_2d(nx, ny, seed, gamma=1.4, extent=(0.0, 1.0, 0.0, 1.0), noise=1e-4):
+    """Smooth random periodic state (4 Fourier modes per field, Mach < 0.5)
+    with small cell-level noise on the moments, for parity tests."""
+    rng = np.random.default_rng([SEED, 12, seed])
+    x0, x1, y0, y1 = extent
+    kx = rng.integers(-3, 4, (4, 4))
+    ky = rng.integers(-3, 4, (4, 4))
+    a = rng.uniform(-1, 1, (4, 4)) * np.array([0.1, 0.15, 0.15, 0.1])[:, None]
+    ph = rng.uniform(0, 2 * np.pi, (4, 4))
+
+    def prim(X, Y):
+        xs = 2 * np.pi * (X - x0) / (x1 - x0)
+        ys = 2 * np.pi * (Y - y0) / (y1 - y0)
+        f = [sum(a[q, m] * np.sin(kx[q, m] * xs + ky[q, m] * ys + ph[q, m]) for m in range(4))
+             for q in range(4)]
+        return 1.0 + f[0], 0.3 + f[1], -0.2 + f[2], 1.0 / gamma + f[3]
+    U = project2d(prim, nx, ny, extent, gamma)
+    U[1:] += noise * rng.standard_normal(U[1:].shape)
+    return U
+
+
+def shear_layer_2d(n=256, gamma=1.4):
+    """Double shear layer on [0,1]^2 periodic: rho = 1, p = 1/gamma,
+    u = tanh(80(y-1/4)) for y <= 1/2 else tanh(80(3/4-y)), v = 0.05 sin(2 pi x)."""
+    def prim(X, Y):
+        u = np.where(Y <= 0.5, np.tanh(80.0 * (Y - 0.25)), np.tanh(80.0 * (0.75 - Y)))
+        return np.ones_like(X), u, 0.05 * np.sin(2 * np.pi * X), np.full_like(X, 1.0 / gamma)
+    return project2d(prim, n, n, (0.0, 1.0, 0.0, 1.0), gamma)
+
+
+def batched_periodic_2d(n_instances=64, gamma=1.4, sizes=(64, 128, 256, 512), modes=8,
+                        amp=0.3):
+    """Instance k (rng([2608, k])): n from ``sizes``, log10 Re ~ U(2, 4),
+    rho = 1, p = 1/gamma, u and v sums of ``modes`` random-phase Fourier modes
+    (wave numbers in {-4..4}^2 without 0) normalised to max |.| = amp.
+    Returns a list of (n, Re, U)."""
+    out = []
+    for k in range(n_instances):
+        rng = np.random.default_rng([SEED, k])
+        n = int(rng.choice(sizes))
+        Re = 10.0 ** rng.uniform(2.0, 4.0)
+        kv = []
+        while len(kv) < 2 * modes:
+            w = rng.integers(-4, 5, 2)
+            if w[0] or w[1]:
+                kv.append(w)
+        kv = np.array(kv).reshape(2, modes, 2)
+        ph = rng.uniform(0, 2 * np.pi, (2, modes))
+        xs = (np.arange(4 * n) + 0.5) / (4 * n)
+        XS, YS = np.meshgrid(xs, xs)
+
+        def field(q, X, Y):
+            return sum(np.cos(2 * np.pi * (kv[q, m, 0] * X + kv[q, m, 1] * Y) + ph[q, m])
+                       for m in range(modes))
+        scale = [amp / np.max(np.abs(field(q, XS, YS))) for q in range(2)]
+
+        def prim(X, Y, scale=scale, field=field):
+            return (np.ones_like(X), scale[0] * field(0, X, Y), scale[1] * field(1, X, Y),
+                    np.full_like(X, 1.0 / gamma))
+        out.append((n, Re, project2d(prim, n, n, (0.0, 1.0, 0.0, 1.0), gamma)))
+    return out
+
+
+def c1_config():
+    """Smooth 1D wave: gamma 1.4, Pr 0.72, mu 0.01, CFL 0.3, to t = 1."""
+    return dict(nx=200, extent=(0.0, 2 * math.pi), gamma=1.4, Pr=0.72, mu_ref=0.01, cfl=0.3,
+                t_final=1.0, bc=('periodic', 'periodic'))

@@ -1,0 +1,100 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol the
+header declares, and validates arguments on the host."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2608_10569_amd import hweno
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, 'include')):
+        if fn.endswith('.h'):
+            text = open(os.path.join(ROOT, 'include', fn)).read()
+            names |= set(re.findall(r'HWENO_API\s+[\w\s\*]+?\b(hweno_\w+)\s*\(', text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hweno.lib()
+    decl = declared_symbols()
+    assert decl, 'no declarations found'
+    assert decl == set(hweno.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def _args(**kw):
+    g = hweno.Grid(2, 16, 8, 0.0, 1.0, 0.0, 0.5)
+    ph = hweno.PhysicsC(1.4, 0.73, 1.0 / 200, 0.0, 1.0)
+    b = hweno.Bcs()
+    for s, k in enumerate((4, 4, 4, 3)):
+        b.kind[s] = k
+    o = hweno.default_options()
+    for k, v in kw.items():
+        for st in (g, ph, o):
+            if hasattr(st, k):
+                setattr(st, k, v)
+    return g, ph, b, o
+
+
+def _create(g, ph, b, o):
+    h = ctypes.c_void_p()
+    code = hweno.lib().hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b),
+                                    ctypes.byref(o), ctypes.byref(h))
+    if code == 0:
+        hweno.lib().hweno_destroy(h)
+    return code
+
+
+def test_default_options_are_the_papers():
+    o = hweno.default_options()
+    assert (o.cfl, o.b_visc, o.eps_pp, o.eps_weno, o.max_halvings) == (0.6, 0.001, 1e-12, 1e-8, 40)
+
+
+def test_create_validates_arguments():
+    assert _create(*_args()) == 0
+    for kw in (dict(dim=3), dict(nx=3), dict(ny=2), dict(gamma=1.0), dict(Pr=0.0),
+               dict(mu_ref=-1e-3), dict(T_ref=0.0), dict(cfl=0.0), dict(eps_pp=0.0),
+               dict(eps_weno=-1.0), dict(max_halvings=-1), dict(x1=0.0)):
+        assert _create(*_args(**kw)) == 1, kw
+    g, ph, b, o = _args()
+    b.kind[0] = 0          # periodic paired with a wall
+    assert _create(g, ph, b, o) == 1
+    b.kind[0] = 7          # unknown kind
+    assert _create(g, ph, b, o) == 1
+    b.kind[0] = 2          # inflow with zero density
+    assert _create(g, ph, b, o) == 1
+    b.inflow[0][0], b.inflow[0][3] = 1.0, 1.0
+    assert _create(g, ph, b, o) == 0
+
+
+def test_workspace_and_state_errors_without_device():
+    g, ph, b, o = _args()
+    h = ctypes.c_void_p()
+    L = hweno.lib()
+    assert L.hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                          ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert L.hweno_workspace_bytes(h, ctypes.byref(n)) == 0
+    assert n.value >= (16 + 8) * (8 + 8) * 300 * 8
+    d = hweno.Diag()
+    assert L.hweno_rk_step(h, 0.0, ctypes.byref(d)) == 3          # no workspace
+    assert L.hweno_set_workspace(h, ctypes.c_void_p(0), n.value) == 1
+    assert L.hweno_set_workspace(h, ctypes.c_void_p(4096), n.value - 1) == 3
+    assert L.hweno_set_workspace(h, ctypes.c_void_p(4096 + 8), n.value) == 3   # misaligned
+    assert L.hweno_destroy(h) == 0
+    assert L.hweno_status_string(4).decode().startswith('stage inadmissible')
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(hweno, 'LIB_PATH', str(tmp_path / 'missing.so'))
+    monkeypatch.setattr(hweno, '_lib', None)
+    with pytest.raises(ImportError):
+        hweno.lib()

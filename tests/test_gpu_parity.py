@@ -1,0 +1,131 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Metric (per field = component x moment): max over cells of |gpu - oracle|
+divided by max over cells of |oracle|.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip('torch')
+
+from oracle import rk  # noqa: E402
+from oracle.common import Options, Physics  # noqa: E402
+from oracle.scheme1d import Scheme1D  # noqa: E402
+from oracle.scheme2d import Scheme2D  # noqa: E402
+from paper_2608_10569_amd import hweno, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = 'cuda:0'
+
+
+def rel_err(A, B):
+    """max over fields of max |A - B| / max |B|; A, B shaped (fields, cells)."""
+    A, B = np.asarray(A), np.asarray(B)
+    out = 0.0
+    for k in range(A.shape[0]):
+        den = np.abs(B[k]).max()
+        num = np.abs(A[k] - B[k]).max()
+        out = max(out, num / den if den > 0 else num)
+    return out
+
+
+def fields2d(U):
+    return np.asarray(U).reshape(-1, U.shape[-2] * U.shape[-1])
+
+
+def fields1d(U):
+    return np.asarray(U).reshape(-1, U.shape[-1])
+
+
+def to_dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U)).to(DEV)
+
+
+BCS_WALL = ('noslip', 'noslip', 'noslip', 'slip')
+
+
+@pytest.mark.parametrize('linear', [False, True])
+@pytest.mark.parametrize('shape', [(37, 29), (8, 5)])
+def test_residual2d_periodic(linear, shape):
+    nx, ny = shape
+    U = workloads.random_smooth_2d(nx, ny, seed=3, noise=1e-3)
+    s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 1.0), mu_ref=0.01, Pr=0.72,
+                     linear_weights=int(linear))
+    R, V, d = s.residual(to_dev(U))
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01, Pr=0.72),
+                  Options(linear_weights=linear))
+    Ro, Vo, do = sc.residual(U)
+    eR = rel_err(fields2d(R.cpu().numpy()), fields2d(Ro))
+    eV = rel_err(fields2d(V.cpu().numpy()), fields2d(Vo.reshape(8, ny, nx)))
+    print('2D residual shape', shape, 'linear', linear, 'R err %.2e V err %.2e' % (eR, eV))
+    assert eR < 1e-11 and eV < 1e-12
+    assert abs(d['alpha_star'] - do['alpha']) < 1e-13 * do['alpha']
+    assert abs(d['beta_max'] - do['beta_max']) < 1e-12 * do['beta_max']
+    assert d['pp_cells'] == do['pp_cells']
+
+
+@pytest.mark.parametrize('bc', [BCS_WALL, ('outflow', 'slip', 'slip', 'outflow')])
+def test_residual2d_walls_and_outflow(bc):
+    nx, ny = 24, 14
+    U = workloads.random_smooth_2d(nx, ny, seed=5, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+    s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 0.5), mu_ref=1 / 200, Pr=0.73, bc=bc)
+    R, V, _ = s.residual(to_dev(U))
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 0.5, Physics(mu_ref=1 / 200, Pr=0.73), Options(), bc=bc)
+    Ro, Vo, _ = sc.residual(U)
+    eR = rel_err(fields2d(R.cpu().numpy()), fields2d(Ro))
+    eV = rel_err(fields2d(V.cpu().numpy()), fields2d(Vo.reshape(8, ny, nx)))
+    print('2D residual bc', bc, 'R err %.2e V err %.2e' % (eR, eV))
+    assert eR < 1e-11 and eV < 1e-12
+
+
+def test_rk_step2d_one_step():
+    nx, ny = 21, 18
+    U = workloads.random_smooth_2d(nx, ny, seed=7, noise=1e-3)
+    s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 1.0), mu_ref=0.01, cfl=0.6)
+    s.set_state(to_dev(U))
+    d = s.rk_step(0.0)
+    Ug, t = s.get_state()
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options(cfl=0.6))
+    Uo, dto, info = rk.rk3_step(sc, U, 0.0)
+    e = rel_err(fields2d(Ug.cpu().numpy()), fields2d(Uo))
+    print('2D one RK3 step: dt gpu %.17g oracle %.17g, state err %.2e' % (d['dt'], dto, e))
+    assert abs(d['dt'] - dto) < 1e-14 * dto
+    assert e < 1e-12
+    assert abs(t - dto) < 1e-14 * dto
+
+
+@pytest.mark.parametrize('linear', [False, True])
+def test_residual1d(linear):
+    nx = 150
+    U = workloads.random_smooth_1d(nx, seed=1)
+    s = hweno.Solver(nx, extent=(0.0, 1.0), mu_ref=0.01, linear_weights=int(linear))
+    R, V, d = s.residual(to_dev(U))
+    sc = Scheme1D(nx, 0.0, 1.0, Physics(mu_ref=0.01), Options(linear_weights=linear))
+    Ro, Vo, do = sc.residual(U)
+    eR = rel_err(fields1d(R.cpu().numpy()), fields1d(Ro))
+    eV = rel_err(fields1d(V.cpu().numpy()), fields1d(Vo[0]))
+    print('1D residual linear', linear, 'R err %.2e V err %.2e' % (eR, eV))
+    assert eR < 1e-11 and eV < 1e-12
+    assert abs(d['alpha_star'] - do['alpha']) < 1e-13 * do['alpha']
+
+
+def test_rk1d_steps_smooth_wave():
+    nx = 200
+    U = workloads.smooth_wave_1d(nx, seed=0)
+    kw = dict(extent=(0.0, 2 * np.pi), mu_ref=0.01, cfl=0.3, b_visc=0.0)
+    s = hweno.Solver(nx, **kw)
+    s.set_state(to_dev(U))
+    sc = Scheme1D(nx, 0.0, 2 * np.pi, Physics(mu_ref=0.01), Options(cfl=0.3, b_visc=np.inf),
+                  bc=('periodic', 'periodic'))
+    Uo, t = U, 0.0
+    for n in range(20):
+        d = s.rk_step(0.0)
+        Uo, dto, _ = rk.rk3_step(sc, Uo, t)
+        t += dto
+    Ug, tg = s.get_state()
+    e = rel_err(fields1d(Ug.cpu().numpy()), fields1d(Uo))
+    print('1D 20 steps: t gpu %.17g oracle %.17g err %.2e' % (tg, t, e))
+    assert e < 1e-12 and abs(tg - t) < 1e-13
