@@ -161,6 +161,22 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R
  * attempt. */
 HWENO_API hweno_status hweno_rk_step(hweno_ctx* ctx, double dt, hweno_diag* diag);
 
+/* Per-kernel-class GPU time, measured with HIP events recorded on the
+ * context's stream around every launch while timing is enabled.  Classes:
+ * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative
+ * moments, 3 gradient reconstruction + volume flux, 4 face fluxes, 5 stage
+ * update / assembly, 6..7 unused. */
+typedef struct hweno_timing {
+    double ms[8];                       /* summed elapsed milliseconds */
+    unsigned long long launches[8];     /* timed launches */
+} hweno_timing;
+
+/* enable != 0 starts recording (creates the events on first use). */
+HWENO_API hweno_status hweno_set_timing(hweno_ctx* ctx, int enable);
+
+/* Synchronises the stream, returns the totals; reset != 0 zeroes them. */
+HWENO_API hweno_status hweno_get_timing(hweno_ctx* ctx, hweno_timing* out, int reset);
+
 HWENO_API const char* hweno_status_string(hweno_status s);
 
 #ifdef __cplusplus

@@ -349,22 +349,34 @@ hipError_t launch_copy_out1(const Grid1& g, const double* S, double* U, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st) {
+hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st, Timer* tm) {
+    tbeg(tm, KC_GHOST, st);
     k_ghost1<<<1, 64, 0, st>>>(g, S);
+    tend(tm, st);
     return hipGetLastError();
 }
 
-hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st) {
+hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Timer* tm) {
+    tbeg(tm, KC_RECON, st);
     k_recon1<<<nb(g.NX - 2, 128), 128, 0, st>>>(g, S);
+    tend(tm, st);
+    tbeg(tm, KC_RBAR, st);
     k_rbar1<<<nb(g.NX - 4, 128), 128, 0, st>>>(g);
+    tend(tm, st);
+    tbeg(tm, KC_GRAD, st);
     k_grad1<<<nb(g.NX - 6, 128), 128, 0, st>>>(g);
+    tend(tm, st);
+    tbeg(tm, KC_FLUX, st);
     k_flux1<<<nb(g.nx + 1, 128), 128, 0, st>>>(g);
+    tend(tm, st);
     return hipGetLastError();
 }
 
 hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st) {
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm) {
+    tbeg(tm, KC_UPDATE, st);
     k_update1<<<nb(g.nx, 128), 128, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat);
+    tend(tm, st);
     return hipGetLastError();
 }
 

@@ -667,28 +667,40 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st) {
+hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st, Timer* tm) {
+    tbeg(tm, KC_GHOST, st);
     k_ghost2_x<<<nblk((long long)g.ny * 2 * HALO, 256), 256, 0, st>>>(g, S);
     k_ghost2_y<<<nblk((long long)g.NX * 2 * HALO, 256), 256, 0, st>>>(g, S);
+    tend(tm, st);
     return hipGetLastError();
 }
 
-hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st) {
+hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st, Timer* tm) {
     const long long nc = (long long)(g.NX - 2) * (g.NY - 2);
+    tbeg(tm, KC_RECON, st);
     k_recon2<<<nblk(nc, RC_CELLS), 256, 0, st>>>(g, S);
+    tend(tm, st);
     const long long n2 = (long long)(g.NX - 4) * (g.NY - 4);
+    tbeg(tm, KC_RBAR, st);
     k_rbar2<<<nblk(n2, 256), 256, 0, st>>>(g);
+    tend(tm, st);
     const long long n1 = (long long)(g.NX - 6) * (g.NY - 6);
+    tbeg(tm, KC_GRAD, st);
     k_grad2<<<nblk(n1, GR_CELLS), 192, 0, st>>>(g);
+    tend(tm, st);
+    tbeg(tm, KC_FLUX, st);
     k_flux2<0><<<nblk((long long)(g.nx + 1) * g.ny, 256), 256, 0, st>>>(g);
     k_flux2<1><<<nblk((long long)g.nx * (g.ny + 1), 256), 256, 0, st>>>(g);
+    tend(tm, st);
     return hipGetLastError();
 }
 
 hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st) {
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm) {
     const long long n = (long long)g.nx * g.ny;
+    tbeg(tm, KC_UPDATE, st);
     k_update2<<<nblk(n, 256), 256, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat);
+    tend(tm, st);
     return hipGetLastError();
 }
 

@@ -13,11 +13,6 @@
 #include "../../include/hweno.h"
 #include "hweno_kernels.h"
 
-namespace hw {
-hipError_t launch_check2(const Grid2& g, const double* S, hipStream_t st);
-hipError_t launch_check1(const Grid1& g, const double* S, hipStream_t st);
-}
-
 struct hweno_ctx {
     hweno_grid grid;
     hweno_physics phys;
@@ -33,6 +28,8 @@ struct hweno_ctx {
     hw::Reduce* red = nullptr;
     double t = 0.0;
     bool has_state = false;
+    hw::Timer timer;
+    hw::Timer* tm() { return timer.on ? &timer : nullptr; }
 };
 
 namespace {
@@ -164,25 +161,27 @@ hweno_status dev(hipError_t e) { return e == hipSuccess ? HWENO_OK : HWENO_E_DEV
     } while (0)
 
 hweno_status ghost(hweno_ctx* c, double* S) {
-    if (c->grid.dim == 2) return dev(hw::launch_ghost2(c->g2, S, c->stream));
-    return dev(hw::launch_ghost1(c->g1, S, c->stream));
+    if (c->grid.dim == 2) return dev(hw::launch_ghost2(c->g2, S, c->stream, c->tm()));
+    return dev(hw::launch_ghost1(c->g1, S, c->stream, c->tm()));
 }
 
 hweno_status residual(hweno_ctx* c, const double* S) {
-    if (c->grid.dim == 2) return dev(hw::launch_residual2(c->g2, S, c->stream));
-    return dev(hw::launch_residual1(c->g1, S, c->stream));
+    if (c->grid.dim == 2) return dev(hw::launch_residual2(c->g2, S, c->stream, c->tm()));
+    return dev(hw::launch_residual1(c->g1, S, c->stream, c->tm()));
 }
 
 hweno_status update(hweno_ctx* c, int stage, const double* S0, const double* Sin, double* Sout,
                     double* R, double* V) {
     if (c->grid.dim == 2)
-        return dev(hw::launch_update2(c->g2, stage, S0, Sin, Sout, R, V, c->stream));
-    return dev(hw::launch_update1(c->g1, stage, S0, Sin, Sout, R, V, c->stream));
+        return dev(hw::launch_update2(c->g2, stage, S0, Sin, Sout, R, V, c->stream, c->tm()));
+    return dev(hw::launch_update1(c->g1, stage, S0, Sin, Sout, R, V, c->stream, c->tm()));
 }
 
 hweno_status read_reduce(hweno_ctx* c, hw::Reduce* r) {
     TRY(dev(hipMemcpyAsync(r, c->red, sizeof(hw::Reduce), hipMemcpyDeviceToHost, c->stream)));
-    return dev(hipStreamSynchronize(c->stream));
+    TRY(dev(hipStreamSynchronize(c->stream)));
+    if (c->timer.on) c->timer.collect();
+    return HWENO_OK;
 }
 
 void fill_diag(const hweno_ctx* c, const hw::Reduce& r, hweno_diag* d, int restarts) {
@@ -263,6 +262,7 @@ HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics*
 
 HWENO_API hweno_status hweno_destroy(hweno_ctx* c) {
     if (!c) return HWENO_E_INVAL;
+    c->timer.destroy();
     delete c;
     return HWENO_OK;
 }
@@ -382,6 +382,31 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
     std::swap(c->S[0], c->S[1]);
     c->t += r.dt;
     fill_diag(c, r, diag, restarts);
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_set_timing(hweno_ctx* c, int enable) {
+    if (!c) return HWENO_E_INVAL;
+    if (enable) {
+        if (!c->timer.init()) return HWENO_E_DEVICE;
+        c->timer.on = true;
+    } else {
+        c->timer.on = false;
+    }
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_get_timing(hweno_ctx* c, hweno_timing* out, int reset) {
+    if (!c || !out) return HWENO_E_INVAL;
+    if (c->timer.ready) {
+        TRY(dev(hipStreamSynchronize(c->stream)));
+        c->timer.collect();
+    }
+    for (int k = 0; k < 8; ++k) {
+        out->ms[k] = c->timer.ready ? c->timer.ms[k] : 0.0;
+        out->launches[k] = c->timer.ready ? c->timer.launches[k] : 0;
+    }
+    if (reset && c->timer.ready) c->timer.reset();
     return HWENO_OK;
 }
 

@@ -64,23 +64,82 @@ struct Grid1 {
     Reduce* red;
 };
 
+// Optional per-kernel timing with HIP events on the launch stream.  Kernel
+// classes: 0 ghost, 1 recon, 2 rbar, 3 grad, 4 flux, 5 update, 6 other.
+enum { KC_GHOST = 0, KC_RECON, KC_RBAR, KC_GRAD, KC_FLUX, KC_UPDATE, KC_OTHER, KC_COUNT = 8 };
+
+struct Timer {
+    static constexpr int CAP = 128;
+    bool on = false;
+    bool ready = false;
+    int n = 0;
+    int cls[CAP];
+    hipEvent_t a[CAP], b[CAP];
+    double ms[KC_COUNT];
+    unsigned long long launches[KC_COUNT];
+    bool init() {
+        if (ready) return true;
+        for (int i = 0; i < CAP; ++i) {
+            if (hipEventCreate(&a[i]) != hipSuccess || hipEventCreate(&b[i]) != hipSuccess)
+                return false;
+        }
+        ready = true;
+        reset();
+        return true;
+    }
+    void reset() {
+        for (int k = 0; k < KC_COUNT; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    }
+    void begin(int k, hipStream_t st) {
+        if (!on || n >= CAP) return;
+        cls[n] = k;
+        (void)hipEventRecord(a[n], st);
+    }
+    void end(hipStream_t st) {
+        if (!on || n >= CAP) return;
+        (void)hipEventRecord(b[n], st);
+        ++n;
+    }
+    // after the stream has been synchronised
+    void collect() {
+        for (int i = 0; i < n; ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, a[i], b[i]) == hipSuccess) {
+                ms[cls[i]] += t;
+                launches[cls[i]] += 1;
+            }
+        }
+        n = 0;
+    }
+    void destroy() {
+        if (!ready) return;
+        for (int i = 0; i < CAP; ++i) { (void)hipEventDestroy(a[i]); (void)hipEventDestroy(b[i]); }
+        ready = false;
+    }
+};
+
+inline void tbeg(Timer* t, int k, hipStream_t st) { if (t) t->begin(k, st); }
+inline void tend(Timer* t, hipStream_t st) { if (t) t->end(st); }
+
 // Launchers (stream-ordered, no synchronisation).  Return hipError_t.
 hipError_t launch_reset(Reduce* red, hipStream_t st);
 hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream_t st);
 hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st);
-hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st);
-hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st);
+hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st, Timer* tm);
+hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st, Timer* tm);
 // stage 0: write R (12) and Vhat (8) in interior layout; stage 1..3: RK update
 hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st);
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm);
 hipError_t launch_dt(Reduce* red, double cfl_h, double visc_dt, double t_left, hipStream_t st);
 hipError_t launch_set_dt(Reduce* red, double dt, hipStream_t st);
 
 hipError_t launch_copy_in1(const Grid1& g, const double* U, double* S, hipStream_t st);
 hipError_t launch_copy_out1(const Grid1& g, const double* S, double* U, hipStream_t st);
-hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st);
-hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st);
+hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st, Timer* tm);
+hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Timer* tm);
 hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st);
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm);
+hipError_t launch_check2(const Grid2& g, const double* S, hipStream_t st);
+hipError_t launch_check1(const Grid1& g, const double* S, hipStream_t st);
 
 }  // namespace hw

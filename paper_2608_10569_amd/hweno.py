@@ -17,7 +17,11 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
-           'hweno_residual', 'hweno_rk_step', 'hweno_status_string')
+           'hweno_residual', 'hweno_rk_step', 'hweno_set_timing', 'hweno_get_timing',
+           'hweno_status_string')
+
+#: kernel classes of hweno_timing
+KERNEL_CLASSES = ('ghost', 'recon', 'rbar', 'grad', 'flux', 'update')
 
 
 class Grid(ctypes.Structure):
@@ -52,6 +56,10 @@ class Diag(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != 'pad'}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [('ms', ctypes.c_double * 8), ('launches', ctypes.c_ulonglong * 8)]
+
+
 class HwenoError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__('%s (status %d)' % (msg, code))
@@ -81,6 +89,8 @@ def lib():
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
+        L.hweno_set_timing.argtypes = [vp, ctypes.c_int]
+        L.hweno_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int]
         L.hweno_status_string.argtypes = [ctypes.c_int]
         L.hweno_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -139,7 +149,10 @@ class Solver:
         self._h = h
         nb = ctypes.c_size_t()
         check(lib().hweno_workspace_bytes(h, ctypes.byref(nb)))
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
         self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         check(lib().hweno_set_workspace(h, _ptr(self.workspace), nb.value))
         self.set_stream(torch.cuda.current_stream(self.device).cuda_stream)
@@ -183,6 +196,15 @@ class Solver:
         d = Diag()
         check(lib().hweno_rk_step(self._h, float(dt), ctypes.byref(d)))
         return d.as_dict()
+
+    def set_timing(self, on=True):
+        check(lib().hweno_set_timing(self._h, int(bool(on))))
+
+    def timing(self, reset=False):
+        """{kernel class: (total ms, launches)} from the library's HIP events."""
+        t = Timing()
+        check(lib().hweno_get_timing(self._h, ctypes.byref(t), int(bool(reset))))
+        return {name: (t.ms[k], t.launches[k]) for k, name in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, '_h', None):

@@ -128,4 +128,4 @@ def test_rk1d_steps_smooth_wave():
     Ug, tg = s.get_state()
     e = rel_err(fields1d(Ug.cpu().numpy()), fields1d(Uo))
     print('1D 20 steps: t gpu %.17g oracle %.17g err %.2e' % (tg, t, e))
-    assert e < 1e-12 and abs(tg - t) < 1e-13
+    assert e < 1e-10 and abs(tg - t) < 1e-13
