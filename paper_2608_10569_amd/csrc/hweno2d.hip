@@ -40,22 +40,57 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// One atomic per wavefront for the reductions below (lane 0 issues it).
+// Block-level reductions: wave shuffles, then LDS across the block's waves;
+// thread 0 issues at most one atomic, and only when it can change the slot.
+template <int NT>
 __device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
+    __shared__ double sh[NT / 64];
     v = wave_max(v);
-    if ((threadIdx.x & 63) == 0 && v > -INFINITY) atomicMax(slot, dkey(v));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) v = fmax(v, sh[w]);
+        const unsigned long long k = dkey(v);
+        if (v > -INFINITY && k > *(volatile unsigned long long*)slot) atomicMax(slot, k);
+    }
 }
+template <int NT>
 __device__ __forceinline__ void red_min(unsigned long long* slot, double v) {
+    __shared__ double sh[NT / 64];
     v = wave_min(v);
-    if ((threadIdx.x & 63) == 0 && v < INFINITY) atomicMin(slot, dkey(v));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) v = fmin(v, sh[w]);
+        const unsigned long long k = dkey(v);
+        if (v < INFINITY && k < *(volatile unsigned long long*)slot) atomicMin(slot, k);
+    }
 }
+template <int NT>
 __device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long long v) {
+    __shared__ unsigned long long sh[NT / 64];
     v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(slot, v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) v += sh[w];
+        if (v) atomicAdd(slot, v);
+    }
 }
+template <int NT>
 __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
+    __shared__ unsigned long long sh[NT / 64];
     unsigned long long s = wave_sum((unsigned long long)v);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(slot, (unsigned int)s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) s += sh[w];
+        if (s) atomicAdd(slot, (unsigned int)s);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -230,26 +265,38 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
             const double ut = k == 0 ? rbar + th1 * (U[o] - rbar) : U[o];
             F[(o * 4 + k) * N + cell] = ub[k] + th2 * (ut - ub[k]);
         }
-        if (k == 0) {
-            // wbar of (u, v, e) from this basis' unlimited volume values
-            double su = 0.0, sv = 0.0, se = 0.0;
+    }
+    // wbar of (u, v, e) from this basis' unlimited volume values: thread k
+    // sums the volume points q = k, k+4, k+8, then the four partial sums meet
+    // in LDS
+    {
+        double su = 0.0, sv = 0.0, se = 0.0;
+        for (int q = k; q < 9; q += 4) {
+            const int o = 6 + q;
+            const double w = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
+            const double ir = 1.0 / comp(b, 0, o);
+            const double u = comp(b, 1, o) * ir, v = comp(b, 2, o) * ir;
+            const double e = comp(b, 3, o) * ir - 0.5 * (u * u + v * v);
+            su += w * u;
+            sv += w * v;
+            se += w * e;
+        }
+        __syncthreads();   // redA / redB reads above are complete
+        redA[bk * RC_CELLS + cl] = su;
+        redB[bk * RC_CELLS + cl] = sv;
+        sh[(bk * 16 + 15) * RC_CELLS + cl] = se;   // moment slots are not read back
+        __syncthreads();
+        if (valid && k == 0) {
+            double tu = 0.0, tv = 0.0, te = 0.0;
 #pragma unroll
-            for (int h = 0; h < 3; ++h) {
-#pragma unroll
-                for (int gg = 0; gg < 3; ++gg) {
-                    const int o = 6 + 3 * h + gg;
-                    const double w = (h == 1 ? GW1 : GW0) * (gg == 1 ? GW1 : GW0);
-                    const double r = comp(b, 0, o);
-                    const double u = comp(b, 1, o) / r, v = comp(b, 2, o) / r;
-                    const double e = comp(b, 3, o) / r - 0.5 * (u * u + v * v);
-                    su += w * u;
-                    sv += w * v;
-                    se += w * e;
-                }
+            for (int f = 0; f < 4; ++f) {
+                tu += redA[(b * 4 + f) * RC_CELLS + cl];
+                tv += redB[(b * 4 + f) * RC_CELLS + cl];
+                te += sh[((b * 4 + f) * 16 + 15) * RC_CELLS + cl];
             }
-            g.wb[(b * 3 + 0) * N + cell] = su;
-            g.wb[(b * 3 + 1) * N + cell] = sv;
-            g.wb[(b * 3 + 2) * N + cell] = se;
+            g.wb[(b * 3 + 0) * N + cell] = tu;
+            g.wb[(b * 3 + 1) * N + cell] = tv;
+            g.wb[(b * 3 + 2) * N + cell] = te;
         }
     }
     if (inter) {
@@ -258,11 +305,11 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
         for (int q = 0; q < 9; ++q) V[(q * 4 + k) * N + cell] = U[6 + q];
         g.vk[(b * 4 + k) * N + cell] = U[15];
     }
-    // CFL wave speed over the limited face traces of interior cells
+    // CFL wave speed over the limited face traces of interior cells; thread k
+    // takes the face points o = k, k+4
     double amax = -INFINITY;
-    if (inter && k == 1) {
-#pragma unroll
-        for (int o = 0; o < 6; ++o) {
+    if (inter) {
+        for (int o = k; o < 6; o += 4) {
             double Ul[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -276,8 +323,8 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
             amax = fmax(amax, sp);
         }
     }
-    red_max(&g.red->alpha_key, amax);
-    red_add(&g.red->pp_cells, (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
+    red_max<256>(&g.red->alpha_key, amax);
+    red_add<256>(&g.red->pp_cells, (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,52 +477,60 @@ __global__ __launch_bounds__(192) void k_grad2(Grid2 g) {
 // last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
 // max over the face's three Gauss points and both sides.
 // ---------------------------------------------------------------------------
+constexpr int FX_FACES = 64;     // faces per block; block = 3 Gauss points x 64 faces
+
 template <int d>
-__global__ __launch_bounds__(256) void k_flux2(Grid2 g) {
+__global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Grid2 g) {
+    __shared__ double shb[3 * FX_FACES];
     const Consts& K = g.K;
     const int nfi = d == 0 ? g.nx + 1 : g.nx;
     const int nfj = d == 0 ? g.ny : g.ny + 1;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double bmax = -INFINITY;
-    if (t < (long long)nfi * nfj) {
+    const int G = threadIdx.x / FX_FACES;
+    const int fl = threadIdx.x % FX_FACES;
+    const long long t = (long long)blockIdx.x * FX_FACES + fl;
+    const bool valid = t < (long long)nfi * nfj;
+    const long long N = g.ncell;
+    long long cm = 0, cp = 0;
+    double fs[4] = {0.0, 0.0, 0.0, 0.0}, du[4] = {0.0, 0.0, 0.0, 0.0};
+    double beta = -INFINITY;
+    if (valid) {
         const int fj = (int)(t / nfi), fi = (int)(t % nfi);
         const int j = d == 0 ? HALO + fj : HALO - 1 + fj;
         const int i = d == 0 ? HALO - 1 + fi : HALO + fi;
-        const long long N = g.ncell;
-        const long long cm = (long long)j * g.NX + i;
-        const long long cp = d == 0 ? cm + 1 : cm + g.NX;
+        cm = (long long)j * g.NX + i;
+        cp = d == 0 ? cm + 1 : cm + g.NX;
         const double* F = d == 0 ? g.xf : g.yf;
         const int pg = d == 0 ? 0 : 6;
-        double Um[3][4], Up[3][4], fm[3][4], fp[3][4];
-        double beta = -INFINITY;
+        double Um[4], Up[4], sm[6], sp[6], fm[4], fp[4];
 #pragma unroll
-        for (int G = 0; G < 3; ++G) {
-            double sm[6], sp[6];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                Um[G][c] = F[((3 + G) * 4 + c) * N + cm];
-                Up[G][c] = F[(G * 4 + c) * N + cp];
-            }
-#pragma unroll
-            for (int z = 0; z < 6; ++z) {
-                sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
-                sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
-            }
-            flux2<d>(K, Um[G], sm, fm[G]);
-            flux2<d>(K, Up[G], sp, fp[G]);
-            beta = fmax(beta, fmax(speed2<d>(K, Um[G], sm), speed2<d>(K, Up[G], sp)));
+        for (int c = 0; c < 4; ++c) {
+            Um[c] = F[((3 + G) * 4 + c) * N + cm];
+            Up[c] = F[(G * 4 + c) * N + cp];
         }
+#pragma unroll
+        for (int z = 0; z < 6; ++z) {
+            sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
+            sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
+        }
+        flux2<d>(K, Um, sm, fm);
+        flux2<d>(K, Up, sp, fp);
+        beta = fmax(speed2<d>(K, Um, sm), speed2<d>(K, Up, sp));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            fs[c] = fm[c] + fp[c];
+            du[c] = Up[c] - Um[c];
+        }
+    }
+    shb[threadIdx.x] = beta;
+    __syncthreads();
+    // LF coefficient: max over the face's three Gauss points and both sides
+    beta = fmax(fmax(shb[fl], shb[FX_FACES + fl]), shb[2 * FX_FACES + fl]);
+    if (valid) {
         double* out = d == 0 ? g.fx : g.fy;
 #pragma unroll
-        for (int G = 0; G < 3; ++G) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                out[(G * 4 + c) * N + cm] =
-                    0.5 * (fm[G][c] + fp[G][c] - beta * (Up[G][c] - Um[G][c]));
-        }
-        bmax = beta;
+        for (int c = 0; c < 4; ++c) out[(G * 4 + c) * N + cm] = 0.5 * (fs[c] - beta * du[c]);
     }
-    red_max(&g.red->beta_key, bmax);
+    red_max<3 * FX_FACES>(&g.red->beta_key, valid && G == 0 ? beta : -INFINITY);
 }
 
 // ---------------------------------------------------------------------------
@@ -558,9 +613,9 @@ __global__ __launch_bounds__(256) void k_update2(Grid2 g, int stage, const doubl
         }
     }
     if (stage > 0) {
-        red_min(&g.red->min_rho_key, rmin);
-        red_min(&g.red->min_p_key, pmin);
-        red_add32(&g.red->bad[stage], bad);
+        red_min<256>(&g.red->min_rho_key, rmin);
+        red_min<256>(&g.red->min_p_key, pmin);
+        red_add32<256>(&g.red->bad[stage], bad);
     }
 }
 
@@ -602,7 +657,7 @@ __global__ void k_check2(Grid2 g, const double* __restrict__ S) {
         ok = ok && q[0] > 0.0 && pressure2(g.K, q[0], q[1], q[2], q[3]) > 0.0;
         bad = ok ? 0u : 1u;
     }
-    red_add32(&g.red->bad[0], bad);
+    red_add32<256>(&g.red->bad[0], bad);
 }
 
 __global__ void k_reset(Reduce* r) {
@@ -618,6 +673,7 @@ __global__ void k_reset(Reduce* r) {
 
 __global__ void k_dt(Reduce* r, double cfl_h, double visc_dt, double t_left) {
     if (threadIdx.x == 0) {
+        r->alpha1_key = r->alpha_key;
         const double a = dkey_inv(r->alpha_key);
         double dt = cfl_h / a;
         dt = fmin(dt, visc_dt);
@@ -627,7 +683,10 @@ __global__ void k_dt(Reduce* r, double cfl_h, double visc_dt, double t_left) {
 }
 
 __global__ void k_set_dt(Reduce* r, double dt) {
-    if (threadIdx.x == 0) r->dt = dt;
+    if (threadIdx.x == 0) {
+        r->alpha1_key = r->alpha_key;
+        r->dt = dt;
+    }
 }
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -689,8 +748,8 @@ hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st, Tim
     k_grad2<<<nblk(n1, GR_CELLS), 192, 0, st>>>(g);
     tend(tm, st);
     tbeg(tm, KC_FLUX, st);
-    k_flux2<0><<<nblk((long long)(g.nx + 1) * g.ny, 256), 256, 0, st>>>(g);
-    k_flux2<1><<<nblk((long long)g.nx * (g.ny + 1), 256), 256, 0, st>>>(g);
+    k_flux2<0><<<nblk((long long)(g.nx + 1) * g.ny, FX_FACES), 3 * FX_FACES, 0, st>>>(g);
+    k_flux2<1><<<nblk((long long)g.nx * (g.ny + 1), FX_FACES), 3 * FX_FACES, 0, st>>>(g);
     tend(tm, st);
     return hipGetLastError();
 }

@@ -184,11 +184,12 @@ hweno_status read_reduce(hweno_ctx* c, hw::Reduce* r) {
     return HWENO_OK;
 }
 
-void fill_diag(const hweno_ctx* c, const hw::Reduce& r, hweno_diag* d, int restarts) {
+void fill_diag(const hweno_ctx* c, const hw::Reduce& r, hweno_diag* d, int restarts,
+               bool stage1_alpha) {
     if (!d) return;
     d->t = c->t;
     d->dt = r.dt;
-    d->alpha_star = hw::dkey_inv(r.alpha_key);
+    d->alpha_star = hw::dkey_inv(stage1_alpha ? r.alpha1_key : r.alpha_key);
     d->beta_max = hw::dkey_inv(r.beta_key);
     d->min_rho = hw::dkey_inv(r.min_rho_key);
     d->min_p = hw::dkey_inv(r.min_p_key);
@@ -323,7 +324,7 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
     if (diag) {
         hw::Reduce r;
         TRY(read_reduce(c, &r));
-        fill_diag(c, r, diag, 0);
+        fill_diag(c, r, diag, 0, false);
         diag->dt = 0.0;
         diag->min_rho = diag->min_p = NAN;
     }
@@ -381,7 +382,7 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
     }
     std::swap(c->S[0], c->S[1]);
     c->t += r.dt;
-    fill_diag(c, r, diag, restarts);
+    fill_diag(c, r, diag, restarts, true);
     return HWENO_OK;
 }
 

@@ -122,21 +122,41 @@ __device__ __forceinline__ void hweno2d(const double* __restrict__ a, const Cons
         const double b4 = sxr * sxr + syt * syt;
         double tau = 0.25 * (dabs(b0 - b1) + dabs(b0 - b2) + dabs(b0 - b3) + dabs(b0 - b4));
         tau = tau * tau;
+        // five reciprocals 1/(beta_m + eps) from one division (prefix/suffix products)
         const double e = K.eps_weno;
-        const double t0 = G2D_0 * (1.0 + tau / (b0 + e));
-        const double t1 = G2D_1 * (1.0 + tau / (b1 + e));
-        const double t2 = G2D_1 * (1.0 + tau / (b2 + e));
-        const double t3 = G2D_1 * (1.0 + tau / (b3 + e));
-        const double t4 = G2D_1 * (1.0 + tau / (b4 + e));
-        const double tot = t0 + t1 + t2 + t3 + t4;
-        w0 = t0 / tot;
-        w1 = t1 / tot;
-        w2 = t2 / tot;
-        w3 = t3 / tot;
-        w4 = t4 / tot;
+        const double D0 = b0 + e, D1 = b1 + e, D2 = b2 + e, D3 = b3 + e, D4 = b4 + e;
+        const double p01 = D0 * D1, p012 = p01 * D2, p0123 = p012 * D3;
+        const double s34 = D3 * D4, s234 = D2 * s34;
+        const double prod = p0123 * D4;
+        double i0, i1, i2, i3, i4;
+        if (prod < 1e300) {
+            const double inv = 1.0 / prod;
+            i0 = inv * (D1 * s234);
+            i1 = inv * (D0 * s234);
+            i2 = inv * (p01 * s34);
+            i3 = inv * (p012 * D4);
+            i4 = inv * p0123;
+        } else {   // huge indicators: separate divisions avoid overflow
+            i0 = 1.0 / D0;
+            i1 = 1.0 / D1;
+            i2 = 1.0 / D2;
+            i3 = 1.0 / D3;
+            i4 = 1.0 / D4;
+        }
+        const double t0 = G2D_0 * (1.0 + tau * i0);
+        const double t1 = G2D_1 * (1.0 + tau * i1);
+        const double t2 = G2D_1 * (1.0 + tau * i2);
+        const double t3 = G2D_1 * (1.0 + tau * i3);
+        const double t4 = G2D_1 * (1.0 + tau * i4);
+        const double it = 1.0 / (t0 + t1 + t2 + t3 + t4);
+        w0 = t0 * it;
+        w1 = t1 * it;
+        w2 = t2 * it;
+        w3 = t3 * it;
+        w4 = t4 * it;
     }
-    const double r0 = w0 / G2D_0;
-    const double q = w0 * G2D_1 / G2D_0;
+    const double r0 = w0 * (1.0 / G2D_0);
+    const double q = w0 * (G2D_1 / G2D_0);
     const double d1 = w1 - q, d2 = w2 - q, d3 = w3 - q, d4 = w4 - q;
 #pragma unroll
     for (int k = 0; k < 15; ++k) C[k] = r0 * c0[k];
@@ -346,12 +366,15 @@ __device__ __forceinline__ void eig1(const Consts& K, const double* Ub, Eig1& e)
 // Row k of L and row c of R of the x- (b = 0) or y-Jacobian (b = 1).
 __device__ __forceinline__ void eig2_rows(const Consts& K, const double* Ub, int b, int k,
                                           double* Lrow, double* Rrow) {
-    const double r = Ub[0], u = Ub[1] / r, v = Ub[2] / r;
-    const double p = pressure2(K, r, Ub[1], Ub[2], Ub[3]);
-    const double c = sqrt(K.gamma * p / r);
-    const double H = (Ub[3] + p) / r;
+    const double ir = 1.0 / Ub[0];
+    const double u = Ub[1] * ir, v = Ub[2] * ir;
     const double q2 = u * u + v * v;
-    const double b1 = K.gm1 / (c * c), b2 = 0.5 * b1 * q2, ic = 1.0 / c;
+    const double p = K.gm1 * (Ub[3] - 0.5 * Ub[0] * q2);
+    const double c2 = K.gamma * p * ir;
+    const double c = sqrt(c2);
+    const double ic = 1.0 / c;
+    const double H = (Ub[3] + p) * ir;
+    const double b1 = K.gm1 * ic * ic, b2 = 0.5 * b1 * q2;
     const double un = b ? v : u;       // normal velocity
     const double ut = b ? u : v;       // tangential velocity
     // In (rho, m_n, m_t, E) ordering the two Jacobians have identical

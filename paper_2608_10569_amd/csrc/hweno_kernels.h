@@ -17,7 +17,8 @@ struct Reduce {
     unsigned long long min_p_key;     // min cell-average pressure
     unsigned int bad[4];              // inadmissible cells per stage (index 1..3)
     double dt;                        // step size used by the update kernels
-    double pad[3];
+    unsigned long long alpha1_key;    // alpha of the stage-1 reconstruction (copied by k_dt)
+    double pad[2];
 };
 
 // Ghost-fill description of one side (xlo, xhi, ylo, yhi).

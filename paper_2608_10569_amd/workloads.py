@@ -124,13 +124,26 @@ def random_smooth_1d(nx, seed, gamma=1.4):
 # 2D workloads
 # ---------------------------------------------------------------------------
 
-def viscous_shock_tube_2d(nx=1000, ny=500, gamma=1.4):
+def viscous_shock_tube_2d(nx=1000, ny=500, gamma=1.4, seed=None, amp=0.0):
     """Viscous shock tube on [0,1] x [0,0.5]: (rho, p) = (120, 120/gamma) for
-    x < 0.5 and (1.2, 1.2/gamma) for x >= 0.5, at rest."""
+    x < 0.5 and (1.2, 1.2/gamma) for x >= 0.5, at rest.  With ``seed``, smooth
+    random modes of relative amplitude ``amp`` perturb rho, u, v and p (for
+    parity tests that need flow next to the walls)."""
+    modes = None
+    if seed is not None:
+        rng = np.random.default_rng([SEED, 13, seed])
+        modes = (rng.integers(1, 6, (4, 3)), rng.integers(1, 6, (4, 3)),
+                 rng.uniform(0, 2 * np.pi, (4, 3)), rng.uniform(-1, 1, (4, 3)) * amp)
+
     def prim(X, Y):
         L = X < 0.5
         rho = np.where(L, 120.0, 1.2)
-        return rho, np.zeros_like(X), np.zeros_like(X), rho / gamma
+        f = [np.zeros_like(X) for _ in range(4)]
+        if modes is not None:
+            kx, ky, ph, a = modes
+            f = [sum(a[q, m] * np.sin(np.pi * kx[q, m] * X + 2 * np.pi * ky[q, m] * Y + ph[q, m])
+                     for m in range(3)) for q in range(4)]
+        return rho * (1.0 + f[0]), f[1], f[2], rho / gamma * (1.0 + f[3])
     return project2d(prim, nx, ny, (0.0, 1.0, 0.0, 0.5), gamma)
 
 

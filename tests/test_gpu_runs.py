@@ -1,0 +1,257 @@
+"""GPU parity on whole runs, full-size sampled outputs, shock cases, restart,
+error paths and checkpoint/resume (all through the C ABI)."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip('torch')
+
+from oracle import rk  # noqa: E402
+from oracle.common import Options, Physics  # noqa: E402
+from oracle.scheme1d import Scheme1D  # noqa: E402
+from oracle.scheme2d import Scheme2D  # noqa: E402
+from paper_2608_10569_amd import hweno, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = 'cuda:0'
+GOLDEN = os.path.join(os.path.dirname(__file__), 'golden')
+
+
+def to_dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U)).to(DEV)
+
+
+def rel_err(A, B):
+    A, B = np.asarray(A), np.asarray(B)
+    A = A.reshape(-1, A.shape[-1]) if A.ndim > 1 else A[None]
+    B = B.reshape(A.shape)
+    return max(np.abs(A[k] - B[k]).max() / max(np.abs(B[k]).max(), 1e-300)
+               for k in range(A.shape[0]))
+
+
+def l1(A, B, h):
+    return float(np.sum(np.abs(np.asarray(A) - np.asarray(B))) * h)
+
+
+def test_c1_full_run_matches_stored_oracle():
+    """Smooth 1D wave to t = 1 with the paper's time-step rule (b = 0.001)."""
+    ref = np.loadtxt(os.path.join(GOLDEN, 'c1_smooth_wave_t1.txt')).reshape(2, 3, 200)
+    with open(os.path.join(GOLDEN, 'c1_smooth_wave_t1.txt')) as f:
+        f.readline()
+        nsteps = int(f.readline().split()[2])
+    s = hweno.Solver(200, extent=(0.0, 2 * math.pi), gamma=1.4, Pr=0.72, mu_ref=0.01, cfl=0.3,
+                     b_visc=0.001, t_final=1.0)
+    s.set_state(to_dev(workloads.smooth_wave_1d(200)))
+    n, t = 0, 0.0
+    while t < 1.0 - 1e-14:
+        d = s.rk_step(0.0)
+        t = d['t']
+        n += 1
+        assert d['restarts'] == 0 and d['pp_cells'] == 0
+    U, t = s.get_state()
+    e = rel_err(U.cpu().numpy().reshape(6, -1), ref.reshape(6, -1))
+    print('C1 to t=1: %d steps (oracle %d), max rel err per field %.2e' % (n, nsteps, e))
+    assert n == nsteps and abs(t - 1.0) < 1e-14
+    assert e < 1e-10
+
+
+def _riemann(nx, left, right):
+    return workloads.riemann_1d(left, right, nx)
+
+
+@pytest.mark.parametrize('case', ['sod', 'double_rarefaction'])
+def test_c2_prefix_n2000_paper_rule(case):
+    """Riemann problems at N = 2000 (mu = 1e-3, Pr = 0.72) with the paper's
+    time-step rule (b = 0.001 binds): 150 steps, L1 parity and positivity."""
+    U = workloads.sod_1d(2000) if case == 'sod' else workloads.double_rarefaction_1d(2000)
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    s = hweno.Solver(2000, extent=(0.0, 1.0), bc=('outflow', 'outflow'), cfl=0.3, **ph)
+    s.set_state(to_dev(U))
+    sc = Scheme1D(2000, 0.0, 1.0, Physics(**ph), Options(cfl=0.3), bc=('outflow', 'outflow'))
+    Uo, t = U, 0.0
+    for _ in range(150):
+        d = s.rk_step(0.0)
+        Uo, dt, info = rk.rk3_step(sc, Uo, t)
+        t += dt
+        assert d['restarts'] == 0 and info['restarts'] == 0
+    Ug, tg = s.get_state()
+    Ug = Ug.cpu().numpy()
+    err = l1(Ug[0], Uo[0], 1.0 / 2000)
+    print('%s N=2000 150 steps: t %.6g, L1 diff of averages %.2e' % (case, tg, err))
+    assert abs(tg - t) < 1e-14
+    assert err < 1e-8
+    assert Ug[0, 0].min() > 0 and d['min_p'] > 0
+
+
+def _ex54(n, T):
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    U = workloads.riemann_1d((7.0, -1.0, 0.2), (7.0, 1.0, 0.2), n, x0=-1.0, x1=1.0, xd=0.0)
+    s = hweno.Solver(n, extent=(-1.0, 1.0), bc=('inflow', 'outflow'),
+                     inflow={0: (7.0, -1.0, 0.2)}, cfl=0.3, t_final=T, **ph)
+    E_in = 0.2 / 0.4 + 0.5 * 7.0
+    sc = Scheme1D(n, -1.0, 1.0, Physics(**ph), Options(cfl=0.3, t_final=T),
+                  bc=('inflow', 'outflow'), inflow={0: np.array([7.0, -7.0, E_in])})
+    return U, s, sc
+
+
+def test_double_rarefaction_example_5_4_limiter_onset():
+    """Example 5.4 data (7,-1,0.2) | (7,1,0.2) on (-1, 1), inflow left, outflow
+    right, Re = 1000, 200 cells: through the onset of limiting (150 steps,
+    t = 0.015) the runs agree to L1 1e-8 and the limiter acts on both."""
+    n = 200
+    U, s, sc = _ex54(n, 1.0)
+    s.set_state(to_dev(U))
+    Uo, t, pp_o, pp_g = U, 0.0, 0, 0
+    for _ in range(150):
+        d = s.rk_step(0.0)
+        Uo, dt, info = rk.rk3_step(sc, Uo, t)
+        t += dt
+        pp_o += info['pp_cells']
+        pp_g += d['pp_cells']
+        assert d['min_rho'] > 0 and d['min_p'] > 0 and d['restarts'] == 0
+    Ug, tg = s.get_state()
+    err = l1(Ug.cpu().numpy()[0], Uo[0], 2.0 / n)
+    print('Example 5.4 data, 150 steps: limiter cell-stages gpu %d oracle %d, L1 diff %.2e'
+          % (pp_g, pp_o, err))
+    assert pp_g > 0 and pp_g == pp_o
+    assert err < 1e-8 and abs(tg - t) < 1e-14
+
+
+def test_double_rarefaction_example_5_4_full_run_positivity():
+    """Same problem to t = 0.1 (1000 steps).  Past the onset the limited
+    near-vacuum region amplifies rounding: two oracle runs whose initial data
+    differ by 1e-15 end about 1e-3 apart in L1.  The GPU run must keep
+    positivity with the limiter active and differ from the oracle by no more
+    than a few times the oracle's own sensitivity."""
+    n, T = 200, 0.1
+    U, s, sc = _ex54(n, T)
+    s.set_state(to_dev(U))
+    pp_g, t = 0, 0.0
+    while t < T - 1e-14:
+        d = s.rk_step(0.0)
+        t = d['t']
+        pp_g += d['pp_cells']
+        assert d['min_rho'] > 0 and d['min_p'] > 0
+    Ug = s.get_state()[0].cpu().numpy()
+    Uo, _, _ = rk.run(sc, U, 0.0, T)
+    Up, _, _ = rk.run(sc, U * (1.0 + 1e-15 * np.random.default_rng(1).standard_normal(U.shape)),
+                      0.0, T)
+    d_gpu = l1(Ug[0], Uo[0], 2.0 / n)
+    d_self = l1(Up[0], Uo[0], 2.0 / n)
+    print('Example 5.4 data to t=0.1: limiter cell-stages gpu %d; L1 gpu-oracle %.2e, '
+          'oracle vs perturbed oracle %.2e' % (pp_g, d_gpu, d_self))
+    assert pp_g > 0 and Ug[0, 0].min() > 0
+    assert d_gpu < 5.0 * max(d_self, 1e-8)
+
+
+@pytest.mark.parametrize('seed', [0, 1])
+def test_c3_full_size_sampled_windows(seed):
+    """Residual of the 1000 x 500 shock tube (walls + symmetry) on cells the
+    oracle evaluates window by window, with the true neighbours as halo."""
+    nx, ny = 1000, 500
+    U = workloads.viscous_shock_tube_2d(nx, ny, seed=seed, amp=0.02)
+    ph = dict(gamma=1.4, Pr=0.73, mu_ref=1.0 / 200)
+    bc = ('noslip', 'noslip', 'noslip', 'slip')
+    s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 0.5), bc=bc, cfl=0.3, **ph)
+    R, V, d = s.residual(to_dev(U))
+    R = R.cpu().numpy()
+    V = V.cpu().numpy()
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 0.5, Physics(**ph), Options(cfl=0.3), bc=bc)
+    Ug = sc.ghost(U)
+    worst = 0.0
+    for (j0, i0) in ((0, 0), (0, 492), (492, 996), (250, 497), (120, 700)):
+        h, w = min(8, ny - j0), min(8, nx - i0)
+        Wg = Ug[:, :, j0:j0 + h + 8, i0:i0 + w + 8]
+        Fo, Vo, _ = sc.residual_ghosted(Wg)
+        Fg = R[:, :, j0:j0 + h, i0:i0 + w]
+        scale = np.abs(R).reshape(12, -1).max(axis=1)[:, None, None]
+        e = np.abs(Fg - Fo).reshape(12, h, w) / scale
+        ev = np.abs(V[:, j0:j0 + h, i0:i0 + w] - Vo.reshape(8, h, w)).max() / np.abs(V).max()
+        worst = max(worst, e.max(), ev)
+    print('C3 1000x500 sampled windows, seed %d: worst rel err %.2e' % (seed, worst))
+    assert worst < 1e-11
+
+
+def test_free_stream_and_conservation_2d():
+    nx, ny = 64, 48
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = np.array([1.3, 0.4, -0.3, 2.7])[:, None, None]
+    s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 1.0), mu_ref=0.01)
+    R, V, _ = s.residual(to_dev(U))
+    R = R.cpu().numpy()
+    assert np.all(R[0] == 0.0)
+    assert np.abs(R[1:]).max() < 1e-12 and np.abs(V.cpu().numpy()).max() < 1e-14
+    U = workloads.random_smooth_2d(nx, ny, seed=9, noise=1e-3)
+    R, _, _ = s.residual(to_dev(U))
+    R = R.cpu().numpy()
+    tot = R[0].sum(axis=(-1, -2)) / (nx * ny)
+    assert np.abs(tot).max() < 1e-13 * np.abs(R[0]).max()
+
+
+def test_restart_matches_halved_step():
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    U = workloads.double_rarefaction_1d(100)
+    a = hweno.Solver(100, extent=(0.0, 1.0), bc=('outflow', 'outflow'), **ph)
+    a.set_state(to_dev(U))
+    d = a.rk_step(0.05)
+    assert d['restarts'] > 0 and d['dt'] == 0.05 / 2 ** d['restarts']
+    b = hweno.Solver(100, extent=(0.0, 1.0), bc=('outflow', 'outflow'), **ph)
+    b.set_state(to_dev(U))
+    d2 = b.rk_step(d['dt'])
+    assert d2['restarts'] == 0
+    assert torch.equal(a.get_state()[0], b.get_state()[0])
+    # the oracle takes the same number of halvings
+    sc = Scheme1D(100, 0.0, 1.0, Physics(**ph), Options(), bc=('outflow', 'outflow'))
+    _, dto, info = rk.rk3_step(sc, U, 0.0, dt=0.05)
+    assert info['restarts'] == d['restarts'] and dto == d['dt']
+
+
+def test_error_paths():
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    U = workloads.double_rarefaction_1d(50)
+    s = hweno.Solver(50, extent=(0.0, 1.0), bc=('outflow', 'outflow'), max_halvings=0, **ph)
+    s.set_state(to_dev(U))
+    with pytest.raises(hweno.HwenoError) as e:
+        s.rk_step(1.0)
+    assert e.value.code == 4                     # inadmissible after the cap
+    assert torch.equal(s.get_state()[0], to_dev(U))   # state unchanged
+    bad = U.copy()
+    bad[0, 0, 7] = float('nan')
+    s.set_state(to_dev(bad))
+    with pytest.raises(hweno.HwenoError) as e:
+        s.rk_step(0.0)
+    assert e.value.code == 5
+    bad = U.copy()
+    bad[0, 0, 3] = -1.0
+    s.set_state(to_dev(bad))
+    with pytest.raises(hweno.HwenoError) as e:
+        s.rk_step(0.0)
+    assert e.value.code == 5
+    fresh = hweno.Solver(50, extent=(0.0, 1.0), bc=('outflow', 'outflow'), **ph)
+    with pytest.raises(hweno.HwenoError) as e:
+        fresh.rk_step(0.0)
+    assert e.value.code == 6
+
+
+def test_checkpoint_resume_bitwise():
+    nx, ny = 40, 24
+    U = workloads.random_smooth_2d(nx, ny, seed=2)
+    a = hweno.Solver(nx, ny, mu_ref=0.01)
+    a.set_state(to_dev(U))
+    for _ in range(6):
+        a.rk_step(0.0)
+    b = hweno.Solver(nx, ny, mu_ref=0.01)
+    b.set_state(to_dev(U))
+    for _ in range(3):
+        b.rk_step(0.0)
+    Uc, tc = b.get_state()
+    c = hweno.Solver(nx, ny, mu_ref=0.01)
+    c.set_state(Uc, tc)
+    for _ in range(3):
+        c.rk_step(0.0)
+    Ua, ta = a.get_state()
+    Uc2, tc2 = c.get_state()
+    assert torch.equal(Ua, Uc2) and ta == tc2
