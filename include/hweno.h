@@ -161,6 +161,22 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R
  * attempt. */
 HWENO_API hweno_status hweno_rk_step(hweno_ctx* ctx, double dt, hweno_diag* diag);
 
+/* Reverse mode (vector-Jacobian product) of hweno_residual at the state U
+ * (device, D1), 2D grids with constant viscosity (mu_exp = 0):
+ *   Ubar = (dR/dU)^T Rbar + (dVhat/dU)^T Vbar        (device, D1, overwritten)
+ *   *mu_bar = (dR/dmu_ref) . Rbar                    (host double; NULL: skip)
+ * Rbar has the layout of R, Vbar that of Vhat (NULL: zero).  The branches of
+ * the forward point are kept (positivity-limiter thetas and their argmin
+ * points, the Lax-Friedrichs maximum and its argmax, |.| in the nonlinear
+ * weights with derivative sign(x), 0 at 0); ties go to the lowest index.
+ * Every sum is a fixed-order gather, so results are bitwise reproducible.
+ * Uses the workspace (the forward intermediates are recomputed); with a
+ * non-NULL mu_bar the call synchronises.  HWENO_E_INVAL for dim = 1 or
+ * mu_exp != 0.  Reverse-mode part of the differentiable rollout (the paper's
+ * scheme of eq. (3.2); adjoint of its Sec. 3 residual). */
+HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const double* Rbar,
+                                          const double* Vbar, double* Ubar, double* mu_bar);
+
 /* Per-kernel-class GPU time, measured with HIP events recorded on the
  * context's stream around every launch while timing is enabled.  Classes:
  * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libhweno.so')
-SOURCES = ['hweno2d.hip', 'hweno1d.hip', 'hweno_api.cpp']
+SOURCES = ['hweno2d.hip', 'hweno1d.hip', 'hweno2d_vjp.hip', 'hweno_api.cpp']
 ARCH = os.environ.get('HWENO_ARCH', 'gfx950')
 
 
@@ -27,7 +27,7 @@ def build(verbose=False):
     tmp = LIB + '.tmp'
     cmd = [hipcc(), '--offload-arch=' + ARCH, '-O3', '-std=c++17', '-fPIC', '-shared',
            '-fvisibility=hidden', '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
-           '-Wall', '-Wno-unused-function', '-o', tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+           '-Wall', '-Wno-unused-function', '-Wno-unused-variable', '-o', tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(' '.join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)

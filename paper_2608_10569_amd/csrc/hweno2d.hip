@@ -299,12 +299,12 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
             g.wb[(b * 3 + 2) * N + cell] = te;
         }
     }
-    if (inter) {
+    if (valid) {
         double* V = b == 0 ? g.xv : g.yv;
 #pragma unroll
         for (int q = 0; q < 9; ++q) V[(q * 4 + k) * N + cell] = U[6 + q];
-        g.vk[(b * 4 + k) * N + cell] = U[15];
     }
+    if (inter) g.vk[(b * 4 + k) * N + cell] = U[15];
     // CFL wave speed over the limited face traces of interior cells; thread k
     // takes the face points o = k, k+4
     double amax = -INFINITY;

@@ -1,0 +1,859 @@
+// Reverse mode (vector-Jacobian product) of the 2D HWENO-GR residual of
+// arXiv 2608.10569 (eq. (3.2) with eqs. (3.3)-(3.9)): given the adjoints of
+// the residual R and of the modified moments, the adjoint of the input state
+// and of the viscosity mu_ref.
+//
+// The forward pipeline is recomputed first (its intermediates stay in the
+// workspace); the adjoint kernels then run in reverse order.  Every adjoint
+// slot has exactly one writer and cross-cell sums are gathers in a fixed
+// order, so the result is deterministic (no floating-point atomics).
+// Branches (limiter thetas, LF-speed maximum, |.| in the weights) follow the
+// forward point; ties go to the lowest index in the order of the oracle.
+//
+//   k_adj_flux<d>  face-flux adjoint (eq. (3.3)) -> trace / face-gradient adjoints
+//   k_adj_grad     volume-flux + gradient-reconstruction adjoint (eq. (3.9))
+//   k_adj_rgather  gather of the weak-moment adjoints from the 3x3 stencils
+//   k_adj_wmom     weak-moment adjoint (eqs. (3.6)-(3.8)) -> trace / volume adjoints
+//   k_adj_recon    limiter, back-transform, scalar HWENO, projection, bases
+//   k_adj_ugather  gather of the state adjoint from the 3x3 stencils
+//   k_adj_ghost_*  adjoint of the ghost fill (Remark 4.1)
+
+#include "hweno_adj.h"
+#include "hweno_vjp.h"
+
+namespace hw {
+
+namespace {
+
+constexpr int HALO = 4;
+
+__device__ __forceinline__ double gw(int g) { return g == 1 ? GW1 : GW0; }
+__device__ __forceinline__ double gx(int g) { return g == 0 ? -GS : (g == 1 ? 0.0 : GS); }
+
+__device__ __forceinline__ bool interior(const Grid2& g, int j, int i) {
+    return j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
+}
+
+// residual adjoint of interior cell (j, i): F1, F2, F3 component c
+__device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, int c, int j, int i) {
+    const long long nint = (long long)g.nx * g.ny;
+    return A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
+}
+
+// fixed-order block sum of the mu adjoint: one partial per block
+template <int NT>
+__device__ __forceinline__ void mu_partial(double v, double* part) {
+    __shared__ double sh[NT];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < NT; ++t) s += sh[t];
+        part[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes: fhat = 1/2 (f(u-,s-) + f(u+,s+) - beta (u+ - u-)), beta the
+// max over the face's 3 Gauss points x 2 sides of max(|u_n| + c, beta_PP).
+// Block: 3 Gauss points x 64 faces.
+// ---------------------------------------------------------------------------
+constexpr int AF = 64;
+
+template <int d>
+__global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) {
+    __shared__ double shs[2][3 * AF];     // speeds of the two sides
+    __shared__ double shb[3 * AF];        // beta-bar partial sums
+    const Consts& K = g.K;
+    const int nfi = d == 0 ? g.nx + 1 : g.nx;
+    const int nfj = d == 0 ? g.ny : g.ny + 1;
+    const int G = threadIdx.x / AF;
+    const int fl = threadIdx.x % AF;
+    const long long t = (long long)blockIdx.x * AF + fl;
+    const bool valid = t < (long long)nfi * nfj;
+    const long long N = g.ncell;
+    int j = HALO, i = HALO;
+    if (valid) {
+        const int fj = (int)(t / nfi), fi = (int)(t % nfi);
+        j = d == 0 ? HALO + fj : HALO - 1 + fj;
+        i = d == 0 ? HALO - 1 + fi : HALO + fi;
+    }
+    const long long cm = (long long)j * g.NX + i;
+    const long long cp = d == 0 ? cm + 1 : cm + g.NX;
+    const int jp = d == 0 ? j : j + 1, ip = d == 0 ? i + 1 : i;
+    const double* F = d == 0 ? g.xf : g.yf;
+    const int pg = d == 0 ? 0 : 6;
+    double Um[4], Up[4], sm[6], sp[6];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        Um[c] = F[((3 + G) * 4 + c) * N + cm];
+        Up[c] = F[(G * 4 + c) * N + cp];
+    }
+#pragma unroll
+    for (int z = 0; z < 6; ++z) {
+        sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
+        sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
+    }
+    const double spm = speed2<d>(K, Um, sm), spp = speed2<d>(K, Up, sp);
+    shs[0][threadIdx.x] = valid ? spm : -INFINITY;
+    shs[1][threadIdx.x] = valid ? spp : -INFINITY;
+    // adjoint of fhat at this Gauss point from the two adjacent residuals
+    double fb[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        const double w = gw(G), x = gx(G);
+        const bool im = interior(g, j, i), ipn = interior(g, jp, ip);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double v = 0.0;
+            if (d == 0) {
+                if (im) v += -w * K.idx * rbar(A, g, 0, c, j, i) - 0.5 * w * K.idx * rbar(A, g, 1, c, j, i)
+                             - w * x * K.idx * rbar(A, g, 2, c, j, i);
+                if (ipn) v += w * K.idx * rbar(A, g, 0, c, jp, ip) - 0.5 * w * K.idx * rbar(A, g, 1, c, jp, ip)
+                              + w * x * K.idx * rbar(A, g, 2, c, jp, ip);
+            } else {
+                if (im) v += -w * K.idy * rbar(A, g, 0, c, j, i) - w * x * K.idy * rbar(A, g, 1, c, j, i)
+                             - 0.5 * w * K.idy * rbar(A, g, 2, c, j, i);
+                if (ipn) v += w * K.idy * rbar(A, g, 0, c, jp, ip) + w * x * K.idy * rbar(A, g, 1, c, jp, ip)
+                              - 0.5 * w * K.idy * rbar(A, g, 2, c, jp, ip);
+            }
+            fb[c] = v;
+        }
+    }
+    __syncthreads();
+    // beta and its argmax in the order (minus side G = 0,1,2, plus side G = 0,1,2)
+    double beta = -INFINITY;
+    int arg = 0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double v = shs[side][q * AF + fl];
+            if (v > beta) {
+                beta = v;
+                arg = side * 3 + q;
+            }
+        }
+    }
+    double Umb[4] = {0.0, 0.0, 0.0, 0.0}, Upb[4] = {0.0, 0.0, 0.0, 0.0};
+    double smb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, spb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double mub = 0.0, betab = 0.0;
+    const double mu = K.mu_ref;
+    if (valid) {
+        double hf[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            hf[c] = 0.5 * fb[c];
+            Umb[c] += 0.5 * beta * fb[c];
+            Upb[c] -= 0.5 * beta * fb[c];
+            betab -= 0.5 * fb[c] * (Up[c] - Um[c]);
+        }
+        flux2_vjp<d>(K, Um, sm, mu, hf, Umb, smb, mub);
+        flux2_vjp<d>(K, Up, sp, mu, hf, Upb, spb, mub);
+    }
+    shb[threadIdx.x] = betab;
+    __syncthreads();
+    if (valid && arg % 3 == G) {
+        const double bsum = shb[fl] + shb[AF + fl] + shb[2 * AF + fl];
+        if (arg < 3) speed2_vjp<d>(K, Um, sm, mu, bsum, Umb, smb, mub);
+        else speed2_vjp<d>(K, Up, sp, mu, bsum, Upb, spb, mub);
+    }
+    if (valid) {
+        double* XB = d == 0 ? W.xfb : W.yfb;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            XB[((3 + G) * 4 + c) * N + cm] = Umb[c];
+            XB[(G * 4 + c) * N + cp] = Upb[c];
+        }
+#pragma unroll
+        for (int z = 0; z < 6; ++z) {
+            W.gfb[((pg + 3 + G) * 6 + z) * N + cm] = smb[z];
+            W.gfb[((pg + G) * 6 + z) * N + cp] = spb[z];
+        }
+    }
+    mu_partial<3 * AF>(valid ? mub : 0.0, W.mupart + (d == 0 ? 0 : W.mu_off1));
+}
+
+// ---------------------------------------------------------------------------
+// Gradient reconstruction (and, on interior cells, the volume fluxes).
+// Block: 32 cells x 6 gradient components s = 2 w + l.
+// ---------------------------------------------------------------------------
+constexpr int AG = 32;
+
+__global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) {
+    __shared__ double shv[6 * 9 * AG];       // forward volume gradients
+    __shared__ double shvb[2][6 * 9 * AG];   // their adjoints from f and from g
+    const Consts& K = g.K;
+    const int tid = threadIdx.x;
+    const int cl = tid % AG;
+    const int s = tid / AG;
+    const int w = s >> 1, l = s & 1;
+    const int wc = g.NX - 6;
+    const long long nreg = (long long)wc * (g.NY - 6);
+    const long long cid = (long long)blockIdx.x * AG + cl;
+    const bool valid = cid < nreg;
+    int j = 3, i = 3;
+    if (valid) {
+        j = 3 + (int)(cid / wc);
+        i = 3 + (int)(cid % wc);
+    }
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    const double* R0 = g.rb + ((l * 3 + w) * 3 + 0) * N;
+    const double* R1 = g.rb + ((l * 3 + w) * 3 + 1) * N;
+    const double* R2 = g.rb + ((l * 3 + w) * 3 + 2) * N;
+    double a[17];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a[q] = R0[cell + (long long)(q / 3 - 1) * g.NX + (q % 3 - 1)];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = 2 * e + 1;
+        const long long nb = cell + (long long)(q / 3 - 1) * g.NX + (q % 3 - 1);
+        a[9 + e] = R1[nb];
+        a[13 + e] = R2[nb];
+    }
+    double C[15], vo[9];
+    hweno2d(a, K, C);
+    eval_vol(C, vo);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        shv[(s * 9 + q) * AG + cl] = vo[q];
+        shvb[0][(s * 9 + q) * AG + cl] = 0.0;
+        shvb[1][(s * 9 + q) * AG + cl] = 0.0;
+    }
+    __syncthreads();
+    const bool inter = valid && interior(g, j, i);
+    double mub = 0.0;
+    if (inter && s < 2) {
+        // volume flux: vf = sum_q w_q f(U_q, s_q); vf-bar = F2-bar/dx (f), F3-bar/dy (g)
+        double fb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            fb[c] = s == 0 ? rbar(A, g, 1, c, j, i) * K.idx : rbar(A, g, 2, c, j, i) * K.idy;
+        const double* V = s == 0 ? g.xv : g.yv;
+        double* VB = s == 0 ? W.xvb : W.yvb;
+        for (int q = 0; q < 9; ++q) {
+            const double wq = gw(q / 3) * gw(q % 3);
+            double Uq[4], sq[6], Uqb[4] = {0.0, 0.0, 0.0, 0.0}, sqb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            double f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                Uq[c] = V[(q * 4 + c) * N + cell];
+                f[c] = wq * fb[c];
+            }
+#pragma unroll
+            for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * AG + cl];
+            if (s == 0) flux2_vjp<0>(K, Uq, sq, K.mu_ref, f, Uqb, sqb, mub);
+            else flux2_vjp<1>(K, Uq, sq, K.mu_ref, f, Uqb, sqb, mub);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] = Uqb[c];
+#pragma unroll
+            for (int z = 0; z < 6; ++z) shvb[s][(z * 9 + q) * AG + cl] = sqb[z];
+        }
+    }
+    __syncthreads();
+    // adjoint of this component's 21 point values
+    double yb[21];
+#pragma unroll
+    for (int p = 0; p < 12; ++p) yb[p] = g_ld(W.gfb, (p * 6 + s) * N + cell);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        yb[12 + q] = shvb[0][(s * 9 + q) * AG + cl] + shvb[1][(s * 9 + q) * AG + cl];
+    double Cb[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) Cb[k] = 0.0;
+    adj::xface_T(yb, Cb);
+    adj::yface_T(yb + 6, Cb);
+    adj::vol_T(yb + 12, Cb);
+    double ab[17];
+    hweno2d_vjp(a, K, Cb, ab);
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 17; ++k) W.rbc[(s * 17 + k) * N + cell] = ab[k];
+    }
+    mu_partial<6 * AG>(mub, W.mupart + W.mu_off2);
+}
+
+// ---------------------------------------------------------------------------
+// Gather of the weak-moment adjoints: cell X is slot k of the 3x3 stencil of
+// cell X - off(k).  Cells of halo ring 2.
+// ---------------------------------------------------------------------------
+__global__ void k_adj_rgather(Grid2 g, AdjWs W) {
+    const int wc = g.NX - 4;
+    const long long nreg = (long long)wc * (g.NY - 4);
+    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cid >= nreg) return;
+    const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    for (int s = 0; s < 6; ++s) {
+        const int w = s >> 1, l = s & 1;
+        double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int ox = k % 3 - 1, oy = k / 3 - 1;
+            const int yj = j - oy, yi = i - ox;
+            if (yj < 3 || yj > g.NY - 4 || yi < 3 || yi > g.NX - 4) continue;   // not in ring 1
+            const long long Y = (long long)yj * g.NX + yi;
+            m0 += W.rbc[(s * 17 + k) * N + Y];
+            if (k & 1) {
+                const int e = k >> 1;     // k = 1, 3, 5, 7 -> edge slot 0..3
+                m1 += W.rbc[(s * 17 + 9 + e) * N + Y];
+                m2 += W.rbc[(s * 17 + 13 + e) * N + Y];
+            }
+        }
+        W.rbb[((l * 3 + w) * 3 + 0) * N + cell] = m0;
+        W.rbb[((l * 3 + w) * 3 + 1) * N + cell] = m1;
+        W.rbb[((l * 3 + w) * 3 + 2) * N + cell] = m2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weak-moment adjoint (eqs. (3.6)-(3.8)) on cells X of ring 3 (every cell
+// with a reconstruction): its four faces' interface averages take adjoints
+// from the weak moments of both adjacent cells; half goes to each trace.
+// The wbar adjoint goes to the volume values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_ring2(const Grid2& g, int j, int i) {
+    return j >= 2 && j <= g.NY - 3 && i >= 2 && i <= g.NX - 3;
+}
+
+__global__ void k_adj_wmom(Grid2 g, AdjWs W) {
+    const int wc = g.NX - 2;
+    const long long nreg = (long long)wc * (g.NY - 2);
+    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cid >= nreg) return;
+    const int j = 1 + (int)(cid / wc), i = 1 + (int)(cid % wc);
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    const double idx = g.K.idx, idy = g.K.idy;
+    auto RB = [&](int jj, int ii, int l, int w, int mom) -> double {
+        if (!in_ring2(g, jj, ii)) return 0.0;
+        return W.rbb[((l * 3 + w) * 3 + mom) * N + (long long)jj * g.NX + ii];
+    };
+    // face adjoints W0-bar, W1-bar per w for the four faces of this cell
+    for (int face = 0; face < 4; ++face) {
+        // face 0: left (x, this cell is the plus side), 1: right (minus side),
+        // 2: bottom (y, plus side), 3: top (minus side)
+        const int dir = face >> 1;
+        const bool hi = face & 1;
+        const int oj = dir == 1 ? (hi ? 1 : -1) : 0, oi = dir == 0 ? (hi ? 1 : -1) : 0;
+        const double* F = dir == 0 ? g.xf : g.yf;
+        double* FB = dir == 0 ? W.xfb : W.yfb;
+        const double ih = dir == 0 ? idx : idy;
+        double W0b[3], W1b[3];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            // contributions of this cell (face on its hi side or lo side) and of the neighbour
+            const double own0 = RB(j, i, dir, w, 0);
+            const double ownm = RB(j, i, dir, w, dir == 0 ? 1 : 2);      // the (W0+ + W0-)/2 moment
+            const double own1 = RB(j, i, dir, w, dir == 0 ? 2 : 1);      // the transverse moment
+            const double nb0 = RB(j + oj, i + oi, dir, w, 0);
+            const double nbm = RB(j + oj, i + oi, dir, w, dir == 0 ? 1 : 2);
+            const double nb1 = RB(j + oj, i + oi, dir, w, dir == 0 ? 2 : 1);
+            if (hi) {   // this cell's upper face = neighbour's lower face
+                W0b[w] = (own0 + 0.5 * ownm) * ih + (-nb0 + 0.5 * nbm) * ih;
+                W1b[w] = own1 * ih - nb1 * ih;
+            } else {
+                W0b[w] = (-own0 + 0.5 * ownm) * ih + (nb0 + 0.5 * nbm) * ih;
+                W1b[w] = -own1 * ih + nb1 * ih;
+            }
+        }
+#pragma unroll
+        for (int G = 0; G < 3; ++G) {
+            const int p = (hi ? 3 : 0) + G;
+            double U[4], wb[3], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) U[c] = F[(p * 4 + c) * N + cell];
+#pragma unroll
+            for (int w = 0; w < 3; ++w) wb[w] = 0.5 * gw(G) * (W0b[w] + gx(G) * W1b[w]);
+            adj::prim2_vjp(U, wb, Ub);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) FB[(p * 4 + c) * N + cell] += Ub[c];
+        }
+    }
+    // wbar adjoints (this cell's own weak moments), to the volume values
+    if (in_ring2(g, j, i)) {
+        for (int dir = 0; dir < 2; ++dir) {
+            const double* V = dir == 0 ? g.xv : g.yv;
+            double* VB = dir == 0 ? W.xvb : W.yvb;
+            double wbb[3];
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+                wbb[w] = -RB(j, i, dir, w, dir == 0 ? 1 : 2) * (dir == 0 ? idx : idy);
+            for (int q = 0; q < 9; ++q) {
+                const double wq = gw(q / 3) * gw(q % 3);
+                double U[4], wb[3], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) U[c] = V[(q * 4 + c) * N + cell];
+#pragma unroll
+                for (int w = 0; w < 3; ++w) wb[w] = wq * wbb[w];
+                adj::prim2_vjp(U, wb, Ub);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] += Ub[c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic reconstruction adjoint.  Block: 16 cells x 8 threads
+// (b = basis, k = characteristic field / conservative component).
+// ---------------------------------------------------------------------------
+constexpr int AC = 16;
+
+__device__ __forceinline__ int pt_index(int b, int o) { return o < 6 ? b * 6 + o : 12 + b * 9 + (o - 6); }
+
+__global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
+                                                      const double* __restrict__ S) {
+    __shared__ double shc[8 * 16 * AC];   // characteristic point values (b, f, o)
+    __shared__ double shu[8 * 16 * AC];   // conservative point values   (b, c, o)
+    __shared__ double shb[8 * 16 * AC];   // adjoints of conservative values
+    __shared__ double sha[8 * 17 * AC];   // adjoints of the projected inputs (b, k, s)
+    __shared__ double shR[8 * 4 * AC];    // rows of R (b, c, f)
+    __shared__ double shL[8 * 4 * AC];    // rows of L (b, k, c)
+    __shared__ double shr[8 * AC];        // reductions (value)
+    __shared__ int shi[8 * AC];           // reductions (index)
+    __shared__ double shx[8 * AC];        // second reduction value
+    // limiter adjoints: slots 0..7 per-thread cell-average part (b*4+c), 8 P1 density,
+    // 9..12 P2 components, 13..16 cell-level part (rbar, pbar, eps)
+    __shared__ double shp[17 * AC];
+    __shared__ int shpi[2 * AC];
+    const Consts& K = g.K;
+    const int tid = threadIdx.x;
+    const int cl = tid % AC;
+    const int bk = tid / AC;
+    const int b = bk >> 2, k = bk & 3;
+    const int wc = g.NX - 2;
+    const long long nreg = (long long)wc * (g.NY - 2);
+    const long long cid = (long long)blockIdx.x * AC + cl;
+    const bool valid = cid < nreg;
+    int j = 1, i = 1;
+    if (valid) {
+        j = 1 + (int)(cid / wc);
+        i = 1 + (int)(cid % wc);
+    }
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    auto C_ = [&](int bb, int f, int o) -> double& { return shc[((bb * 4 + f) * 16 + o) * AC + cl]; };
+    auto U_ = [&](int bb, int c, int o) -> double& { return shu[((bb * 4 + c) * 16 + o) * AC + cl]; };
+    auto B_ = [&](int bb, int c, int o) -> double& { return shb[((bb * 4 + c) * 16 + o) * AC + cl]; };
+
+    // ---- forward recompute (as the forward reconstruction kernel) ----
+    double ub[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ub[c] = S[c * N + cell];
+    double Lr[4], Rr[4];
+    eig2_rows(K, ub, b, k, Lr, Rr);
+    double a[17];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += Lr[c] * S[c * N + nb];
+        a[s] = acc;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int s = 2 * e + 1;
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+        double ax = 0.0, ay = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ax += Lr[c] * S[(4 + c) * N + nb];
+            ay += Lr[c] * S[(8 + c) * N + nb];
+        }
+        a[9 + e] = ax;
+        a[13 + e] = ay;
+    }
+    {
+        double C[15], out[16];
+        hweno2d(a, K, C);
+        if (b == 0) eval_xface(C, out);
+        else eval_yface(C, out);
+        eval_vol(C, out + 6);
+        out[15] = b == 0 ? moment_xi(C) : moment_eta(C);
+#pragma unroll
+        for (int o = 0; o < 16; ++o) C_(b, k, o) = out[o];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        shR[(bk * 4 + f) * AC + cl] = Rr[f];
+        shL[(bk * 4 + f) * AC + cl] = Lr[f];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        double acc = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc += Rr[f] * C_(b, f, o);
+        U_(b, k, o) = acc;
+    }
+    __syncthreads();
+    // limiter forward: rho_min (argmin in the point order), theta1, then theta2
+    const double rbar = ub[0];
+    const double pbar = pressure2(K, ub[0], ub[1], ub[2], ub[3]);
+    const double e1 = K.eps_pp <= rbar ? K.eps_pp : rbar;
+    const int esrc1 = K.eps_pp <= rbar ? 0 : 1;
+    const double eps = e1 <= pbar ? e1 : pbar;
+    const int esrc = e1 <= pbar ? esrc1 : 2;
+    {
+        double v = INFINITY;
+        int ix = 1 << 30;
+        for (int o = k; o < 15; o += 4) {
+            const double r = U_(b, 0, o);
+            const int id = pt_index(b, o);
+            if (r < v || (r == v && id < ix)) { v = r; ix = id; }
+        }
+        shr[bk * AC + cl] = v;
+        shi[bk * AC + cl] = ix;
+    }
+    __syncthreads();
+    double rmin = INFINITY;
+    int irmin = 1 << 30;
+    for (int q = 0; q < 8; ++q) {
+        const double v = shr[q * AC + cl];
+        const int id = shi[q * AC + cl];
+        if (v < rmin || (v == rmin && id < irmin)) { rmin = v; irmin = id; }
+    }
+    const bool low1 = rmin < eps;
+    const double th1 = low1 ? (rbar - eps) / (rbar - rmin) : 1.0;
+    __syncthreads();
+    {
+        double v = INFINITY;
+        int ix = 1 << 30;
+        for (int o = k; o < 15; o += 4) {
+            const double rt = rbar + th1 * (U_(b, 0, o) - rbar);
+            const double pt = pressure2(K, rt, U_(b, 1, o), U_(b, 2, o), U_(b, 3, o));
+            const double t = pt < eps ? (pbar - eps) / (pbar - pt) : 1.0;
+            const int id = pt_index(b, o);
+            if (t < v || (t == v && id < ix)) { v = t; ix = id; }
+        }
+        shr[bk * AC + cl] = v;
+        shi[bk * AC + cl] = ix;
+    }
+    __syncthreads();
+    double tmin = INFINITY;
+    int itmin = 1 << 30;
+    for (int q = 0; q < 8; ++q) {
+        const double v = shr[q * AC + cl];
+        const int id = shi[q * AC + cl];
+        if (v < tmin || (v == tmin && id < itmin)) { tmin = v; itmin = id; }
+    }
+    const double th2 = tmin <= 1.0 ? tmin : 1.0;
+    const bool low2 = tmin < 1.0;
+
+    // ---- adjoint of the outputs of this thread's component k ----
+    const bool inter = valid && interior(g, j, i);
+    double Ub[16];
+    double th1b = 0.0, th2b = 0.0, ubb0 = 0.0;
+    {
+        const double* FB = b == 0 ? W.xfb : W.yfb;
+        const double* VB = b == 0 ? W.xvb : W.yvb;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            const double lb = valid ? FB[(o * 4 + k) * N + cell] : 0.0;
+            const double x = U_(b, k, o);
+            if (k == 0) {
+                const double ut = rbar + th1 * (x - rbar);
+                Ub[o] = th2 * th1 * lb;
+                ubb0 += lb * (1.0 - th2 * th1);
+                th2b += lb * (ut - rbar);
+                th1b += th2 * lb * (x - rbar);
+            } else {
+                Ub[o] = th2 * lb;
+                ubb0 += lb * (1.0 - th2);
+                th2b += lb * (x - ub[k]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ub[6 + q] = valid ? VB[(q * 4 + k) * N + cell] : 0.0;
+        const long long nint = (long long)g.nx * g.ny;
+        Ub[15] = (inter && A.Vb) ? A.Vb[(b * 4 + k) * nint + (long long)(j - HALO) * g.nx + (i - HALO)]
+                                 : 0.0;
+    }
+    shr[bk * AC + cl] = th1b;
+    shx[bk * AC + cl] = th2b;
+    shp[bk * AC + cl] = ubb0;            // this thread's cell-average adjoint, component k
+    __syncthreads();
+    if (bk == 0) {
+        // cell-level limiter adjoint: thetas -> rbar, pbar, eps and the argmin points
+        double T1b = 0.0, T2b = 0.0;
+        for (int q = 0; q < 8; ++q) {
+            T1b += shr[q * AC + cl];
+            T2b += shx[q * AC + cl];
+        }
+        double rbb = 0.0, pbb = 0.0, epsb = 0.0;
+        double P2b[4] = {0.0, 0.0, 0.0, 0.0}, P1b = 0.0;
+        int b2 = 0, o2 = 0, b1 = 0, o1 = 0;
+        auto unidx = [&](int id, int& bb, int& oo) {
+            if (id < 12) { bb = id / 6; oo = id % 6; }
+            else { bb = (id - 12) / 9; oo = 6 + (id - 12) % 9; }
+        };
+        if (low2) {
+            unidx(itmin, b2, o2);
+            const double rho = U_(b2, 0, o2);
+            double Ut[4] = {rbar + th1 * (rho - rbar), U_(b2, 1, o2), U_(b2, 2, o2), U_(b2, 3, o2)};
+            const double pt = pressure2(K, Ut[0], Ut[1], Ut[2], Ut[3]);
+            const double den = pbar - pt;
+            pbb += T2b * (eps - pt) / (den * den);
+            epsb += -T2b / den;
+            const double ptb = T2b * (pbar - eps) / (den * den);
+            double Utb[4] = {0.0, 0.0, 0.0, 0.0};
+            adj::pres2_vjp(K, Ut, ptb, Utb);
+            rbb += Utb[0] * (1.0 - th1);
+            P2b[0] = Utb[0] * th1;
+            P2b[1] = Utb[1];
+            P2b[2] = Utb[2];
+            P2b[3] = Utb[3];
+            T1b += Utb[0] * (rho - rbar);
+        }
+        if (low1) {
+            unidx(irmin, b1, o1);
+            const double den = rbar - rmin;
+            rbb += T1b * (eps - rmin) / (den * den);
+            epsb += -T1b / den;
+            P1b = T1b * (rbar - eps) / (den * den);
+        }
+        if (esrc == 1) rbb += epsb;
+        double ubar_b[4] = {rbb, 0.0, 0.0, 0.0};
+        if (esrc == 2) pbb += epsb;
+        if (pbb != 0.0) adj::pres2_vjp(K, ub, pbb, ubar_b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) shp[(13 + c) * AC + cl] = ubar_b[c];
+        // point adjoints: P2 (4 components) and P1 (density), marked by index
+        shp[8 * AC + cl] = P1b;
+        shpi[0 * AC + cl] = low1 ? (b1 * 16 + o1) : -1;
+        shpi[1 * AC + cl] = low2 ? (b2 * 16 + o2) : -1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) shp[(9 + c) * AC + cl] = P2b[c];
+    }
+    __syncthreads();
+    {
+        const int p1 = shpi[0 * AC + cl], p2 = shpi[1 * AC + cl];
+        if (p1 >= 0 && k == 0 && p1 / 16 == b) Ub[p1 % 16] += shp[8 * AC + cl];
+        if (p2 >= 0 && p2 / 16 == b) Ub[p2 % 16] += shp[(9 + k) * AC + cl];
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) B_(b, k, o) = Ub[o];
+    __syncthreads();
+    // ---- back-transform adjoint: char-bar_f = sum_c R[c][f] Ub_c; R-bar row k ----
+    double Rb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) Rb[f] += Ub[o] * C_(b, f, o);
+    }
+    double cb[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += shR[((b * 4 + c) * 4 + k) * AC + cl] * B_(b, c, o);
+        cb[o] = acc;
+    }
+    // ---- scalar reconstruction adjoint ----
+    double Cb[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) Cb[q] = 0.0;
+    if (b == 0) adj::xface_T(cb, Cb);
+    else adj::yface_T(cb, Cb);
+    adj::vol_T(cb + 6, Cb);
+    if (b == 0) moment_xi_T(cb[15], Cb);
+    else moment_eta_T(cb[15], Cb);
+    double ab[17];
+    hweno2d_vjp(a, K, Cb, ab);
+#pragma unroll
+    for (int s = 0; s < 17; ++s) sha[(bk * 17 + s) * AC + cl] = ab[s];
+    // L-bar row k: sum_s ab[s] * stencil value (component c)
+    double Lb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Lb[c] += ab[s] * S[c * N + nb];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int s = 2 * e + 1;
+        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            Lb[c] += ab[9 + e] * S[(4 + c) * N + nb] + ab[13 + e] * S[(8 + c) * N + nb];
+    }
+    double ubp[4] = {0.0, 0.0, 0.0, 0.0};
+    if (b == 0) adj::eig2_vjp_0(K, ub, k, Lb, Rb, ubp);
+    else adj::eig2_vjp_1(K, ub, k, Lb, Rb, ubp);
+    __syncthreads();
+    // cell-average adjoint of this thread: eigen part (4 comps) -> LDS for the owner threads
+#pragma unroll
+    for (int c = 0; c < 4; ++c) shb[((b * 4 + k) * 16 + c) * AC + cl] = ubp[c];
+    __syncthreads();
+    // ---- projection adjoint, thread (b, c): sum_k L[k][c] ab_k[s] ----
+    if (valid) {
+        const int c = k;
+        double* UC = W.uc + (long long)b * 68 * N;
+#pragma unroll
+        for (int s = 0; s < 17; ++s) {
+            double acc = 0.0;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) acc += shL[((b * 4 + f) * 4 + c) * AC + cl] * sha[((b * 4 + f) * 17 + s) * AC + cl];
+            if (s == 4) {
+                // own cell average: eigenvector dependence (both fields' rows of this basis)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc += shb[((b * 4 + f) * 16 + c) * AC + cl];
+                // limiter: per-component pass-through of theta and the cell-level part
+                if (b == 0) {
+                    acc += shp[(0 * 4 + c) * AC + cl] + shp[(1 * 4 + c) * AC + cl];
+                    acc += shp[(13 + c) * AC + cl];
+                }
+            }
+            UC[(s * 4 + c) * N + cell] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// State adjoint on the ghosted grid: cell X is slot k of the stencil of
+// cell X - off(k) (averages: all 9 slots; moments: the 4 edge slots).
+// ---------------------------------------------------------------------------
+__global__ void k_adj_ugather(Grid2 g, AdjWs W) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.ncell) return;
+    const int j = (int)(t / g.NX), i = (int)(t % g.NX);
+    const long long N = g.ncell;
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int b = 0; b < 2; ++b) {
+        const double* UC = W.uc + (long long)b * 68 * N;
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            const int ox = s % 3 - 1, oy = s / 3 - 1;
+            const int yj = j - oy, yi = i - ox;
+            if (yj < 1 || yj > g.NY - 2 || yi < 1 || yi > g.NX - 2) continue;
+            const long long Y = (long long)yj * g.NX + yi;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += UC[(s * 4 + c) * N + Y];
+            if (s & 1) {
+                const int e = s >> 1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[4 + c] += UC[((9 + e) * 4 + c) * N + Y];
+                    acc[8 + c] += UC[((13 + e) * 4 + c) * N + Y];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) W.ubb[q * N + t] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the ghost fill: the y sweep is undone first (its sources include
+// the x-ghost columns), then the x sweep.  Each source cell gathers the
+// ghost cells copied from it, in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ghost_src(int kind, int side, int d, int n) {
+    if (kind == 2) return -1;                 // inflow: constant
+    if (side == 0) return kind == 0 ? HALO + n - d : (kind == 1 ? HALO : HALO + d - 1);
+    return kind == 0 ? HALO + d - 1 : (kind == 1 ? HALO + n - 1 : HALO + n - d);
+}
+
+__global__ void k_adj_ghost_y(Grid2 g, AdjWs W) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.ny * g.NX) return;
+    const int r = HALO + (int)(t / g.NX), i = (int)(t % g.NX);
+    const long long N = g.ncell;
+    const long long dst = (long long)r * g.NX + i;
+    for (int side = 0; side < 2; ++side) {
+        const Side& sd = g.side[2 + side];
+        for (int d = 1; d <= HALO; ++d) {
+            if (ghost_src(sd.kind, side, d, g.ny) != r) continue;
+            const int gj = side == 0 ? HALO - d : HALO + g.ny - 1 + d;
+            const long long gc = (long long)gj * g.NX + i;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) W.ubb[q * N + dst] += sd.sign[q] * W.ubb[q * N + gc];
+        }
+    }
+}
+
+__global__ void k_adj_ghost_x(Grid2 g, AdjWs W) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.ny * g.nx) return;
+    const int j = HALO + (int)(t / g.nx), c0 = HALO + (int)(t % g.nx);
+    const long long N = g.ncell;
+    const long long dst = (long long)j * g.NX + c0;
+    for (int side = 0; side < 2; ++side) {
+        const Side& sd = g.side[side];
+        for (int d = 1; d <= HALO; ++d) {
+            if (ghost_src(sd.kind, side, d, g.nx) != c0) continue;
+            const int gi = side == 0 ? HALO - d : HALO + g.nx - 1 + d;
+            const long long gc = (long long)j * g.NX + gi;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) W.ubb[q * N + dst] += sd.sign[q] * W.ubb[q * N + gc];
+        }
+    }
+}
+
+__global__ void k_adj_out(Grid2 g, AdjWs W, double* __restrict__ Ubar) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nint * 12) return;
+    const int q = (int)(t / nint);
+    const long long r = t % nint;
+    const int jj = (int)(r / g.nx), ii = (int)(r % g.nx);
+    Ubar[t] = W.ubb[q * g.ncell + (long long)(jj + HALO) * g.NX + ii + HALO];
+}
+
+__global__ void k_fill(double* p, long long n, double v) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long q = t; q < n; q += (long long)gridDim.x * blockDim.x) p[q] = v;
+}
+
+// mu-bar = fixed-order sum of the block partials
+__global__ void k_mu_sum(const double* part, int n, double* out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) s += part[q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < 256; ++q) tot += sh[q];
+        *out = tot;
+    }
+}
+
+inline unsigned nb2(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+long long adj_mu_partials2(const Grid2& g) {
+    return (long long)nb2((long long)(g.nx + 1) * g.ny, AF) + nb2((long long)g.nx * (g.ny + 1), AF) +
+           nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
+}
+
+hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
+                       double* mu_out, hipStream_t st) {
+    k_fill<<<1024, 256, 0, st>>>(W.base, W.count, 0.0);
+    const unsigned bx = nb2((long long)(g.nx + 1) * g.ny, AF);
+    const unsigned by = nb2((long long)g.nx * (g.ny + 1), AF);
+    const unsigned bg = nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
+    W.mu_off1 = bx;
+    W.mu_off2 = bx + by;
+    k_adj_flux<0><<<bx, 3 * AF, 0, st>>>(g, A, W);
+    k_adj_flux<1><<<by, 3 * AF, 0, st>>>(g, A, W);
+    k_adj_grad<<<bg, 6 * AG, 0, st>>>(g, A, W);
+    k_adj_rgather<<<nb2((long long)(g.NX - 4) * (g.NY - 4), 256), 256, 0, st>>>(g, W);
+    k_adj_wmom<<<nb2((long long)(g.NX - 2) * (g.NY - 2), 128), 128, 0, st>>>(g, W);
+    k_adj_recon<<<nb2((long long)(g.NX - 2) * (g.NY - 2), AC), 8 * AC, 0, st>>>(g, A, W, S);
+    k_adj_ugather<<<nb2(g.ncell, 256), 256, 0, st>>>(g, W);
+    k_adj_ghost_y<<<nb2((long long)g.ny * g.NX, 256), 256, 0, st>>>(g, W);
+    k_adj_ghost_x<<<nb2((long long)g.ny * g.nx, 256), 256, 0, st>>>(g, W);
+    k_adj_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar);
+    k_mu_sum<<<1, 256, 0, st>>>(W.mupart, (int)(bx + by + bg), mu_out);
+    return hipGetLastError();
+}
+
+}  // namespace hw

@@ -12,6 +12,7 @@
 
 #include "../../include/hweno.h"
 #include "hweno_kernels.h"
+#include "hweno_vjp.h"
 
 struct hweno_ctx {
     hweno_grid grid;
@@ -26,6 +27,8 @@ struct hweno_ctx {
     hw::Grid2 g2{};
     hw::Grid1 g1{};
     hw::Reduce* red = nullptr;
+    hw::AdjWs adj{};
+    double* mu_dev = nullptr;
     double t = 0.0;
     bool has_state = false;
     hw::Timer timer;
@@ -144,6 +147,25 @@ size_t layout(hweno_ctx* c, char* base) {
         g.gr = take(8 * n);
         g.fh = take(3 * n);
         g.vf = take(3 * n);
+    }
+    if (c->grid.dim == 2) {
+        // reverse-mode workspace (zero-filled at the start of every adjoint call)
+        const size_t n = (size_t)c->g2.ncell;
+        hw::AdjWs& A = c->adj;
+        const size_t first = off;
+        A.xfb = take(24 * n);
+        A.yfb = take(24 * n);
+        A.xvb = take(36 * n);
+        A.yvb = take(36 * n);
+        A.gfb = take(72 * n);
+        A.rbc = take(102 * n);
+        A.rbb = take(18 * n);
+        A.uc = take(136 * n);
+        A.ubb = take(12 * n);
+        A.base = A.xfb;
+        A.count = (long long)((off - first) / sizeof(double));
+        A.mupart = take((size_t)hw::adj_mu_partials2(c->g2));
+        c->mu_dev = take(1);
     }
     c->red = base ? reinterpret_cast<hw::Reduce*>(base + off) : nullptr;
     off += up(sizeof(hw::Reduce));
@@ -383,6 +405,26 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
     std::swap(c->S[0], c->S[1]);
     c->t += r.dt;
     fill_diag(c, r, diag, restarts, true);
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,
+                                          const double* Vbar, double* Ubar, double* mu_bar) {
+    if (!c || !U || !Rbar || !Ubar) return HWENO_E_INVAL;
+    if (c->grid.dim != 2 || c->phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    double* S = c->S[2];
+    TRY(dev(hw::launch_copy_in2(c->g2, U, S, c->stream)));
+    TRY(dev(hw::launch_reset(c->red, c->stream)));
+    TRY(ghost(c, S));
+    TRY(residual(c, S));
+    hw::AdjIn A{Rbar, Vbar};
+    TRY(dev(hw::launch_vjp2(c->g2, A, c->adj, S, Ubar, c->mu_dev, c->stream)));
+    if (mu_bar) {
+        TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream)));
+        TRY(dev(hipStreamSynchronize(c->stream)));
+    }
     return HWENO_OK;
 }
 

@@ -1,0 +1,73 @@
+// Interfaces of the reverse-mode kernels: adjoint inputs, adjoint workspace
+// and thin wrappers over the generated vector-Jacobian products.
+#pragma once
+
+#include "hweno_adj.h"
+#include "hweno_kernels.h"
+
+namespace hw {
+
+struct AdjIn {
+    const double* Rb;   // residual adjoint, D1 interior layout (12 or 6 per cell)
+    const double* Vb;   // modified-moment adjoint, interior layout (8 or 3 per cell)
+};
+
+// Adjoint workspace (component-major over the ghosted grid, like Grid2/Grid1).
+struct AdjWs {
+    double* base;       // start of the zero-filled region
+    long long count;    // doubles in that region
+    double* xfb;        // 24 / 12: face-trace adjoints
+    double* yfb;        // 24
+    double* xvb;        // 36: volume-value adjoints
+    double* yvb;        // 36
+    double* gfb;        // 72 / 8: face-gradient adjoints
+    double* rbc;        // 102 / 10: weak-moment contributions to the 3x3 stencil
+    double* rbb;        // 18 / 4: gathered weak-moment adjoints
+    double* uc;         // 136 / 15: state contributions to the stencil
+    double* ubb;        // 12 / 6: gathered state adjoint (ghosted)
+    double* mupart;     // block partials of the mu adjoint
+    int mu_off1, mu_off2;
+};
+
+__device__ __forceinline__ double g_ld(const double* p, long long idx) { return p[idx]; }
+
+template <int d>
+__device__ __forceinline__ void flux2_vjp(const Consts& K, const double* U, const double* s,
+                                          double mu, const double* fb, double* Ub, double* sb,
+                                          double& mub) {
+    if (d == 0) adj::flux2_vjp_0(K, U, s, mu, fb, Ub, sb, mub);
+    else adj::flux2_vjp_1(K, U, s, mu, fb, Ub, sb, mub);
+}
+
+// adjoint of speed2<d> = max(|u_n| + c, beta_PP) (ties to the first branch)
+template <int d>
+__device__ __forceinline__ void speed2_vjp(const Consts& K, const double* U, const double* s,
+                                           double mu, double yb, double* Ub, double* sb,
+                                           double& mub) {
+    const double r = U[0];
+    const double p = pressure2(K, r, U[1], U[2], U[3]);
+    const double e = p / (K.gm1 * r);
+    const Stress t = stresses(mu, s);
+    const double kq = K.gamma * mu / K.Pr;
+    const double un = (d == 0 ? U[1] : U[2]) / r;
+    const double q = kq * s[4 + d];
+    const double t2 = d == 0 ? (t.xx - p) * (t.xx - p) + t.xy * t.xy
+                             : t.xy * t.xy + (t.yy - p) * (t.yy - p);
+    const double r2e = r * r * e;
+    const double bpp = fabs(un) + (sqrt(r * r * q * q + 2.0 * r2e * t2) + r * fabs(q)) / (2.0 * r2e);
+    const double ac = fabs(un) + sqrt(K.gamma * p / r);
+    const double sgu = sgn(un);
+    if (ac >= bpp) {
+        if (d == 0) adj::speed2_ac_vjp_0(K, U, sgu, yb, Ub);
+        else adj::speed2_ac_vjp_1(K, U, sgu, yb, Ub);
+    } else {
+        if (d == 0) adj::speed2_bpp_vjp_0(K, U, s, mu, sgu, sgn(q), yb, Ub, sb, mub);
+        else adj::speed2_bpp_vjp_1(K, U, s, mu, sgu, sgn(q), yb, Ub, sb, mub);
+    }
+}
+
+long long adj_mu_partials2(const Grid2& g);
+hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
+                       double* mu_out, hipStream_t st);
+
+}  // namespace hw

@@ -17,7 +17,8 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
-           'hweno_residual', 'hweno_rk_step', 'hweno_set_timing', 'hweno_get_timing',
+           'hweno_residual', 'hweno_rk_step', 'hweno_residual_vjp', 'hweno_set_timing',
+           'hweno_get_timing',
            'hweno_status_string')
 
 #: kernel classes of hweno_timing
@@ -89,6 +90,7 @@ def lib():
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
+        L.hweno_residual_vjp.argtypes = [vp, vp, vp, vp, vp, dp]
         L.hweno_set_timing.argtypes = [vp, ctypes.c_int]
         L.hweno_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int]
         L.hweno_status_string.argtypes = [ctypes.c_int]
@@ -190,6 +192,21 @@ class Solver:
         check(lib().hweno_residual(self._h, _ptr(U), _ptr(R), _ptr(V),
                                    ctypes.byref(d) if diag else None))
         return R, V, (d.as_dict() if diag else None)
+
+    def residual_vjp(self, U, Rbar, Vbar=None, want_mu=True):
+        """(Ubar, mu_bar): adjoint of the residual (and Vhat) at U."""
+        import torch
+        self._dev(U)
+        self._dev(Rbar)
+        if Vbar is not None and (tuple(Vbar.shape) != self.vhat_shape or not Vbar.is_contiguous()
+                                 or Vbar.dtype != torch.float64):
+            raise ValueError('Vbar shape %s, expected %s' % (tuple(Vbar.shape), self.vhat_shape))
+        Ub = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        mu = ctypes.c_double(0.0)
+        check(lib().hweno_residual_vjp(self._h, _ptr(U), _ptr(Rbar),
+                                       _ptr(Vbar) if Vbar is not None else None, _ptr(Ub),
+                                       ctypes.byref(mu) if want_mu else None))
+        return Ub, (mu.value if want_mu else None)
 
     def rk_step(self, dt=0.0):
         """One SSP-RK3 step (dt <= 0: the paper's time-step rule); diag dict."""

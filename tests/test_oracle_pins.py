@@ -650,3 +650,24 @@ def test_rk_stages_use_modified_moments():
     v3 = v1 / 3.0 + 2.0 / 3.0 * T(ub, v2)
     assert np.abs(Un[0] - ub).max() < 4e-16 * np.abs(ub).max()
     assert np.abs(Un[1] - v3).max() < 1e-14
+
+
+def test_complex_step_tangent_matches_finite_differences():
+    """The oracle run on complex inputs is the exact tangent-linear model
+    (reference for the adjoint): central differences converge to it at second
+    order."""
+    from paper_2608_10569_amd import workloads
+    nx, ny = 10, 9
+    U = workloads.random_smooth_2d(nx, ny, seed=4, noise=1e-3)
+    s = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, PH, Options())
+    rng = np.random.default_rng(0)
+    dU = rng.standard_normal(U.shape) * np.abs(U).reshape(3, 4, -1).max(axis=-1)[..., None, None]
+    h = 1e-30
+    Fc, Vc, _ = s.residual(U + 1j * h * dU)
+    J = Fc.imag / h
+    errs = []
+    for eps in (1e-4, 1e-5):
+        Fp, _, _ = s.residual(U + eps * dU)
+        Fm, _, _ = s.residual(U - eps * dU)
+        errs.append(np.abs((Fp - Fm) / (2 * eps) - J).max() / np.abs(J).max())
+    assert errs[1] < 1e-5 and errs[0] / errs[1] > 50.0     # O(eps^2)
