@@ -177,6 +177,21 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* ctx, double dt, hweno_diag* diag
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar);
 
+/* Reverse mode of one SSP-RK3 step of eq. (2.12) taken with the fixed step
+ * dt > 0 from the state U0 (device, D1), 2D grids with mu_exp = 0: with
+ * U3 = step(U0) as hweno_rk_step computes it for that dt,
+ *   U0bar = (dU3/dU0)^T U3bar              (device, D1, overwritten)
+ *   *mu_bar = (dU3/dmu_ref) . U3bar        (host double; NULL: skip)
+ * dt is held constant (the time-step rule is not differentiated).  The two
+ * intermediate stages are recomputed from U0 with the forward kernels; the
+ * three stage residual adjoints then run in reverse, branch and tie rules as
+ * in hweno_residual_vjp, bitwise reproducible.  U3bar must not overlap U0.
+ * Uses the workspace; leaves the context state alone; with a non-NULL
+ * mu_bar the call synchronises.  HWENO_E_INVAL for dt <= 0, dim = 1 or
+ * mu_exp != 0. */
+HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, double dt,
+                                         const double* U3bar, double* U0bar, double* mu_bar);
+
 /* Per-kernel-class GPU time, measured with HIP events recorded on the
  * context's stream around every launch while timing is enabled.  Classes:
  * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative

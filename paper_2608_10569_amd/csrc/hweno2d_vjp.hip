@@ -37,7 +37,7 @@ __device__ __forceinline__ bool interior(const Grid2& g, int j, int i) {
 // residual adjoint of interior cell (j, i): F1, F2, F3 component c
 __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, int c, int j, int i) {
     const long long nint = (long long)g.nx * g.ny;
-    return A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
+    return A.rs * A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
 }
 
 // fixed-order block sum of the mu adjoint: one partial per block
@@ -569,8 +569,9 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ub[6 + q] = valid ? VB[(q * 4 + k) * N + cell] : 0.0;
         const long long nint = (long long)g.nx * g.ny;
-        Ub[15] = (inter && A.Vb) ? A.Vb[(b * 4 + k) * nint + (long long)(j - HALO) * g.nx + (i - HALO)]
-                                 : 0.0;
+        Ub[15] = (inter && A.Vb)
+                     ? A.vs * A.Vb[(b * 4 + k) * nint + (long long)(j - HALO) * g.nx + (i - HALO)]
+                     : 0.0;
     }
     shr[bk * AC + cl] = th1b;
     shx[bk * AC + cl] = th2b;
@@ -811,8 +812,8 @@ __global__ void k_fill(double* p, long long n, double v) {
     for (long long q = t; q < n; q += (long long)gridDim.x * blockDim.x) p[q] = v;
 }
 
-// mu-bar = fixed-order sum of the block partials
-__global__ void k_mu_sum(const double* part, int n, double* out) {
+// mu-bar = fixed-order sum of the block partials (added to *out if acc)
+__global__ void k_mu_sum(const double* part, int n, double* out, int acc) {
     __shared__ double sh[256];
     double s = 0.0;
     for (int q = threadIdx.x; q < n; q += 256) s += part[q];
@@ -821,8 +822,19 @@ __global__ void k_mu_sum(const double* part, int n, double* out) {
     if (threadIdx.x == 0) {
         double tot = 0.0;
         for (int q = 0; q < 256; ++q) tot += sh[q];
-        *out = tot;
+        *out = acc ? *out + tot : tot;
     }
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+
+__global__ void k_lin3(double* __restrict__ y, const double* __restrict__ u, double a, double b,
+                       const double* __restrict__ x, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a * u[t] + b * y[t] + x[t];
 }
 
 inline unsigned nb2(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -835,7 +847,7 @@ long long adj_mu_partials2(const Grid2& g) {
 }
 
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
-                       double* mu_out, hipStream_t st) {
+                       double* mu_out, int mu_acc, hipStream_t st) {
     k_fill<<<1024, 256, 0, st>>>(W.base, W.count, 0.0);
     const unsigned bx = nb2((long long)(g.nx + 1) * g.ny, AF);
     const unsigned by = nb2((long long)g.nx * (g.ny + 1), AF);
@@ -852,7 +864,18 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     k_adj_ghost_y<<<nb2((long long)g.ny * g.NX, 256), 256, 0, st>>>(g, W);
     k_adj_ghost_x<<<nb2((long long)g.ny * g.nx, 256), 256, 0, st>>>(g, W);
     k_adj_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar);
-    k_mu_sum<<<1, 256, 0, st>>>(W.mupart, (int)(bx + by + bg), mu_out);
+    k_mu_sum<<<1, 256, 0, st>>>(W.mupart, (int)(bx + by + bg), mu_out, mu_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st) {
+    if (n > 0) k_axpy<<<nb2(n, 256), 256, 0, st>>>(y, x, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin3(double* y, const double* u, double a, double b, const double* x, long long n,
+                       hipStream_t st) {
+    if (n > 0) k_lin3<<<nb2(n, 256), 256, 0, st>>>(y, u, a, b, x, n);
     return hipGetLastError();
 }
 

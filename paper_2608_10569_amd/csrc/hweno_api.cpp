@@ -29,6 +29,9 @@ struct hweno_ctx {
     hw::Reduce* red = nullptr;
     hw::AdjWs adj{};
     double* mu_dev = nullptr;
+    double* S3 = nullptr;       // 2D adjoint: fourth ghosted state (RK-step recomputation)
+    double* X1 = nullptr;       // 2D adjoint: interior stage cotangents (12 per cell)
+    double* X2 = nullptr;
     double t = 0.0;
     bool has_state = false;
     hw::Timer timer;
@@ -166,6 +169,10 @@ size_t layout(hweno_ctx* c, char* base) {
         A.count = (long long)((off - first) / sizeof(double));
         A.mupart = take((size_t)hw::adj_mu_partials2(c->g2));
         c->mu_dev = take(1);
+        const size_t nint = (size_t)c->g2.nx * c->g2.ny;
+        c->S3 = take(12 * n);
+        c->X1 = take(12 * nint);
+        c->X2 = take(12 * nint);
     }
     c->red = base ? reinterpret_cast<hw::Reduce*>(base + off) : nullptr;
     off += up(sizeof(hw::Reduce));
@@ -418,8 +425,65 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
     TRY(dev(hw::launch_reset(c->red, c->stream)));
     TRY(ghost(c, S));
     TRY(residual(c, S));
-    hw::AdjIn A{Rbar, Vbar};
-    TRY(dev(hw::launch_vjp2(c->g2, A, c->adj, S, Ubar, c->mu_dev, c->stream)));
+    hw::AdjIn A{Rbar, Vbar, 1.0, 1.0};
+    TRY(dev(hw::launch_vjp2(c->g2, A, c->adj, S, Ubar, c->mu_dev, 0, c->stream)));
+    if (mu_bar) {
+        TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream)));
+        TRY(dev(hipStreamSynchronize(c->stream)));
+    }
+    return HWENO_OK;
+}
+
+// Reverse mode of one SSP-RK3 step with the step size frozen (eq. (2.12)):
+//   U1 = B(U0) + dt F(U0),  U2 = 3/4 B(U0) + 1/4 (B(U1) + dt F(U1)),
+//   U3 = 1/3 B(U0) + 2/3 (B(U2) + dt F(U2)),   B(U) = (ubar, hat-v(U)).
+// The stages are recomputed from U0 with the forward kernels, then the three
+// residual adjoints run in reverse with the stage cotangents as seeds.
+HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double dt,
+                                         const double* U3bar, double* U0bar, double* mu_bar) {
+    if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt)) return HWENO_E_INVAL;
+    if (c->grid.dim != 2 || c->phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    const hw::Grid2& g = c->g2;
+    const long long nint = (long long)g.nx * g.ny;
+    double* Sa = c->S[1];   // U0
+    double* Sb = c->S[2];   // U1
+    double* Sc = c->S3;     // U2
+    // forward recomputation of the two intermediate stages
+    TRY(dev(hw::launch_copy_in2(g, U0, Sa, c->stream)));
+    TRY(dev(hw::launch_reset(c->red, c->stream)));
+    TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
+    TRY(ghost(c, Sa));
+    TRY(residual(c, Sa));
+    TRY(update(c, 1, Sa, Sa, Sb, nullptr, nullptr));
+    TRY(ghost(c, Sb));
+    TRY(residual(c, Sb));
+    TRY(update(c, 2, Sa, Sb, Sc, nullptr, nullptr));
+    auto vjp_at = [&](double* S, const double* Rb, double rs, double vs, double* out, int acc) {
+        TRY(dev(hw::launch_reset(c->red, c->stream)));
+        TRY(ghost(c, S));
+        TRY(residual(c, S));
+        hw::AdjIn A{Rb, Rb + 4 * nint, rs, vs};
+        return dev(hw::launch_vjp2(g, A, c->adj, S, out, c->mu_dev, acc, c->stream));
+    };
+    // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified moments)
+    TRY(vjp_at(Sc, U3bar, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
+    TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
+    // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar
+    TRY(vjp_at(Sb, c->X2, 0.25 * dt, 0.25, c->X1, 1));
+    TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
+    // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
+    TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
+    // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar
+    TRY(dev(hw::launch_reset(c->red, c->stream)));
+    TRY(ghost(c, Sa));
+    TRY(residual(c, Sa));
+    {
+        hw::AdjIn A{c->X1, c->X2 + 4 * nint, dt, 1.0};
+        TRY(dev(hw::launch_vjp2(g, A, c->adj, Sa, U0bar, c->mu_dev, 1, c->stream)));
+    }
+    TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));

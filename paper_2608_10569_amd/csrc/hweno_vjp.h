@@ -10,6 +10,7 @@ namespace hw {
 struct AdjIn {
     const double* Rb;   // residual adjoint, D1 interior layout (12 or 6 per cell)
     const double* Vb;   // modified-moment adjoint, interior layout (8 or 3 per cell)
+    double rs, vs;      // scale factors applied to Rb and Vb as they are read
 };
 
 // Adjoint workspace (component-major over the ghosted grid, like Grid2/Grid1).
@@ -67,7 +68,13 @@ __device__ __forceinline__ void speed2_vjp(const Consts& K, const double* U, con
 }
 
 long long adj_mu_partials2(const Grid2& g);
+// mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar)
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
-                       double* mu_out, hipStream_t st);
+                       double* mu_out, int mu_acc, hipStream_t st);
+// y[0:n] += a x[0:n]
+hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
+// y[0:n] = a u[0:n] + b y[0:n] + x[0:n]
+hipError_t launch_lin3(double* y, const double* u, double a, double b, const double* x, long long n,
+                       hipStream_t st);
 
 }  // namespace hw

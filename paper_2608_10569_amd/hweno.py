@@ -17,7 +17,8 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
-           'hweno_residual', 'hweno_rk_step', 'hweno_residual_vjp', 'hweno_set_timing',
+           'hweno_residual', 'hweno_rk_step', 'hweno_residual_vjp', 'hweno_rk_step_vjp',
+           'hweno_set_timing',
            'hweno_get_timing',
            'hweno_status_string')
 
@@ -91,6 +92,7 @@ def lib():
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
         L.hweno_residual_vjp.argtypes = [vp, vp, vp, vp, vp, dp]
+        L.hweno_rk_step_vjp.argtypes = [vp, vp, ctypes.c_double, vp, vp, dp]
         L.hweno_set_timing.argtypes = [vp, ctypes.c_int]
         L.hweno_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int]
         L.hweno_status_string.argtypes = [ctypes.c_int]
@@ -134,6 +136,10 @@ class Solver:
         import torch
         self.dim = 1 if ny is None else 2
         self.nx, self.ny = nx, (ny or 1)
+        self.extent = tuple(float(v) for v in extent)
+        self.gamma, self.mu_ref = float(gamma), float(mu_ref)
+        self.dx = (self.extent[1] - self.extent[0]) / nx
+        self.dy = (self.extent[3] - self.extent[2]) / ny if ny else None
         g = Grid(self.dim, nx, ny or 1, *[float(v) for v in
                                           (list(extent) + [0.0, 1.0])[:4]])
         ph = PhysicsC(gamma, Pr, mu_ref, mu_exp, T_ref)
@@ -207,6 +213,17 @@ class Solver:
                                        _ptr(Vbar) if Vbar is not None else None, _ptr(Ub),
                                        ctypes.byref(mu) if want_mu else None))
         return Ub, (mu.value if want_mu else None)
+
+    def rk_step_vjp(self, U0, dt, U3bar, want_mu=True):
+        """(U0bar, mu_bar): adjoint of one RK3 step of size dt (held fixed) from U0."""
+        import torch
+        self._dev(U0)
+        self._dev(U3bar)
+        U0b = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        mu = ctypes.c_double(0.0)
+        check(lib().hweno_rk_step_vjp(self._h, _ptr(U0), float(dt), _ptr(U3bar), _ptr(U0b),
+                                      ctypes.byref(mu) if want_mu else None))
+        return U0b, (mu.value if want_mu else None)
 
     def rk_step(self, dt=0.0):
         """One SSP-RK3 step (dt <= 0: the paper's time-step rule); diag dict."""

@@ -1,0 +1,235 @@
+"""Reverse mode of the SSP-RK3 step (fixed dt) and the checkpointed rollout.
+
+The step adjoint is checked against the oracle's complex-step tangent of its
+own RK3 step (dot-product test), the rollout against a step-by-step chain of
+HwenoStep and against central differences of the GPU forward, up to the
+double-shear-layer experiment at full size (256^2, 200 steps, checkpoints
+every 20 steps)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip('torch')
+
+from oracle.common import Options, Physics  # noqa: E402
+from oracle.rk import rk3_step  # noqa: E402
+from oracle.scheme2d import Scheme2D  # noqa: E402
+from paper_2608_10569_amd import adjoint, hweno, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = 'cuda:0'
+H = 1e-30
+
+
+def to_dev(U):
+    return torch.from_numpy(np.ascontiguousarray(U)).to(DEV)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+def rule_dt(s, U):
+    s.set_state(to_dev(U))
+    return s.rk_step(0.0)['dt']
+
+
+def step_dot_test(U, bc, extent, mu, seed, dt=None):
+    ny, nx = U.shape[2:]
+    s = hweno.Solver(nx, ny, extent=extent, bc=bc, mu_ref=mu)
+    dt = dt or rule_dt(s, U)
+    rng = np.random.default_rng([2608, 77, seed])
+    scale = np.abs(U).reshape(3, 4, -1).max(axis=-1)[..., None, None]
+    dU = rng.standard_normal(U.shape) * scale
+    Wb = rng.standard_normal(U.shape)
+    sc = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu), Options(), bc=bc)
+    U3c, used, info = rk3_step(sc, U + 1j * H * dU, 0.0, dt)
+    assert used == dt and info['restarts'] == 0
+    lhs = np.sum(U3c.imag / H * Wb)
+    Ub, mub = s.rk_step_vjp(to_dev(U), dt, to_dev(Wb))
+    rhs = np.sum(dU * Ub.cpu().numpy())
+    sm = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu + 1j * H), Options(), bc=bc)
+    U3m, _, _ = rk3_step(sm, U.astype(complex), 0.0, dt)
+    mref = np.sum(U3m.imag / H * Wb)
+    return lhs, rhs, mref, mub, info
+
+
+def test_step_vjp_periodic():
+    U = workloads.random_smooth_2d(13, 11, seed=21, noise=1e-3)
+    lhs, rhs, mref, mub, _ = step_dot_test(U, ('periodic',) * 4, (0.0, 1.0, 0.0, 1.0), 0.01, 0)
+    print('step periodic: %.15e vs %.15e rel %.2e; mu %.6e vs %.6e rel %.2e'
+          % (lhs, rhs, rel(lhs, rhs), mref, mub, rel(mref, mub)))
+    assert rel(lhs, rhs) < 1e-10
+    assert rel(mref, mub) < 1e-10
+
+
+def test_step_vjp_walls():
+    U = workloads.random_smooth_2d(12, 10, seed=22, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+    lhs, rhs, mref, mub, _ = step_dot_test(U, ('noslip', 'noslip', 'noslip', 'slip'),
+                                           (0.0, 1.0, 0.0, 0.5), 1 / 200, 1)
+    print('step walls: rel %.2e mu rel %.2e' % (rel(lhs, rhs), rel(mref, mub)))
+    assert rel(lhs, rhs) < 1e-10
+    assert rel(mref, mub) < 1e-10
+
+
+def test_step_vjp_limiter_active():
+    """Near-vacuum trough: the limiter acts in all three stages.  The tangent
+    there is ill-conditioned (the oracle's own tangent moves by ~1e-6 under
+    1e-15 relative perturbations of the state), so the GPU adjoint must agree
+    with it within a few times that self-sensitivity."""
+    U = workloads.random_smooth_2d(12, 12, seed=7, noise=1e-3)
+    U[0, 0, 5:7, 4:8] = 2e-3
+    U[0, 3, 5:7, 4:8] = 0.5 * (U[0, 1, 5:7, 4:8] ** 2 + U[0, 2, 5:7, 4:8] ** 2) / 2e-3 + 2e-3
+    U[1:, :, 5:7, 4:8] = 0.0
+    dt = 1e-6
+    lhs, rhs, mref, mub, info = step_dot_test(U, ('periodic',) * 4, (0.0, 1.0, 0.0, 1.0), 0.01, 2,
+                                              dt=dt)
+    # the oracle's self-sensitivity of the same tangent
+    rng = np.random.default_rng([2608, 77, 2])
+    scale = np.abs(U).reshape(3, 4, -1).max(axis=-1)[..., None, None]
+    dU = rng.standard_normal(U.shape) * scale
+    Wb = rng.standard_normal(U.shape)
+    sc = Scheme2D(12, 12, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options())
+    pr = np.random.default_rng([2608, 78])
+    spread = 0.0
+    for _ in range(3):
+        Up = U * (1.0 + 1e-15 * pr.standard_normal(U.shape))
+        U3c, _, _ = rk3_step(sc, Up + 1j * H * dU, 0.0, dt)
+        spread = max(spread, rel(np.sum(U3c.imag / H * Wb), lhs))
+    print('step limiter (pp cell-stages %d): rel %.2e mu rel %.2e; oracle self-sensitivity %.2e'
+          % (info['pp_cells'], rel(lhs, rhs), rel(mref, mub), spread))
+    assert info['pp_cells'] > 0
+    assert rel(lhs, rhs) < max(1e-10, 5.0 * spread)
+    assert rel(mref, mub) < max(1e-10, 5.0 * spread)
+
+
+def test_step_vjp_rejects_bad_arguments():
+    s = hweno.Solver(8, 8)
+    U = to_dev(workloads.random_smooth_2d(8, 8, seed=1))
+    with pytest.raises(hweno.HwenoError):
+        s.rk_step_vjp(U, 0.0, U.clone())
+    s1 = hweno.Solver(16)
+    U1 = to_dev(workloads.random_smooth_1d(16, seed=1))
+    with pytest.raises(hweno.HwenoError):
+        s1.rk_step_vjp(U1, 1e-3, U1.clone())
+
+
+def test_rollout_checkpointing_is_exact():
+    """Checkpoint spacing does not change the gradient (bitwise), and the
+    rollout equals a chain of HwenoStep."""
+    nx = ny = 16
+    U0 = to_dev(workloads.random_smooth_2d(nx, ny, seed=23, noise=1e-3))
+    s = hweno.Solver(nx, ny, mu_ref=0.01)
+    dt = rule_dt(s, U0.cpu().numpy())
+    nsteps = 7
+    grads = []
+    for every in (1, 3, 7, 50):
+        U = U0.clone().requires_grad_(True)
+        mu = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
+        J = adjoint.kinetic_energy(adjoint.rollout(s, U, mu, dt, nsteps, every), s.dx, s.dy)
+        J.backward()
+        grads.append((U.grad.clone(), mu.grad.item(), J.item()))
+    for g in grads[1:]:
+        assert torch.equal(g[0], grads[0][0]) and g[1] == grads[0][1] and g[2] == grads[0][2]
+    U = U0.clone().requires_grad_(True)
+    mu = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
+    X = U
+    for _ in range(nsteps):
+        X = adjoint.HwenoStep.apply(X, mu, s, dt)
+    J = adjoint.kinetic_energy(X, s.dx, s.dy)
+    J.backward()
+    assert J.item() == grads[0][2]
+    assert torch.equal(U.grad, grads[0][0]) and mu.grad.item() == grads[0][1]
+
+
+def rollout_gradient(n, nsteps, every, mu, fields):
+    """J and its gradient w.r.t. the node fields (rho, u, v) and mu."""
+    gamma = 1.4
+    rho, u, v = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in fields[:3]]
+    p = fields[3]
+    s = hweno.Solver(n, n, mu_ref=mu)
+    U0 = adjoint.project_fields(rho, u, v, p, gamma)
+    dt = rule_dt(s, U0.cpu().numpy())
+    r = rho.clone().requires_grad_(True)
+    uu = u.clone().requires_grad_(True)
+    vv = v.clone().requires_grad_(True)
+    m = torch.tensor(mu, dtype=torch.float64, device=DEV, requires_grad=True)
+    J = adjoint.kinetic_energy(
+        adjoint.rollout(s, adjoint.project_fields(r, uu, vv, p, gamma), m, dt, nsteps, every),
+        s.dx, s.dy)
+    J.backward()
+
+    def J_at(d, e, mv=mu):
+        sm = s if mv == mu else hweno.Solver(n, n, mu_ref=mv)
+        U = adjoint.project_fields(rho + e * d[0], u + e * d[1], v + e * d[2], p, gamma)
+        with torch.no_grad():
+            return adjoint.kinetic_energy(adjoint.rollout(sm, U, None, dt, nsteps, every),
+                                          s.dx, s.dy).item()
+    return J.item(), (r.grad, uu.grad, vv.grad), m.grad.item(), dt, J_at
+
+
+def oracle_tangent(fields, d, n, nsteps, dt, mu, dmu=0.0):
+    """The oracle's complex-step directional derivative of J (same dt)."""
+    g, w = np.polynomial.legendre.leggauss(6)
+    g, w = 0.5 * g, 0.5 * w
+    W = np.outer(w, w)[:, :, None, None]
+    rho, u, v, p = fields
+
+    def proj(r, uu, vv):
+        Q = np.stack([r, r * uu, r * vv, p / 0.4 + 0.5 * r * (uu * uu + vv * vv)])
+        return np.stack([(W * Q).sum(axis=(1, 2)), (W * g[None, :, None, None] * Q).sum(axis=(1, 2)),
+                         (W * g[:, None, None, None] * Q).sum(axis=(1, 2))])
+    sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=mu + 1j * H * dmu), Options())
+    U = proj(rho + 1j * H * d[0], u + 1j * H * d[1], v + 1j * H * d[2])
+    for _ in range(nsteps):
+        U, used, info = rk3_step(sc, U, 0.0, dt)
+        assert used == dt and info['restarts'] == 0
+    a = U[0]
+    return (0.5 / n / n * ((a[1] ** 2 + a[2] ** 2) / a[0]).sum()).imag / H
+
+
+def test_rollout_vs_oracle_tangent():
+    """12 steps on 24^2 with checkpoints every 5: the gradient against the
+    oracle's complex-step tangent (fields and mu) and central differences."""
+    n, nsteps = 24, 12
+    X, Y = adjoint.gauss_nodes_2d(n, n, (0.0, 1.0, 0.0, 1.0))
+    fields = (1.0 + 0.1 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y),
+              0.3 * np.sin(2 * np.pi * Y), 0.2 * np.cos(2 * np.pi * X), 1.0 / 1.4)
+    J, grads, gmu, dt, J_at = rollout_gradient(n, nsteps, 5, 0.01, fields)
+    rng = np.random.default_rng([2608, 88, 0])
+    d = [rng.standard_normal(X.shape) for _ in range(3)]
+    ad = float(sum((gr.cpu().numpy() * q).sum() for gr, q in zip(grads, d)))
+    ref = oracle_tangent(fields, d, n, nsteps, dt, 0.01)
+    ref_mu = oracle_tangent(fields, [np.zeros_like(X)] * 3, n, nsteps, dt, 0.01, dmu=1.0)
+    dd = [torch.from_numpy(q).to(DEV) for q in d]
+    fd = (J_at(dd, 1e-7) - J_at(dd, -1e-7)) / 2e-7
+    print('24^2 x 12: fields adjoint %.12e oracle %.12e rel %.2e (fd rel %.2e); '
+          'mu %.12e oracle %.12e rel %.2e' % (ad, ref, rel(ad, ref), rel(ad, fd), gmu, ref_mu,
+                                              rel(gmu, ref_mu)))
+    assert rel(ad, ref) < 1e-9
+    assert rel(gmu, ref_mu) < 1e-9
+    assert rel(ad, fd) < 1e-6
+
+
+def test_double_shear_layer_full_size():
+    """The experiment itself: 256^2, Re = 1000, 200 steps with dt frozen at the
+    step-0 value, checkpoints every 20 steps; central differences along the
+    gradient direction (where the directional derivative is largest, so that
+    rounding in J does not swamp it) and in mu."""
+    n, nsteps, mu = 256, 200, 1e-3
+    fields = adjoint.shear_layer_fields(n)
+    J, grads, gmu, dt, J_at = rollout_gradient(n, nsteps, 20, mu, fields)
+    gmax = max(float(gr.abs().max()) for gr in grads)
+    d = [gr / gmax for gr in grads]
+    ad = float(sum((gr * q).sum() for gr, q in zip(grads, d)))
+    res = []
+    for eps in (1e-6, 1e-7):
+        fd = (J_at(d, eps) - J_at(d, -eps)) / (2 * eps)
+        res.append(rel(ad, fd))
+    zero = [torch.zeros_like(q) for q in d]
+    fdm = (J_at(zero, 0.0, mu + 1e-8) - J_at(zero, 0.0, mu - 1e-8)) / 2e-8
+    print('double shear layer 256^2 x 200 (dt %.6e): J %.12e  along the gradient: %.12e, fd rel %s; '
+          'mu %.12e fd %.12e rel %.2e' % (dt, J, ad, ['%.2e' % x for x in res], gmu, fdm,
+                                          rel(gmu, fdm)))
+    assert min(res) < 1e-6
+    assert rel(gmu, fdm) < 1e-6
