@@ -196,7 +196,7 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, doubl
  * context's stream around every launch while timing is enabled.  Classes:
  * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative
  * moments, 3 gradient reconstruction + volume flux, 4 face fluxes, 5 stage
- * update / assembly, 6..7 unused. */
+ * update / assembly, 6 a whole batched run (hweno_batch_run), 7 unused. */
 typedef struct hweno_timing {
     double ms[8];                       /* summed elapsed milliseconds */
     unsigned long long launches[8];     /* timed launches */
@@ -209,6 +209,63 @@ HWENO_API hweno_status hweno_set_timing(hweno_ctx* ctx, int enable);
 HWENO_API hweno_status hweno_get_timing(hweno_ctx* ctx, hweno_timing* out, int reset);
 
 HWENO_API const char* hweno_status_string(hweno_status s);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent 2D grids of different sizes and physics advanced
+ * together.  Every kernel launch of the pipeline covers all instances (a
+ * block finds its instance from a prefix table of block counts), and a run of
+ * nsteps steps is recorded once as a HIP graph and replayed with one launch.
+ * Each instance keeps its own step rule (Sec. 5 preamble: dt from its stage-1
+ * wave speed, its viscosity and its t_final, computed on the device), its own
+ * restarts (a rejected step is retried with dt/2 in the next step slot) and
+ * its own diagnostics.  The workspace, stream and timing calls above apply to
+ * a batch context; the single-grid state, residual, step and adjoint calls
+ * return HWENO_E_INVAL for it.
+ * ------------------------------------------------------------------------- */
+#define HWENO_BATCH_MAX 4096
+
+/* n instances (1 <= n <= HWENO_BATCH_MAX); grids[i].dim must be 2; each
+ * instance is validated as by hweno_create.  Arrays of length n. */
+HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
+                                          const hweno_physics* phys, const hweno_bcs* bcs,
+                                          const hweno_options* opts, hweno_ctx** out);
+
+/* State and time of instance i (device, D1 layout of that instance). */
+HWENO_API hweno_status hweno_batch_set_state(hweno_ctx* ctx, int i, const double* U, double t);
+HWENO_API hweno_status hweno_batch_get_state(hweno_ctx* ctx, int i, double* U, double* t);
+
+/* Advances every instance by nsteps accepted SSP-RK3 steps (fewer if its
+ * t_final is reached).  One graph launch covers the run; instances that needed
+ * restarts finish with extra single-step launches.  Checks the input states
+ * first (HWENO_E_NONFINITE for an instance with a bad cell; it is not
+ * advanced).  An instance that exhausts max_halvings stops at its last
+ * accepted state and the call returns HWENO_E_INADMISSIBLE after the others
+ * have finished.  Synchronises. */
+HWENO_API hweno_status hweno_batch_run(hweno_ctx* ctx, int nsteps);
+
+/* Diagnostics of instance i from the last run: t, dt of its last accepted
+ * step, alpha_star / beta_max / min_rho / min_p of its last attempt,
+ * pp_cells summed over the run's accepted steps, restarts in the run; pad
+ * holds the number of accepted steps. */
+HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* ctx, int i, hweno_diag* out);
+
+/* Work per block of the tunable kernels and the instance order of a launch. */
+typedef struct hweno_tiles {
+    int recon;      /* cells per block of the characteristic reconstruction: 16 or 32 */
+    int grad;       /* cells per block of the gradient reconstruction: 32 or 64 */
+    int flux;       /* faces per block of the face fluxes: 64 or 128 */
+    int order;      /* batch schedule: 0 instances as given, 1 largest first */
+} hweno_tiles;
+
+/* 2D contexts (single grid or batch).  Results do not depend on the tiles. */
+HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* ctx, hweno_tiles* out);
+HWENO_API hweno_status hweno_set_tiles(hweno_ctx* ctx, const hweno_tiles* tiles);
+
+/* Autotuner: times `reps` residual evaluations of the current state(s) for
+ * each candidate tile of every tunable kernel, keeps the fastest per kernel,
+ * then (batches) the faster instance order, and sets them; `chosen` may be
+ * NULL.  Needs the state(s) set; leaves them unchanged.  Synchronises. */
+HWENO_API hweno_status hweno_autotune(hweno_ctx* ctx, int reps, hweno_tiles* chosen);
 
 #ifdef __cplusplus
 }

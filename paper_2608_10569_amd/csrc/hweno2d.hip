@@ -93,6 +93,22 @@ __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
     }
 }
 
+// Slot of the instance that owns this block and the block's index within it
+// (uniform per block: binary search of the launch's block prefix table).
+struct Loc {
+    int p, b;
+};
+__device__ __forceinline__ Loc locate(const Batch& B) {
+    const int bid = (int)blockIdx.x;
+    int lo = 0, hi = B.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.start[mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    return Loc{lo, bid - B.start[lo]};
+}
+
 // ---------------------------------------------------------------------------
 // Ghost cells (Remark 4.1).  x sweep on interior rows, then y sweep on every
 // column, so corner cells compose the two rules.
@@ -112,8 +128,12 @@ __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N,
     for (int q = 0; q < 12; ++q) S[q * N + dst] = sd.sign[q] * S[q * N + src];
 }
 
-__global__ void k_ghost2_x(Grid2 g, double* S) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ghost2_x(Batch bt, int sidx) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
+    double* S = g.S[sidx];
+    const int t = lc.b * blockDim.x + threadIdx.x;
     if (t >= g.ny * 2 * HALO) return;
     const int j = HALO + t / (2 * HALO);
     const int gi = t % (2 * HALO);
@@ -132,8 +152,12 @@ __global__ void k_ghost2_x(Grid2 g, double* S) {
     fill_one(sd, S, g.ncell, row + di, row + si);
 }
 
-__global__ void k_ghost2_y(Grid2 g, double* S) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ghost2_y(Batch bt, int sidx) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
+    double* S = g.S[sidx];
+    const int t = lc.b * blockDim.x + threadIdx.x;
     if (t >= g.NX * 2 * HALO) return;
     const int i = t % g.NX;
     const int gj = t / g.NX;
@@ -157,12 +181,15 @@ __global__ void k_ghost2_y(Grid2 g, double* S) {
 // field k of basis b (0: x-Jacobian, 1: y-Jacobian), reconstructs it, and
 // after an LDS exchange owns conservative component k of basis b.
 // ---------------------------------------------------------------------------
-constexpr int RC_CELLS = 32;
-
-__global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restrict__ S) {
+template <int RC_CELLS>
+__global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     __shared__ double sh[8 * 16 * RC_CELLS];
     __shared__ double redA[8 * RC_CELLS];
     __shared__ double redB[8 * RC_CELLS];
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
+    const double* __restrict__ S = g.S[si];
     const Consts& K = g.K;
     const int tid = threadIdx.x;
     const int cl = tid & (RC_CELLS - 1);
@@ -170,7 +197,7 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
     const int b = bk >> 2, k = bk & 3;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)blockIdx.x * RC_CELLS + cl;
+    const long long cid = (long long)lc.b * RC_CELLS + cl;
     const bool valid = cid < nreg;
     int j = 1, i = 1;
     if (valid) {
@@ -323,8 +350,9 @@ __global__ __launch_bounds__(256) void k_recon2(Grid2 g, const double* __restric
             amax = fmax(amax, sp);
         }
     }
-    red_max<256>(&g.red->alpha_key, amax);
-    red_add<256>(&g.red->pp_cells, (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
+    red_max<8 * RC_CELLS>(&g.red->alpha_key, amax);
+    red_add<8 * RC_CELLS>(&g.red->pp_cells,
+                          (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,10 +368,13 @@ __device__ __forceinline__ void prim3(const double* F, long long N, long long ce
     w[2] = F[(p * 4 + 3) * N + cell] / r - 0.5 * (u * u + v * v);
 }
 
-__global__ __launch_bounds__(256) void k_rbar2(Grid2 g) {
+__global__ __launch_bounds__(256) void k_rbar2(Batch bt) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
     const int wc = g.NX - 4;
     const long long nreg = (long long)wc * (g.NY - 4);
-    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cid = (long long)lc.b * blockDim.x + threadIdx.x;
     if (cid >= nreg) return;
     const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -399,10 +430,12 @@ __global__ __launch_bounds__(256) void k_rbar2(Grid2 g) {
 // (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also form
 // the volume-flux quadratures of eq. (3.2).
 // ---------------------------------------------------------------------------
-constexpr int GR_CELLS = 32;
-
-__global__ __launch_bounds__(192) void k_grad2(Grid2 g) {
+template <int GR_CELLS>
+__global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     __shared__ double shv[6 * 9 * GR_CELLS];
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
     const Consts& K = g.K;
     const int tid = threadIdx.x;
     const int cl = tid % GR_CELLS;
@@ -410,7 +443,7 @@ __global__ __launch_bounds__(192) void k_grad2(Grid2 g) {
     const int w = s >> 1, l = s & 1;
     const int wc = g.NX - 6;
     const long long nreg = (long long)wc * (g.NY - 6);
-    const long long cid = (long long)blockIdx.x * GR_CELLS + cl;
+    const long long cid = (long long)lc.b * GR_CELLS + cl;
     const bool valid = cid < nreg;
     int j = 3, i = 3;
     if (valid) {
@@ -477,17 +510,18 @@ __global__ __launch_bounds__(192) void k_grad2(Grid2 g) {
 // last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
 // max over the face's three Gauss points and both sides.
 // ---------------------------------------------------------------------------
-constexpr int FX_FACES = 64;     // faces per block; block = 3 Gauss points x 64 faces
-
-template <int d>
-__global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Grid2 g) {
+template <int d, int FX_FACES>   // block = 3 Gauss points x FX_FACES faces
+__global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __shared__ double shb[3 * FX_FACES];
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
     const Consts& K = g.K;
     const int nfi = d == 0 ? g.nx + 1 : g.nx;
     const int nfj = d == 0 ? g.ny : g.ny + 1;
     const int G = threadIdx.x / FX_FACES;
     const int fl = threadIdx.x % FX_FACES;
-    const long long t = (long long)blockIdx.x * FX_FACES + fl;
+    const long long t = (long long)lc.b * FX_FACES + fl;
     const bool valid = t < (long long)nfi * nfj;
     const long long N = g.ncell;
     long long cm = 0, cp = 0;
@@ -537,11 +571,17 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Grid2 g) {
 // Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form).
 // stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3 stage.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_update2(Grid2 g, int stage, const double* __restrict__ S0,
-                          const double* __restrict__ Sin, double* __restrict__ Sout,
-                          double* __restrict__ Rout, double* __restrict__ Vout) {
+__global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, int iin, int iout,
+                                                 double* __restrict__ Rout,
+                                                 double* __restrict__ Vout) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
+    const double* __restrict__ S0 = g.S[i0];
+    const double* __restrict__ Sin = g.S[iin];
+    double* __restrict__ Sout = g.S[iout];
     const long long nint = (long long)g.nx * g.ny;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     double rmin = INFINITY, pmin = INFINITY;
     unsigned int bad = 0;
     if (t < nint) {
@@ -640,9 +680,13 @@ __global__ void k_copy_out2(Grid2 g, const double* __restrict__ S, double* __res
 }
 
 // Input admissibility (finite values, positive density and pressure).
-__global__ void k_check2(Grid2 g, const double* __restrict__ S) {
+__global__ __launch_bounds__(256) void k_check2(Batch bt, int si) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active) return;
+    const double* __restrict__ S = g.S[si];
     const long long nint = (long long)g.nx * g.ny;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     unsigned int bad = 0;
     if (t < nint) {
         const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
@@ -689,6 +733,83 @@ __global__ void k_set_dt(Reduce* r, double dt) {
     }
 }
 
+// Per-instance kernels of a batch: thread p serves the instance in slot p.
+__global__ void k_reset2(const Grid2* __restrict__ gs, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    Reduce* r = gs[p].red;
+    r->alpha_key = dkey(-INFINITY);
+    r->beta_key = dkey(-INFINITY);
+    r->pp_cells = 0;
+    r->min_rho_key = dkey(INFINITY);
+    r->min_p_key = dkey(INFINITY);
+    r->bad[0] = r->bad[1] = r->bad[2] = r->bad[3] = 0;
+}
+
+// Trial step of the time-step rule from the stage-1 wave speed, halved once
+// per rejected attempt of the current step.
+__global__ void k_dt2(const Grid2* __restrict__ gs, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const InstState* st = gs[p].st;
+    if (!st->active) return;
+    Reduce* r = gs[p].red;
+    r->alpha1_key = r->alpha_key;
+    double dt = fmin(st->cfl_h / dkey_inv(r->alpha_key), st->visc_dt);
+    if (st->t_final > 0.0) dt = fmin(dt, st->t_final - st->t);
+    r->dt = ldexp(dt, -st->halvings);
+}
+
+__device__ __forceinline__ bool accepted(const Grid2& g) {
+    const Reduce* r = g.red;
+    const double dt = r->dt;
+    return r->bad[1] == 0 && r->bad[2] == 0 && r->bad[3] == 0 && dt > 0.0 && isfinite(dt);
+}
+
+// Accepted instances: interior of S[1] (the stage-3 output) -> S[0].
+__global__ __launch_bounds__(256) void k_commit_copy(Batch bt) {
+    const Loc lc = locate(bt);
+    const Grid2 g = bt.g[lc.p];
+    if (!g.st->active || !accepted(g)) return;
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
+    if (t >= nint) return;
+    const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
+    const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) g.S[0][q * g.ncell + cell] = g.S[1][q * g.ncell + cell];
+}
+
+__global__ void k_commit_state(const Grid2* __restrict__ gs, int n, int code_inadmissible) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const Grid2& g = gs[p];
+    InstState* st = g.st;
+    if (!st->active) return;
+    const Reduce* r = g.red;
+    st->alpha = dkey_inv(r->alpha1_key);
+    st->beta_max = dkey_inv(r->beta_key);
+    st->min_rho = dkey_inv(r->min_rho_key);
+    st->min_p = dkey_inv(r->min_p_key);
+    if (accepted(g)) {
+        st->t += r->dt;
+        st->dt_last = r->dt;
+        st->steps += 1;
+        st->halvings = 0;
+        st->pp_cells += r->pp_cells;
+        const bool at_end = st->t_final > 0.0 && !(st->t < st->t_final);
+        if (st->steps >= st->target || at_end) st->active = 0;
+    } else {
+        st->restarts += 1;
+        if (st->halvings >= st->max_halvings) {
+            st->status = code_inadmissible;
+            st->active = 0;
+        } else {
+            st->halvings += 1;
+        }
+    }
+}
+
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -708,9 +829,31 @@ hipError_t launch_set_dt(Reduce* red, double dt, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_check2(const Grid2& g, const double* S, hipStream_t st) {
-    const long long n = (long long)g.nx * g.ny;
-    k_check2<<<nblk(n, 256), 256, 0, st>>>(g, S);
+void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
+    for (int k = 0; k < KB_COUNT; ++k) {
+        int* st = out + k * (n + 1);
+        st[0] = 0;
+        for (int p = 0; p < n; ++p) {
+            const Grid2& g = hg[p];
+            long long work = 0;
+            int per = 256;
+            switch (k) {
+                case KB_GHOSTX: work = (long long)g.ny * 2 * HALO; break;
+                case KB_GHOSTY: work = (long long)g.NX * 2 * HALO; break;
+                case KB_RECON: work = (long long)(g.NX - 2) * (g.NY - 2); per = t.recon; break;
+                case KB_RBAR: work = (long long)(g.NX - 4) * (g.NY - 4); break;
+                case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
+                case KB_FLUX0: work = (long long)(g.nx + 1) * g.ny; per = t.flux; break;
+                case KB_FLUX1: work = (long long)g.nx * (g.ny + 1); per = t.flux; break;
+                default: work = (long long)g.nx * g.ny; break;
+            }
+            st[p + 1] = st[p] + (int)nblk(work, per);
+        }
+    }
+}
+
+hipError_t launch_check2(const BatchL& b, int si, hipStream_t st) {
+    k_check2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), si);
     return hipGetLastError();
 }
 
@@ -726,40 +869,59 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st, Timer* tm) {
+hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm) {
     tbeg(tm, KC_GHOST, st);
-    k_ghost2_x<<<nblk((long long)g.ny * 2 * HALO, 256), 256, 0, st>>>(g, S);
-    k_ghost2_y<<<nblk((long long)g.NX * 2 * HALO, 256), 256, 0, st>>>(g, S);
+    k_ghost2_x<<<b.blocks(KB_GHOSTX), 256, 0, st>>>(b.arg(KB_GHOSTX), si);
+    k_ghost2_y<<<b.blocks(KB_GHOSTY), 256, 0, st>>>(b.arg(KB_GHOSTY), si);
     tend(tm, st);
     return hipGetLastError();
 }
 
-hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st, Timer* tm) {
-    const long long nc = (long long)(g.NX - 2) * (g.NY - 2);
+hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) {
     tbeg(tm, KC_RECON, st);
-    k_recon2<<<nblk(nc, RC_CELLS), 256, 0, st>>>(g, S);
+    if (b.tiles.recon == 16) k_recon2<16><<<b.blocks(KB_RECON), 128, 0, st>>>(b.arg(KB_RECON), si);
+    else k_recon2<32><<<b.blocks(KB_RECON), 256, 0, st>>>(b.arg(KB_RECON), si);
     tend(tm, st);
-    const long long n2 = (long long)(g.NX - 4) * (g.NY - 4);
     tbeg(tm, KC_RBAR, st);
-    k_rbar2<<<nblk(n2, 256), 256, 0, st>>>(g);
+    k_rbar2<<<b.blocks(KB_RBAR), 256, 0, st>>>(b.arg(KB_RBAR));
     tend(tm, st);
-    const long long n1 = (long long)(g.NX - 6) * (g.NY - 6);
     tbeg(tm, KC_GRAD, st);
-    k_grad2<<<nblk(n1, GR_CELLS), 192, 0, st>>>(g);
+    if (b.tiles.grad == 64) k_grad2<64><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
+    else k_grad2<32><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
     tend(tm, st);
     tbeg(tm, KC_FLUX, st);
-    k_flux2<0><<<nblk((long long)(g.nx + 1) * g.ny, FX_FACES), 3 * FX_FACES, 0, st>>>(g);
-    k_flux2<1><<<nblk((long long)g.nx * (g.ny + 1), FX_FACES), 3 * FX_FACES, 0, st>>>(g);
+    if (b.tiles.flux == 128) {
+        k_flux2<0, 128><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
+        k_flux2<1, 128><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
+    } else {
+        k_flux2<0, 64><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
+        k_flux2<1, 64><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
+    }
     tend(tm, st);
     return hipGetLastError();
 }
 
-hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm) {
-    const long long n = (long long)g.nx * g.ny;
+hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
+                          double* Vhat, hipStream_t st, Timer* tm) {
     tbeg(tm, KC_UPDATE, st);
-    k_update2<<<nblk(n, 256), 256, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat);
+    k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R, Vhat);
     tend(tm, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset2(const BatchL& b, hipStream_t st) {
+    k_reset2<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt2(const BatchL& b, hipStream_t st) {
+    k_dt2<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit2(const BatchL& b, hipStream_t st) {
+    k_commit_copy<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS));
+    k_commit_state<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n, 4);
     return hipGetLastError();
 }
 

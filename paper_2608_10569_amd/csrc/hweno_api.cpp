@@ -1,41 +1,75 @@
-// Host side of libhweno.so: context, workspace carving, the SSP-RK3 driver
-// with the time-step rule and stage restart (Sec. 5 preamble of
-// arXiv 2608.10569), and the C ABI of include/hweno.h.
+// Host side of libhweno.so: contexts (one grid, or a batch of 2D grids),
+// workspace carving, the SSP-RK3 driver with the time-step rule and stage
+// restart (Sec. 5 preamble of arXiv 2608.10569), the graph-captured batched
+// run, the tile autotuner, and the C ABI of include/hweno.h.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
 #include <utility>
+#include <vector>
 
 #include "../../include/hweno.h"
 #include "hweno_kernels.h"
 #include "hweno_vjp.h"
 
-struct hweno_ctx {
+namespace {
+
+// One grid's problem statement.
+struct Inst {
     hweno_grid grid;
     hweno_physics phys;
     hweno_bcs bcs;
     hweno_options opt;
+};
+
+}  // namespace
+
+struct hweno_ctx {
+    bool batch = false;
+    std::vector<Inst> in;              // instances (one for a single grid)
     hipStream_t stream = nullptr;
     int device = 0;
     size_t ws_bytes = 0;
     char* ws = nullptr;
-    double* S[3] = {nullptr, nullptr, nullptr};   // ghosted states; S[0] = current
-    hw::Grid2 g2{};
+    // 2D: host copies of every instance's grid (by instance id), their device
+    // copies in schedule order, the block tables and the per-instance state
+    std::vector<hw::Grid2> hg;
+    std::vector<int> order;            // slot -> instance id
+    hw::Grid2* dg = nullptr;
+    int* dstart = nullptr;
+    std::vector<int> hstart;
+    hw::Tiles tiles;
+    int order_mode = 0;                // 0: as given, 1: largest first
+    hw::BatchL bl;
+    hw::InstState* dst = nullptr;      // device, by instance id
+    std::vector<hw::InstState> hst;    // host copy
+    hw::Reduce* red = nullptr;         // device, by instance id
+    int cur = 0;                       // single 2D grid: current state is hg[0].S[cur]
+    // 1D
+    double* S1[3] = {nullptr, nullptr, nullptr};   // ghosted states; S1[0] = current
     hw::Grid1 g1{};
-    hw::Reduce* red = nullptr;
+    // reverse mode (single 2D grid)
     hw::AdjWs adj{};
     double* mu_dev = nullptr;
-    double* S3 = nullptr;       // 2D adjoint: fourth ghosted state (RK-step recomputation)
-    double* X1 = nullptr;       // 2D adjoint: interior stage cotangents (12 per cell)
+    double* X1 = nullptr;              // interior stage cotangents (12 per cell)
     double* X2 = nullptr;
     double t = 0.0;
     bool has_state = false;
+    std::vector<char> have;            // batch: state set, per instance
+    // batched run: graphs of `gsteps` steps and of one step
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    hipGraphExec_t gexec1 = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the graphs are recorded on
     hw::Timer timer;
     hw::Timer* tm() { return timer.on ? &timer : nullptr; }
+    const Inst& i0() const { return in[0]; }
+    int dim() const { return in[0].grid.dim; }
 };
 
 namespace {
@@ -45,21 +79,21 @@ constexpr size_t ALIGN = 256;
 
 size_t up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
 
-hw::Consts make_consts(const hweno_ctx* c) {
+hw::Consts make_consts(const Inst& c) {
     hw::Consts K{};
-    K.gamma = c->phys.gamma;
-    K.gm1 = c->phys.gamma - 1.0;
-    K.Pr = c->phys.Pr;
-    K.mu_ref = c->phys.mu_ref;
-    K.mu_exp = c->phys.mu_exp;
-    K.T_ref = c->phys.T_ref;
-    K.eps_pp = c->opt.eps_pp;
-    K.eps_weno = c->opt.eps_weno;
-    K.linear = c->opt.linear_weights ? 1 : 0;
-    K.dx = (c->grid.x1 - c->grid.x0) / c->grid.nx;
+    K.gamma = c.phys.gamma;
+    K.gm1 = c.phys.gamma - 1.0;
+    K.Pr = c.phys.Pr;
+    K.mu_ref = c.phys.mu_ref;
+    K.mu_exp = c.phys.mu_exp;
+    K.T_ref = c.phys.T_ref;
+    K.eps_pp = c.opt.eps_pp;
+    K.eps_weno = c.opt.eps_weno;
+    K.linear = c.opt.linear_weights ? 1 : 0;
+    K.dx = (c.grid.x1 - c.grid.x0) / c.grid.nx;
     K.idx = 1.0 / K.dx;
-    if (c->grid.dim == 2) {
-        K.dy = (c->grid.y1 - c->grid.y0) / c->grid.ny;
+    if (c.grid.dim == 2) {
+        K.dy = (c.grid.y1 - c.grid.y0) / c.grid.ny;
         K.idy = 1.0 / K.dy;
     } else {
         K.dy = K.dx;
@@ -69,11 +103,11 @@ hw::Consts make_consts(const hweno_ctx* c) {
 }
 
 // Wall parities (Remark 4.1): multiplier per (moment, component).
-void make_side(const hweno_ctx* c, int s, hw::Side& sd) {
-    const int dim = c->grid.dim;
+void make_side(const Inst& c, int s, hw::Side& sd) {
+    const int dim = c.grid.dim;
     const int ncomp = dim + 2;
     const int axis = s / 2;               // 0: x-wall, 1: y-wall
-    sd.kind = c->bcs.kind[s];
+    sd.kind = c.bcs.kind[s];
     for (int q = 0; q < 12; ++q) sd.sign[q] = 1.0;
     if (sd.kind == HWENO_BC_SLIP || sd.kind == HWENO_BC_NOSLIP) {
         for (int m = 0; m <= dim; ++m) {
@@ -90,8 +124,8 @@ void make_side(const hweno_ctx* c, int s, hw::Side& sd) {
         }
     }
     // inflow: primitive -> conservative
-    const double* pr = c->bcs.inflow[s];
-    const double g = c->phys.gamma;
+    const double* pr = c.bcs.inflow[s];
+    const double g = c.phys.gamma;
     for (int q = 0; q < 4; ++q) sd.inflow[q] = 0.0;
     if (dim == 1) {
         const double r = pr[0], u = pr[1], p = pr[2];
@@ -107,7 +141,16 @@ void make_side(const hweno_ctx* c, int s, hw::Side& sd) {
     }
 }
 
-// Carves the workspace into the grid's arrays (or just sizes it if base == nullptr).
+// Step-rule constants of an instance (Sec. 5 preamble).
+void rule(const Inst& c, double* cfl_h, double* visc_dt) {
+    const double dx = (c.grid.x1 - c.grid.x0) / c.grid.nx;
+    const double h = c.grid.dim == 2 ? std::fmin(dx, (c.grid.y1 - c.grid.y0) / c.grid.ny) : dx;
+    *cfl_h = c.opt.cfl * h;
+    *visc_dt = INFINITY;
+    if (c.opt.b_visc > 0.0 && c.phys.mu_ref > 0.0) *visc_dt = c.opt.b_visc * h * h / c.phys.mu_ref;
+}
+
+// Carves the workspace into the grids' arrays (or just sizes it if base == nullptr).
 size_t layout(hweno_ctx* c, char* base) {
     size_t off = 0;
     auto take = [&](size_t ndouble) -> double* {
@@ -115,73 +158,88 @@ size_t layout(hweno_ctx* c, char* base) {
         off += up(ndouble * sizeof(double));
         return p;
     };
-    if (c->grid.dim == 2) {
-        hw::Grid2& g = c->g2;
-        g.nx = c->grid.nx;
-        g.ny = c->grid.ny;
-        g.NX = g.nx + 2 * HALO;
-        g.NY = g.ny + 2 * HALO;
-        g.ncell = (long long)g.NX * g.NY;
-        const size_t n = (size_t)g.ncell;
-        for (int k = 0; k < 3; ++k) c->S[k] = take(12 * n);
-        g.xf = take(24 * n);
-        g.yf = take(24 * n);
-        g.xv = take(36 * n);
-        g.yv = take(36 * n);
-        g.wb = take(6 * n);
-        g.vk = take(8 * n);
-        g.vn = take(8 * n);
-        g.rb = take(18 * n);
-        g.gf = take(72 * n);
-        g.vf = take(8 * n);
-        g.fx = take(12 * n);
-        g.fy = take(12 * n);
-    } else {
+    auto take_bytes = [&](size_t nb) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += up(nb);
+        return p;
+    };
+    const int n = (int)c->in.size();
+    if (c->dim() == 1) {
         hw::Grid1& g = c->g1;
-        g.nx = c->grid.nx;
+        g.nx = c->i0().grid.nx;
         g.NX = g.nx + 2 * HALO;
-        const size_t n = (size_t)g.NX;
-        for (int k = 0; k < 3; ++k) c->S[k] = take(6 * n);
-        g.pts = take(12 * n);
-        g.wb = take(2 * n);
-        g.vk = take(3 * n);
-        g.vn = take(3 * n);
-        g.rb = take(4 * n);
-        g.gr = take(8 * n);
-        g.fh = take(3 * n);
-        g.vf = take(3 * n);
+        const size_t m = (size_t)g.NX;
+        for (int k = 0; k < 3; ++k) c->S1[k] = take(6 * m);
+        g.pts = take(12 * m);
+        g.wb = take(2 * m);
+        g.vk = take(3 * m);
+        g.vn = take(3 * m);
+        g.rb = take(4 * m);
+        g.gr = take(8 * m);
+        g.fh = take(3 * m);
+        g.vf = take(3 * m);
+        c->red = reinterpret_cast<hw::Reduce*>(take_bytes(sizeof(hw::Reduce)));
+        g.red = c->red;
+        return off;
     }
-    if (c->grid.dim == 2) {
+    for (int p = 0; p < n; ++p) {
+        hw::Grid2& g = c->hg[p];
+        const size_t m = (size_t)g.ncell;
+        for (int k = 0; k < 3; ++k) g.S[k] = take(12 * m);
+        g.S[3] = c->batch ? nullptr : take(12 * m);   // reverse-mode recomputation
+        g.xf = take(24 * m);
+        g.yf = take(24 * m);
+        g.xv = take(36 * m);
+        g.yv = take(36 * m);
+        g.wb = take(6 * m);
+        g.vk = take(8 * m);
+        g.vn = take(8 * m);
+        g.rb = take(18 * m);
+        g.gf = take(72 * m);
+        g.vf = take(8 * m);
+        g.fx = take(12 * m);
+        g.fy = take(12 * m);
+    }
+    if (!c->batch) {
         // reverse-mode workspace (zero-filled at the start of every adjoint call)
-        const size_t n = (size_t)c->g2.ncell;
+        const size_t m = (size_t)c->hg[0].ncell;
         hw::AdjWs& A = c->adj;
         const size_t first = off;
-        A.xfb = take(24 * n);
-        A.yfb = take(24 * n);
-        A.xvb = take(36 * n);
-        A.yvb = take(36 * n);
-        A.gfb = take(72 * n);
-        A.rbc = take(102 * n);
-        A.rbb = take(18 * n);
-        A.uc = take(136 * n);
-        A.ubb = take(12 * n);
+        A.xfb = take(24 * m);
+        A.yfb = take(24 * m);
+        A.xvb = take(36 * m);
+        A.yvb = take(36 * m);
+        A.gfb = take(72 * m);
+        A.rbc = take(102 * m);
+        A.rbb = take(18 * m);
+        A.uc = take(136 * m);
+        A.ubb = take(12 * m);
         A.base = A.xfb;
         A.count = (long long)((off - first) / sizeof(double));
-        A.mupart = take((size_t)hw::adj_mu_partials2(c->g2));
+        A.mupart = take((size_t)hw::adj_mu_partials2(c->hg[0]));
         c->mu_dev = take(1);
-        const size_t nint = (size_t)c->g2.nx * c->g2.ny;
-        c->S3 = take(12 * n);
+        const size_t nint = (size_t)c->hg[0].nx * c->hg[0].ny;
         c->X1 = take(12 * nint);
         c->X2 = take(12 * nint);
     }
-    c->red = base ? reinterpret_cast<hw::Reduce*>(base + off) : nullptr;
-    off += up(sizeof(hw::Reduce));
-    c->g2.red = c->red;
-    c->g1.red = c->red;
+    c->red = reinterpret_cast<hw::Reduce*>(take_bytes(n * sizeof(hw::Reduce)));
+    c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
+    c->dg = reinterpret_cast<hw::Grid2*>(take_bytes(n * sizeof(hw::Grid2)));
+    c->dstart = reinterpret_cast<int*>(take_bytes(hw::KB_COUNT * (n + 1) * sizeof(int)));
+    for (int p = 0; p < n; ++p) {
+        c->hg[p].red = c->red ? c->red + p : nullptr;
+        c->hg[p].st = c->dst ? c->dst + p : nullptr;
+    }
     return off;
 }
 
-hweno_status dev(hipError_t e) { return e == hipSuccess ? HWENO_OK : HWENO_E_DEVICE; }
+// A failed call leaves its error pending in the runtime; it is cleared here so
+// that it is reported once, by the call that caused it.
+hweno_status dev(hipError_t e) {
+    if (e == hipSuccess) return HWENO_OK;
+    (void)hipGetLastError();
+    return HWENO_E_DEVICE;
+}
 
 #define TRY(x)                                   \
     do {                                         \
@@ -189,21 +247,75 @@ hweno_status dev(hipError_t e) { return e == hipSuccess ? HWENO_OK : HWENO_E_DEV
         if (s_ != HWENO_OK) return s_;           \
     } while (0)
 
-hweno_status ghost(hweno_ctx* c, double* S) {
-    if (c->grid.dim == 2) return dev(hw::launch_ghost2(c->g2, S, c->stream, c->tm()));
-    return dev(hw::launch_ghost1(c->g1, S, c->stream, c->tm()));
+void drop_graphs(hweno_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gexec1) (void)hipGraphExecDestroy(c->gexec1);
+    c->gexec = c->gexec1 = nullptr;
+    c->gsteps = 0;
 }
 
-hweno_status residual(hweno_ctx* c, const double* S) {
-    if (c->grid.dim == 2) return dev(hw::launch_residual2(c->g2, S, c->stream, c->tm()));
-    return dev(hw::launch_residual1(c->g1, S, c->stream, c->tm()));
+// Schedule order, block tables and device grid array (synchronous).
+hweno_status upload_grids(hweno_ctx* c) {
+    const int n = (int)c->hg.size();
+    c->order.resize(n);
+    for (int p = 0; p < n; ++p) c->order[p] = p;
+    if (c->order_mode == 1) {
+        std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
+            return c->hg[a].ncell > c->hg[b].ncell;
+        });
+    }
+    std::vector<hw::Grid2> slots(n);
+    for (int p = 0; p < n; ++p) slots[p] = c->hg[c->order[p]];
+    c->hstart.assign(hw::KB_COUNT * (n + 1), 0);
+    hw::batch_blocks(slots.data(), n, c->tiles, c->hstart.data());
+    TRY(dev(hipMemcpyAsync(c->dg, slots.data(), n * sizeof(hw::Grid2), hipMemcpyHostToDevice,
+                           c->stream)));
+    TRY(dev(hipMemcpyAsync(c->dstart, c->hstart.data(), c->hstart.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream)));
+    TRY(dev(hipStreamSynchronize(c->stream)));
+    c->bl.dg = c->dg;
+    c->bl.dstart = c->dstart;
+    c->bl.hstart = c->hstart.data();
+    c->bl.n = n;
+    c->bl.tiles = c->tiles;
+    drop_graphs(c);
+    return HWENO_OK;
 }
 
-hweno_status update(hweno_ctx* c, int stage, const double* S0, const double* Sin, double* Sout,
-                    double* R, double* V) {
-    if (c->grid.dim == 2)
-        return dev(hw::launch_update2(c->g2, stage, S0, Sin, Sout, R, V, c->stream, c->tm()));
-    return dev(hw::launch_update1(c->g1, stage, S0, Sin, Sout, R, V, c->stream, c->tm()));
+hweno_status upload_state(hweno_ctx* c) {
+    TRY(dev(hipMemcpyAsync(c->dst, c->hst.data(), c->hst.size() * sizeof(hw::InstState),
+                           hipMemcpyHostToDevice, c->stream)));
+    return dev(hipStreamSynchronize(c->stream));
+}
+
+hweno_status download_state(hweno_ctx* c) {
+    TRY(dev(hipMemcpyAsync(c->hst.data(), c->dst, c->hst.size() * sizeof(hw::InstState),
+                           hipMemcpyDeviceToHost, c->stream)));
+    return dev(hipStreamSynchronize(c->stream));
+}
+
+hw::Grid2& g2(hweno_ctx* c) { return c->hg[0]; }
+
+hweno_status ghost(hweno_ctx* c, int si) {
+    if (c->dim() == 2) return dev(hw::launch_ghost2(c->bl, si, c->stream, c->tm()));
+    return dev(hw::launch_ghost1(c->g1, c->S1[si], c->stream, c->tm()));
+}
+
+hweno_status residual(hweno_ctx* c, int si) {
+    if (c->dim() == 2) return dev(hw::launch_residual2(c->bl, si, c->stream, c->tm()));
+    return dev(hw::launch_residual1(c->g1, c->S1[si], c->stream, c->tm()));
+}
+
+hweno_status update(hweno_ctx* c, int stage, int i0, int iin, int iout, double* R, double* V) {
+    if (c->dim() == 2)
+        return dev(hw::launch_update2(c->bl, stage, i0, iin, iout, R, V, c->stream, c->tm()));
+    return dev(hw::launch_update1(c->g1, stage, c->S1[i0], c->S1[iin], c->S1[iout], R, V,
+                                  c->stream, c->tm()));
+}
+
+hweno_status reset(hweno_ctx* c) {
+    if (c->dim() == 2) return dev(hw::launch_reset2(c->bl, c->stream));
+    return dev(hw::launch_reset(c->red, c->stream));
 }
 
 hweno_status read_reduce(hweno_ctx* c, hw::Reduce* r) {
@@ -213,10 +325,9 @@ hweno_status read_reduce(hweno_ctx* c, hw::Reduce* r) {
     return HWENO_OK;
 }
 
-void fill_diag(const hweno_ctx* c, const hw::Reduce& r, hweno_diag* d, int restarts,
-               bool stage1_alpha) {
+void fill_diag(double t, const hw::Reduce& r, hweno_diag* d, int restarts, bool stage1_alpha) {
     if (!d) return;
-    d->t = c->t;
+    d->t = t;
     d->dt = r.dt;
     d->alpha_star = hw::dkey_inv(stage1_alpha ? r.alpha1_key : r.alpha_key);
     d->beta_max = hw::dkey_inv(r.beta_key);
@@ -229,27 +340,9 @@ void fill_diag(const hweno_ctx* c, const hw::Reduce& r, hweno_diag* d, int resta
 
 bool valid_kind(int k) { return k >= HWENO_BC_PERIODIC && k <= HWENO_BC_NOSLIP; }
 
-}  // namespace
-
-extern "C" {
-
-HWENO_API hweno_status hweno_default_options(hweno_options* o) {
-    if (!o) return HWENO_E_INVAL;
-    o->cfl = 0.6;
-    o->b_visc = 0.001;
-    o->eps_pp = 1e-12;
-    o->eps_weno = 1e-8;
-    o->t_final = 0.0;
-    o->linear_weights = 0;
-    o->max_halvings = 40;
-    return HWENO_OK;
-}
-
-HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
-                                    const hweno_bcs* bcs, const hweno_options* opt,
-                                    hweno_ctx** out) {
-    if (!grid || !phys || !bcs || !opt || !out) return HWENO_E_INVAL;
-    *out = nullptr;
+hweno_status validate(const hweno_grid* grid, const hweno_physics* phys, const hweno_bcs* bcs,
+                      const hweno_options* opt) {
+    if (!grid || !phys || !bcs || !opt) return HWENO_E_INVAL;
     if (grid->dim != 1 && grid->dim != 2) return HWENO_E_INVAL;
     if (grid->nx < 4 || !(grid->x1 > grid->x0)) return HWENO_E_INVAL;
     if (grid->dim == 2 && (grid->ny < 4 || !(grid->y1 > grid->y0))) return HWENO_E_INVAL;
@@ -273,25 +366,139 @@ HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics*
         const bool p1 = bcs->kind[2 * a + 1] == HWENO_BC_PERIODIC;
         if (p0 != p1) return HWENO_E_INVAL;
     }
+    return HWENO_OK;
+}
+
+// Builds the context of n validated instances (host side only).
+hweno_ctx* make_ctx(int n, const hweno_grid* grids, const hweno_physics* phys,
+                    const hweno_bcs* bcs, const hweno_options* opts, bool batch) {
     hweno_ctx* c = new (std::nothrow) hweno_ctx;
-    if (!c) return HWENO_E_INVAL;
-    c->grid = *grid;
-    c->phys = *phys;
-    c->bcs = *bcs;
-    c->opt = *opt;
+    if (!c) return nullptr;
+    c->batch = batch;
+    c->in.resize(n);
+    for (int p = 0; p < n; ++p) c->in[p] = Inst{grids[p], phys[p], bcs[p], opts[p]};
     if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+    if (c->dim() == 2) {
+        c->hg.assign(n, hw::Grid2{});
+        c->hst.assign(n, hw::InstState{});
+        c->have.assign(n, 0);
+        for (int p = 0; p < n; ++p) {
+            hw::Grid2& g = c->hg[p];
+            g.nx = grids[p].nx;
+            g.ny = grids[p].ny;
+            g.NX = g.nx + 2 * HALO;
+            g.NY = g.ny + 2 * HALO;
+            g.ncell = (long long)g.NX * g.NY;
+            g.K = make_consts(c->in[p]);
+            for (int s = 0; s < 4; ++s) make_side(c->in[p], s, g.side[s]);
+            hw::InstState& st = c->hst[p];
+            rule(c->in[p], &st.cfl_h, &st.visc_dt);
+            st.t_final = opts[p].t_final;
+            st.max_halvings = opts[p].max_halvings;
+            st.active = batch ? 0 : 1;       // a single grid is always active
+        }
+    } else {
+        c->g1.K = make_consts(c->in[0]);
+        for (int s = 0; s < 2; ++s) make_side(c->in[0], s, c->g1.side[s]);
+    }
     c->ws_bytes = layout(c, nullptr);
-    const hw::Consts K = make_consts(c);
-    c->g2.K = K;
-    c->g1.K = K;
-    for (int s = 0; s < 4; ++s) make_side(c, s, c->g2.side[s]);
-    for (int s = 0; s < 2; ++s) make_side(c, s, c->g1.side[s]);
+    return c;
+}
+
+// One step of every active instance of a batch (eq. (2.12) with the step rule
+// on the device); recorded into a graph by hweno_batch_run.
+hweno_status batch_step(hweno_ctx* c) {
+    const hw::BatchL& b = c->bl;
+    hipStream_t st = c->stream;
+    TRY(dev(hw::launch_reset2(b, st)));
+    TRY(dev(hw::launch_ghost2(b, 0, st, nullptr)));
+    TRY(dev(hw::launch_residual2(b, 0, st, nullptr)));
+    TRY(dev(hw::launch_dt2(b, st)));
+    TRY(dev(hw::launch_update2(b, 1, 0, 0, 1, nullptr, nullptr, st, nullptr)));
+    TRY(dev(hw::launch_ghost2(b, 1, st, nullptr)));
+    TRY(dev(hw::launch_residual2(b, 1, st, nullptr)));
+    TRY(dev(hw::launch_update2(b, 2, 0, 1, 2, nullptr, nullptr, st, nullptr)));
+    TRY(dev(hw::launch_ghost2(b, 2, st, nullptr)));
+    TRY(dev(hw::launch_residual2(b, 2, st, nullptr)));
+    TRY(dev(hw::launch_update2(b, 3, 0, 2, 1, nullptr, nullptr, st, nullptr)));
+    return dev(hw::launch_commit2(b, st));
+}
+
+// Records nsteps batch steps on the context's private stream (the caller's
+// stream may be the legacy default stream, which cannot be captured); the
+// graph is then launched on the caller's stream.
+hweno_status capture(hweno_ctx* c, int nsteps, hipGraphExec_t* out) {
+    if (!c->cap_stream) TRY(dev(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)));
+    hipGraph_t graph = nullptr;
+    hipStream_t user = c->stream;
+    TRY(dev(hipStreamSynchronize(user)));
+    c->stream = c->cap_stream;
+    hweno_status s = dev(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    if (s != HWENO_OK) {
+        c->stream = user;
+        return s;
+    }
+    for (int k = 0; k < nsteps && s == HWENO_OK; ++k) s = batch_step(c);
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->stream = user;
+    if (s != HWENO_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    TRY(dev(e));
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return dev(ei);
+}
+
+}  // namespace
+
+extern "C" {
+
+HWENO_API hweno_status hweno_default_options(hweno_options* o) {
+    if (!o) return HWENO_E_INVAL;
+    o->cfl = 0.6;
+    o->b_visc = 0.001;
+    o->eps_pp = 1e-12;
+    o->eps_weno = 1e-8;
+    o->t_final = 0.0;
+    o->linear_weights = 0;
+    o->max_halvings = 40;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
+                                    const hweno_bcs* bcs, const hweno_options* opt,
+                                    hweno_ctx** out) {
+    if (!out) return HWENO_E_INVAL;
+    *out = nullptr;
+    TRY(validate(grid, phys, bcs, opt));
+    hweno_ctx* c = make_ctx(1, grid, phys, bcs, opt, false);
+    if (!c) return HWENO_E_INVAL;
+    *out = c;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
+                                          const hweno_physics* phys, const hweno_bcs* bcs,
+                                          const hweno_options* opts, hweno_ctx** out) {
+    if (!out) return HWENO_E_INVAL;
+    *out = nullptr;
+    if (n < 1 || n > HWENO_BATCH_MAX || !grids || !phys || !bcs || !opts) return HWENO_E_INVAL;
+    for (int p = 0; p < n; ++p) {
+        TRY(validate(grids + p, phys + p, bcs + p, opts + p));
+        if (grids[p].dim != 2) return HWENO_E_INVAL;
+    }
+    hweno_ctx* c = make_ctx(n, grids, phys, bcs, opts, true);
+    if (!c) return HWENO_E_INVAL;
     *out = c;
     return HWENO_OK;
 }
 
 HWENO_API hweno_status hweno_destroy(hweno_ctx* c) {
     if (!c) return HWENO_E_INVAL;
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->timer.destroy();
     delete c;
     return HWENO_OK;
@@ -310,6 +517,16 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) 
     c->ws = static_cast<char*>(p);
     layout(c, c->ws);
     c->has_state = false;
+    c->cur = 0;
+    std::fill(c->have.begin(), c->have.end(), 0);
+    if (c->dim() == 2) {
+        for (auto& st : c->hst) {
+            st.t = 0.0;
+            st.status = 0;
+        }
+        TRY(upload_state(c));
+        TRY(upload_grids(c));
+    }
     return HWENO_OK;
 }
 
@@ -320,40 +537,39 @@ HWENO_API hweno_status hweno_set_stream(hweno_ctx* c, void* s) {
 }
 
 HWENO_API hweno_status hweno_set_state(hweno_ctx* c, const double* U, double t) {
-    if (!c || !U || !std::isfinite(t)) return HWENO_E_INVAL;
+    if (!c || !U || !std::isfinite(t) || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
-    if (c->grid.dim == 2) TRY(dev(hw::launch_copy_in2(c->g2, U, c->S[0], c->stream)));
-    else TRY(dev(hw::launch_copy_in1(c->g1, U, c->S[0], c->stream)));
+    if (c->dim() == 2) TRY(dev(hw::launch_copy_in2(g2(c), U, g2(c).S[c->cur], c->stream)));
+    else TRY(dev(hw::launch_copy_in1(c->g1, U, c->S1[0], c->stream)));
     c->t = t;
     c->has_state = true;
     return HWENO_OK;
 }
 
 HWENO_API hweno_status hweno_get_state(hweno_ctx* c, double* U, double* t) {
-    if (!c || !U) return HWENO_E_INVAL;
+    if (!c || !U || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
-    if (c->grid.dim == 2) TRY(dev(hw::launch_copy_out2(c->g2, c->S[0], U, c->stream)));
-    else TRY(dev(hw::launch_copy_out1(c->g1, c->S[0], U, c->stream)));
+    if (c->dim() == 2) TRY(dev(hw::launch_copy_out2(g2(c), g2(c).S[c->cur], U, c->stream)));
+    else TRY(dev(hw::launch_copy_out1(c->g1, c->S1[0], U, c->stream)));
     if (t) *t = c->t;
     return HWENO_OK;
 }
 
 HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, double* V,
                                       hweno_diag* diag) {
-    if (!c || !U || !R || !V) return HWENO_E_INVAL;
+    if (!c || !U || !R || !V || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
-    double* S = c->S[2];
-    if (c->grid.dim == 2) TRY(dev(hw::launch_copy_in2(c->g2, U, S, c->stream)));
-    else TRY(dev(hw::launch_copy_in1(c->g1, U, S, c->stream)));
-    TRY(dev(hw::launch_reset(c->red, c->stream)));
-    TRY(ghost(c, S));
-    TRY(residual(c, S));
-    TRY(update(c, 0, S, S, S, R, V));
+    if (c->dim() == 2) TRY(dev(hw::launch_copy_in2(g2(c), U, g2(c).S[2], c->stream)));
+    else TRY(dev(hw::launch_copy_in1(c->g1, U, c->S1[2], c->stream)));
+    TRY(reset(c));
+    TRY(ghost(c, 2));
+    TRY(residual(c, 2));
+    TRY(update(c, 0, 2, 2, 2, R, V));
     if (diag) {
         hw::Reduce r;
         TRY(read_reduce(c, &r));
-        fill_diag(c, r, diag, 0, false);
+        fill_diag(c->t, r, diag, 0, false);
         diag->dt = 0.0;
         diag->min_rho = diag->min_p = NAN;
     }
@@ -361,14 +577,14 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
 }
 
 HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) {
-    if (!c || std::isnan(dt)) return HWENO_E_INVAL;
+    if (!c || std::isnan(dt) || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
+    const bool two = c->dim() == 2;
     const bool auto_dt = !(dt > 0.0);
-    const double h = c->grid.dim == 2 ? std::fmin(c->g2.K.dx, c->g2.K.dy) : c->g1.K.dx;
-    double visc = INFINITY;
-    if (c->opt.b_visc > 0.0 && c->phys.mu_ref > 0.0) visc = c->opt.b_visc * h * h / c->phys.mu_ref;
-    const double t_left = c->opt.t_final > 0.0 ? c->opt.t_final - c->t : INFINITY;
+    double cfl_h, visc;
+    rule(c->i0(), &cfl_h, &visc);
+    const double t_left = c->i0().opt.t_final > 0.0 ? c->i0().opt.t_final - c->t : INFINITY;
     if (auto_dt && !(t_left > 0.0)) {   // already at t_final: nothing to do
         if (diag) {
             std::memset(diag, 0, sizeof(*diag));
@@ -376,57 +592,58 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
         }
         return HWENO_OK;
     }
-    double cur = dt;
+    // state buffers: 2D by index into Grid2::S (the current one is `cur`);
+    // 1D by index into S1 with S1[0] current
+    const int a = two ? c->cur : 0, b = two ? 1 - c->cur : 1, s2 = 2;
+    double cur_dt = dt;
     int restarts = 0;
     hw::Reduce r;
     for (;;) {
-        double* S0 = c->S[0];
-        double* S1 = c->S[1];
-        double* S2 = c->S[2];
-        TRY(dev(hw::launch_reset(c->red, c->stream)));
+        TRY(reset(c));
         if (restarts == 0) {
-            if (c->grid.dim == 2) TRY(dev(hw::launch_check2(c->g2, S0, c->stream)));
-            else TRY(dev(hw::launch_check1(c->g1, S0, c->stream)));
+            if (two) TRY(dev(hw::launch_check2(c->bl, a, c->stream)));
+            else TRY(dev(hw::launch_check1(c->g1, c->S1[0], c->stream)));
         }
-        TRY(ghost(c, S0));
-        TRY(residual(c, S0));
+        TRY(ghost(c, a));
+        TRY(residual(c, a));
         if (auto_dt && restarts == 0)
-            TRY(dev(hw::launch_dt(c->red, c->opt.cfl * h, visc, t_left, c->stream)));
+            TRY(dev(hw::launch_dt(c->red, cfl_h, visc, t_left, c->stream)));
         else
-            TRY(dev(hw::launch_set_dt(c->red, cur, c->stream)));
-        TRY(update(c, 1, S0, S0, S1, nullptr, nullptr));
-        TRY(ghost(c, S1));
-        TRY(residual(c, S1));
-        TRY(update(c, 2, S0, S1, S2, nullptr, nullptr));
-        TRY(ghost(c, S2));
-        TRY(residual(c, S2));
-        TRY(update(c, 3, S0, S2, S1, nullptr, nullptr));
+            TRY(dev(hw::launch_set_dt(c->red, cur_dt, c->stream)));
+        TRY(update(c, 1, a, a, b, nullptr, nullptr));
+        TRY(ghost(c, b));
+        TRY(residual(c, b));
+        TRY(update(c, 2, a, b, s2, nullptr, nullptr));
+        TRY(ghost(c, s2));
+        TRY(residual(c, s2));
+        TRY(update(c, 3, a, s2, b, nullptr, nullptr));
         TRY(read_reduce(c, &r));
         if (restarts == 0 && r.bad[0] != 0) return HWENO_E_NONFINITE;
         if (!(r.dt > 0.0) || !std::isfinite(r.dt)) return HWENO_E_NONFINITE;
         if (r.bad[1] == 0 && r.bad[2] == 0 && r.bad[3] == 0) break;
-        if (restarts >= c->opt.max_halvings) return HWENO_E_INADMISSIBLE;
+        if (restarts >= c->i0().opt.max_halvings) return HWENO_E_INADMISSIBLE;
         ++restarts;
-        cur = 0.5 * r.dt;
+        cur_dt = 0.5 * r.dt;
     }
-    std::swap(c->S[0], c->S[1]);
+    if (two) c->cur = b;
+    else std::swap(c->S1[0], c->S1[1]);
     c->t += r.dt;
-    fill_diag(c, r, diag, restarts, true);
+    fill_diag(c->t, r, diag, restarts, true);
     return HWENO_OK;
 }
 
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar) {
-    if (!c || !U || !Rbar || !Ubar) return HWENO_E_INVAL;
-    if (c->grid.dim != 2 || c->phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
-    double* S = c->S[2];
-    TRY(dev(hw::launch_copy_in2(c->g2, U, S, c->stream)));
-    TRY(dev(hw::launch_reset(c->red, c->stream)));
-    TRY(ghost(c, S));
-    TRY(residual(c, S));
+    const hw::Grid2& g = g2(c);
+    TRY(dev(hw::launch_copy_in2(g, U, g.S[2], c->stream)));
+    TRY(reset(c));
+    TRY(ghost(c, 2));
+    TRY(residual(c, 2));
     hw::AdjIn A{Rbar, Vbar, 1.0, 1.0};
-    TRY(dev(hw::launch_vjp2(c->g2, A, c->adj, S, Ubar, c->mu_dev, 0, c->stream)));
+    TRY(dev(hw::launch_vjp2(g, A, c->adj, g.S[2], Ubar, c->mu_dev, 0, c->stream)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));
@@ -442,53 +659,250 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
 // residual adjoints run in reverse with the stage cotangents as seeds.
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar) {
-    if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt)) return HWENO_E_INVAL;
-    if (c->grid.dim != 2 || c->phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
+        return HWENO_E_INVAL;
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
-    const hw::Grid2& g = c->g2;
+    const hw::Grid2& g = g2(c);
     const long long nint = (long long)g.nx * g.ny;
-    double* Sa = c->S[1];   // U0
-    double* Sb = c->S[2];   // U1
-    double* Sc = c->S3;     // U2
+    const int ia = 1 - c->cur, ib = 2, ic = 3;   // U0, U1, U2 (the current state is kept)
     // forward recomputation of the two intermediate stages
-    TRY(dev(hw::launch_copy_in2(g, U0, Sa, c->stream)));
-    TRY(dev(hw::launch_reset(c->red, c->stream)));
+    TRY(dev(hw::launch_copy_in2(g, U0, g.S[ia], c->stream)));
+    TRY(reset(c));
     TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
-    TRY(ghost(c, Sa));
-    TRY(residual(c, Sa));
-    TRY(update(c, 1, Sa, Sa, Sb, nullptr, nullptr));
-    TRY(ghost(c, Sb));
-    TRY(residual(c, Sb));
-    TRY(update(c, 2, Sa, Sb, Sc, nullptr, nullptr));
-    auto vjp_at = [&](double* S, const double* Rb, double rs, double vs, double* out, int acc) {
-        TRY(dev(hw::launch_reset(c->red, c->stream)));
-        TRY(ghost(c, S));
-        TRY(residual(c, S));
-        hw::AdjIn A{Rb, Rb + 4 * nint, rs, vs};
-        return dev(hw::launch_vjp2(g, A, c->adj, S, out, c->mu_dev, acc, c->stream));
+    TRY(ghost(c, ia));
+    TRY(residual(c, ia));
+    TRY(update(c, 1, ia, ia, ib, nullptr, nullptr));
+    TRY(ghost(c, ib));
+    TRY(residual(c, ib));
+    TRY(update(c, 2, ia, ib, ic, nullptr, nullptr));
+    auto vjp_at = [&](int si, const double* Rb, const double* Vb, double rs, double vs,
+                      double* out, int acc) {
+        TRY(reset(c));
+        TRY(ghost(c, si));
+        TRY(residual(c, si));
+        hw::AdjIn A{Rb, Vb, rs, vs};
+        return dev(hw::launch_vjp2(g, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream));
     };
     // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified moments)
-    TRY(vjp_at(Sc, U3bar, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
+    TRY(vjp_at(ic, U3bar, U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
     TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
     // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar
-    TRY(vjp_at(Sb, c->X2, 0.25 * dt, 0.25, c->X1, 1));
+    TRY(vjp_at(ib, c->X2, c->X2 + 4 * nint, 0.25 * dt, 0.25, c->X1, 1));
     TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
     // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar
-    TRY(dev(hw::launch_reset(c->red, c->stream)));
-    TRY(ghost(c, Sa));
-    TRY(residual(c, Sa));
-    {
-        hw::AdjIn A{c->X1, c->X2 + 4 * nint, dt, 1.0};
-        TRY(dev(hw::launch_vjp2(g, A, c->adj, Sa, U0bar, c->mu_dev, 1, c->stream)));
-    }
+    TRY(vjp_at(ia, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
     TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));
         TRY(dev(hipStreamSynchronize(c->stream)));
     }
+    return HWENO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+HWENO_API hweno_status hweno_batch_set_state(hweno_ctx* c, int i, const double* U, double t) {
+    if (!c || !c->batch || !U || i < 0 || i >= (int)c->in.size() || !std::isfinite(t))
+        return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    const hw::Grid2& g = c->hg[i];
+    TRY(dev(hw::launch_copy_in2(g, U, g.S[0], c->stream)));
+    TRY(download_state(c));
+    c->hst[i].t = t;
+    c->hst[i].status = 0;
+    c->hst[i].halvings = 0;
+    TRY(upload_state(c));
+    c->have[i] = 1;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_batch_get_state(hweno_ctx* c, int i, double* U, double* t) {
+    if (!c || !c->batch || !U || i < 0 || i >= (int)c->in.size()) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (!c->have[i]) return HWENO_E_STATE;
+    const hw::Grid2& g = c->hg[i];
+    TRY(dev(hw::launch_copy_out2(g, g.S[0], U, c->stream)));
+    if (t) *t = c->hst[i].t;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_batch_run(hweno_ctx* c, int nsteps) {
+    if (!c || !c->batch || nsteps < 1) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    const int n = (int)c->in.size();
+    for (int p = 0; p < n; ++p)
+        if (!c->have[p]) return HWENO_E_STATE;
+    // run set-up: counters, activity, input admissibility
+    TRY(download_state(c));
+    int max_halv = 0;
+    for (auto& st : c->hst) {
+        st.steps = 0;
+        st.target = nsteps;
+        st.halvings = 0;
+        st.restarts = 0;
+        st.pp_cells = 0;
+        st.active = st.status == 0 && (st.t_final <= 0.0 || st.t < st.t_final);
+        max_halv = std::max(max_halv, st.max_halvings);
+    }
+    TRY(upload_state(c));
+    TRY(dev(hw::launch_reset2(c->bl, c->stream)));
+    TRY(dev(hw::launch_check2(c->bl, 0, c->stream)));
+    std::vector<hw::Reduce> rr(n);
+    TRY(dev(hipMemcpyAsync(rr.data(), c->red, n * sizeof(hw::Reduce), hipMemcpyDeviceToHost,
+                           c->stream)));
+    TRY(dev(hipStreamSynchronize(c->stream)));
+    bool bad_input = false;
+    for (int p = 0; p < n; ++p) {
+        if (c->hst[p].active && rr[p].bad[0] != 0) {
+            c->hst[p].status = HWENO_E_NONFINITE;
+            c->hst[p].active = 0;
+            bad_input = true;
+        }
+    }
+    if (bad_input) TRY(upload_state(c));
+    // the whole run as one graph launch
+    if (!c->gexec || c->gsteps != nsteps) {
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        TRY(capture(c, nsteps, &c->gexec));
+        c->gsteps = nsteps;
+    }
+    hw::Timer* tm = c->tm();
+    hw::tbeg(tm, hw::KC_OTHER, c->stream);
+    TRY(dev(hipGraphLaunch(c->gexec, c->stream)));
+    hw::tend(tm, c->stream);
+    TRY(download_state(c));
+    if (tm) tm->collect();
+    // instances that needed restarts: one more attempt per launch until done
+    const long long limit = (long long)nsteps * (max_halv + 1);
+    for (long long k = 0; k < limit; ++k) {
+        bool any = false;
+        for (auto& st : c->hst) any = any || st.active;
+        if (!any) break;
+        if (!c->gexec1) TRY(capture(c, 1, &c->gexec1));
+        TRY(dev(hipGraphLaunch(c->gexec1, c->stream)));
+        TRY(download_state(c));
+    }
+    for (auto& st : c->hst)
+        if (st.status != 0) return (hweno_status)st.status;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* c, int i, hweno_diag* d) {
+    if (!c || !c->batch || !d || i < 0 || i >= (int)c->in.size()) return HWENO_E_INVAL;
+    const hw::InstState& st = c->hst[i];
+    d->t = st.t;
+    d->dt = st.dt_last;
+    d->alpha_star = st.alpha;
+    d->beta_max = st.beta_max;
+    d->min_rho = st.min_rho;
+    d->min_p = st.min_p;
+    d->pp_cells = st.pp_cells;
+    d->restarts = (int)st.restarts;
+    d->pad = st.steps;
+    return HWENO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tiles and the autotuner (2D contexts)
+// ---------------------------------------------------------------------------
+HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
+    if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
+    t->recon = c->tiles.recon;
+    t->grad = c->tiles.grad;
+    t->flux = c->tiles.flux;
+    t->order = c->order_mode;
+    return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
+    if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
+    if ((t->recon != 16 && t->recon != 32) || (t->grad != 32 && t->grad != 64) ||
+        (t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1))
+        return HWENO_E_INVAL;
+    c->tiles.recon = t->recon;
+    c->tiles.grad = t->grad;
+    c->tiles.flux = t->flux;
+    c->order_mode = t->order;
+    if (!c->ws) return HWENO_OK;
+    return upload_grids(c);
+}
+
+HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chosen) {
+    if (!c || c->dim() != 2 || reps < 1) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (c->batch) {
+        for (char h : c->have)
+            if (!h) return HWENO_E_STATE;
+    } else if (!c->has_state) {
+        return HWENO_E_STATE;
+    }
+    if (!c->timer.init()) return HWENO_E_DEVICE;
+    const bool was_on = c->timer.on;
+    const int si = c->batch ? 0 : c->cur;
+    if (c->batch) {
+        // every instance active for the timing passes
+        TRY(download_state(c));
+        for (auto& st : c->hst) st.active = 1;
+        TRY(upload_state(c));
+    }
+    // `reps` residual evaluations of the current states; ms per kernel class
+    auto measure = [&](double* ms) -> hweno_status {
+        TRY(reset(c));
+        TRY(ghost(c, si));
+        TRY(residual(c, si));                        // warm-up
+        TRY(dev(hipStreamSynchronize(c->stream)));
+        c->timer.collect();
+        c->timer.reset();
+        c->timer.on = true;
+        for (int r = 0; r < reps; ++r) {
+            TRY(reset(c));
+            TRY(ghost(c, si));
+            TRY(residual(c, si));
+        }
+        TRY(dev(hipStreamSynchronize(c->stream)));
+        c->timer.collect();
+        for (int k = 0; k < hw::KC_COUNT; ++k) ms[k] = c->timer.ms[k];
+        c->timer.on = was_on;
+        c->timer.reset();
+        return HWENO_OK;
+    };
+    const hw::Tiles cand[2] = {{16, 32, 64}, {32, 64, 128}};
+    double ms[2][hw::KC_COUNT];
+    for (int q = 0; q < 2; ++q) {
+        c->tiles = cand[q];
+        TRY(upload_grids(c));
+        TRY(measure(ms[q]));
+    }
+    hw::Tiles best;
+    best.recon = ms[0][hw::KC_RECON] <= ms[1][hw::KC_RECON] ? cand[0].recon : cand[1].recon;
+    best.grad = ms[0][hw::KC_GRAD] <= ms[1][hw::KC_GRAD] ? cand[0].grad : cand[1].grad;
+    best.flux = ms[0][hw::KC_FLUX] <= ms[1][hw::KC_FLUX] ? cand[0].flux : cand[1].flux;
+    c->tiles = best;
+    if (c->batch && c->in.size() > 1) {
+        // schedule order: as given vs largest instance first
+        double tot[2];
+        for (int o = 0; o < 2; ++o) {
+            c->order_mode = o;
+            TRY(upload_grids(c));
+            double m[hw::KC_COUNT];
+            TRY(measure(m));
+            tot[o] = 0.0;
+            for (int k = 0; k < hw::KC_COUNT; ++k) tot[o] += m[k];
+        }
+        c->order_mode = tot[1] < tot[0] ? 1 : 0;
+    }
+    TRY(upload_grids(c));
+    if (c->batch) {
+        for (auto& st : c->hst) st.active = 0;
+        TRY(upload_state(c));
+    }
+    if (chosen) TRY(hweno_get_tiles(c, chosen));
     return HWENO_OK;
 }
 

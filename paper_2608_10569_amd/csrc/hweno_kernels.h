@@ -28,6 +28,21 @@ struct Side {
     double inflow[4];     // conservative inflow state
 };
 
+// Persistent per-instance state of a batched run (device memory).  Kernels
+// of the 2D pipeline skip every instance whose `active` is 0.
+struct InstState {
+    double t, t_final;        // time; end time (<= 0: none)
+    double cfl_h, visc_dt;    // step rule: min(cfl_h / alpha*, visc_dt, t_final - t)
+    double dt_last;           // step size of the last accepted step
+    double alpha, beta_max, min_rho, min_p;   // diagnostics of the last attempt
+    unsigned long long restarts;   // rejected attempts in this run
+    unsigned long long pp_cells;   // limiter cell-stages of accepted steps in this run
+    int steps, target;        // accepted steps in this run and the goal
+    int halvings, max_halvings;
+    int active;               // 1 while steps < target, t < t_final and no error
+    int status;               // 0, or the hweno_status that stopped the instance
+};
+
 // Pointers and sizes of one 2D grid's workspace (all arrays SoA over the
 // ghosted grid NX x NY, component-major: a[q * ncell + j * NX + i]).
 struct Grid2 {
@@ -35,6 +50,8 @@ struct Grid2 {
     long long ncell;          // NX * NY
     Consts K;
     Side side[4];
+    double* S[4];  // 12 each: ghosted states (current, stage outputs, scratch)
+    InstState* st;
     double* xf;   // 24: x-face traces (p*4 + c), p 0..2 left face, 3..5 right face
     double* yf;   // 24: y-face traces, p 0..2 bottom face, 3..5 top face
     double* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g
@@ -122,15 +139,59 @@ struct Timer {
 inline void tbeg(Timer* t, int k, hipStream_t st) { if (t) t->begin(k, st); }
 inline void tend(Timer* t, hipStream_t st) { if (t) t->end(st); }
 
+// ---------------------------------------------------------------------------
+// Instance mapping of the 2D kernels.  One launch of a kernel class covers
+// every instance of a batch (a single grid is a batch of one): the device
+// array g holds the instances in schedule order and start[p] is the first
+// block of the instance in slot p (start[n] = the launch's block count).
+// ---------------------------------------------------------------------------
+enum { KB_GHOSTX = 0, KB_GHOSTY, KB_RECON, KB_RBAR, KB_GRAD, KB_FLUX0, KB_FLUX1, KB_CELLS,
+       KB_COUNT };
+
+struct Batch {
+    const Grid2* g;
+    const int* start;
+    int n;
+};
+
+// Work per block of the tunable kernels (cells, cells, faces).
+struct Tiles {
+    int recon = 32;   // 16 or 32
+    int grad = 32;    // 32 or 64
+    int flux = 64;    // 64 or 128
+};
+
+struct BatchL {
+    const Grid2* dg = nullptr;     // device, n instances in schedule order
+    const int* dstart = nullptr;   // device, KB_COUNT x (n + 1)
+    const int* hstart = nullptr;   // host copy of dstart
+    int n = 0;
+    Tiles tiles;
+    Batch arg(int k) const { return Batch{dg, dstart + k * (n + 1), n}; }
+    unsigned blocks(int k) const { return (unsigned)hstart[k * (n + 1) + n]; }
+};
+
+// Block prefix tables of every kernel class for the instances hg[0..n) (in
+// schedule order) and the given tiles; out has KB_COUNT x (n + 1) entries.
+void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out);
+
 // Launchers (stream-ordered, no synchronisation).  Return hipError_t.
 hipError_t launch_reset(Reduce* red, hipStream_t st);
 hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream_t st);
 hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st);
-hipError_t launch_ghost2(const Grid2& g, double* S, hipStream_t st, Timer* tm);
-hipError_t launch_residual2(const Grid2& g, const double* S, hipStream_t st, Timer* tm);
-// stage 0: write R (12) and Vhat (8) in interior layout; stage 1..3: RK update
-hipError_t launch_update2(const Grid2& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm);
+// 2D pipeline over every instance of b; state buffers by index into Grid2::S
+hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm);
+hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm);
+// stage 0: write R (12) and Vhat (8) in interior layout (single grid);
+// stage 1..3: RK update S[iout] from S[i0] (U^n) and S[iin] (stage input)
+hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
+                          double* Vhat, hipStream_t st, Timer* tm);
+hipError_t launch_check2(const BatchL& b, int si, hipStream_t st);
+hipError_t launch_reset2(const BatchL& b, hipStream_t st);
+// per-instance step size from its InstState rule, halved per pending restart
+hipError_t launch_dt2(const BatchL& b, hipStream_t st);
+// accept (S[1] -> S[0], time, counters) or reject (halve) every active instance
+hipError_t launch_commit2(const BatchL& b, hipStream_t st);
 hipError_t launch_dt(Reduce* red, double cfl_h, double visc_dt, double t_left, hipStream_t st);
 hipError_t launch_set_dt(Reduce* red, double dt, hipStream_t st);
 
@@ -140,7 +201,6 @@ hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st, Timer* tm);
 hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Timer* tm);
 hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
                           double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm);
-hipError_t launch_check2(const Grid2& g, const double* S, hipStream_t st);
 hipError_t launch_check1(const Grid1& g, const double* S, hipStream_t st);
 
 }  // namespace hw

@@ -18,12 +18,13 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_rk_step', 'hweno_residual_vjp', 'hweno_rk_step_vjp',
-           'hweno_set_timing',
-           'hweno_get_timing',
-           'hweno_status_string')
+           'hweno_set_timing', 'hweno_get_timing', 'hweno_status_string',
+           'hweno_batch_create', 'hweno_batch_set_state', 'hweno_batch_get_state',
+           'hweno_batch_run', 'hweno_batch_get_diag', 'hweno_get_tiles', 'hweno_set_tiles',
+           'hweno_autotune')
 
-#: kernel classes of hweno_timing
-KERNEL_CLASSES = ('ghost', 'recon', 'rbar', 'grad', 'flux', 'update')
+#: kernel classes of hweno_timing ('batch' = a whole hweno_batch_run graph)
+KERNEL_CLASSES = ('ghost', 'recon', 'rbar', 'grad', 'flux', 'update', 'batch')
 
 
 class Grid(ctypes.Structure):
@@ -56,6 +57,14 @@ class Diag(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != 'pad'}
+
+
+class TilesC(ctypes.Structure):
+    _fields_ = [('recon', ctypes.c_int), ('grad', ctypes.c_int), ('flux', ctypes.c_int),
+                ('order', ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Timing(ctypes.Structure):
@@ -95,6 +104,16 @@ def lib():
         L.hweno_rk_step_vjp.argtypes = [vp, vp, ctypes.c_double, vp, vp, dp]
         L.hweno_set_timing.argtypes = [vp, ctypes.c_int]
         L.hweno_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int]
+        L.hweno_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Grid),
+                                         ctypes.POINTER(PhysicsC), ctypes.POINTER(Bcs),
+                                         ctypes.POINTER(OptionsC), ctypes.POINTER(vp)]
+        L.hweno_batch_set_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double]
+        L.hweno_batch_get_state.argtypes = [vp, ctypes.c_int, vp, dp]
+        L.hweno_batch_run.argtypes = [vp, ctypes.c_int]
+        L.hweno_batch_get_diag.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Diag)]
+        L.hweno_get_tiles.argtypes = [vp, ctypes.POINTER(TilesC)]
+        L.hweno_set_tiles.argtypes = [vp, ctypes.POINTER(TilesC)]
+        L.hweno_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(TilesC)]
         L.hweno_status_string.argtypes = [ctypes.c_int]
         L.hweno_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -234,6 +253,21 @@ class Solver:
     def set_timing(self, on=True):
         check(lib().hweno_set_timing(self._h, int(bool(on))))
 
+    def tiles(self):
+        t = TilesC()
+        check(lib().hweno_get_tiles(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tiles(self, recon=32, grad=32, flux=64, order=0):
+        t = TilesC(recon, grad, flux, order)
+        check(lib().hweno_set_tiles(self._h, ctypes.byref(t)))
+
+    def autotune(self, reps=3):
+        """Times the candidate tiles on the current state(s), keeps the fastest."""
+        t = TilesC()
+        check(lib().hweno_autotune(self._h, int(reps), ctypes.byref(t)))
+        return t.as_dict()
+
     def timing(self, reset=False):
         """{kernel class: (total ms, launches)} from the library's HIP events."""
         t = Timing()
@@ -250,3 +284,75 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Batch(Solver):
+    """Many independent 2D grids advanced together (hweno_batch_*).
+
+    ``problems`` is a list of dicts with the keyword arguments of Solver
+    (nx, ny, extent, gamma, Pr, mu_ref, mu_exp, T_ref, bc, inflow and option
+    overrides) for each instance.
+    """
+
+    def __init__(self, problems, device='cuda'):
+        import torch
+        n = len(problems)
+        grids, phys, bcs, opts = (Grid * n)(), (PhysicsC * n)(), (Bcs * n)(), (OptionsC * n)()
+        self.shapes = []
+        self.problems = [dict(p) for p in problems]
+        for k, pr in enumerate(self.problems):
+            pr = dict(pr)
+            nx, ny = pr.pop('nx'), pr.pop('ny')
+            extent = pr.pop('extent', (0.0, 1.0, 0.0, 1.0))
+            grids[k] = Grid(2, nx, ny, *[float(v) for v in extent])
+            phys[k] = PhysicsC(pr.pop('gamma', 1.4), pr.pop('Pr', 0.72), pr.pop('mu_ref', 0.01),
+                               pr.pop('mu_exp', 0.0), pr.pop('T_ref', 1.0))
+            kinds = pr.pop('bc', None) or ['periodic'] * 4
+            for s_, kd in enumerate(kinds):
+                bcs[k].kind[s_] = BC[kd] if isinstance(kd, str) else int(kd)
+            for s_, st in (pr.pop('inflow', None) or {}).items():
+                for q, v in enumerate(st):
+                    bcs[k].inflow[s_][q] = float(v)
+            opts[k] = default_options(**pr)
+            self.shapes.append((3, 4, ny, nx))
+        h = ctypes.c_void_p()
+        check(lib().hweno_batch_create(n, grids, phys, bcs, opts, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        nb = ctypes.c_size_t()
+        check(lib().hweno_workspace_bytes(h, ctypes.byref(nb)))
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        check(lib().hweno_set_workspace(h, _ptr(self.workspace), nb.value))
+        self.set_stream(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _chk(self, i, U):
+        import torch
+        if U.device != self.device or U.dtype != torch.float64 or not U.is_contiguous():
+            raise ValueError('expected a contiguous float64 tensor on %s' % self.device)
+        if tuple(U.shape) != self.shapes[i]:
+            raise ValueError('instance %d: shape %s, expected %s' % (i, tuple(U.shape), self.shapes[i]))
+        return U
+
+    def set_state(self, i, U, t=0.0):
+        check(lib().hweno_batch_set_state(self._h, int(i), _ptr(self._chk(i, U)), float(t)))
+
+    def get_state(self, i):
+        import torch
+        U = torch.empty(self.shapes[i], dtype=torch.float64, device=self.device)
+        t = ctypes.c_double()
+        check(lib().hweno_batch_get_state(self._h, int(i), _ptr(U), ctypes.byref(t)))
+        return U, t.value
+
+    def run(self, nsteps):
+        check(lib().hweno_batch_run(self._h, int(nsteps)))
+
+    def diag(self, i):
+        d = Diag()
+        check(lib().hweno_batch_get_diag(self._h, int(i), ctypes.byref(d)))
+        out = d.as_dict()
+        out['steps'] = d.pad
+        return out
