@@ -10,7 +10,16 @@ fill, characteristic HWENO reconstruction with the positivity limiter, weak
 derivative moments, gradient reconstruction, fluxes) plus the stage update.
 The state lives in HBM before the timed region starts.
 
-Prints one JSON line.  ``value`` = cell-stage updates per second.
+Prints one JSON line.  ``value`` = cell-stage updates per second of that
+grid.  Two more measurements ride along in the same line:
+
+* ``batched``: 64 periodic 2D grids (64^2..512^2, Re log-uniform in
+  [1e2, 1e4], random-phase Fourier velocity fields) advanced 100 steps each by
+  one graph launch, against the same 64 problems run one after another through
+  the single-grid path;
+* ``adjoint``: the double shear layer on 256^2 (Re 1000), 200 steps with dt
+  frozen, forward plus checkpointed backward (every 20 steps) against the
+  plain forward.
 """
 
 import argparse
@@ -54,6 +63,10 @@ FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400}
 ALGO_BYTES_PER_CELL_STAGE = 277.0
 
 
+def log(msg):
+    print('[bench] ' + msg, file=sys.stderr, flush=True)
+
+
 def units_per_launch(kind):
     if kind == 'recon':
         return (NX + 6) * (NY + 6)
@@ -90,6 +103,90 @@ def cpu_baseline(rows=64):
                       % (NX, rows, j0, j0 + rows - 1, el)}
 
 
+def bench_batched(nsteps, sequential=True):
+    """64 instances in one graph launch vs one after another (plain path)."""
+    import torch
+    from paper_2608_10569_amd import hweno, workloads
+    inst = workloads.batched_periodic_2d()
+    probs = [dict(nx=n, ny=n, mu_ref=1.0 / Re) for n, Re, _ in inst]
+    cells = sum(n * n for n, _, _ in inst)
+    states = [torch.from_numpy(U).cuda() for _, _, U in inst]
+    b = hweno.Batch(probs)
+    for i, U in enumerate(states):
+        b.set_state(i, U)
+    tiles = b.autotune(reps=3)
+    b.run(nsteps)                       # records and instantiates the graph
+    for i, U in enumerate(states):      # timed run from the initial states
+        b.set_state(i, U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(nsteps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {'workload': '64 periodic 2D grids from {64,128,256,512}^2, Re log-uniform [1e2,1e4], '
+                       '8 random-phase Fourier modes amplitude 0.3, %d SSP-RK3 steps each, one graph '
+                       'launch' % nsteps,
+           'instances': len(inst), 'cells': cells, 'steps': nsteps, 'seconds': el,
+           'value': cells * 3 * nsteps / el, 'unit': UNIT, 'tiles': tiles,
+           'restarts': sum(b.diag(i)['restarts'] for i in range(len(inst)))}
+    del b
+    torch.cuda.empty_cache()
+    if sequential:
+        el2 = 0.0
+        for (n, Re, _), U in zip(inst, states):
+            s = hweno.Solver(n, n, mu_ref=1.0 / Re)
+            s.set_state(U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                s.rk_step(0.0)
+            torch.cuda.synchronize()
+            el2 += time.perf_counter() - t0
+            s.close()
+        out['sequential_seconds'] = el2
+        out['sequential_value'] = cells * 3 * nsteps / el2
+        out['speedup_vs_sequential'] = el2 / el
+    return out
+
+
+def bench_adjoint(nsteps=200, every=20):
+    """Double shear layer: forward + checkpointed backward vs plain forward."""
+    import numpy as np
+    import torch
+    from paper_2608_10569_amd import adjoint, hweno
+    n, mu, gamma = 256, 1e-3, 1.4
+    f = adjoint.shear_layer_fields(n)
+    rho, u, v = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f[:3]]
+    s = hweno.Solver(n, n, mu_ref=mu)
+    U0 = adjoint.project_fields(rho, u, v, f[3], gamma)
+    s.set_state(U0)
+    dt = s.rk_step(0.0)['dt']
+    # plain forward: the same fixed-step steps through rk_step
+    s.set_state(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        s.rk_step(dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    r = rho.clone().requires_grad_(True)
+    m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = adjoint.kinetic_energy(adjoint.rollout(s, adjoint.project_fields(r, u, v, f[3], gamma), m,
+                                               dt, nsteps, every), s.dx, s.dy)
+    J.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    cs = n * n * 3 * nsteps
+    return {'workload': 'double shear layer 256^2, Re 1000, %d steps with dt frozen, checkpoints '
+                        'every %d; d KE / d (rho, u, v node fields, mu)' % (nsteps, every),
+            'forward_seconds': t_fwd, 'forward_backward_seconds': t_all,
+            'ratio_to_forward': t_all / t_fwd, 'forward_value': cs / t_fwd,
+            'value': cs / t_all, 'unit': UNIT + ' (forward-equivalent, with gradient)',
+            'J': J.item(), 'dJ_dmu': m.grad.item()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument('--gpus', type=int, default=1)
@@ -97,6 +194,11 @@ def main():
     ap.add_argument('--warmup', type=int, default=10)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-rows', type=int, default=192)
+    ap.add_argument('--batch-steps', type=int, default=100)
+    ap.add_argument('--no-batched', action='store_true')
+    ap.add_argument('--no-sequential', action='store_true')
+    ap.add_argument('--no-adjoint', action='store_true')
+    ap.add_argument('--no-autotune', action='store_true')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py measures one GPU only: this build has no multi-GPU path '
@@ -112,6 +214,7 @@ def main():
     U0 = torch.from_numpy(workloads.viscous_shock_tube_2d(NX, NY)).to(dev)
     s = hweno.Solver(NX, NY, extent=EXTENT, bc=BCS, device=dev, cfl=0.3, t_final=1.0, **PHYS)
     s.set_state(U0)
+    tiles = s.tiles() if args.no_autotune else s.autotune(reps=3)
     for _ in range(args.warmup):
         s.rk_step(0.0)
     torch.cuda.synchronize()
@@ -150,7 +253,7 @@ def main():
         'config': {'workload': '2D viscous shock tube 1000x500, Re=200, Pr=0.73, no-slip walls + '
                                'symmetry top, SSP-RK3 CFL 0.3 from t=0, paper dt rule',
                    'cells': NX * NY, 'stages_per_step': 3, 't_end': t_end,
-                   'restarts': restarts, 'pp_cell_stages': pp},
+                   'restarts': restarts, 'pp_cell_stages': pp, 'tiles': tiles},
         'roofline': {'bound': 'alu', 'kernel': dom, 'achieved': achieved,
                      'peak': PEAK_FP64_TFLOPS, 'unit': 'TFLOP/s',
                      'frac': achieved / PEAK_FP64_TFLOPS, 'traffic': None,
@@ -160,8 +263,19 @@ def main():
         'path_fp64_tflops_algorithmic': value * path_flops / 1e12,
         'kernels': kern,
     }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    log('single grid: %.3e %s, %.3f ms/step' % (value, UNIT, 1e3 * el / args.steps))
+    if not args.no_batched:
+        out['batched'] = bench_batched(args.batch_steps, sequential=not args.no_sequential)
+        log('batched: %.3e %s' % (out['batched']['value'], UNIT))
+    if not args.no_adjoint:
+        out['adjoint'] = bench_adjoint()
+        log('adjoint: forward+backward / forward = %.2f' % out['adjoint']['ratio_to_forward'])
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(args.cpu_rows)
+        log('cpu baseline: %.3e %s' % (out['cpu_baseline']['value'], UNIT))
     print(json.dumps(out), flush=True)
 
 

@@ -130,16 +130,17 @@ __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N,
 
 __global__ void k_ghost2_x(Batch bt, int sidx) {
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
-    double* S = g.S[sidx];
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    double* S = gsrc.S[sidx];
     const int t = lc.b * blockDim.x + threadIdx.x;
     if (t >= g.ny * 2 * HALO) return;
     const int j = HALO + t / (2 * HALO);
     const int gi = t % (2 * HALO);
     const int right = gi >= HALO;
     const int d = (gi % HALO) + 1;                      // distance from the boundary
-    const Side& sd = g.side[right];
+    const Side& sd = gsrc.side[right];
     int di, si;
     if (!right) {
         di = HALO - d;
@@ -154,16 +155,17 @@ __global__ void k_ghost2_x(Batch bt, int sidx) {
 
 __global__ void k_ghost2_y(Batch bt, int sidx) {
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
-    double* S = g.S[sidx];
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    double* S = gsrc.S[sidx];
     const int t = lc.b * blockDim.x + threadIdx.x;
     if (t >= g.NX * 2 * HALO) return;
     const int i = t % g.NX;
     const int gj = t / g.NX;
     const int top = gj >= HALO;
     const int d = (gj % HALO) + 1;
-    const Side& sd = g.side[2 + top];
+    const Side& sd = gsrc.side[2 + top];
     int dj, sj;
     if (!top) {
         dj = HALO - d;
@@ -187,9 +189,10 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     __shared__ double redA[8 * RC_CELLS];
     __shared__ double redB[8 * RC_CELLS];
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
-    const double* __restrict__ S = g.S[si];
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const double* __restrict__ S = gsrc.S[si];
     const Consts& K = g.K;
     const int tid = threadIdx.x;
     const int cl = tid & (RC_CELLS - 1);
@@ -370,8 +373,9 @@ __device__ __forceinline__ void prim3(const double* F, long long N, long long ce
 
 __global__ __launch_bounds__(256) void k_rbar2(Batch bt) {
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
     const int wc = g.NX - 4;
     const long long nreg = (long long)wc * (g.NY - 4);
     const long long cid = (long long)lc.b * blockDim.x + threadIdx.x;
@@ -434,8 +438,9 @@ template <int GR_CELLS>
 __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     __shared__ double shv[6 * 9 * GR_CELLS];
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
     const Consts& K = g.K;
     const int tid = threadIdx.x;
     const int cl = tid % GR_CELLS;
@@ -514,8 +519,9 @@ template <int d, int FX_FACES>   // block = 3 Gauss points x FX_FACES faces
 __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __shared__ double shb[3 * FX_FACES];
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
     const Consts& K = g.K;
     const int nfi = d == 0 ? g.nx + 1 : g.nx;
     const int nfj = d == 0 ? g.ny : g.ny + 1;
@@ -575,11 +581,12 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
                                                  double* __restrict__ Rout,
                                                  double* __restrict__ Vout) {
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
-    const double* __restrict__ S0 = g.S[i0];
-    const double* __restrict__ Sin = g.S[iin];
-    double* __restrict__ Sout = g.S[iout];
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const double* __restrict__ S0 = gsrc.S[i0];
+    const double* __restrict__ Sin = gsrc.S[iin];
+    double* __restrict__ Sout = gsrc.S[iout];
     const long long nint = (long long)g.nx * g.ny;
     const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     double rmin = INFINITY, pmin = INFINITY;
@@ -682,9 +689,10 @@ __global__ void k_copy_out2(Grid2 g, const double* __restrict__ S, double* __res
 // Input admissibility (finite values, positive density and pressure).
 __global__ __launch_bounds__(256) void k_check2(Batch bt, int si) {
     const Loc lc = locate(bt);
-    const Grid2 g = bt.g[lc.p];
-    if (!g.st->active) return;
-    const double* __restrict__ S = g.S[si];
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const double* __restrict__ S = gsrc.S[si];
     const long long nint = (long long)g.nx * g.ny;
     const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     unsigned int bad = 0;
