@@ -199,6 +199,9 @@ def main():
     ap.add_argument('--no-sequential', action='store_true')
     ap.add_argument('--no-adjoint', action='store_true')
     ap.add_argument('--no-autotune', action='store_true')
+    ap.add_argument('--calib-copy-mib', type=int, default=0,
+                    help='first run one device-to-device copy of this many MiB (a plain copy '
+                         'kernel of known size, for calibrating HBM byte counters)')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py measures one GPU only: this build has no multi-GPU path '
@@ -211,6 +214,15 @@ def main():
 
     dev = torch.device('cuda:0')
     torch.cuda.set_device(dev)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log('calibration copy: %d bytes read, %d bytes written' % (8 * n, 8 * n))
+        del src, dst
     U0 = torch.from_numpy(workloads.viscous_shock_tube_2d(NX, NY)).to(dev)
     s = hweno.Solver(NX, NY, extent=EXTENT, bc=BCS, device=dev, cfl=0.3, t_final=1.0, **PHYS)
     s.set_state(U0)

@@ -255,6 +255,8 @@ typedef struct hweno_tiles {
     int grad;       /* cells per block of the gradient reconstruction: 32 or 64 */
     int flux;       /* faces per block of the face fluxes: 64 or 128 */
     int order;      /* batch schedule: 0 instances as given, 1 largest first */
+    int xcd;        /* 1: each of the 8 XCDs (own L2) takes a contiguous range of a
+                       launch's blocks, so neighbouring rows share an L2; 0: launch order */
 } hweno_tiles;
 
 /* 2D contexts (single grid or batch).  Results do not depend on the tiles. */

@@ -93,13 +93,24 @@ __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
     }
 }
 
+// The hardware hands a launch's blocks to the 8 XCDs round-robin, and each
+// XCD has its own L2.  With xcd set, XCD x takes the contiguous range x of the
+// logical blocks, so blocks of neighbouring rows (which share stencil rows)
+// run on the same XCD.  A bijection of [0, nb).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int x = b % NUM_XCD, k = b / NUM_XCD;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // Slot of the instance that owns this block and the block's index within it
 // (uniform per block: binary search of the launch's block prefix table).
 struct Loc {
     int p, b;
 };
 __device__ __forceinline__ Loc locate(const Batch& B) {
-    const int bid = (int)blockIdx.x;
+    const int bid = B.xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     int lo = 0, hi = B.n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -485,28 +496,40 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * GR_CELLS + cl] = vo[q];
     __syncthreads();
-    if (inter && s < 2) {
-        const double* V = s == 0 ? g.xv : g.yv;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // volume-flux quadratures of interior cells: 2 directions x 9 points over
+    // the cell's 6 threads, 3 points each (thread s: direction s / 3, points
+    // 3 (s % 3) .. 3 (s % 3) + 2); partial sums meet in LDS
+    const bool dy = s >= 3;
+    const int q0 = 3 * (s % 3);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (inter) {
+        const double* V = dy ? g.yv : g.xv;
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
+        for (int qq = 0; qq < 3; ++qq) {
+            const int q = q0 + qq;
+            const double wq = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
+            double Uq[4], sq[6], f[4];
 #pragma unroll
-            for (int gg = 0; gg < 3; ++gg) {
-                const int q = 3 * h + gg;
-                const double wq = (h == 1 ? GW1 : GW0) * (gg == 1 ? GW1 : GW0);
-                double Uq[4], sq[6], f[4];
+            for (int c = 0; c < 4; ++c) Uq[c] = V[(q * 4 + c) * N + cell];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) Uq[c] = V[(q * 4 + c) * N + cell];
+            for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
+            flux2_dir(K, Uq, sq, dy, f);
 #pragma unroll
-                for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
-                if (s == 0) flux2<0>(K, Uq, sq, f);
-                else flux2<1>(K, Uq, sq, f);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
-            }
+            for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
         }
+    }
+    __syncthreads();   // every read of the gradient values is done
 #pragma unroll
-        for (int c = 0; c < 4; ++c) g.vf[(s * 4 + c) * N + cell] = acc[c];
+    for (int c = 0; c < 4; ++c) shv[(s * 4 + c) * GR_CELLS + cl] = acc[c];
+    __syncthreads();
+    if (inter && s < 2) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double t0 = shv[((3 * s + 0) * 4 + c) * GR_CELLS + cl];
+            const double t1 = shv[((3 * s + 1) * 4 + c) * GR_CELLS + cl];
+            const double t2 = shv[((3 * s + 2) * 4 + c) * GR_CELLS + cl];
+            g.vf[(s * 4 + c) * N + cell] = t0 + t1 + t2;
+        }
     }
 }
 

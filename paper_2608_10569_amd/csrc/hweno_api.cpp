@@ -817,17 +817,20 @@ HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
     t->grad = c->tiles.grad;
     t->flux = c->tiles.flux;
     t->order = c->order_mode;
+    t->xcd = c->tiles.xcd;
     return HWENO_OK;
 }
 
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
     if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
     if ((t->recon != 16 && t->recon != 32) || (t->grad != 32 && t->grad != 64) ||
-        (t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1))
+        (t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1) ||
+        (t->xcd != 0 && t->xcd != 1))
         return HWENO_E_INVAL;
     c->tiles.recon = t->recon;
     c->tiles.grad = t->grad;
     c->tiles.flux = t->flux;
+    c->tiles.xcd = t->xcd;
     c->order_mode = t->order;
     if (!c->ws) return HWENO_OK;
     return upload_grids(c);
@@ -872,7 +875,7 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         c->timer.reset();
         return HWENO_OK;
     };
-    const hw::Tiles cand[2] = {{16, 32, 64}, {32, 64, 128}};
+    const hw::Tiles cand[2] = {{16, 32, 64, 1}, {32, 64, 128, 1}};
     double ms[2][hw::KC_COUNT];
     for (int q = 0; q < 2; ++q) {
         c->tiles = cand[q];
@@ -884,6 +887,19 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
     best.grad = ms[0][hw::KC_GRAD] <= ms[1][hw::KC_GRAD] ? cand[0].grad : cand[1].grad;
     best.flux = ms[0][hw::KC_FLUX] <= ms[1][hw::KC_FLUX] ? cand[0].flux : cand[1].flux;
     c->tiles = best;
+    {
+        // block order: XCD-aware or as launched
+        double tot[2];
+        for (int x = 0; x < 2; ++x) {
+            c->tiles.xcd = x;
+            TRY(upload_grids(c));
+            double m[hw::KC_COUNT];
+            TRY(measure(m));
+            tot[x] = 0.0;
+            for (int k = 0; k < hw::KC_COUNT; ++k) tot[x] += m[k];
+        }
+        c->tiles.xcd = tot[1] <= tot[0] ? 1 : 0;
+    }
     if (c->batch && c->in.size() > 1) {
         // schedule order: as given vs largest instance first
         double tot[2];

@@ -324,6 +324,27 @@ __device__ __forceinline__ void flux2(const Consts& K, const double* U, const do
     }
 }
 
+// The same flux with the direction a run-time value (dy: g instead of f);
+// selects instead of branches, so lanes of one wave may take different
+// directions without diverging.
+__device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, const double* s,
+                                          bool dy, double* f) {
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double u = m / r, v = n / r;
+    const double p = pressure2(K, r, m, n, E);
+    const double mu = viscosity(K, r, p);
+    const Stress t = stresses(mu, s);
+    const double kq = K.gamma * mu / K.Pr;
+    const double un = dy ? v : u;           // velocity along the direction
+    const double tnx = dy ? t.xy : t.xx;    // stress (x, direction)
+    const double tny = dy ? t.yy : t.xy;    // stress (y, direction)
+    const double qd = dy ? s[5] : s[4];
+    f[0] = dy ? n : m;
+    f[1] = m * un + (dy ? 0.0 : p) - tnx;
+    f[2] = n * un + (dy ? p : 0.0) - tny;
+    f[3] = (E + p) * un - (tnx * u + tny * v + kq * qd);
+}
+
 // PP wave-speed bound of eq. (3.3) in direction d, no smaller than |u_d| + c.
 template <int d>
 __device__ __forceinline__ double speed2(const Consts& K, const double* U, const double* s) {

@@ -152,6 +152,7 @@ struct Batch {
     const Grid2* g;
     const int* start;
     int n;
+    int xcd;          // 1: XCD-aware order of the launch's blocks
 };
 
 // Work per block of the tunable kernels (cells, cells, faces).
@@ -159,6 +160,7 @@ struct Tiles {
     int recon = 32;   // 16 or 32
     int grad = 32;    // 32 or 64
     int flux = 64;    // 64 or 128
+    int xcd = 1;      // 1: each XCD takes a contiguous range of a launch's blocks
 };
 
 struct BatchL {
@@ -167,7 +169,7 @@ struct BatchL {
     const int* hstart = nullptr;   // host copy of dstart
     int n = 0;
     Tiles tiles;
-    Batch arg(int k) const { return Batch{dg, dstart + k * (n + 1), n}; }
+    Batch arg(int k) const { return Batch{dg, dstart + k * (n + 1), n, tiles.xcd}; }
     unsigned blocks(int k) const { return (unsigned)hstart[k * (n + 1) + n]; }
 };
 

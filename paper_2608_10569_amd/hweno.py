@@ -61,7 +61,7 @@ class Diag(ctypes.Structure):
 
 class TilesC(ctypes.Structure):
     _fields_ = [('recon', ctypes.c_int), ('grad', ctypes.c_int), ('flux', ctypes.c_int),
-                ('order', ctypes.c_int)]
+                ('order', ctypes.c_int), ('xcd', ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -258,8 +258,8 @@ class Solver:
         check(lib().hweno_get_tiles(self._h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tiles(self, recon=32, grad=32, flux=64, order=0):
-        t = TilesC(recon, grad, flux, order)
+    def set_tiles(self, recon=32, grad=32, flux=64, order=0, xcd=1):
+        t = TilesC(recon, grad, flux, order, xcd)
         check(lib().hweno_set_tiles(self._h, ctypes.byref(t)))
 
     def autotune(self, reps=3):
