@@ -196,7 +196,13 @@ __global__ void k_ghost2_y(Batch bt, int sidx) {
 // ---------------------------------------------------------------------------
 template <int RC_CELLS>
 __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
-    __shared__ double sh[8 * 16 * RC_CELLS];
+    // one block = RC_CELLS consecutive cells of one row; the 3-row stencil
+    // tile of all 12 fields is staged in LDS first, then the same memory holds
+    // the exchange of the 16 outputs of every (basis, field) thread
+    constexpr int TW = RC_CELLS + 2;                 // tile width (columns)
+    constexpr int TILE = 12 * 3 * TW;
+    constexpr int SH = 8 * 16 * RC_CELLS;
+    __shared__ double sh[SH > TILE ? SH : TILE];
     __shared__ double redA[8 * RC_CELLS];
     __shared__ double redB[8 * RC_CELLS];
     const Loc lc = locate(bt);
@@ -209,46 +215,53 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     const int cl = tid & (RC_CELLS - 1);
     const int bk = tid / RC_CELLS;
     const int b = bk >> 2, k = bk & 3;
-    const int wc = g.NX - 2;
-    const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)lc.b * RC_CELLS + cl;
-    const bool valid = cid < nreg;
-    int j = 1, i = 1;
-    if (valid) {
-        j = 1 + (int)(cid / wc);
-        i = 1 + (int)(cid % wc);
-    }
+    // region: rows 1..NY-2, columns 1..NX-2, in row segments of RC_CELLS
+    const int segs = (g.NX - 2 + RC_CELLS - 1) / RC_CELLS;
+    const int j = 1 + lc.b / segs;
+    const int i0 = 1 + (lc.b % segs) * RC_CELLS;
+    const int i = i0 + cl;
+    const bool valid = i <= g.NX - 2;
     const long long N = g.ncell;
     const long long cell = (long long)j * g.NX + i;
+    // stencil tile: rows j-1..j+1, columns i0-1..i0+RC_CELLS (clamped to the grid)
+    for (int t = tid; t < TILE; t += 8 * RC_CELLS) {
+        const int c = t / (3 * TW), rem = t % (3 * TW);
+        const int r = rem / TW, col = rem % TW;
+        const int gi = min(i0 - 1 + col, g.NX - 1);
+        sh[t] = S[c * N + (long long)(j - 1 + r) * g.NX + gi];
+    }
+    __syncthreads();
+    auto T = [&](int c, int oy, int ox) -> double {
+        return sh[(c * 3 + 1 + oy) * TW + cl + 1 + ox];
+    };
 
     double ub[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ub[c] = S[c * N + cell];
+    for (int c = 0; c < 4; ++c) ub[c] = T(c, 0, 0);
     double Lr[4], Rr[4];
     eig2_rows(K, ub, b, k, Lr, Rr);
 
     double a[17];
 #pragma unroll
     for (int s = 0; s < 9; ++s) {
-        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc += Lr[c] * S[c * N + nb];
+        for (int c = 0; c < 4; ++c) acc += Lr[c] * T(c, s / 3 - 1, s % 3 - 1);
         a[s] = acc;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int s = 2 * e + 1;   // cells 2, 4, 6, 8
-        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
         double ax = 0.0, ay = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            ax += Lr[c] * S[(4 + c) * N + nb];
-            ay += Lr[c] * S[(8 + c) * N + nb];
+            ax += Lr[c] * T(4 + c, s / 3 - 1, s % 3 - 1);
+            ay += Lr[c] * T(8 + c, s / 3 - 1, s % 3 - 1);
         }
         a[9 + e] = ax;
         a[13 + e] = ay;
     }
+    __syncthreads();   // the tile is dead; sh holds the output exchange from here
     double C[15];
     hweno2d(a, K, C);
     double out[16];
@@ -871,7 +884,10 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
             switch (k) {
                 case KB_GHOSTX: work = (long long)g.ny * 2 * HALO; break;
                 case KB_GHOSTY: work = (long long)g.NX * 2 * HALO; break;
-                case KB_RECON: work = (long long)(g.NX - 2) * (g.NY - 2); per = t.recon; break;
+                case KB_RECON:   // row segments of t.recon cells
+                    work = (long long)(g.NY - 2) * ((g.NX - 2 + t.recon - 1) / t.recon);
+                    per = 1;
+                    break;
                 case KB_RBAR: work = (long long)(g.NX - 4) * (g.NY - 4); break;
                 case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
                 case KB_FLUX0: work = (long long)(g.nx + 1) * g.ny; per = t.flux; break;
