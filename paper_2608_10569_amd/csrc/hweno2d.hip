@@ -371,9 +371,10 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
                 const double ut = c == 0 ? rbar + th1 * (x - rbar) : x;
                 Ul[c] = ub[c] + th2 * (ut - ub[c]);
             }
-            const double p = pressure2(K, Ul[0], Ul[1], Ul[2], Ul[3]);
-            const double cs = sqrt(K.gamma * p / Ul[0]);
-            const double sp = fmax(fabs(Ul[1] / Ul[0]), fabs(Ul[2] / Ul[0])) + cs;
+            const double ir = 1.0 / Ul[0];
+            const double u = Ul[1] * ir, v = Ul[2] * ir;
+            const double p = K.gm1 * (Ul[3] - 0.5 * (Ul[1] * u + Ul[2] * v));
+            const double sp = fmax(fabs(u), fabs(v)) + sqrt(K.gamma * p * ir);
             amax = fmax(amax, sp);
         }
     }
@@ -385,71 +386,68 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
 // ---------------------------------------------------------------------------
 // Weak-derivative moments (eqs. (3.6)-(3.8)) on cells of halo ring 2.
 // ---------------------------------------------------------------------------
+// Primitives (u, v, e) of face point p of `cell` (one reciprocal of rho).
 __device__ __forceinline__ void prim3(const double* F, long long N, long long cell, int p,
                                       double* w) {
     const double r = F[(p * 4 + 0) * N + cell];
-    const double u = F[(p * 4 + 1) * N + cell] / r;
-    const double v = F[(p * 4 + 2) * N + cell] / r;
+    const double ir = 1.0 / r;
+    const double u = F[(p * 4 + 1) * N + cell] * ir;
+    const double v = F[(p * 4 + 2) * N + cell] * ir;
     w[0] = u;
     w[1] = v;
-    w[2] = F[(p * 4 + 3) * N + cell] / r - 0.5 * (u * u + v * v);
+    w[2] = F[(p * 4 + 3) * N + cell] * ir - 0.5 * (u * u + v * v);
 }
 
-__global__ __launch_bounds__(256) void k_rbar2(Batch bt) {
+// One thread per (cell, direction l): block = RB_CELLS cells x 2 directions,
+// the direction uniform per wavefront.  Direction l averages the traces of the
+// cell's two l-faces (interface averages) and forms the three weak moments of
+// d w / d x_l (w = u, v, e).
+constexpr int RB_CELLS = 128;
+
+__global__ __launch_bounds__(2 * RB_CELLS) void k_rbar2(Batch bt) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
     const Grid2 g = gsrc;
+    const int l = threadIdx.x / RB_CELLS;
     const int wc = g.NX - 4;
     const long long nreg = (long long)wc * (g.NY - 4);
-    const long long cid = (long long)lc.b * blockDim.x + threadIdx.x;
+    const long long cid = (long long)lc.b * RB_CELLS + threadIdx.x % RB_CELLS;
     if (cid >= nreg) return;
     const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
     const long long N = g.ncell;
     const long long cell = (long long)j * g.NX + i;
-    const long long L = cell - 1, Rt = cell + 1, B = cell - g.NX, T = cell + g.NX;
-    double hl[3][3], hr[3][3], hb[3][3], ht[3][3];   // [G][w]
+    const double* F = l ? g.yf : g.xf;
+    const long long off = l ? (long long)g.NX : 1;
+    const long long lo = cell - off, hi = cell + off;
+    double hlo[3][3], hhi[3][3];   // [G][w] interface averages of the low / high face
 #pragma unroll
     for (int G = 0; G < 3; ++G) {
         double a[3], c[3];
-        prim3(g.xf, N, L, 3 + G, a);
-        prim3(g.xf, N, cell, G, c);
+        prim3(F, N, lo, 3 + G, a);
+        prim3(F, N, cell, G, c);
 #pragma unroll
-        for (int w = 0; w < 3; ++w) hl[G][w] = 0.5 * (a[w] + c[w]);
-        prim3(g.xf, N, cell, 3 + G, a);
-        prim3(g.xf, N, Rt, G, c);
+        for (int w = 0; w < 3; ++w) hlo[G][w] = 0.5 * (a[w] + c[w]);
+        prim3(F, N, cell, 3 + G, a);
+        prim3(F, N, hi, G, c);
 #pragma unroll
-        for (int w = 0; w < 3; ++w) hr[G][w] = 0.5 * (a[w] + c[w]);
-        prim3(g.yf, N, B, 3 + G, a);
-        prim3(g.yf, N, cell, G, c);
-#pragma unroll
-        for (int w = 0; w < 3; ++w) hb[G][w] = 0.5 * (a[w] + c[w]);
-        prim3(g.yf, N, cell, 3 + G, a);
-        prim3(g.yf, N, T, G, c);
-#pragma unroll
-        for (int w = 0; w < 3; ++w) ht[G][w] = 0.5 * (a[w] + c[w]);
+        for (int w = 0; w < 3; ++w) hhi[G][w] = 0.5 * (a[w] + c[w]);
     }
-    const double idx = g.K.idx, idy = g.K.idy;
+    const double ih = l ? g.K.idy : g.K.idx;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-        const double Wl0 = GW0 * hl[0][w] + GW1 * hl[1][w] + GW0 * hl[2][w];
-        const double Wr0 = GW0 * hr[0][w] + GW1 * hr[1][w] + GW0 * hr[2][w];
-        const double Wl1 = GW0 * GS * (hl[2][w] - hl[0][w]);
-        const double Wr1 = GW0 * GS * (hr[2][w] - hr[0][w]);
-        const double Wb0 = GW0 * hb[0][w] + GW1 * hb[1][w] + GW0 * hb[2][w];
-        const double Wt0 = GW0 * ht[0][w] + GW1 * ht[1][w] + GW0 * ht[2][w];
-        const double Wb1 = GW0 * GS * (hb[2][w] - hb[0][w]);
-        const double Wt1 = GW0 * GS * (ht[2][w] - ht[0][w]);
-        const double wbx = g.wb[(0 * 3 + w) * N + cell];
-        const double wby = g.wb[(1 * 3 + w) * N + cell];
-        // l = 0 (x): moments 0, xi, eta
-        g.rb[((0 * 3 + w) * 3 + 0) * N + cell] = (Wr0 - Wl0) * idx;
-        g.rb[((0 * 3 + w) * 3 + 1) * N + cell] = (0.5 * (Wr0 + Wl0) - wbx) * idx;
-        g.rb[((0 * 3 + w) * 3 + 2) * N + cell] = (Wr1 - Wl1) * idx;
-        // l = 1 (y)
-        g.rb[((1 * 3 + w) * 3 + 0) * N + cell] = (Wt0 - Wb0) * idy;
-        g.rb[((1 * 3 + w) * 3 + 1) * N + cell] = (Wt1 - Wb1) * idy;
-        g.rb[((1 * 3 + w) * 3 + 2) * N + cell] = (0.5 * (Wt0 + Wb0) - wby) * idy;
+        const double W0lo = GW0 * hlo[0][w] + GW1 * hlo[1][w] + GW0 * hlo[2][w];
+        const double W0hi = GW0 * hhi[0][w] + GW1 * hhi[1][w] + GW0 * hhi[2][w];
+        const double W1lo = GW0 * GS * (hlo[2][w] - hlo[0][w]);
+        const double W1hi = GW0 * GS * (hhi[2][w] - hhi[0][w]);
+        const double wbl = g.wb[(l * 3 + w) * N + cell];
+        const double d0 = (W0hi - W0lo) * ih;                    // moment 0
+        const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
+        const double d1 = (W1hi - W1lo) * ih;                    // transverse moment
+        double* R = g.rb + ((l * 3 + w) * 3) * N + cell;
+        R[0] = d0;
+        R[N] = l ? d1 : dm;       // xi moment
+        R[2 * N] = l ? dm : d1;   // eta moment
     }
 }
 
@@ -888,7 +886,7 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                     work = (long long)(g.NY - 2) * ((g.NX - 2 + t.recon - 1) / t.recon);
                     per = 1;
                     break;
-                case KB_RBAR: work = (long long)(g.NX - 4) * (g.NY - 4); break;
+                case KB_RBAR: work = (long long)(g.NX - 4) * (g.NY - 4); per = RB_CELLS; break;
                 case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
                 case KB_FLUX0: work = (long long)(g.nx + 1) * g.ny; per = t.flux; break;
                 case KB_FLUX1: work = (long long)g.nx * (g.ny + 1); per = t.flux; break;
@@ -930,7 +928,7 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
     else k_recon2<32><<<b.blocks(KB_RECON), 256, 0, st>>>(b.arg(KB_RECON), si);
     tend(tm, st);
     tbeg(tm, KC_RBAR, st);
-    k_rbar2<<<b.blocks(KB_RBAR), 256, 0, st>>>(b.arg(KB_RBAR));
+    k_rbar2<<<b.blocks(KB_RBAR), 2 * RB_CELLS, 0, st>>>(b.arg(KB_RBAR));
     tend(tm, st);
     tbeg(tm, KC_GRAD, st);
     if (b.tiles.grad == 64) k_grad2<64><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
