@@ -317,10 +317,16 @@ __device__ __forceinline__ bool in_ring2(const Grid2& g, int j, int i) {
     return j >= 2 && j <= g.NY - 3 && i >= 2 && i <= g.NX - 3;
 }
 
-__global__ void k_adj_wmom(Grid2 g, AdjWs W) {
+// Six independent tasks per cell, one per wavefront of the block: tasks 0..3
+// the four faces (left, right, bottom, top), tasks 4..5 the volume values of
+// the x and y bases.  Every task owns the cotangent slots it adds to.
+constexpr int WM_CELLS = 64;
+
+__global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
+    const int task = threadIdx.x / WM_CELLS;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cid = (long long)blockIdx.x * WM_CELLS + threadIdx.x % WM_CELLS;
     if (cid >= nreg) return;
     const int j = 1 + (int)(cid / wc), i = 1 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -330,10 +336,10 @@ __global__ void k_adj_wmom(Grid2 g, AdjWs W) {
         if (!in_ring2(g, jj, ii)) return 0.0;
         return W.rbb[((l * 3 + w) * 3 + mom) * N + (long long)jj * g.NX + ii];
     };
-    // face adjoints W0-bar, W1-bar per w for the four faces of this cell
-    for (int face = 0; face < 4; ++face) {
-        // face 0: left (x, this cell is the plus side), 1: right (minus side),
-        // 2: bottom (y, plus side), 3: top (minus side)
+    if (task < 4) {
+        // face `task`: 0 left (x, this cell is the plus side), 1 right (minus
+        // side), 2 bottom (y, plus side), 3 top (minus side)
+        const int face = task;
         const int dir = face >> 1;
         const bool hi = face & 1;
         const int oj = dir == 1 ? (hi ? 1 : -1) : 0, oi = dir == 0 ? (hi ? 1 : -1) : 0;
@@ -370,27 +376,25 @@ __global__ void k_adj_wmom(Grid2 g, AdjWs W) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) FB[(p * 4 + c) * N + cell] += Ub[c];
         }
-    }
-    // wbar adjoints (this cell's own weak moments), to the volume values
-    if (in_ring2(g, j, i)) {
-        for (int dir = 0; dir < 2; ++dir) {
-            const double* V = dir == 0 ? g.xv : g.yv;
-            double* VB = dir == 0 ? W.xvb : W.yvb;
-            double wbb[3];
+    } else if (in_ring2(g, j, i)) {
+        // wbar adjoint of this cell's own weak moments, to its volume values
+        const int dir = task - 4;
+        const double* V = dir == 0 ? g.xv : g.yv;
+        double* VB = dir == 0 ? W.xvb : W.yvb;
+        double wbb[3];
 #pragma unroll
-            for (int w = 0; w < 3; ++w)
-                wbb[w] = -RB(j, i, dir, w, dir == 0 ? 1 : 2) * (dir == 0 ? idx : idy);
-            for (int q = 0; q < 9; ++q) {
-                const double wq = gw(q / 3) * gw(q % 3);
-                double U[4], wb[3], Ub[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < 3; ++w)
+            wbb[w] = -RB(j, i, dir, w, dir == 0 ? 1 : 2) * (dir == 0 ? idx : idy);
+        for (int q = 0; q < 9; ++q) {
+            const double wq = gw(q / 3) * gw(q % 3);
+            double U[4], wb[3], Ub[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < 4; ++c) U[c] = V[(q * 4 + c) * N + cell];
+            for (int c = 0; c < 4; ++c) U[c] = V[(q * 4 + c) * N + cell];
 #pragma unroll
-                for (int w = 0; w < 3; ++w) wb[w] = wq * wbb[w];
-                adj::prim2_vjp(U, wb, Ub);
+            for (int w = 0; w < 3; ++w) wb[w] = wq * wbb[w];
+            adj::prim2_vjp(U, wb, Ub);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] += Ub[c];
-            }
+            for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] += Ub[c];
         }
     }
 }
@@ -858,7 +862,7 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     k_adj_flux<1><<<by, 3 * AF, 0, st>>>(g, A, W);
     k_adj_grad<<<bg, 6 * AG, 0, st>>>(g, A, W);
     k_adj_rgather<<<nb2((long long)(g.NX - 4) * (g.NY - 4), 256), 256, 0, st>>>(g, W);
-    k_adj_wmom<<<nb2((long long)(g.NX - 2) * (g.NY - 2), 128), 128, 0, st>>>(g, W);
+    k_adj_wmom<<<nb2((long long)(g.NX - 2) * (g.NY - 2), WM_CELLS), 6 * WM_CELLS, 0, st>>>(g, W);
     k_adj_recon<<<nb2((long long)(g.NX - 2) * (g.NY - 2), AC), 8 * AC, 0, st>>>(g, A, W, S);
     k_adj_ugather<<<nb2(g.ncell, 256), 256, 0, st>>>(g, W);
     k_adj_ghost_y<<<nb2((long long)g.ny * g.NX, 256), 256, 0, st>>>(g, W);

@@ -210,12 +210,14 @@ size_t layout(hweno_ctx* c, char* base) {
         A.xvb = take(36 * m);
         A.yvb = take(36 * m);
         A.gfb = take(72 * m);
+        // only the arrays above are accumulated into or read where no kernel
+        // writes them; every slot of the ones below has one writer before it is read
+        A.base = A.xfb;
+        A.count = (long long)((off - first) / sizeof(double));
         A.rbc = take(102 * m);
         A.rbb = take(18 * m);
         A.uc = take(136 * m);
         A.ubb = take(12 * m);
-        A.base = A.xfb;
-        A.count = (long long)((off - first) / sizeof(double));
         A.mupart = take((size_t)hw::adj_mu_partials2(c->hg[0]));
         c->mu_dev = take(1);
         const size_t nint = (size_t)c->hg[0].nx * c->hg[0].ny;
