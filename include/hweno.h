@@ -161,6 +161,17 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R
  * attempt. */
 HWENO_API hweno_status hweno_rk_step(hweno_ctx* ctx, double dt, hweno_diag* diag);
 
+/* One SSP-RK3 step of size dt > 0 with a prescribed source added to the
+ * residual of every stage (manufactured solutions, Examples 5.1 and 5.2):
+ * src1, src2, src3 (device, layout of R in hweno_residual) are the source
+ * moments at the stage times t, t + dt and t + dt/2.  Since the sources fix
+ * the stage times there are no restarts: a stage with a nonpositive density
+ * or pressure returns HWENO_E_INADMISSIBLE with the state unchanged.
+ * Synchronises once. */
+HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* ctx, double dt, const double* src1,
+                                            const double* src2, const double* src3,
+                                            hweno_diag* diag);
+
 /* Reverse mode (vector-Jacobian product) of hweno_residual at the state U
  * (device, D1), 2D grids with constant viscosity (mu_exp = 0):
  *   Ubar = (dR/dU)^T Rbar + (dVhat/dU)^T Vbar        (device, D1, overwritten)

@@ -50,6 +50,7 @@ class MMS1D:
         Uc = [rho, rho * u, E]
         f = [rho * u, rho * u * u + p - tau, (E + p) * u - (tau * u - q)]
         S = [sp.diff(Uc[c], t) + sp.diff(f[c], x) for c in range(3)]
+        self.symbols, self.source_expr, self.state_expr = (x, t), S, Uc
         self._S = sp.lambdify((x, t), S, 'numpy')
         self._U = sp.lambdify((x, t), Uc, 'numpy')
         self._Ut = sp.lambdify((x, t), [sp.diff(q, t) for q in Uc], 'numpy')
@@ -99,6 +100,7 @@ class MMS2D:
         gg = [rho * v, rho * u * v - txy, rho * v * v + p - tyy,
               (E + p) * v - (txy * u + tyy * v + g * mu * sp.diff(e, y) / Pr)]
         S = [sp.diff(Uc[c], t) + sp.diff(f[c], x) + sp.diff(gg[c], y) for c in range(4)]
+        self.symbols, self.source_expr, self.state_expr = (x, y, t), S, Uc
         self._S = sp.lambdify((x, y, t), S, 'numpy')
         self._U = sp.lambdify((x, y, t), Uc, 'numpy')
         self._Ut = sp.lambdify((x, y, t), [sp.diff(q, t) for q in Uc], 'numpy')

@@ -234,7 +234,8 @@ __global__ void k_flux1(Grid1 g) {
 
 __global__ void k_update1(Grid1 g, int stage, const double* __restrict__ S0,
                           const double* __restrict__ Sin, double* __restrict__ Sout,
-                          double* __restrict__ Rout, double* __restrict__ Vout) {
+                          double* __restrict__ Rout, double* __restrict__ Vout,
+                          const double* __restrict__ src) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     double rmin = INFINITY, pmin = INFINITY;
     unsigned long long bad = 0;
@@ -247,6 +248,13 @@ __global__ void k_update1(Grid1 g, int stage, const double* __restrict__ S0,
             const double fr = g.fh[c * N + i], fl = g.fh[c * N + i - 1];
             F1[c] = -(fr - fl) * g.K.idx;
             F2[c] = -(fl + fr) * (0.5 * g.K.idx) + g.vf[c * N + i] * g.K.idx;
+        }
+        if (src) {   // prescribed source moments (layout of R)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F1[c] += src[c * g.nx + t];
+                F2[c] += src[(3 + c) * g.nx + t];
+            }
         }
         if (stage == 0) {
 #pragma unroll
@@ -373,9 +381,10 @@ hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Tim
 }
 
 hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm) {
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm,
+                          const double* src) {
     tbeg(tm, KC_UPDATE, st);
-    k_update1<<<nb(g.nx, 128), 128, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat);
+    k_update1<<<nb(g.nx, 128), 128, 0, st>>>(g, stage, S0, Sin, Sout, R, Vhat, src);
     tend(tm, st);
     return hipGetLastError();
 }

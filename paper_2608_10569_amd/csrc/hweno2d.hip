@@ -613,7 +613,8 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, int iin, int iout,
                                                  double* __restrict__ Rout,
-                                                 double* __restrict__ Vout) {
+                                                 double* __restrict__ Vout,
+                                                 const double* __restrict__ src) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -652,6 +653,12 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
             Fm[0][c] = -dfx * idx - dgy * idy;
             Fm[1][c] = -sfx * (0.5 * idx) - dgyx * idy + g.vf[c * N + cell] * idx;
             Fm[2][c] = -dfxe * idx - sgy * (0.5 * idy) + g.vf[(4 + c) * N + cell] * idy;
+        }
+        if (src) {   // prescribed source moments (layout of R; single grid)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Fm[m][c] += src[(m * 4 + c) * nint + t];
         }
         if (stage == 0) {
 #pragma unroll
@@ -947,9 +954,10 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
 }
 
 hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
-                          double* Vhat, hipStream_t st, Timer* tm) {
+                          double* Vhat, hipStream_t st, Timer* tm, const double* src) {
     tbeg(tm, KC_UPDATE, st);
-    k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R, Vhat);
+    k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R, Vhat,
+                                                  src);
     tend(tm, st);
     return hipGetLastError();
 }

@@ -308,11 +308,12 @@ hweno_status residual(hweno_ctx* c, int si) {
     return dev(hw::launch_residual1(c->g1, c->S1[si], c->stream, c->tm()));
 }
 
-hweno_status update(hweno_ctx* c, int stage, int i0, int iin, int iout, double* R, double* V) {
+hweno_status update(hweno_ctx* c, int stage, int i0, int iin, int iout, double* R, double* V,
+                    const double* src = nullptr) {
     if (c->dim() == 2)
-        return dev(hw::launch_update2(c->bl, stage, i0, iin, iout, R, V, c->stream, c->tm()));
+        return dev(hw::launch_update2(c->bl, stage, i0, iin, iout, R, V, c->stream, c->tm(), src));
     return dev(hw::launch_update1(c->g1, stage, c->S1[i0], c->S1[iin], c->S1[iout], R, V,
-                                  c->stream, c->tm()));
+                                  c->stream, c->tm(), src));
 }
 
 hweno_status reset(hweno_ctx* c) {
@@ -578,10 +579,14 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
     return HWENO_OK;
 }
 
-HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) {
-    if (!c || std::isnan(dt) || c->batch) return HWENO_E_INVAL;
-    if (!c->ws) return HWENO_E_WORKSPACE;
-    if (!c->has_state) return HWENO_E_STATE;
+}  // extern "C"
+
+namespace {
+
+// One SSP-RK3 step of a single grid (eq. (2.12)); src[k] (may be null) are
+// source moments added to the residual of stage k+1; with sources the step
+// size is fixed and a rejected stage is an error instead of a restart.
+hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag* diag) {
     const bool two = c->dim() == 2;
     const bool auto_dt = !(dt > 0.0);
     double cfl_h, visc;
@@ -594,9 +599,13 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
         }
         return HWENO_OK;
     }
+    const int max_halvings = src ? 0 : c->i0().opt.max_halvings;
     // state buffers: 2D by index into Grid2::S (the current one is `cur`);
     // 1D by index into S1 with S1[0] current
     const int a = two ? c->cur : 0, b = two ? 1 - c->cur : 1, s2 = 2;
+    const double* src1 = src ? src[0] : nullptr;
+    const double* src2 = src ? src[1] : nullptr;
+    const double* src3 = src ? src[2] : nullptr;
     double cur_dt = dt;
     int restarts = 0;
     hw::Reduce r;
@@ -612,18 +621,18 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
             TRY(dev(hw::launch_dt(c->red, cfl_h, visc, t_left, c->stream)));
         else
             TRY(dev(hw::launch_set_dt(c->red, cur_dt, c->stream)));
-        TRY(update(c, 1, a, a, b, nullptr, nullptr));
+        TRY(update(c, 1, a, a, b, nullptr, nullptr, src1));
         TRY(ghost(c, b));
         TRY(residual(c, b));
-        TRY(update(c, 2, a, b, s2, nullptr, nullptr));
+        TRY(update(c, 2, a, b, s2, nullptr, nullptr, src2));
         TRY(ghost(c, s2));
         TRY(residual(c, s2));
-        TRY(update(c, 3, a, s2, b, nullptr, nullptr));
+        TRY(update(c, 3, a, s2, b, nullptr, nullptr, src3));
         TRY(read_reduce(c, &r));
         if (restarts == 0 && r.bad[0] != 0) return HWENO_E_NONFINITE;
         if (!(r.dt > 0.0) || !std::isfinite(r.dt)) return HWENO_E_NONFINITE;
         if (r.bad[1] == 0 && r.bad[2] == 0 && r.bad[3] == 0) break;
-        if (restarts >= c->i0().opt.max_halvings) return HWENO_E_INADMISSIBLE;
+        if (restarts >= max_halvings) return HWENO_E_INADMISSIBLE;
         ++restarts;
         cur_dt = 0.5 * r.dt;
     }
@@ -632,6 +641,28 @@ HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) 
     c->t += r.dt;
     fill_diag(c->t, r, diag, restarts, true);
     return HWENO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) {
+    if (!c || std::isnan(dt) || c->batch) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (!c->has_state) return HWENO_E_STATE;
+    return step(c, dt, nullptr, diag);
+}
+
+HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* c, double dt, const double* src1,
+                                            const double* src2, const double* src3,
+                                            hweno_diag* diag) {
+    if (!c || !(dt > 0.0) || !std::isfinite(dt) || c->batch || !src1 || !src2 || !src3)
+        return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (!c->has_state) return HWENO_E_STATE;
+    const double* src[3] = {src1, src2, src3};
+    return step(c, dt, src, diag);
 }
 
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,

@@ -185,9 +185,11 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
 hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm);
 hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm);
 // stage 0: write R (12) and Vhat (8) in interior layout (single grid);
-// stage 1..3: RK update S[iout] from S[i0] (U^n) and S[iin] (stage input)
+// stage 1..3: RK update S[iout] from S[i0] (U^n) and S[iin] (stage input);
+// src (single grid, may be null): source moments added to the residual
 hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
-                          double* Vhat, hipStream_t st, Timer* tm);
+                          double* Vhat, hipStream_t st, Timer* tm,
+                          const double* src = nullptr);
 hipError_t launch_check2(const BatchL& b, int si, hipStream_t st);
 hipError_t launch_reset2(const BatchL& b, hipStream_t st);
 // per-instance step size from its InstState rule, halved per pending restart
@@ -202,7 +204,8 @@ hipError_t launch_copy_out1(const Grid1& g, const double* S, double* U, hipStrea
 hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st, Timer* tm);
 hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Timer* tm);
 hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const double* Sin,
-                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm);
+                          double* Sout, double* R, double* Vhat, hipStream_t st, Timer* tm,
+                          const double* src = nullptr);
 hipError_t launch_check1(const Grid1& g, const double* S, hipStream_t st);
 
 }  // namespace hw

@@ -17,7 +17,8 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
-           'hweno_residual', 'hweno_rk_step', 'hweno_residual_vjp', 'hweno_rk_step_vjp',
+           'hweno_residual', 'hweno_rk_step', 'hweno_rk_step_source', 'hweno_residual_vjp',
+           'hweno_rk_step_vjp',
            'hweno_set_timing', 'hweno_get_timing', 'hweno_status_string',
            'hweno_batch_create', 'hweno_batch_set_state', 'hweno_batch_get_state',
            'hweno_batch_run', 'hweno_batch_get_diag', 'hweno_get_tiles', 'hweno_set_tiles',
@@ -100,6 +101,7 @@ def lib():
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
+        L.hweno_rk_step_source.argtypes = [vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_residual_vjp.argtypes = [vp, vp, vp, vp, vp, dp]
         L.hweno_rk_step_vjp.argtypes = [vp, vp, ctypes.c_double, vp, vp, dp]
         L.hweno_set_timing.argtypes = [vp, ctypes.c_int]
@@ -232,6 +234,15 @@ class Solver:
                                        _ptr(Vbar) if Vbar is not None else None, _ptr(Ub),
                                        ctypes.byref(mu) if want_mu else None))
         return Ub, (mu.value if want_mu else None)
+
+    def rk_step_source(self, dt, src1, src2, src3):
+        """One RK3 step of size dt with source moments (layout of R) at t, t+dt, t+dt/2."""
+        for q in (src1, src2, src3):
+            self._dev(q)
+        d = Diag()
+        check(lib().hweno_rk_step_source(self._h, float(dt), _ptr(src1), _ptr(src2), _ptr(src3),
+                                         ctypes.byref(d)))
+        return d.as_dict()
 
     def rk_step_vjp(self, U0, dt, U3bar, want_mu=True):
         """(U0bar, mu_bar): adjoint of one RK3 step of size dt (held fixed) from U0."""

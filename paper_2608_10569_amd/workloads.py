@@ -181,8 +181,13 @@ def batched_periodic_2d(n_instances=64, gamma=1.4, sizes=(64, 128, 256, 512), mo
                         amp=0.3):
     """Instance k (rng([2608, k])): n from ``sizes``, log10 Re ~ U(2, 4),
     rho = 1, p = 1/gamma, u and v sums of ``modes`` random-phase Fourier modes
-    (wave numbers in {-4..4}^2 without 0) normalised to max |.| = amp.
-    Returns a list of (n, Re, U)."""
+    (wave numbers in {-4..4}^2 without 0) normalised to max |.| = amp (the max
+    taken on a 4n x 4n point grid).  Returns a list of (n, Re, U).
+
+    A mode cos(2 pi (kx x + ky y) + phi) is separable,
+    cos(2 pi kx x) cos(2 pi ky y + phi) - sin(2 pi kx x) sin(2 pi ky y + phi),
+    so every field on a tensor grid is a (modes x ny)^T (modes x nx) product."""
+    gx, gw = _gauss6()
     out = []
     for k in range(n_instances):
         rng = np.random.default_rng([SEED, k])
@@ -195,18 +200,28 @@ def batched_periodic_2d(n_instances=64, gamma=1.4, sizes=(64, 128, 256, 512), mo
                 kv.append(w)
         kv = np.array(kv).reshape(2, modes, 2)
         ph = rng.uniform(0, 2 * np.pi, (2, modes))
-        xs = (np.arange(4 * n) + 0.5) / (4 * n)
-        XS, YS = np.meshgrid(xs, xs)
 
-        def field(q, X, Y):
-            return sum(np.cos(2 * np.pi * (kv[q, m, 0] * X + kv[q, m, 1] * Y) + ph[q, m])
-                       for m in range(modes))
-        scale = [amp / np.max(np.abs(field(q, XS, YS))) for q in range(2)]
-
-        def prim(X, Y, scale=scale, field=field):
-            return (np.ones_like(X), scale[0] * field(0, X, Y), scale[1] * field(1, X, Y),
-                    np.full_like(X, 1.0 / gamma))
-        out.append((n, Re, project2d(prim, n, n, (0.0, 1.0, 0.0, 1.0), gamma)))
+        def field(q, xs, ys):
+            ax = 2 * np.pi * np.outer(kv[q, :, 0], xs)                   # (modes, nx)
+            by = 2 * np.pi * np.outer(kv[q, :, 1], ys) + ph[q][:, None]  # (modes, ny)
+            return np.cos(by).T @ np.cos(ax) - np.sin(by).T @ np.sin(ax)
+        xs4 = (np.arange(4 * n) + 0.5) / (4 * n)
+        scale = [amp / np.max(np.abs(field(q, xs4, xs4))) for q in range(2)]
+        h = 1.0 / n
+        xc = (np.arange(n) + 0.5) * h
+        U = np.zeros((3, 4, n, n))
+        for b in range(6):            # eta points
+            yb = xc + gx[b] * h
+            for a in range(6):        # xi points
+                xa = xc + gx[a] * h
+                u = scale[0] * field(0, xa, yb)
+                v = scale[1] * field(1, xa, yb)
+                Q = _cons2(np.ones_like(u), u, v, np.full_like(u, 1.0 / gamma), gamma)
+                w = gw[a] * gw[b]
+                U[0] += w * Q
+                U[1] += w * gx[a] * Q
+                U[2] += w * gx[b] * Q
+        out.append((n, Re, U))
     return out
 
 
