@@ -57,6 +57,13 @@ PEAK_HBM_GBS = 8000.0
 #   flux:  per face 6 point fluxes and PP speed bounds, 12 LF combinations.
 #   update: assembly of 12 residual entries and the stage combination.
 FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400}
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) scaled by the factors a 1 GiB copy gives in
+# the same process (FETCH x 2.0, WRITE x 1.0): recon reads 25,005 KiB and
+# writes 533,876 KiB per launch on this grid (tiles recon 32 / grad 32 /
+# flux 64, XCD-aware order), i.e. 51.2 MB in + 546.7 MB out.
+TRAFFIC_BYTES = {'recon': 597896744}
+TRAFFIC_TILES = {'recon': 32, 'grad': 32, 'flux': 64, 'order': 0, 'xcd': 1}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).
@@ -268,7 +275,10 @@ def main():
                    'restarts': restarts, 'pp_cell_stages': pp, 'tiles': tiles},
         'roofline': {'bound': 'alu', 'kernel': dom, 'achieved': achieved,
                      'peak': PEAK_FP64_TFLOPS, 'unit': 'TFLOP/s',
-                     'frac': achieved / PEAK_FP64_TFLOPS, 'traffic': None,
+                     'frac': achieved / PEAK_FP64_TFLOPS,
+                     'traffic': TRAFFIC_BYTES.get(dom),
+                     'traffic_unit': 'bytes per launch (counters, tiles %s)' % TRAFFIC_TILES,
+                     'traffic_gbs': (TRAFFIC_BYTES[dom] / avg_s / 1e9) if dom in TRAFFIC_BYTES else None,
                      'flops_per_unit': FLOPS[dom], 'units_per_launch': units_per_launch(dom),
                      'us_per_launch': avg_s * 1e6},
         'hbm_frac_algorithmic': value * ALGO_BYTES_PER_CELL_STAGE / (PEAK_HBM_GBS * 1e9),
