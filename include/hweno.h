@@ -98,6 +98,8 @@ typedef struct hweno_options {
     double t_final;             /* steps are clipped to end at t_final; <= 0: no clipping */
     int linear_weights;         /* 1: omega = gamma (test mode); 0: nonlinear weights */
     int max_halvings;           /* restarts with dt/2 allowed per step (>= 0) */
+    int linear_gradients;       /* 1: omega = gamma in the gradient reconstruction only
+                                   (the linear counterpart of Remark 3.1); 0: paper */
 } hweno_options;
 
 /* Diagnostics of the last call (Sec. 5 preamble; Table 5.3 PP activity). */

@@ -103,7 +103,9 @@ class Options:
     eps_weno: float = 1e-8      #: epsilon of the nonlinear weights
     t_final: float = math.inf   #: last step is clipped to reach t_final
     linear_weights: bool = False  #: test mode: omega = gamma (no nonlinearity)
-    max_halvings: int = 40      #: restarts allowed per step before giving up
+    #: Remark 3.1 ablation: omega = gamma in the gradient reconstruction only
+    linear_gradients: bool = False
+    max_halvings: int = 64      #: restarts allowed per step before giving up
     #: linear weights gamma_m (1D: eq. (A.3); 2D: eq. (A.6))
     gamma1d: tuple = field(default=(199.0 / 200.0, 1.0 / 400.0, 1.0 / 400.0))
     gamma2d: tuple = field(default=(99.0 / 100.0, 1.0 / 400.0, 1.0 / 400.0,

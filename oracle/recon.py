@@ -98,11 +98,11 @@ class Hweno1D:
         self.G = G
         self.own_moment = np.array([mom_integral(k, 0) for k in n])
 
-    def combined(self, a, opts):
+    def combined(self, a, opts, gradient=False):
         """Coefficients (5, ...) of the nonlinear combination of eq. (2.4)."""
         gam = opts.gamma1d
         c = [np.tensordot(Q, a, axes=1) for Q in self.Q]
-        if opts.linear_weights:
+        if opts.linear_weights or (gradient and opts.linear_gradients):
             om = list(gam)
         else:
             beta = [np.einsum('k...,kl,l...->...', cm, self.G, cm) for cm in c]
@@ -208,11 +208,11 @@ class Hweno2D:
         self.mom_xi = np.array(self._row('xi', 5))
         self.mom_eta = np.array(self._row('eta', 5))
 
-    def combined(self, a, opts):
+    def combined(self, a, opts, gradient=False):
         """Coefficients (15, ...) of the nonlinear combination of eq. (3.4)."""
         gam = opts.gamma2d
         c = [np.tensordot(Q, a, axes=1) for Q in self.Q]
-        if opts.linear_weights:
+        if opts.linear_weights or (gradient and opts.linear_gradients):
             om = list(gam)
         else:
             beta = [np.einsum('k...,kl,l...->...', cm, self.G, cm) for cm in c]

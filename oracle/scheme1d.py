@@ -140,7 +140,7 @@ class Scheme1D:
 
         # 5. gradient reconstruction on cells 3 .. NG-4
         ar = np.stack([rb0[:, :-2], rb0[:, 1:-1], rb0[:, 2:], rb1[:, :-2], rb1[:, 2:]])
-        Cg = rec.combined(ar, op)                          # (5, 2, m)
+        Cg = rec.combined(ar, op, gradient=True)           # (5, 2, m)
         grads = rec.evaluate(Cg, LGL_NODES)                # (4, 2, m) m: cells 3..NG-4
         # align region-c arrays with gradient cells: c index = ghosted - 1
         Ug_c = Ulim[:, :, 2:-2]                            # (4, c, m)

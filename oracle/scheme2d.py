@@ -204,7 +204,7 @@ class Scheme2D:
         ar = np.stack([rcell(0, k) for k in range(1, 10)] +
                       [rcell(1, k) for k in Hweno2D.EDGE] +
                       [rcell(2, k) for k in Hweno2D.EDGE])           # (17, l, w, ...)
-        Cg = rec.combined(ar, op)
+        Cg = rec.combined(ar, op, gradient=True)
         gv = rec.evaluate(Cg, XFACE + YFACE + VOL)                    # (21, l, w, ...)
         # s = (u_x, u_y, v_x, v_y, e_x, e_y): index 2*w + l
         s = np.stack([gv[:, l, w] for w in range(3) for l in range(2)], axis=1)  # (21, 6, ...)

@@ -182,7 +182,7 @@ __global__ void k_grad1(Grid1 g) {
         const double* r1 = g.rb + (w * 2 + 1) * N;
         const double a[5] = {r0[i - 1], r0[i], r0[i + 1], r1[i - 1], r1[i + 1]};
         double C[5], v[4];
-        hweno1d(a, g.K, C);
+        hweno1d(a, grad_consts(g.K), C);
         eval1d(C, v);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
         a[13 + e] = R2[nb];
     }
     double C[15];
-    hweno2d(a, K, C);
+    hweno2d(a, grad_consts(K), C);
     double fo[12], vo[9];
     eval_xface(C, fo);
     eval_yface(C, fo + 6);

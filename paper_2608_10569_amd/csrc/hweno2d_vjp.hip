@@ -212,7 +212,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
         a[13 + e] = R2[nb];
     }
     double C[15], vo[9];
-    hweno2d(a, K, C);
+    hweno2d(a, grad_consts(K), C);
     eval_vol(C, vo);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
     adj::yface_T(yb + 6, Cb);
     adj::vol_T(yb + 12, Cb);
     double ab[17];
-    hweno2d_vjp(a, K, Cb, ab);
+    hweno2d_vjp(a, grad_consts(K), Cb, ab);
     if (valid) {
 #pragma unroll
         for (int k = 0; k < 17; ++k) W.rbc[(s * 17 + k) * N + cell] = ab[k];

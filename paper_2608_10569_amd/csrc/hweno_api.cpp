@@ -90,6 +90,7 @@ hw::Consts make_consts(const Inst& c) {
     K.eps_pp = c.opt.eps_pp;
     K.eps_weno = c.opt.eps_weno;
     K.linear = c.opt.linear_weights ? 1 : 0;
+    K.linear_grad = c.opt.linear_gradients ? 1 : 0;
     K.dx = (c.grid.x1 - c.grid.x0) / c.grid.nx;
     K.idx = 1.0 / K.dx;
     if (c.grid.dim == 2) {
@@ -466,7 +467,8 @@ HWENO_API hweno_status hweno_default_options(hweno_options* o) {
     o->eps_weno = 1e-8;
     o->t_final = 0.0;
     o->linear_weights = 0;
-    o->max_halvings = 40;
+    o->max_halvings = 64;
+    o->linear_gradients = 0;
     return HWENO_OK;
 }
 

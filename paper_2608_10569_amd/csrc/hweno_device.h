@@ -37,10 +37,19 @@ struct Consts {
     double mu_ref, mu_exp, T_ref;   // mu(T) = mu_ref (T/T_ref)^mu_exp, T = p/rho
     double eps_pp, eps_weno;
     int linear;                 // 1: omega = gamma (test mode)
+    int linear_grad;            // 1: omega = gamma in the gradient reconstruction only
     double dx, dy, idx, idy;    // cell sizes and inverses
 };
 
 __device__ __forceinline__ double dabs(double x) { return fabs(x); }
+
+// Constants of the gradient reconstruction: linear weights also when only the
+// gradients are asked to use them.
+__device__ __forceinline__ Consts grad_consts(const Consts& K) {
+    Consts G = K;
+    G.linear = K.linear | K.linear_grad;
+    return G;
+}
 
 __device__ __forceinline__ double viscosity(const Consts& K, double rho, double p) {
     if (K.mu_exp == 0.0) return K.mu_ref;

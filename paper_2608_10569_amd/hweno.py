@@ -47,7 +47,7 @@ class OptionsC(ctypes.Structure):
     _fields_ = [('cfl', ctypes.c_double), ('b_visc', ctypes.c_double),
                 ('eps_pp', ctypes.c_double), ('eps_weno', ctypes.c_double),
                 ('t_final', ctypes.c_double), ('linear_weights', ctypes.c_int),
-                ('max_halvings', ctypes.c_int)]
+                ('max_halvings', ctypes.c_int), ('linear_gradients', ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):

@@ -103,6 +103,23 @@ def double_rarefaction_1d(nx=2000, gamma=1.4):
     return riemann_1d((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), nx, gamma=gamma)
 
 
+def sedov_1d(nx=400, gamma=1.4, e_blast=3200000.0):
+    """Example 5.5: (rho, u, E) = (1, 0, 1e-12) on [-2, 2], the cell right of
+    x = 0 (the centre cell for even nx) holding E = e_blast / dx.  Returns U
+    (2, 3, nx); zero moments."""
+    dx = 4.0 / nx
+    U = np.zeros((2, 3, nx))
+    U[0, 0] = 1.0
+    U[0, 2] = 1e-12
+    U[0, 2, nx // 2] = e_blast / dx
+    return U
+
+
+def leblanc_1d(nx=3200, gamma=1.4):
+    """Example 5.6: (rho, u, p) = (2, 0, 1e9) on [-10, 0), (0.001, 0, 1) on [0, 10]."""
+    return riemann_1d((2.0, 0.0, 1e9), (0.001, 0.0, 1.0), nx, -10.0, 10.0, 0.0, gamma)
+
+
 def random_smooth_1d(nx, seed, gamma=1.4):
     """Smooth random periodic state on [0, 1] (modes 1..4) plus small
     cell-level noise on the moments, for parity tests."""
@@ -145,6 +162,18 @@ def viscous_shock_tube_2d(nx=1000, ny=500, gamma=1.4, seed=None, amp=0.0):
                      for m in range(3)) for q in range(4)]
         return rho * (1.0 + f[0]), f[1], f[2], rho / gamma * (1.0 + f[3])
     return project2d(prim, nx, ny, (0.0, 1.0, 0.0, 0.5), gamma)
+
+
+def sedov_2d(n=160, gamma=1.4, e_blast=0.244816, extent=1.1):
+    """Example 5.7: on [0, 1.1]^2, (rho, u, v, E) = (1, 0, 0, 1e-12), the
+    corner cell [0, dx] x [0, dy] holding E = e_blast / (dx dy).  Returns U
+    (3, 4, n, n); zero moments."""
+    h = extent / n
+    U = np.zeros((3, 4, n, n))
+    U[0, 0] = 1.0
+    U[0, 3] = 1e-12
+    U[0, 3, 0, 0] = e_blast / (h * h)
+    return U
 
 
 def random_smooth_2d(nx, ny, seed, gamma=1.4, extent=(0.0, 1.0, 0.0, 1.0), noise=1e-4):

@@ -55,7 +55,7 @@ def _create(g, ph, b, o):
 
 def test_default_options_are_the_papers():
     o = hweno.default_options()
-    assert (o.cfl, o.b_visc, o.eps_pp, o.eps_weno, o.max_halvings) == (0.6, 0.001, 1e-12, 1e-8, 40)
+    assert (o.cfl, o.b_visc, o.eps_pp, o.eps_weno, o.max_halvings) == (0.6, 0.001, 1e-12, 1e-8, 64)
 
 
 def test_create_validates_arguments():
