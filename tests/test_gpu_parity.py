@@ -47,21 +47,33 @@ def to_dev(U):
 BCS_WALL = ('noslip', 'noslip', 'noslip', 'slip')
 
 
-@pytest.mark.parametrize('linear', [False, True])
+# weights: nonlinear (the paper), linear everywhere (test mode), and linear in
+# the gradient reconstruction only (the counterpart discussed in Remark 3.1)
+MODES = {'nonlinear': {}, 'linear': dict(linear_weights=True),
+         'linear_gradients': dict(linear_gradients=True)}
+
+
+@pytest.mark.parametrize('mode', list(MODES))
 @pytest.mark.parametrize('shape', [(37, 29), (8, 5)])
-def test_residual2d_periodic(linear, shape):
+def test_residual2d_periodic(mode, shape):
     nx, ny = shape
     U = workloads.random_smooth_2d(nx, ny, seed=3, noise=1e-3)
+    opt = MODES[mode]
     s = hweno.Solver(nx, ny, extent=(0.0, 1.0, 0.0, 1.0), mu_ref=0.01, Pr=0.72,
-                     linear_weights=int(linear))
+                     **{k: int(v) for k, v in opt.items()})
     R, V, d = s.residual(to_dev(U))
-    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01, Pr=0.72),
-                  Options(linear_weights=linear))
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01, Pr=0.72), Options(**opt))
     Ro, Vo, do = sc.residual(U)
     eR = rel_err(fields2d(R.cpu().numpy()), fields2d(Ro))
     eV = rel_err(fields2d(V.cpu().numpy()), fields2d(Vo.reshape(8, ny, nx)))
-    print('2D residual shape', shape, 'linear', linear, 'R err %.2e V err %.2e' % (eR, eV))
+    print('2D residual shape', shape, mode, 'R err %.2e V err %.2e' % (eR, eV))
     assert eR < 1e-11 and eV < 1e-12
+    if mode == 'linear_gradients':
+        # the option changes only the viscous part: visibly, and not the moments
+        Rn, Vn, _ = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01, Pr=0.72),
+                             Options()).residual(U)
+        assert rel_err(fields2d(Rn), fields2d(Ro)) > 1e-8
+        assert np.array_equal(Vn, Vo)
     assert abs(d['alpha_star'] - do['alpha']) < 1e-13 * do['alpha']
     assert abs(d['beta_max'] - do['beta_max']) < 1e-12 * do['beta_max']
     assert d['pp_cells'] == do['pp_cells']
@@ -97,17 +109,21 @@ def test_rk_step2d_one_step():
     assert abs(t - dto) < 1e-14 * dto
 
 
-@pytest.mark.parametrize('linear', [False, True])
-def test_residual1d(linear):
+@pytest.mark.parametrize('mode', list(MODES))
+def test_residual1d(mode):
     nx = 150
     U = workloads.random_smooth_1d(nx, seed=1)
-    s = hweno.Solver(nx, extent=(0.0, 1.0), mu_ref=0.01, linear_weights=int(linear))
+    opt = MODES[mode]
+    s = hweno.Solver(nx, extent=(0.0, 1.0), mu_ref=0.01, **{k: int(v) for k, v in opt.items()})
     R, V, d = s.residual(to_dev(U))
-    sc = Scheme1D(nx, 0.0, 1.0, Physics(mu_ref=0.01), Options(linear_weights=linear))
+    sc = Scheme1D(nx, 0.0, 1.0, Physics(mu_ref=0.01), Options(**opt))
     Ro, Vo, do = sc.residual(U)
     eR = rel_err(fields1d(R.cpu().numpy()), fields1d(Ro))
     eV = rel_err(fields1d(V.cpu().numpy()), fields1d(Vo[0]))
-    print('1D residual linear', linear, 'R err %.2e V err %.2e' % (eR, eV))
+    print('1D residual', mode, 'R err %.2e V err %.2e' % (eR, eV))
+    if mode == 'linear_gradients':
+        Rn, _, _ = Scheme1D(nx, 0.0, 1.0, Physics(mu_ref=0.01), Options()).residual(U)
+        assert rel_err(fields1d(Rn), fields1d(Ro)) > 1e-8
     assert eR < 1e-11 and eV < 1e-12
     assert abs(d['alpha_star'] - do['alpha']) < 1e-13 * do['alpha']
 
