@@ -11,8 +11,10 @@ derivative moments, gradient reconstruction, fluxes) plus the stage update.
 The state lives in HBM before the timed region starts.
 
 Prints one JSON line.  ``value`` = cell-stage updates per second of that
-grid.  Two more measurements ride along in the same line:
+grid.  Three more measurements ride along in the same line:
 
+* ``developed``: the same grid timed from its t = 0.3 state (shocks, contact
+  and wall layers present);
 * ``batched``: 64 periodic 2D grids (64^2..512^2, Re log-uniform in
   [1e2, 1e4], random-phase Fourier velocity fields) advanced 100 steps each by
   one graph launch, against the same 64 problems run one after another through
@@ -156,6 +158,44 @@ def bench_batched(nsteps, sequential=True):
     return out
 
 
+def bench_developed(nsteps, t_dev=0.3):
+    """The same grid from a developed state: the shock tube advanced to
+    t = 0.3 on the GPU (shock, contact and wall layers present) with the
+    viscous step bound off (CFL 0.3, restarts keep the stages admissible),
+    then ``nsteps`` timed steps with the paper's rule."""
+    import torch
+    from paper_2608_10569_amd import hweno, workloads
+    kw = dict(extent=EXTENT, bc=BCS, cfl=0.3, **PHYS)
+    s = hweno.Solver(NX, NY, b_visc=0.0, t_final=t_dev, **kw)
+    s.set_state(torch.from_numpy(workloads.viscous_shock_tube_2d(NX, NY)).cuda())
+    t0 = time.perf_counter()
+    steps = 0
+    while s.rk_step(0.0)['dt'] > 0.0:
+        steps += 1
+    t_prep = time.perf_counter() - t0
+    U, t = s.get_state()
+    s.close()
+    s = hweno.Solver(NX, NY, t_final=1.0, **kw)
+    s.set_state(U, t)
+    for _ in range(5):
+        s.rk_step(0.0)
+    restarts = pp = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        d = s.rk_step(0.0)
+        restarts += d['restarts']
+        pp += d['pp_cells']
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    return {'workload': 'the same 1000x500 shock tube from its t=%.1f state (%d preparation steps '
+                        'with the viscous bound off, %.1f s), paper dt rule' % (t_dev, steps, t_prep),
+            'steps': nsteps, 'ms_per_step': 1e3 * el / nsteps,
+            'value': nsteps * 3 * NX * NY / el, 'unit': UNIT, 'restarts': restarts,
+            'pp_cell_stages': pp}
+
+
 def bench_adjoint(nsteps=200, every=20):
     """Double shear layer: forward + checkpointed backward vs plain forward."""
     import numpy as np
@@ -205,6 +245,7 @@ def main():
     ap.add_argument('--no-batched', action='store_true')
     ap.add_argument('--no-sequential', action='store_true')
     ap.add_argument('--no-adjoint', action='store_true')
+    ap.add_argument('--no-developed', action='store_true')
     ap.add_argument('--no-autotune', action='store_true')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='first run one device-to-device copy of this many MiB (a plain copy '
@@ -289,6 +330,9 @@ def main():
     del s
     torch.cuda.empty_cache()
     log('single grid: %.3e %s, %.3f ms/step' % (value, UNIT, 1e3 * el / args.steps))
+    if not args.no_developed:
+        out['developed'] = bench_developed(args.steps)
+        log('developed state: %.3e %s' % (out['developed']['value'], UNIT))
     if not args.no_batched:
         out['batched'] = bench_batched(args.batch_steps, sequential=not args.no_sequential)
         log('batched: %.3e %s' % (out['batched']['value'], UNIT))

@@ -175,15 +175,29 @@ def test_leblanc_hardest_steps_match_oracle():
 
 def test_leblanc_full_run():
     """Example 5.6 to T = 1e-4 on the GPU: admissible throughout, mass and
-    energy conserved (the waves stay inside the domain)."""
+    energy conserved (the waves stay inside the domain), and close to the
+    exact Riemann solution as the paper reports (the kinematic viscosity
+    mu/rho is at most 1 and the layers stay thin).  Schemes of this kind put
+    the Leblanc shock slightly ahead of its exact place; the oracle's run is
+    0.13 ahead at this resolution, with density L1 error 4.8e-4 relative."""
+    import riemann_exact as R
     U, s, _ = leblanc()
     Ug, tg, steps, restarts, pp, _ = gpu_run(s, U)
     m0, e0 = totals(U)
     m1, e1 = totals(Ug)
-    print('Leblanc to T=1e-4: %d steps, %d restarts, PP %.4f%%; mass %.1e energy %.1e'
-          % (steps, restarts, 100.0 * pp / (3 * 3200 * steps), abs(m1 / m0 - 1), abs(e1 / e0 - 1)))
+    n, h = 3200, 20.0 / 3200
+    E = R.cell_averages((2.0, 0.0, 1e9), (0.001, 0.0, 1.0), -10.0, 10.0, 0.0, 1e-4, n)
+    e_rho = np.abs(Ug[0, 0] - E[0]).sum() / np.abs(E[0]).sum()
+    x = -10.0 + h * (np.arange(n) + 0.5)
+    x_num = x[np.max(np.nonzero(Ug[0, 0] > 0.002)[0])]
+    x_ex = x[np.max(np.nonzero(E[0] > 0.002)[0])]
+    print('Leblanc to T=1e-4: %d steps, %d restarts, PP %.4f%%; mass %.1e energy %.1e; density '
+          'L1 vs exact %.2e relative, shock at %.4f (exact %.4f)'
+          % (steps, restarts, 100.0 * pp / (3 * n * steps), abs(m1 / m0 - 1), abs(e1 / e0 - 1),
+             e_rho, x_num, x_ex))
     assert abs(tg - 1e-4) < 1e-18
     assert abs(m1 / m0 - 1) < 1e-12 and abs(e1 / e0 - 1) < 1e-12
+    assert e_rho < 1e-3 and 0.0 <= x_num - x_ex < 0.25
     # the rarefaction and the shock are still inside [-10, 10]
     assert np.all(Ug[0, 0, :100] == Ug[0, 0, 0]) and abs(Ug[0, 0, 0] - 2.0) < 1e-12
 

@@ -671,3 +671,42 @@ def test_complex_step_tangent_matches_finite_differences():
         Fm, _, _ = s.residual(U - eps * dU)
         errs.append(np.abs((Fp - Fm) / (2 * eps) - J).max() / np.abs(J).max())
     assert errs[1] < 1e-5 and errs[0] / errs[1] > 50.0     # O(eps^2)
+
+
+def test_exact_riemann_solver_star_states():
+    """The exact Riemann solver used as a reference below reproduces the
+    star-region values tabulated for the standard tests of the textbook
+    construction (Sod; the 123 problem; the left half of the blast wave;
+    two colliding shocks)."""
+    import riemann_exact as R
+    cases = [((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.30313, 0.92745),
+             ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.00189, 0.0),
+             ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01), 460.894, 19.5975),
+             ((5.99924, 19.5975, 460.894), (5.99242, -6.19633, 46.0950), 1691.64, 8.68975)]
+    for left, right, p, u in cases:
+        ps, us = R.star_state(left, right)
+        assert abs(ps - p) <= 5e-6 * max(p, 1e-3) + 5e-6
+        assert abs(us - u) <= 5e-6 * max(abs(u), 1.0)
+
+
+@pytest.mark.parametrize('case', ['sod', '123'])
+def test_high_reynolds_riemann_approaches_exact_solution(case):
+    """At Re = 1e5 the viscous layers are far thinner than a cell, so the
+    scheme's Riemann solutions (the C2 data) must approach the exact inviscid
+    ones: density L1 errors fall by at least 1.5x per refinement (first order
+    is the rate at discontinuities) and stay below typical fifth-order WENO
+    levels."""
+    import riemann_exact as R
+    from paper_2608_10569_amd import workloads
+    L, Rt, T = (((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2) if case == 'sod'
+                else ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.15))
+    errs = []
+    for n in (100, 200, 400):
+        sc = Scheme1D(n, 0.0, 1.0, Physics(gamma=1.4, Pr=0.72, mu_ref=1e-5), Options(),
+                      bc=('outflow', 'outflow'))
+        U, _, _ = rk.run(sc, workloads.riemann_1d(L, Rt, n), 0.0, T)
+        E = R.cell_averages(L, Rt, 0.0, 1.0, 0.5, T, n)
+        errs.append(np.abs(U[0, 0] - E[0]).mean())
+    print(case, 'density L1 errors at N = 100, 200, 400:', ['%.2e' % e for e in errs])
+    assert errs[0] / errs[1] > 1.5 and errs[1] / errs[2] > 1.5
+    assert errs[2] < (1.5e-3 if case == 'sod' else 3e-3)
