@@ -223,12 +223,28 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     const bool valid = i <= g.NX - 2;
     const long long N = g.ncell;
     const long long cell = (long long)j * g.NX + i;
-    // stencil tile: rows j-1..j+1, columns i0-1..i0+RC_CELLS (clamped to the grid)
-    for (int t = tid; t < TILE; t += 8 * RC_CELLS) {
-        const int c = t / (3 * TW), rem = t % (3 * TW);
-        const int r = rem / TW, col = rem % TW;
-        const int gi = min(i0 - 1 + col, g.NX - 1);
-        sh[t] = S[c * N + (long long)(j - 1 + r) * g.NX + gi];
+    // stencil tile: rows j-1..j+1, columns i0-1..i0+RC_CELLS (clamped to the
+    // grid); tile row R = 3 c + r holds field c of grid row j-1+r.  All of a
+    // thread's loads are issued before the first LDS write.
+    {
+        constexpr int NT = 8 * RC_CELLS;
+        constexpr int NIT = (TILE + NT - 1) / NT;
+        double v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * NT;
+            if (t < TILE) {
+                const int R = t / TW, col = t - R * TW;
+                const int c = R / 3, r = R - 3 * c;
+                const int gi = min(i0 - 1 + col, g.NX - 1);
+                v[it] = S[c * N + (long long)(j - 1 + r) * g.NX + gi];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * NT;
+            if (t < TILE) sh[t] = v[it];
+        }
     }
     __syncthreads();
     auto T = [&](int c, int oy, int ox) -> double {
@@ -328,7 +344,7 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
         for (int q = k; q < 9; q += 4) {
             const int o = 6 + q;
             const double w = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
-            const double ir = 1.0 / comp(b, 0, o);
+            const double ir = rcp(comp(b, 0, o));
             const double u = comp(b, 1, o) * ir, v = comp(b, 2, o) * ir;
             const double e = comp(b, 3, o) * ir - 0.5 * (u * u + v * v);
             su += w * u;
@@ -371,7 +387,7 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
                 const double ut = c == 0 ? rbar + th1 * (x - rbar) : x;
                 Ul[c] = ub[c] + th2 * (ut - ub[c]);
             }
-            const double ir = 1.0 / Ul[0];
+            const double ir = rcp(Ul[0]);
             const double u = Ul[1] * ir, v = Ul[2] * ir;
             const double p = K.gm1 * (Ul[3] - 0.5 * (Ul[1] * u + Ul[2] * v));
             const double sp = fmax(fabs(u), fabs(v)) + sqrt(K.gamma * p * ir);
@@ -390,7 +406,7 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
 __device__ __forceinline__ void prim3(const double* F, long long N, long long cell, int p,
                                       double* w) {
     const double r = F[(p * 4 + 0) * N + cell];
-    const double ir = 1.0 / r;
+    const double ir = rcp(r);
     const double u = F[(p * 4 + 1) * N + cell] * ir;
     const double v = F[(p * 4 + 2) * N + cell] * ir;
     w[0] = u;
@@ -398,56 +414,87 @@ __device__ __forceinline__ void prim3(const double* F, long long N, long long ce
     w[2] = F[(p * 4 + 3) * N + cell] * ir - 0.5 * (u * u + v * v);
 }
 
-// One thread per (cell, direction l): block = RB_CELLS cells x 2 directions,
-// the direction uniform per wavefront.  Direction l averages the traces of the
-// cell's two l-faces (interface averages) and forms the three weak moments of
-// d w / d x_l (w = u, v, e).
-constexpr int RB_CELLS = 128;
+// Block = RB_TX x RB_TY cells of the region (rows and columns 2 .. N-3).
+// First every face of the tile gets its interface averages w^ = (w- + w+)/2
+// at the three Gauss points, once (a face is shared by two cells): the x-faces
+// of each tile row and the y-faces of each tile column, into LDS.  Then each
+// cell forms the 18 weak moments of d w / d x_l from its four faces and w-bar.
+constexpr int RB_TX = 32, RB_TY = 8;
 
-__global__ __launch_bounds__(2 * RB_CELLS) void k_rbar2(Batch bt) {
+__global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
+    constexpr int NXF = RB_TY * (RB_TX + 1), NYF = (RB_TY + 1) * RB_TX;
+    __shared__ double hx[9][RB_TY][RB_TX + 1];   // [3 G + w][row][face i - 1/2]
+    __shared__ double hy[9][RB_TY + 1][RB_TX];   // [3 G + w][face j - 1/2][column]
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
     const Grid2 g = gsrc;
-    const int l = threadIdx.x / RB_CELLS;
-    const int wc = g.NX - 4;
-    const long long nreg = (long long)wc * (g.NY - 4);
-    const long long cid = (long long)lc.b * RB_CELLS + threadIdx.x % RB_CELLS;
-    if (cid >= nreg) return;
-    const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
+    const int tiles_x = (g.NX - 4 + RB_TX - 1) / RB_TX;
+    const int i0 = 2 + (lc.b % tiles_x) * RB_TX;
+    const int j0 = 2 + (lc.b / tiles_x) * RB_TY;
     const long long N = g.ncell;
-    const long long cell = (long long)j * g.NX + i;
-    const double* F = l ? g.yf : g.xf;
-    const long long off = l ? (long long)g.NX : 1;
-    const long long lo = cell - off, hi = cell + off;
-    double hlo[3][3], hhi[3][3];   // [G][w] interface averages of the low / high face
+    for (int t = threadIdx.x; t < NXF + NYF; t += RB_TX * RB_TY) {
+        const bool xd = t < NXF;
+        const int q = xd ? t : t - NXF;
+        // face between cells (ilo, jlo) and (i, j): i - 1/2 (x) or j - 1/2 (y)
+        int i, j, ilo, jlo;
+        if (xd) {
+            i = i0 + q % (RB_TX + 1);
+            j = j0 + q / (RB_TX + 1);
+            ilo = i - 1;
+            jlo = j;
+            if (j > g.NY - 3 || i > g.NX - 2) continue;
+        } else {
+            i = i0 + q % RB_TX;
+            j = j0 + q / RB_TX;
+            ilo = i;
+            jlo = j - 1;
+            if (i > g.NX - 3 || j > g.NY - 2) continue;
+        }
+        const double* F = xd ? g.xf : g.yf;
+        const long long lo = (long long)jlo * g.NX + ilo, hi = (long long)j * g.NX + i;
 #pragma unroll
-    for (int G = 0; G < 3; ++G) {
-        double a[3], c[3];
-        prim3(F, N, lo, 3 + G, a);
-        prim3(F, N, cell, G, c);
+        for (int G = 0; G < 3; ++G) {
+            double a[3], c[3];
+            prim3(F, N, lo, 3 + G, a);
+            prim3(F, N, hi, G, c);
 #pragma unroll
-        for (int w = 0; w < 3; ++w) hlo[G][w] = 0.5 * (a[w] + c[w]);
-        prim3(F, N, cell, 3 + G, a);
-        prim3(F, N, hi, G, c);
-#pragma unroll
-        for (int w = 0; w < 3; ++w) hhi[G][w] = 0.5 * (a[w] + c[w]);
+            for (int w = 0; w < 3; ++w) {
+                const double h = 0.5 * (a[w] + c[w]);
+                if (xd) hx[3 * G + w][j - j0][i - i0] = h;
+                else hy[3 * G + w][j - j0][i - i0] = h;
+            }
+        }
     }
-    const double ih = l ? g.K.idy : g.K.idx;
+    __syncthreads();
+    const int tx = threadIdx.x % RB_TX, ty = threadIdx.x / RB_TX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i > g.NX - 3 || j > g.NY - 3) return;
+    const long long cell = (long long)j * g.NX + i;
 #pragma unroll
-    for (int w = 0; w < 3; ++w) {
-        const double W0lo = GW0 * hlo[0][w] + GW1 * hlo[1][w] + GW0 * hlo[2][w];
-        const double W0hi = GW0 * hhi[0][w] + GW1 * hhi[1][w] + GW0 * hhi[2][w];
-        const double W1lo = GW0 * GS * (hlo[2][w] - hlo[0][w]);
-        const double W1hi = GW0 * GS * (hhi[2][w] - hhi[0][w]);
-        const double wbl = g.wb[(l * 3 + w) * N + cell];
-        const double d0 = (W0hi - W0lo) * ih;                    // moment 0
-        const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
-        const double d1 = (W1hi - W1lo) * ih;                    // transverse moment
-        double* R = g.rb + ((l * 3 + w) * 3) * N + cell;
-        R[0] = d0;
-        R[N] = l ? d1 : dm;       // xi moment
-        R[2 * N] = l ? dm : d1;   // eta moment
+    for (int l = 0; l < 2; ++l) {
+        const double ih = l ? g.K.idy : g.K.idx;
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            double hlo[3], hhi[3];
+#pragma unroll
+            for (int G = 0; G < 3; ++G) {
+                hlo[G] = l ? hy[3 * G + w][ty][tx] : hx[3 * G + w][ty][tx];
+                hhi[G] = l ? hy[3 * G + w][ty + 1][tx] : hx[3 * G + w][ty][tx + 1];
+            }
+            const double W0lo = GW0 * hlo[0] + GW1 * hlo[1] + GW0 * hlo[2];
+            const double W0hi = GW0 * hhi[0] + GW1 * hhi[1] + GW0 * hhi[2];
+            const double W1lo = GW0 * GS * (hlo[2] - hlo[0]);
+            const double W1hi = GW0 * GS * (hhi[2] - hhi[0]);
+            const double wbl = g.wb[(l * 3 + w) * N + cell];
+            const double d0 = (W0hi - W0lo) * ih;                    // moment 0
+            const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
+            const double d1 = (W1hi - W1lo) * ih;                    // transverse moment
+            double* R = g.rb + ((l * 3 + w) * 3) * N + cell;
+            R[0] = d0;
+            R[N] = l ? d1 : dm;       // xi moment
+            R[2 * N] = l ? dm : d1;   // eta moment
+        }
     }
 }
 
@@ -893,7 +940,11 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                     work = (long long)(g.NY - 2) * ((g.NX - 2 + t.recon - 1) / t.recon);
                     per = 1;
                     break;
-                case KB_RBAR: work = (long long)(g.NX - 4) * (g.NY - 4); per = RB_CELLS; break;
+                case KB_RBAR:    // tiles of RB_TX x RB_TY cells
+                    work = (long long)((g.NX - 4 + RB_TX - 1) / RB_TX) *
+                           ((g.NY - 4 + RB_TY - 1) / RB_TY);
+                    per = 1;
+                    break;
                 case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
                 case KB_FLUX0: work = (long long)(g.nx + 1) * g.ny; per = t.flux; break;
                 case KB_FLUX1: work = (long long)g.nx * (g.ny + 1); per = t.flux; break;
@@ -935,7 +986,7 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
     else k_recon2<32><<<b.blocks(KB_RECON), 256, 0, st>>>(b.arg(KB_RECON), si);
     tend(tm, st);
     tbeg(tm, KC_RBAR, st);
-    k_rbar2<<<b.blocks(KB_RBAR), 2 * RB_CELLS, 0, st>>>(b.arg(KB_RBAR));
+    k_rbar2<<<b.blocks(KB_RBAR), RB_TX * RB_TY, 0, st>>>(b.arg(KB_RBAR));
     tend(tm, st);
     tbeg(tm, KC_GRAD, st);
     if (b.tiles.grad == 64) k_grad2<64><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));

@@ -83,6 +83,7 @@ hw::Consts make_consts(const Inst& c) {
     hw::Consts K{};
     K.gamma = c.phys.gamma;
     K.gm1 = c.phys.gamma - 1.0;
+    K.igm1 = 1.0 / K.gm1;
     K.Pr = c.phys.Pr;
     K.mu_ref = c.phys.mu_ref;
     K.mu_exp = c.phys.mu_exp;

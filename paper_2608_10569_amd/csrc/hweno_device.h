@@ -32,7 +32,7 @@ constexpr double G2D_1 = 1.0 / 400.0;
 
 // Scheme constants shared by every kernel of one grid.
 struct Consts {
-    double gamma, gm1;          // ratio of specific heats, gamma - 1
+    double gamma, gm1, igm1;    // ratio of specific heats, gamma - 1, 1 / (gamma - 1)
     double Pr;
     double mu_ref, mu_exp, T_ref;   // mu(T) = mu_ref (T/T_ref)^mu_exp, T = p/rho
     double eps_pp, eps_weno;
@@ -42,6 +42,17 @@ struct Consts {
 };
 
 __device__ __forceinline__ double dabs(double x) { return fabs(x); }
+
+// 1/d for normal d of either sign: the hardware reciprocal estimate refined by
+// two Newton steps r <- r + r (1 - d r) (within an ulp of the correctly
+// rounded reciprocal; about half the instructions of an IEEE division).  Used
+// where d is a density, a sound speed or a sum of positive terms.
+__device__ __forceinline__ double rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
 
 // Constants of the gradient reconstruction: linear weights also when only the
 // gradients are asked to use them.
@@ -139,7 +150,7 @@ __device__ __forceinline__ void hweno2d(const double* __restrict__ a, const Cons
         const double prod = p0123 * D4;
         double i0, i1, i2, i3, i4;
         if (prod < 1e300) {
-            const double inv = 1.0 / prod;
+            const double inv = rcp(prod);
             i0 = inv * (D1 * s234);
             i1 = inv * (D0 * s234);
             i2 = inv * (p01 * s34);
@@ -157,7 +168,7 @@ __device__ __forceinline__ void hweno2d(const double* __restrict__ a, const Cons
         const double t2 = G2D_1 * (1.0 + tau * i2);
         const double t3 = G2D_1 * (1.0 + tau * i3);
         const double t4 = G2D_1 * (1.0 + tau * i4);
-        const double it = 1.0 / (t0 + t1 + t2 + t3 + t4);
+        const double it = rcp(t0 + t1 + t2 + t3 + t4);
         w0 = t0 * it;
         w1 = t1 * it;
         w2 = t2 * it;
@@ -267,7 +278,7 @@ __device__ __forceinline__ double pressure1(const Consts& K, double r, double m,
 }
 __device__ __forceinline__ double pressure2(const Consts& K, double r, double m, double n,
                                             double E) {
-    return K.gm1 * (E - 0.5 * (m * m + n * n) / r);
+    return K.gm1 * (E - 0.5 * (m * m + n * n) * rcp(r));
 }
 
 // 1D total flux f = f^a - f^d with tau = (4/3) mu u_x, q = -gamma mu e_x / Pr.
@@ -315,8 +326,9 @@ template <int d>
 __device__ __forceinline__ void flux2(const Consts& K, const double* U, const double* s,
                                       double* f) {
     const double r = U[0], m = U[1], n = U[2], E = U[3];
-    const double u = m / r, v = n / r;
-    const double p = pressure2(K, r, m, n, E);
+    const double ir = rcp(r);
+    const double u = m * ir, v = n * ir;
+    const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gamma * mu / K.Pr;
@@ -339,8 +351,9 @@ __device__ __forceinline__ void flux2(const Consts& K, const double* U, const do
 __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, const double* s,
                                           bool dy, double* f) {
     const double r = U[0], m = U[1], n = U[2], E = U[3];
-    const double u = m / r, v = n / r;
-    const double p = pressure2(K, r, m, n, E);
+    const double ir = rcp(r);
+    const double u = m * ir, v = n * ir;
+    const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gamma * mu / K.Pr;
@@ -358,19 +371,19 @@ __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, cons
 template <int d>
 __device__ __forceinline__ double speed2(const Consts& K, const double* U, const double* s) {
     const double r = U[0], m = U[1], n = U[2], E = U[3];
-    const double p = pressure2(K, r, m, n, E);
-    const double e = p / (K.gm1 * r);
+    const double ir = rcp(r);
+    const double p = K.gm1 * (E - 0.5 * (m * m + n * n) * ir);
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gamma * mu / K.Pr;
-    const double un = (d == 0 ? m : n) / r;
+    const double un = (d == 0 ? m : n) * ir;
     const double q = kq * s[4 + d];
     const double t2 = d == 0 ? (t.xx - p) * (t.xx - p) + t.xy * t.xy
                              : t.xy * t.xy + (t.yy - p) * (t.yy - p);
-    const double r2e = r * r * e;
+    const double r2e = r * p * K.igm1;      // rho^2 e with e = p / ((gamma - 1) rho)
     const double root = sqrt(r * r * q * q + 2.0 * r2e * t2);
-    const double bpp = fabs(un) + (root + r * fabs(q)) / (2.0 * r2e);
-    const double ac = fabs(un) + sqrt(K.gamma * p / r);
+    const double bpp = fabs(un) + (root + r * fabs(q)) * (0.5 * rcp(r2e));
+    const double ac = fabs(un) + sqrt(K.gamma * p * ir);
     return ac >= bpp ? ac : bpp;
 }
 
@@ -396,13 +409,13 @@ __device__ __forceinline__ void eig1(const Consts& K, const double* Ub, Eig1& e)
 // Row k of L and row c of R of the x- (b = 0) or y-Jacobian (b = 1).
 __device__ __forceinline__ void eig2_rows(const Consts& K, const double* Ub, int b, int k,
                                           double* Lrow, double* Rrow) {
-    const double ir = 1.0 / Ub[0];
+    const double ir = rcp(Ub[0]);
     const double u = Ub[1] * ir, v = Ub[2] * ir;
     const double q2 = u * u + v * v;
     const double p = K.gm1 * (Ub[3] - 0.5 * Ub[0] * q2);
     const double c2 = K.gamma * p * ir;
     const double c = sqrt(c2);
-    const double ic = 1.0 / c;
+    const double ic = rcp(c);
     const double H = (Ub[3] + p) * ir;
     const double b1 = K.gm1 * ic * ic, b2 = 0.5 * b1 * q2;
     const double un = b ? v : u;       // normal velocity

@@ -23,3 +23,5 @@ inline hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t) { return h
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 inline long long __double_as_longlong(double x) { long long r; std::memcpy(&r, &x, 8); return r; }
 inline double __longlong_as_double(long long x) { double r; std::memcpy(&r, &x, 8); return r; }
+// the device reciprocal estimate; exact here, the Newton steps keep it so
+inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
