@@ -215,7 +215,11 @@ typedef struct hweno_timing {
     unsigned long long launches[8];     /* timed launches */
 } hweno_timing;
 
-/* enable != 0 starts recording (creates the events on first use). */
+/* enable = bit mask of the kernel classes above to record (bit k = class k;
+ * 0 stops recording; events are created on first use).  Each recorded launch
+ * adds two event records to the stream, so time a long run with the classes
+ * of interest only.  At most 1024 launches are recorded between two reads of
+ * the totals (rk_step reads them at the end of every step). */
 HWENO_API hweno_status hweno_set_timing(hweno_ctx* ctx, int enable);
 
 /* Synchronises the stream, returns the totals; reset != 0 zeroes them. */

@@ -213,8 +213,11 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     const Consts& K = g.K;
     const int tid = threadIdx.x;
     const int cl = tid & (RC_CELLS - 1);
-    const int bk = tid / RC_CELLS;
-    const int b = bk >> 2, k = bk & 3;
+    // 32 cells: wavefront w holds field k = w of both bases (lanes 0..31 the
+    // x-basis, 32..63 the y-basis), so k is uniform per wavefront
+    const int k = RC_CELLS == 32 ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid / RC_CELLS) & 3;
+    const int b = RC_CELLS == 32 ? (tid >> 5) & 1 : (tid / RC_CELLS) >> 2;
+    const int bk = b * 4 + k;
     // region: rows 1..NY-2, columns 1..NX-2, in row segments of RC_CELLS
     const int segs = (g.NX - 2 + RC_CELLS - 1) / RC_CELLS;
     const int j = 1 + lc.b / segs;
@@ -226,7 +229,23 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     // stencil tile: rows j-1..j+1, columns i0-1..i0+RC_CELLS (clamped to the
     // grid); tile row R = 3 c + r holds field c of grid row j-1+r.  All of a
     // thread's loads are issued before the first LDS write.
-    {
+    if constexpr (RC_CELLS == 32) {
+        // wavefront wv loads tile rows 9 wv .. 9 wv + 8, lane = column: the row
+        // base is wave-uniform and the lane offset is fixed
+        const int lane = tid & 63;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int gi = min(i0 - 1 + lane, g.NX - 1);
+        const bool col_ok = lane < TW;
+        double v[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int R = 9 * wv + q, c = R / 3, r = R - 3 * c;
+            if (col_ok) v[q] = S[c * N + (long long)(j - 1 + r) * g.NX + gi];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            if (col_ok) sh[(9 * wv + q) * TW + lane] = v[q];
+    } else {
         constexpr int NT = 8 * RC_CELLS;
         constexpr int NIT = (TILE + NT - 1) / NT;
         double v[NIT];
@@ -329,11 +348,11 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
 
     const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
     if (valid) {
-        double* F = b == 0 ? g.xf : g.yf;
+        double* F = (b == 0 ? g.xf : g.yf) + k * N + cell;
 #pragma unroll
         for (int o = 0; o < 6; ++o) {
             const double ut = k == 0 ? rbar + th1 * (U[o] - rbar) : U[o];
-            F[(o * 4 + k) * N + cell] = ub[k] + th2 * (ut - ub[k]);
+            F[o * 4 * N] = ub[k] + th2 * (ut - ub[k]);
         }
     }
     // wbar of (u, v, e) from this basis' unlimited volume values: thread k
@@ -370,9 +389,9 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
         }
     }
     if (valid) {
-        double* V = b == 0 ? g.xv : g.yv;
+        double* V = (b == 0 ? g.xv : g.yv) + k * N + cell;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) V[(q * 4 + k) * N + cell] = U[6 + q];
+        for (int q = 0; q < 9; ++q) V[q * 4 * N] = U[6 + q];
     }
     if (inter) g.vk[(b * 4 + k) * N + cell] = U[15];
     // CFL wave speed over the limited face traces of interior cells; thread k
@@ -551,27 +570,33 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
         for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
     }
     const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
+    // volume-flux quadratures of interior cells: 2 directions x 9 points over
+    // the cell's 6 threads, 3 points each (thread s: direction s / 3, points
+    // 3 (s % 3) .. 3 (s % 3) + 2); partial sums meet in LDS.  The state at the
+    // thread's points is loaded before the barrier.
+    const bool dy = s >= 3;
+    const int q0 = 3 * (s % 3);
+    double Uv[3][4];
+    if (inter) {
+        const double* V = (dy ? g.yv : g.xv) + cell;
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Uv[qq][c] = V[((q0 + qq) * 4 + c) * N];
+    }
 #pragma unroll
     for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * GR_CELLS + cl] = vo[q];
     __syncthreads();
-    // volume-flux quadratures of interior cells: 2 directions x 9 points over
-    // the cell's 6 threads, 3 points each (thread s: direction s / 3, points
-    // 3 (s % 3) .. 3 (s % 3) + 2); partial sums meet in LDS
-    const bool dy = s >= 3;
-    const int q0 = 3 * (s % 3);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (inter) {
-        const double* V = dy ? g.yv : g.xv;
 #pragma unroll
         for (int qq = 0; qq < 3; ++qq) {
             const int q = q0 + qq;
             const double wq = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
-            double Uq[4], sq[6], f[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) Uq[c] = V[(q * 4 + c) * N + cell];
+            double sq[6], f[4];
 #pragma unroll
             for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
-            flux2_dir(K, Uq, sq, dy, f);
+            flux2_dir(K, Uv[qq], sq, dy, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
         }

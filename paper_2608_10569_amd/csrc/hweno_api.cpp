@@ -84,6 +84,7 @@ hw::Consts make_consts(const Inst& c) {
     K.gamma = c.phys.gamma;
     K.gm1 = c.phys.gamma - 1.0;
     K.igm1 = 1.0 / K.gm1;
+    K.gPr = c.phys.gamma / c.phys.Pr;
     K.Pr = c.phys.Pr;
     K.mu_ref = c.phys.mu_ref;
     K.mu_exp = c.phys.mu_exp;
@@ -883,6 +884,7 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
     }
     if (!c->timer.init()) return HWENO_E_DEVICE;
     const bool was_on = c->timer.on;
+    const unsigned was_mask = c->timer.mask;
     const int si = c->batch ? 0 : c->cur;
     if (c->batch) {
         // every instance active for the timing passes
@@ -899,6 +901,7 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         c->timer.collect();
         c->timer.reset();
         c->timer.on = true;
+        c->timer.mask = (1u << hw::KC_COUNT) - 1u;
         for (int r = 0; r < reps; ++r) {
             TRY(reset(c));
             TRY(ghost(c, si));
@@ -908,6 +911,7 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         c->timer.collect();
         for (int k = 0; k < hw::KC_COUNT; ++k) ms[k] = c->timer.ms[k];
         c->timer.on = was_on;
+        c->timer.mask = was_mask;
         c->timer.reset();
         return HWENO_OK;
     };
@@ -963,6 +967,7 @@ HWENO_API hweno_status hweno_set_timing(hweno_ctx* c, int enable) {
     if (enable) {
         if (!c->timer.init()) return HWENO_E_DEVICE;
         c->timer.on = true;
+        c->timer.mask = (unsigned)enable & ((1u << hw::KC_COUNT) - 1u);
     } else {
         c->timer.on = false;
     }

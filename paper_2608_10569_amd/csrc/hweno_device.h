@@ -33,7 +33,7 @@ constexpr double G2D_1 = 1.0 / 400.0;
 // Scheme constants shared by every kernel of one grid.
 struct Consts {
     double gamma, gm1, igm1;    // ratio of specific heats, gamma - 1, 1 / (gamma - 1)
-    double Pr;
+    double Pr, gPr;             // Prandtl number, gamma / Pr
     double mu_ref, mu_exp, T_ref;   // mu(T) = mu_ref (T/T_ref)^mu_exp, T = p/rho
     double eps_pp, eps_weno;
     int linear;                 // 1: omega = gamma (test mode)
@@ -331,7 +331,7 @@ __device__ __forceinline__ void flux2(const Consts& K, const double* U, const do
     const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
-    const double kq = K.gamma * mu / K.Pr;
+    const double kq = K.gPr * mu;
     if (d == 0) {
         f[0] = m;
         f[1] = m * u + p - t.xx;
@@ -356,7 +356,7 @@ __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, cons
     const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
-    const double kq = K.gamma * mu / K.Pr;
+    const double kq = K.gPr * mu;
     const double un = dy ? v : u;           // velocity along the direction
     const double tnx = dy ? t.xy : t.xx;    // stress (x, direction)
     const double tny = dy ? t.yy : t.xy;    // stress (y, direction)
@@ -375,7 +375,7 @@ __device__ __forceinline__ double speed2(const Consts& K, const double* U, const
     const double p = K.gm1 * (E - 0.5 * (m * m + n * n) * ir);
     const double mu = viscosity(K, r, p);
     const Stress t = stresses(mu, s);
-    const double kq = K.gamma * mu / K.Pr;
+    const double kq = K.gPr * mu;
     const double un = (d == 0 ? m : n) * ir;
     const double q = kq * s[4 + d];
     const double t2 = d == 0 ? (t.xx - p) * (t.xx - p) + t.xy * t.xy

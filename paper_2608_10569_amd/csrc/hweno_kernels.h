@@ -87,9 +87,11 @@ struct Grid1 {
 enum { KC_GHOST = 0, KC_RECON, KC_RBAR, KC_GRAD, KC_FLUX, KC_UPDATE, KC_OTHER, KC_COUNT = 8 };
 
 struct Timer {
-    static constexpr int CAP = 128;
+    static constexpr int CAP = 1024;
     bool on = false;
     bool ready = false;
+    bool open = false;          // a begin() was recorded and awaits its end()
+    unsigned mask = 0;          // kernel classes recorded (bit k = class k)
     int n = 0;
     int cls[CAP];
     hipEvent_t a[CAP], b[CAP];
@@ -109,14 +111,17 @@ struct Timer {
         for (int k = 0; k < KC_COUNT; ++k) { ms[k] = 0.0; launches[k] = 0; }
     }
     void begin(int k, hipStream_t st) {
-        if (!on || n >= CAP) return;
+        open = false;
+        if (!on || !((mask >> k) & 1u) || n >= CAP) return;
         cls[n] = k;
         (void)hipEventRecord(a[n], st);
+        open = true;
     }
     void end(hipStream_t st) {
-        if (!on || n >= CAP) return;
+        if (!open) return;
         (void)hipEventRecord(b[n], st);
         ++n;
+        open = false;
     }
     // after the stream has been synchronised
     void collect() {

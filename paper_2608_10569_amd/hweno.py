@@ -261,8 +261,15 @@ class Solver:
         check(lib().hweno_rk_step(self._h, float(dt), ctypes.byref(d)))
         return d.as_dict()
 
-    def set_timing(self, on=True):
-        check(lib().hweno_set_timing(self._h, int(bool(on))))
+    def set_timing(self, on=True, classes=None):
+        """Record HIP events around the launches of the given kernel classes
+        (names of KERNEL_CLASSES; all of them by default) until switched off."""
+        mask = 0
+        if on:
+            names = KERNEL_CLASSES if classes is None else classes
+            for nm in names:
+                mask |= 1 << KERNEL_CLASSES.index(nm)
+        check(lib().hweno_set_timing(self._h, mask))
 
     def tiles(self):
         t = TilesC()

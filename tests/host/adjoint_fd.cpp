@@ -27,6 +27,7 @@ static Consts consts(bool linear) {
     K.gm1 = 0.4;
     K.igm1 = 2.5;
     K.Pr = 0.72;
+    K.gPr = 1.4 / 0.72;
     K.mu_ref = 0.01;
     K.mu_exp = 0.0;
     K.T_ref = 1.0;

@@ -255,3 +255,25 @@ def test_checkpoint_resume_bitwise():
     Ua, ta = a.get_state()
     Uc2, tc2 = c.get_state()
     assert torch.equal(Ua, Uc2) and ta == tc2
+
+
+def test_timing_records_selected_classes_only():
+    """The event timer records the kernel classes asked for, over every step,
+    and the autotuner's own measurements leave that choice in place."""
+    U = workloads.random_smooth_2d(40, 30, seed=11, noise=1e-3)
+    s = hweno.Solver(40, 30, mu_ref=0.01)
+    s.set_state(to_dev(U))
+    s.set_timing(True, classes=['recon'])
+    for _ in range(4):
+        s.rk_step(0.0)
+    tm = s.timing(reset=True)
+    assert tm['recon'][1] == 12 and tm['recon'][0] > 0.0
+    assert all(v[1] == 0 for k, v in tm.items() if k != 'recon')
+    s.autotune(reps=1)
+    s.rk_step(0.0)
+    tm = s.timing(reset=True)
+    assert tm['recon'][1] == 3 and all(v[1] == 0 for k, v in tm.items() if k != 'recon')
+    s.set_timing(True)
+    s.rk_step(0.0)
+    tm = s.timing()
+    assert tm['ghost'][1] == 3 and tm['grad'][1] == 3 and tm['flux'][1] == 3
