@@ -136,6 +136,20 @@ HWENO_API hweno_status hweno_workspace_bytes(const hweno_ctx* ctx, size_t* bytes
  * it stays owned by the caller and must outlive the context's use. */
 HWENO_API hweno_status hweno_set_workspace(hweno_ctx* ctx, void* dev_ptr, size_t bytes);
 
+/* Inflow that varies along a side (Remark 4.1's prescribed inflow state, per
+ * boundary cell; Example 5.9's jet).  Single 2D grids only; `side` (0 xlo,
+ * 1 xhi, 2 ylo, 3 yhi) must be of kind HWENO_BC_INFLOW.  prim: host array of
+ * n primitive states (rho, u, v, p), row-major (n, 4), copied before return:
+ * n = ny for an x side (boundary rows bottom to top), n = nx for a y side
+ * (boundary columns left to right; the ghost columns beyond the corners take
+ * the end states).  Every ghost cell of boundary cell k gets state k with zero
+ * moments.  prim = NULL returns the side to its constant state.  Errors:
+ * HWENO_E_INVAL for a batch or 1D context, a side of another kind, a wrong n,
+ * or a state that is not finite with rho > 0 and p > 0.  Kept across
+ * hweno_set_workspace. */
+HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* ctx, int side, const double* prim,
+                                                int n);
+
 /* Stream (hipStream_t) on which all later work of this context is ordered. */
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* ctx, void* hip_stream);
 

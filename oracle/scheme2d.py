@@ -49,7 +49,11 @@ class Scheme2D:
 
     ``bc`` = (xlo, xhi, ylo, yhi) with kinds 'periodic', 'outflow', 'inflow',
     'slip' (reflective / symmetry) or 'noslip' (adiabatic no-slip wall).
-    ``inflow`` maps a side index to a conservative state (4,).
+    ``inflow`` maps a side index to a conservative state (4,), or to a profile
+    (4, n) with one state per boundary cell along the side (n = ny for the x
+    sides, bottom to top; n = nx for the y sides, left to right; the y-sweep's
+    ghost columns take the end states).  Remark 4.1 prescribes the inflow
+    state; Example 5.9 varies it along the boundary.
     """
 
     def __init__(self, nx, ny, x0, x1, y0, y1, phys=None, opts=None,
@@ -94,7 +98,11 @@ class Scheme2D:
                     Ug[(m,) + at(dst)[1:]] = (sgn[m] * s)[:, None] * Ug[(m,) + at(src)[1:]]
             elif kind == 'inflow':
                 st = np.asarray(self.inflow[2 * axis + side])
-                Ug[(0,) + at(dst)[1:]] = st[:, None]
+                if st.ndim == 2:                      # one state per boundary cell
+                    val = st if axis == 0 else np.pad(st, ((0, 0), (H, H)), mode='edge')
+                else:
+                    val = st[:, None]
+                Ug[(0,) + at(dst)[1:]] = val
                 for m in (1, 2):
                     Ug[(m,) + at(dst)[1:]] = 0.0
             else:

@@ -125,11 +125,12 @@ __device__ __forceinline__ Loc locate(const Batch& B) {
 // column, so corner cells compose the two rules.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N, long long dst,
-                                         long long src) {
-    if (sd.kind == 2) {   // inflow: prescribed average, zero moments
+                                         long long src, int k) {
+    if (sd.kind == 2) {   // inflow: prescribed average (of boundary cell k), zero moments
+        const double* st = sd.prof ? sd.prof + 4 * k : sd.inflow;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            S[c * N + dst] = sd.inflow[c];
+            S[c * N + dst] = st[c];
             S[(4 + c) * N + dst] = 0.0;
             S[(8 + c) * N + dst] = 0.0;
         }
@@ -161,7 +162,7 @@ __global__ void k_ghost2_x(Batch bt, int sidx) {
         si = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.nx - 1 : HALO + g.nx - d);
     }
     const long long row = (long long)j * g.NX;
-    fill_one(sd, S, g.ncell, row + di, row + si);
+    fill_one(sd, S, g.ncell, row + di, row + si, j - HALO);
 }
 
 __global__ void k_ghost2_y(Batch bt, int sidx) {
@@ -185,7 +186,9 @@ __global__ void k_ghost2_y(Batch bt, int sidx) {
         dj = HALO + g.ny - 1 + d;
         sj = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.ny - 1 : HALO + g.ny - d);
     }
-    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i);
+    // ghost columns take the profile's end states
+    const int k = min(max(i - HALO, 0), g.nx - 1);
+    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i, k);
 }
 
 // ---------------------------------------------------------------------------

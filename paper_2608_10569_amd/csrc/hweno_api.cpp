@@ -67,6 +67,10 @@ struct hweno_ctx {
     hipGraphExec_t gexec1 = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the graphs are recorded on
     hw::Timer timer;
+    // single 2D grid: inflow profiles (conservative, 4 per boundary cell) and
+    // their workspace copies
+    std::vector<double> prof_host[4];
+    double* prof_dev[4] = {nullptr, nullptr, nullptr, nullptr};
     hw::Timer* tm() { return timer.on ? &timer : nullptr; }
     const Inst& i0() const { return in[0]; }
     int dim() const { return in[0].grid.dim; }
@@ -111,6 +115,7 @@ void make_side(const Inst& c, int s, hw::Side& sd) {
     const int ncomp = dim + 2;
     const int axis = s / 2;               // 0: x-wall, 1: y-wall
     sd.kind = c.bcs.kind[s];
+    sd.prof = nullptr;
     for (int q = 0; q < 12; ++q) sd.sign[q] = 1.0;
     if (sd.kind == HWENO_BC_SLIP || sd.kind == HWENO_BC_NOSLIP) {
         for (int m = 0; m <= dim; ++m) {
@@ -226,6 +231,8 @@ size_t layout(hweno_ctx* c, char* base) {
         const size_t nint = (size_t)c->hg[0].nx * c->hg[0].ny;
         c->X1 = take(12 * nint);
         c->X2 = take(12 * nint);
+        for (int sd = 0; sd < 4; ++sd)
+            c->prof_dev[sd] = take(4 * (size_t)(sd < 2 ? c->hg[0].ny : c->hg[0].nx));
     }
     c->red = reinterpret_cast<hw::Reduce*>(take_bytes(n * sizeof(hw::Reduce)));
     c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
@@ -285,6 +292,20 @@ hweno_status upload_grids(hweno_ctx* c) {
     c->bl.tiles = c->tiles;
     drop_graphs(c);
     return HWENO_OK;
+}
+
+// Inflow profiles of a single 2D grid into the workspace; the grid's sides
+// point at them (or at nothing).  The grid descriptors are uploaded after.
+hweno_status upload_profiles(hweno_ctx* c) {
+    for (int sd = 0; sd < 4; ++sd) {
+        const std::vector<double>& h = c->prof_host[sd];
+        c->hg[0].side[sd].prof = nullptr;
+        if (h.empty()) continue;
+        TRY(dev(hipMemcpyAsync(c->prof_dev[sd], h.data(), h.size() * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream)));
+        c->hg[0].side[sd].prof = c->prof_dev[sd];
+    }
+    return dev(hipStreamSynchronize(c->stream));
 }
 
 hweno_status upload_state(hweno_ctx* c) {
@@ -532,9 +553,38 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) 
             st.status = 0;
         }
         TRY(upload_state(c));
+        if (!c->batch) TRY(upload_profiles(c));
         TRY(upload_grids(c));
     }
     return HWENO_OK;
+}
+
+HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* c, int side, const double* prim,
+                                                int n) {
+    if (!c || c->batch || c->dim() != 2 || side < 0 || side > 3) return HWENO_E_INVAL;
+    const Inst& in = c->i0();
+    if (in.bcs.kind[side] != HWENO_BC_INFLOW) return HWENO_E_INVAL;
+    std::vector<double> cons;
+    if (prim) {
+        if (n != (side < 2 ? in.grid.ny : in.grid.nx)) return HWENO_E_INVAL;
+        const double g = in.phys.gamma;
+        cons.resize(4 * (size_t)n);
+        for (int k = 0; k < n; ++k) {
+            const double r = prim[4 * k], u = prim[4 * k + 1], v = prim[4 * k + 2];
+            const double p = prim[4 * k + 3];
+            if (!std::isfinite(r) || !std::isfinite(u) || !std::isfinite(v) ||
+                !std::isfinite(p) || !(r > 0.0) || !(p > 0.0))
+                return HWENO_E_INVAL;
+            cons[4 * k] = r;
+            cons[4 * k + 1] = r * u;
+            cons[4 * k + 2] = r * v;
+            cons[4 * k + 3] = p / (g - 1.0) + 0.5 * r * (u * u + v * v);
+        }
+    }
+    c->prof_host[side] = std::move(cons);
+    if (!c->ws) return HWENO_OK;
+    TRY(upload_profiles(c));
+    return upload_grids(c);
 }
 
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* c, void* s) {

@@ -26,6 +26,9 @@ struct Side {
     int kind;             // HWENO_BC_* value
     double sign[12];      // multiplier per (moment, component) for walls
     double inflow[4];     // conservative inflow state
+    const double* prof;   // inflow profile: conservative state of boundary cell k at
+                          // prof[4 k .. 4 k + 3] (rows of an x side, columns of a y
+                          // side); null: the constant state above
 };
 
 // Persistent per-instance state of a batched run (device memory).  Kernels

@@ -16,7 +16,8 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
-           'hweno_set_workspace', 'hweno_set_stream', 'hweno_set_state', 'hweno_get_state',
+           'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_stream',
+           'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_rk_step', 'hweno_rk_step_source', 'hweno_residual_vjp',
            'hweno_rk_step_vjp',
            'hweno_set_timing', 'hweno_get_timing', 'hweno_status_string',
@@ -97,6 +98,7 @@ def lib():
         L.hweno_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.hweno_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.hweno_set_stream.argtypes = [vp, vp]
+        L.hweno_set_inflow_profile.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
@@ -190,6 +192,20 @@ class Solver:
 
     def set_stream(self, stream):
         check(lib().hweno_set_stream(self._h, ctypes.c_void_p(stream)))
+
+    def set_inflow_profile(self, side, prim):
+        """Inflow state per boundary cell of an inflow side (2D): ``prim`` of
+        shape (n, 4) with rows (rho, u, v, p), n = ny for sides 0/1 and nx for
+        sides 2/3; None restores the side's constant state."""
+        import numpy as np
+        if prim is None:
+            check(lib().hweno_set_inflow_profile(self._h, int(side), None, 0))
+            return
+        a = np.ascontiguousarray(prim, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != 4:
+            raise ValueError('inflow profile of shape (n, 4) expected')
+        check(lib().hweno_set_inflow_profile(self._h, int(side),
+                                             a.ctypes.data_as(ctypes.c_void_p), a.shape[0]))
 
     def _dev(self, U):
         import torch

@@ -176,6 +176,21 @@ def sedov_2d(n=160, gamma=1.4, e_blast=0.244816, extent=1.1):
     return U
 
 
+def mach2000_jet(nx=640, ny=320, gamma=5.0 / 3.0):
+    """Example 5.9 on [0, 1] x [-0.25, 0.25]: ambient (rho, u, v, p) =
+    (0.5, 0, 0, 0.4127) everywhere; the left side takes (5, 800, 0, 0.4127)
+    where the boundary cell's centre has |y| < 0.05 and (5, 0, 0, 0.4127)
+    elsewhere.  Returns U (3, 4, ny, nx) (zero moments) and the inflow profile
+    (ny, 4) of primitive states."""
+    U = np.zeros((3, 4, ny, nx))
+    U[0, 0] = 0.5
+    U[0, 3] = 0.4127 / (gamma - 1.0)
+    yc = -0.25 + (np.arange(ny) + 0.5) * (0.5 / ny)
+    prof = np.tile(np.array([5.0, 0.0, 0.0, 0.4127]), (ny, 1))
+    prof[np.abs(yc) < 0.05, 1] = 800.0
+    return U, prof
+
+
 def random_smooth_2d(nx, ny, seed, gamma=1.4, extent=(0.0, 1.0, 0.0, 1.0), noise=1e-4):
     """Smooth random periodic state (4 Fourier modes per field, Mach < 0.5)
     with small cell-level noise on the moments, for parity tests."""

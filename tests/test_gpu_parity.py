@@ -145,3 +145,56 @@ def test_rk1d_steps_smooth_wave():
     e = rel_err(fields1d(Ug.cpu().numpy()), fields1d(Uo))
     print('1D 20 steps: t gpu %.17g oracle %.17g err %.2e' % (tg, t, e))
     assert e < 1e-10 and abs(tg - t) < 1e-13
+
+
+def _cons(P, gamma=1.4):
+    """(n, 4) primitive rows -> (4, n) conservative states."""
+    r, u, v, p = P.T
+    return np.stack([r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)])
+
+
+def test_inflow_profile_residual_step_and_errors():
+    """Inflow that varies along two sides (x-low: one state per row, y-high:
+    one per column) against the oracle's profile ghosts; clearing a profile
+    restores the constant state; bad profiles are refused."""
+    nx, ny = 24, 20
+    U = workloads.random_smooth_2d(nx, ny, seed=9, noise=1e-3)
+    rng = np.random.default_rng(9)
+
+    def prof(n):
+        return np.column_stack([1.0 + 0.2 * rng.random(n), 0.3 * rng.standard_normal(n),
+                                0.3 * rng.standard_normal(n), 1.0 + 0.2 * rng.random(n)])
+    px, py = prof(ny), prof(nx)
+    bc = ('inflow', 'outflow', 'slip', 'inflow')
+    const = (1.1, 0.2, 0.0, 0.9)
+    s = hweno.Solver(nx, ny, mu_ref=0.01, bc=bc, inflow={0: const, 3: const})
+    s.set_inflow_profile(0, px)
+    s.set_inflow_profile(3, py)
+    R, V, _ = s.residual(to_dev(U))
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options(), bc=bc,
+                  inflow={0: _cons(px), 3: _cons(py)})
+    Ro, Vo, _ = sc.residual(U)
+    eR = rel_err(fields2d(R.cpu().numpy()), fields2d(Ro))
+    s.set_state(to_dev(U))
+    d = s.rk_step(0.0)
+    Uo, dto, _ = rk.rk3_step(sc, U, 0.0)
+    eS = rel_err(fields2d(s.get_state()[0].cpu().numpy()), fields2d(Uo))
+    print('inflow profiles: residual err %.2e, one step err %.2e' % (eR, eS))
+    assert eR < 1e-11 and eS < 1e-12 and abs(d['dt'] - dto) < 1e-14 * dto
+    # back to the constant state on both sides
+    s.set_inflow_profile(0, None)
+    s.set_inflow_profile(3, None)
+    R2, _, _ = s.residual(to_dev(U))
+    c = _cons(np.array([const]))[:, 0]
+    Rc, _, _ = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options(), bc=bc,
+                        inflow={0: c, 3: c}).residual(U)
+    assert rel_err(fields2d(R2.cpu().numpy()), fields2d(Rc)) < 1e-11
+    for side, p in ((0, px[:-1]), (1, px), (3, px)):          # wrong n, wrong kinds
+        with pytest.raises(hweno.HwenoError):
+            s.set_inflow_profile(side, p)
+    bad = px.copy()
+    bad[3, 0] = -1.0
+    with pytest.raises(hweno.HwenoError):
+        s.set_inflow_profile(0, bad)
+    b = hweno.Batch([dict(nx=8, ny=8, bc=bc, inflow={0: const, 3: const})])
+    assert hweno.lib().hweno_set_inflow_profile(b._h, 0, None, 0) == 1

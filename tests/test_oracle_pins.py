@@ -710,3 +710,28 @@ def test_high_reynolds_riemann_approaches_exact_solution(case):
     print(case, 'density L1 errors at N = 100, 200, 400:', ['%.2e' % e for e in errs])
     assert errs[0] / errs[1] > 1.5 and errs[1] / errs[2] > 1.5
     assert errs[2] < (1.5e-3 if case == 'sod' else 3e-3)
+
+
+def test_inflow_profile_ghosts():
+    """An inflow profile (one state per boundary cell, Example 5.9's jet) puts
+    each cell's state into its ghost cells with zero moments; a constant
+    profile is the constant inflow state exactly."""
+    nx, ny = 7, 5
+    rng = np.random.default_rng(5)
+    U = _random_state_2d(nx, ny, 3)
+    st = np.array([1.2, 0.3, -0.1, 2.5])
+    bc = ('inflow', 'outflow', 'slip', 'inflow')
+    a = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, PH, Options(), bc=bc, inflow={0: st, 3: st})
+    b = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, PH, Options(), bc=bc,
+                 inflow={0: np.tile(st[:, None], (1, ny)), 3: np.tile(st[:, None], (1, nx))})
+    assert np.array_equal(a.ghost(U), b.ghost(U))
+    prof_x = 1.0 + rng.random((4, ny))
+    prof_y = 1.0 + rng.random((4, nx))
+    c = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, PH, Options(), bc=bc, inflow={0: prof_x, 3: prof_y})
+    G = c.ghost(U)
+    H = 4
+    for k in range(H):
+        assert np.array_equal(G[0, :, H:H + ny, k], prof_x)
+        assert np.array_equal(G[0, :, H + ny + k, H:H + nx], prof_y)
+        assert np.array_equal(G[0, :, H + ny + k, :H], np.repeat(prof_y[:, :1], H, axis=1))
+        assert not G[1:, :, H:H + ny, k].any() and not G[1:, :, H + ny + k, :].any()
