@@ -198,3 +198,61 @@ def test_inflow_profile_residual_step_and_errors():
         s.set_inflow_profile(0, bad)
     b = hweno.Batch([dict(nx=8, ny=8, bc=bc, inflow={0: const, 3: const})])
     assert hweno.lib().hweno_set_inflow_profile(b._h, 0, None, 0) == 1
+
+
+def _equivariance_errors(residual, U):
+    """max field errors of residual(U) -> (F, V) under x -> -x and x <-> y."""
+    F, V = residual(U)
+    par = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None]
+    sg = np.array([1.0, -1.0, 1.0])
+    Um = np.stack([sg[m] * par * U[m][..., ::-1] for m in range(3)])
+    Fm, _ = residual(np.ascontiguousarray(Um))
+    want = np.stack([sg[m] * par * F[m][..., ::-1] for m in range(3)])
+    e_ref = rel_err(fields2d(Fm), fields2d(want))
+    perm = [0, 2, 1, 3]
+    Us = np.stack([U[m][perm].swapaxes(-1, -2) for m in (0, 2, 1)])
+    Fs, Vs = residual(np.ascontiguousarray(Us))
+    want = np.stack([F[m][perm].swapaxes(-1, -2) for m in (0, 2, 1)])
+    e_swap = rel_err(fields2d(Fs), fields2d(want))
+    V4 = V.reshape(2, 4, *V.shape[-2:])
+    wantV = np.stack([V4[m][perm].swapaxes(-1, -2) for m in (1, 0)])
+    e_v = rel_err(fields2d(Vs.reshape(wantV.shape)), fields2d(wantV))
+    return e_ref, e_swap, e_v
+
+
+def test_gpu_residual_equivariance():
+    """P13 on the device path: reflecting x (u odd, xi-moments flipped) or
+    exchanging x and y (with u <-> v and the xi/eta moments) commutes with the
+    GPU residual on a square no-slip box.  Smooth state: to rounding.  With
+    the limiter active (the 2D Sedov blast after three oracle steps, beta up
+    to 1e10) rounding is amplified, for the oracle as well: the GPU's error
+    stays within 10x the oracle's own."""
+    n = 28
+    bc = ('noslip',) * 4
+    s = hweno.Solver(n, n, mu_ref=0.01, bc=bc)
+
+    def gpu(U):
+        F, V, _ = s.residual(to_dev(U))
+        return F.cpu().numpy(), V.cpu().numpy()
+    sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options(), bc=bc)
+
+    def ora(U):
+        F, V, _ = sc.residual(U)
+        return F, V
+    U = workloads.random_smooth_2d(n, n, seed=21, noise=1e-3)
+    e = _equivariance_errors(gpu, U)
+    print('smooth: reflection %.2e, swap %.2e, swap of V %.2e' % e)
+    assert max(e) < 1e-11
+    ph = Physics(mu_ref=1e-3)
+    sed = Scheme2D(n, n, 0.0, 1.1, 0.0, 1.1, ph, Options(), bc=('slip', 'outflow') * 2)
+    X, t = workloads.sedov_2d(n), 0.0
+    for _ in range(3):
+        X, dt, _ = rk.rk3_step(sed, X, t)
+        t += dt
+    _, _, dg = s.residual(to_dev(X))
+    eg, eo = _equivariance_errors(gpu, X), _equivariance_errors(ora, X)
+    print('Sedov state (limiter cells %d): gpu %s, oracle %s'
+          % (dg['pp_cells'], ['%.1e' % v for v in eg], ['%.1e' % v for v in eo]))
+    assert dg['pp_cells'] > 0
+    for a, b in zip(eg, eo):
+        assert a < 10.0 * max(b, 1e-13)
