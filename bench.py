@@ -59,13 +59,14 @@ PEAK_HBM_GBS = 8000.0
 #   flux:  per face 6 point fluxes and PP speed bounds, 12 LF combinations.
 #   update: assembly of 12 residual entries and the stage combination.
 FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400}
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) scaled by the factors a 1 GiB copy gives in
-# the same process (FETCH x 2.0, WRITE x 1.0): recon reads 25,005 KiB and
-# writes 533,876 KiB per launch on this grid (tiles recon 32 / grad 32 /
-# flux 64, XCD-aware order), i.e. 51.2 MB in + 546.7 MB out.
-TRAFFIC_BYTES = {'recon': 597896744}
-TRAFFIC_TILES = {'recon': 32, 'grad': 32, 'flux': 64, 'order': 0, 'xcd': 1}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by the factors a 1 GiB device copy gives in the same process
+# (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
+# and for the kernels as they are now: e.g. recon with 16-cell tiles reads
+# 64.1 MB and writes 554.7 MB per launch.
+TRAFFIC_BYTES = {('recon', 16): 618803036, ('recon', 32): 604279657,
+                 ('grad', 32): 744265548, ('grad', 64): 701270401,
+                 ('rbar', None): 327999173, ('update', None): 272461195}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).
@@ -305,6 +306,7 @@ def main():
     value = cell_stages / el
     avg_s = ms / n / 1e3
     achieved = FLOPS[dom] * units_per_launch(dom) / avg_s / 1e12
+    traffic = TRAFFIC_BYTES.get((dom, tiles.get(dom)), TRAFFIC_BYTES.get((dom, None)))
     kern = {k: {'ms_total': round(v[0], 3), 'launches': v[1],
                 'us_avg': round(1e3 * v[0] / v[1], 2) if v[1] else None}
             for k, v in tm.items()}
@@ -322,9 +324,9 @@ def main():
         'roofline': {'bound': 'alu', 'kernel': dom, 'achieved': achieved,
                      'peak': PEAK_FP64_TFLOPS, 'unit': 'TFLOP/s',
                      'frac': achieved / PEAK_FP64_TFLOPS,
-                     'traffic': TRAFFIC_BYTES.get(dom),
-                     'traffic_unit': 'bytes per launch (counters, tiles %s)' % TRAFFIC_TILES,
-                     'traffic_gbs': (TRAFFIC_BYTES[dom] / avg_s / 1e9) if dom in TRAFFIC_BYTES else None,
+                     'traffic': traffic,
+                     'traffic_unit': 'HBM bytes per launch (rocprofv3 counters, calibrated)',
+                     'traffic_gbs': traffic / avg_s / 1e9 if traffic else None,
                      'flops_per_unit': FLOPS[dom], 'units_per_launch': units_per_launch(dom),
                      'us_per_launch': avg_s * 1e6, 'launches_timed': n},
         'hbm_frac_algorithmic': value * ALGO_BYTES_PER_CELL_STAGE / (PEAK_HBM_GBS * 1e9),
