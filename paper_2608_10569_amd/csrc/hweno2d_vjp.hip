@@ -448,29 +448,34 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     for (int c = 0; c < 4; ++c) ub[c] = S[c * N + cell];
     double Lr[4], Rr[4];
     eig2_rows(K, ub, b, k, Lr, Rr);
-    double a[17];
+    // projected stencil data of field k (recomputed before the scalar adjoint
+    // instead of being kept live through the limiter)
+    auto project = [&](const double* Lrow, double* a) {
 #pragma unroll
-    for (int s = 0; s < 9; ++s) {
-        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
-        double acc = 0.0;
+        for (int s = 0; s < 9; ++s) {
+            const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+            double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc += Lr[c] * S[c * N + nb];
-        a[s] = acc;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int s = 2 * e + 1;
-        const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
-        double ax = 0.0, ay = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            ax += Lr[c] * S[(4 + c) * N + nb];
-            ay += Lr[c] * S[(8 + c) * N + nb];
+            for (int c = 0; c < 4; ++c) acc += Lrow[c] * S[c * N + nb];
+            a[s] = acc;
         }
-        a[9 + e] = ax;
-        a[13 + e] = ay;
-    }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int s = 2 * e + 1;
+            const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+            double ax = 0.0, ay = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ax += Lrow[c] * S[(4 + c) * N + nb];
+                ay += Lrow[c] * S[(8 + c) * N + nb];
+            }
+            a[9 + e] = ax;
+            a[13 + e] = ay;
+        }
+    };
     {
+        double a[17];
+        project(Lr, a);
         double C[15], out[16];
         hweno2d(a, K, C);
         if (b == 0) eval_xface(C, out);
@@ -667,7 +672,13 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     if (b == 0) moment_xi_T(cb[15], Cb);
     else moment_eta_T(cb[15], Cb);
     double ab[17];
-    hweno2d_vjp(a, K, Cb, ab);
+    {
+        double Lk[4], a[17];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Lk[c] = shL[(bk * 4 + c) * AC + cl];
+        project(Lk, a);
+        hweno2d_vjp(a, K, Cb, ab);
+    }
 #pragma unroll
     for (int s = 0; s < 17; ++s) sha[(bk * 17 + s) * AC + cl] = ab[s];
     // L-bar row k: sum_s ab[s] * stencil value (component c)
