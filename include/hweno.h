@@ -150,6 +150,23 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* ctx, void* dev_ptr, size_t
 HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* ctx, int side, const double* prim,
                                                 int n);
 
+/* Inflow data that vary in time (Example 5.11's forced inflow).  Stores for
+ * `side` (kind HWENO_BC_INFLOW, single 2D grid) the profiles in force at the
+ * three stage times of the next hweno_rk_step_inflow call: prim1 at t^n,
+ * prim2 at t^n + dt, prim3 at t^n + dt/2 (the stage times of eq. (2.12)), each
+ * in the layout and with the checks of hweno_set_inflow_profile.  All three
+ * NULL clears the side's stage profiles.  Other calls keep using the side's
+ * profile or constant state. */
+HWENO_API hweno_status hweno_set_inflow_stages(hweno_ctx* ctx, int side, const double* prim1,
+                                               const double* prim2, const double* prim3, int n);
+
+/* One SSP-RK3 step of fixed size dt > 0 in which every side with stage
+ * profiles (hweno_set_inflow_stages) fills its ghost cells of stage k from
+ * profile k.  Stage times are fixed by dt, so a rejected stage is an error
+ * (HWENO_E_INADMISSIBLE) instead of a restart.  Single 2D grids only
+ * (HWENO_E_INVAL otherwise); diag as for hweno_rk_step. */
+HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* ctx, double dt, hweno_diag* diag);
+
 /* Stream (hipStream_t) on which all later work of this context is ordered. */
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* ctx, void* hip_stream);
 

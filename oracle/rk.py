@@ -61,15 +61,23 @@ def trial_dt(scheme, alpha, t, rule='paper'):
     return dt
 
 
-def rk3_step(scheme, U, t, dt=None, rule='paper', source=None):
+def rk3_step(scheme, U, t, dt=None, rule='paper', source=None, inflow=None):
     """One SSP-RK3 step.  Returns (U_new, dt_used, info).
 
     ``dt`` fixed, or None for the time-step rule.  ``source(t)`` returns the
     source moments to add to the residual at time t (manufactured solutions).
+    ``inflow(t)`` returns {side: inflow state or profile} in force at time t
+    (boundary data that vary in time, Example 5.11); each stage's residual
+    sees the boundary data of its own time, as it sees the source.
     """
     g = scheme.phys.gamma
     src = (lambda tt: None) if source is None else source
-    F0, V0, d0 = scheme.residual(U, src(t))
+
+    def residual(V, tt):
+        if inflow is not None:
+            scheme.inflow.update(inflow(tt))
+        return scheme.residual(V, src(tt))
+    F0, V0, d0 = residual(U, t)
     if dt is None:
         dt = trial_dt(scheme, d0['alpha'], t, rule)
     B0 = _base(U, V0)
@@ -79,12 +87,12 @@ def rk3_step(scheme, U, t, dt=None, rule='paper', source=None):
         U1 = B0 + dt * F0
         ok = admissible(U1, g)
         if ok:
-            F1, V1, d1 = scheme.residual(U1, src(t + dt))
+            F1, V1, d1 = residual(U1, t + dt)
             U2 = 0.75 * B0 + 0.25 * (_base(U1, V1) + dt * F1)
             ok = admissible(U2, g)
             pp += d1['pp_cells']
         if ok:
-            F2, V2, d2 = scheme.residual(U2, src(t + 0.5 * dt))
+            F2, V2, d2 = residual(U2, t + 0.5 * dt)
             U3 = (1.0 / 3.0) * B0 + (2.0 / 3.0) * (_base(U2, V2) + dt * F2)
             ok = admissible(U3, g)
             pp += d2['pp_cells']
@@ -98,14 +106,14 @@ def rk3_step(scheme, U, t, dt=None, rule='paper', source=None):
         dt = 0.5 * dt
 
 
-def run(scheme, U, t0, t1, rule='paper', source=None, dt=None, max_steps=10 ** 7):
+def run(scheme, U, t0, t1, rule='paper', source=None, dt=None, max_steps=10 ** 7, inflow=None):
     """Advance from t0 to t1 (the last step clipped).  Returns (U, t, nsteps)."""
     scheme.opts.t_final = t1
     t = t0
     n = 0
     while t < t1 - 1e-14 * max(1.0, abs(t1)) and n < max_steps:
         step_dt = None if dt is None else min(dt, t1 - t)
-        U, used, _ = rk3_step(scheme, U, t, step_dt, rule, source)
+        U, used, _ = rk3_step(scheme, U, t, step_dt, rule, source, inflow)
         t += used
         n += 1
     return U, t, n

@@ -125,9 +125,11 @@ __device__ __forceinline__ Loc locate(const Batch& B) {
 // column, so corner cells compose the two rules.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N, long long dst,
-                                         long long src, int k) {
+                                         long long src, int k, int n, int stage) {
     if (sd.kind == 2) {   // inflow: prescribed average (of boundary cell k), zero moments
-        const double* st = sd.prof ? sd.prof + 4 * k : sd.inflow;
+        const double* st = (stage >= 0 && sd.prof_stage) ? sd.prof_stage + 4 * (stage * n + k)
+                           : sd.prof                      ? sd.prof + 4 * k
+                                                          : sd.inflow;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             S[c * N + dst] = st[c];
@@ -140,7 +142,7 @@ __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N,
     for (int q = 0; q < 12; ++q) S[q * N + dst] = sd.sign[q] * S[q * N + src];
 }
 
-__global__ void k_ghost2_x(Batch bt, int sidx) {
+__global__ void k_ghost2_x(Batch bt, int sidx, int stage) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -162,10 +164,10 @@ __global__ void k_ghost2_x(Batch bt, int sidx) {
         si = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.nx - 1 : HALO + g.nx - d);
     }
     const long long row = (long long)j * g.NX;
-    fill_one(sd, S, g.ncell, row + di, row + si, j - HALO);
+    fill_one(sd, S, g.ncell, row + di, row + si, j - HALO, g.ny, stage);
 }
 
-__global__ void k_ghost2_y(Batch bt, int sidx) {
+__global__ void k_ghost2_y(Batch bt, int sidx, int stage) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -188,7 +190,7 @@ __global__ void k_ghost2_y(Batch bt, int sidx) {
     }
     // ghost columns take the profile's end states
     const int k = min(max(i - HALO, 0), g.nx - 1);
-    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i, k);
+    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i, k, g.nx, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,10 +1002,10 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm) {
+hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int stage) {
     tbeg(tm, KC_GHOST, st);
-    k_ghost2_x<<<b.blocks(KB_GHOSTX), 256, 0, st>>>(b.arg(KB_GHOSTX), si);
-    k_ghost2_y<<<b.blocks(KB_GHOSTY), 256, 0, st>>>(b.arg(KB_GHOSTY), si);
+    k_ghost2_x<<<b.blocks(KB_GHOSTX), 256, 0, st>>>(b.arg(KB_GHOSTX), si, stage);
+    k_ghost2_y<<<b.blocks(KB_GHOSTY), 256, 0, st>>>(b.arg(KB_GHOSTY), si, stage);
     tend(tm, st);
     return hipGetLastError();
 }

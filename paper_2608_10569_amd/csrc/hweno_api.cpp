@@ -71,6 +71,9 @@ struct hweno_ctx {
     // their workspace copies
     std::vector<double> prof_host[4];
     double* prof_dev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // inflow profiles of the three stages of the next fixed-step call, per side
+    std::vector<double> stage_host[4];
+    double* stage_dev[4] = {nullptr, nullptr, nullptr, nullptr};
     hw::Timer* tm() { return timer.on ? &timer : nullptr; }
     const Inst& i0() const { return in[0]; }
     int dim() const { return in[0].grid.dim; }
@@ -116,6 +119,7 @@ void make_side(const Inst& c, int s, hw::Side& sd) {
     const int axis = s / 2;               // 0: x-wall, 1: y-wall
     sd.kind = c.bcs.kind[s];
     sd.prof = nullptr;
+    sd.prof_stage = nullptr;
     for (int q = 0; q < 12; ++q) sd.sign[q] = 1.0;
     if (sd.kind == HWENO_BC_SLIP || sd.kind == HWENO_BC_NOSLIP) {
         for (int m = 0; m <= dim; ++m) {
@@ -231,8 +235,11 @@ size_t layout(hweno_ctx* c, char* base) {
         const size_t nint = (size_t)c->hg[0].nx * c->hg[0].ny;
         c->X1 = take(12 * nint);
         c->X2 = take(12 * nint);
-        for (int sd = 0; sd < 4; ++sd)
-            c->prof_dev[sd] = take(4 * (size_t)(sd < 2 ? c->hg[0].ny : c->hg[0].nx));
+        for (int sd = 0; sd < 4; ++sd) {
+            const size_t len = (size_t)(sd < 2 ? c->hg[0].ny : c->hg[0].nx);
+            c->prof_dev[sd] = take(4 * len);
+            c->stage_dev[sd] = take(12 * len);
+        }
     }
     c->red = reinterpret_cast<hw::Reduce*>(take_bytes(n * sizeof(hw::Reduce)));
     c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
@@ -300,10 +307,18 @@ hweno_status upload_profiles(hweno_ctx* c) {
     for (int sd = 0; sd < 4; ++sd) {
         const std::vector<double>& h = c->prof_host[sd];
         c->hg[0].side[sd].prof = nullptr;
-        if (h.empty()) continue;
-        TRY(dev(hipMemcpyAsync(c->prof_dev[sd], h.data(), h.size() * sizeof(double),
-                               hipMemcpyHostToDevice, c->stream)));
-        c->hg[0].side[sd].prof = c->prof_dev[sd];
+        if (!h.empty()) {
+            TRY(dev(hipMemcpyAsync(c->prof_dev[sd], h.data(), h.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, c->stream)));
+            c->hg[0].side[sd].prof = c->prof_dev[sd];
+        }
+        const std::vector<double>& q = c->stage_host[sd];
+        c->hg[0].side[sd].prof_stage = nullptr;
+        if (!q.empty()) {
+            TRY(dev(hipMemcpyAsync(c->stage_dev[sd], q.data(), q.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, c->stream)));
+            c->hg[0].side[sd].prof_stage = c->stage_dev[sd];
+        }
     }
     return dev(hipStreamSynchronize(c->stream));
 }
@@ -322,8 +337,8 @@ hweno_status download_state(hweno_ctx* c) {
 
 hw::Grid2& g2(hweno_ctx* c) { return c->hg[0]; }
 
-hweno_status ghost(hweno_ctx* c, int si) {
-    if (c->dim() == 2) return dev(hw::launch_ghost2(c->bl, si, c->stream, c->tm()));
+hweno_status ghost(hweno_ctx* c, int si, int stage = -1) {
+    if (c->dim() == 2) return dev(hw::launch_ghost2(c->bl, si, c->stream, c->tm(), stage));
     return dev(hw::launch_ghost1(c->g1, c->S1[si], c->stream, c->tm()));
 }
 
@@ -638,9 +653,12 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
 namespace {
 
 // One SSP-RK3 step of a single grid (eq. (2.12)); src[k] (may be null) are
-// source moments added to the residual of stage k+1; with sources the step
-// size is fixed and a rejected stage is an error instead of a restart.
-hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag* diag) {
+// source moments added to the residual of stage k+1; `staged`: the ghost fill
+// of stage k+1 takes the sides' stage-k+1 inflow profiles.  With sources or
+// staged inflow the step size is fixed and a rejected stage is an error
+// instead of a restart.
+hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag* diag,
+                  bool staged = false) {
     const bool two = c->dim() == 2;
     const bool auto_dt = !(dt > 0.0);
     double cfl_h, visc;
@@ -653,7 +671,7 @@ hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag*
         }
         return HWENO_OK;
     }
-    const int max_halvings = src ? 0 : c->i0().opt.max_halvings;
+    const int max_halvings = (src || staged) ? 0 : c->i0().opt.max_halvings;
     // state buffers: 2D by index into Grid2::S (the current one is `cur`);
     // 1D by index into S1 with S1[0] current
     const int a = two ? c->cur : 0, b = two ? 1 - c->cur : 1, s2 = 2;
@@ -669,17 +687,17 @@ hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag*
             if (two) TRY(dev(hw::launch_check2(c->bl, a, c->stream)));
             else TRY(dev(hw::launch_check1(c->g1, c->S1[0], c->stream)));
         }
-        TRY(ghost(c, a));
+        TRY(ghost(c, a, staged ? 0 : -1));
         TRY(residual(c, a));
         if (auto_dt && restarts == 0)
             TRY(dev(hw::launch_dt(c->red, cfl_h, visc, t_left, c->stream)));
         else
             TRY(dev(hw::launch_set_dt(c->red, cur_dt, c->stream)));
         TRY(update(c, 1, a, a, b, nullptr, nullptr, src1));
-        TRY(ghost(c, b));
+        TRY(ghost(c, b, staged ? 1 : -1));
         TRY(residual(c, b));
         TRY(update(c, 2, a, b, s2, nullptr, nullptr, src2));
-        TRY(ghost(c, s2));
+        TRY(ghost(c, s2, staged ? 2 : -1));
         TRY(residual(c, s2));
         TRY(update(c, 3, a, s2, b, nullptr, nullptr, src3));
         TRY(read_reduce(c, &r));
@@ -717,6 +735,47 @@ HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* c, double dt, const doubl
     if (!c->has_state) return HWENO_E_STATE;
     const double* src[3] = {src1, src2, src3};
     return step(c, dt, src, diag);
+}
+
+HWENO_API hweno_status hweno_set_inflow_stages(hweno_ctx* c, int side, const double* prim1,
+                                               const double* prim2, const double* prim3, int n) {
+    if (!c || c->batch || c->dim() != 2 || side < 0 || side > 3) return HWENO_E_INVAL;
+    const Inst& in = c->i0();
+    if (in.bcs.kind[side] != HWENO_BC_INFLOW) return HWENO_E_INVAL;
+    std::vector<double> cons;
+    if (prim1 || prim2 || prim3) {
+        if (!prim1 || !prim2 || !prim3 || n != (side < 2 ? in.grid.ny : in.grid.nx))
+            return HWENO_E_INVAL;
+        const double g = in.phys.gamma;
+        cons.resize(12 * (size_t)n);
+        const double* P[3] = {prim1, prim2, prim3};
+        for (int st = 0; st < 3; ++st) {
+            for (int k = 0; k < n; ++k) {
+                const double* q = P[st] + 4 * k;
+                const double r = q[0], u = q[1], v = q[2], p = q[3];
+                if (!std::isfinite(r) || !std::isfinite(u) || !std::isfinite(v) ||
+                    !std::isfinite(p) || !(r > 0.0) || !(p > 0.0))
+                    return HWENO_E_INVAL;
+                double* o = cons.data() + 4 * ((size_t)st * n + k);
+                o[0] = r;
+                o[1] = r * u;
+                o[2] = r * v;
+                o[3] = p / (g - 1.0) + 0.5 * r * (u * u + v * v);
+            }
+        }
+    }
+    c->stage_host[side] = std::move(cons);
+    if (!c->ws) return HWENO_OK;
+    TRY(upload_profiles(c));
+    return upload_grids(c);
+}
+
+HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* c, double dt, hweno_diag* diag) {
+    if (!c || !(dt > 0.0) || !std::isfinite(dt) || c->batch || c->dim() != 2)
+        return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (!c->has_state) return HWENO_E_STATE;
+    return step(c, dt, nullptr, diag, true);
 }
 
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,

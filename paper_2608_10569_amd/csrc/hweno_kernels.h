@@ -29,6 +29,9 @@ struct Side {
     const double* prof;   // inflow profile: conservative state of boundary cell k at
                           // prof[4 k .. 4 k + 3] (rows of an x side, columns of a y
                           // side); null: the constant state above
+    const double* prof_stage;   // profiles of the three RK stages, n cells each
+                                // (stage s, cell k at 4 (s n + k)); used only by
+                                // ghost fills that name a stage
 };
 
 // Persistent per-instance state of a batched run (device memory).  Kernels
@@ -190,7 +193,7 @@ hipError_t launch_reset(Reduce* red, hipStream_t st);
 hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream_t st);
 hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st);
 // 2D pipeline over every instance of b; state buffers by index into Grid2::S
-hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm);
+hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int stage = -1);
 hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm);
 // stage 0: write R (12) and Vhat (8) in interior layout (single grid);
 // stage 1..3: RK update S[iout] from S[i0] (U^n) and S[iin] (stage input);

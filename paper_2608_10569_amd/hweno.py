@@ -16,7 +16,8 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
-           'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_stream',
+           'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_inflow_stages',
+           'hweno_rk_step_inflow', 'hweno_set_stream',
            'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_rk_step', 'hweno_rk_step_source', 'hweno_residual_vjp',
            'hweno_rk_step_vjp',
@@ -99,6 +100,8 @@ def lib():
         L.hweno_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.hweno_set_stream.argtypes = [vp, vp]
         L.hweno_set_inflow_profile.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+        L.hweno_set_inflow_stages.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
+        L.hweno_rk_step_inflow.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
@@ -206,6 +209,27 @@ class Solver:
             raise ValueError('inflow profile of shape (n, 4) expected')
         check(lib().hweno_set_inflow_profile(self._h, int(side),
                                              a.ctypes.data_as(ctypes.c_void_p), a.shape[0]))
+
+    def set_inflow_stages(self, side, prim1, prim2, prim3):
+        """Inflow profiles of side ``side`` at the three stage times (t, t + dt,
+        t + dt/2) of the next rk_step_inflow; each of shape (n, 4), rows
+        (rho, u, v, p).  All None clears them."""
+        import numpy as np
+        if prim1 is None and prim2 is None and prim3 is None:
+            check(lib().hweno_set_inflow_stages(self._h, int(side), None, None, None, 0))
+            return
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (prim1, prim2, prim3)]
+        if any(a.ndim != 2 or a.shape[1] != 4 or a.shape != arrs[0].shape for a in arrs):
+            raise ValueError('three inflow profiles of equal shape (n, 4) expected')
+        check(lib().hweno_set_inflow_stages(self._h, int(side),
+                                            *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs],
+                                            arrs[0].shape[0]))
+
+    def rk_step_inflow(self, dt):
+        """One step of fixed dt with the stage inflow profiles; returns diag."""
+        d = Diag()
+        check(lib().hweno_rk_step_inflow(self._h, float(dt), ctypes.byref(d)))
+        return d.as_dict()
 
     def _dev(self, U):
         import torch

@@ -191,6 +191,40 @@ def mach2000_jet(nx=640, ny=320, gamma=5.0 / 3.0):
     return U, prof
 
 
+class ShockMixingLayer:
+    """Example 5.11 on [0, 200] x [-20, 20]: a mixing layer u = 2.5 +
+    0.5 tanh(2y), rho = 1.6374 above y = 0 and 0.3626 below, p = 0.3327,
+    forced at the inflow by v'(y, t) = sum_k a_k cos(2 pi k t / T0 + phi_k)
+    exp(-y^2 / b) (a_1 = a_2 = 0.05, phi = (0, pi/2), b = 10, T0 = 30 / 2.68);
+    the post-shock state (2.1101, 2.9709, -0.1367, 0.4754) enters through the
+    top, slip wall at the bottom, outflow on the right.  Initial state: the
+    inflow state at t = 0 in every column."""
+
+    extent = (0.0, 200.0, -20.0, 20.0)
+    bc = ('inflow', 'outflow', 'slip', 'inflow')
+    top = (2.1101, 2.9709, -0.1367, 0.4754)
+
+    def __init__(self, nx=500, ny=100, gamma=1.4):
+        self.nx, self.ny, self.gamma = nx, ny, gamma
+        self.yc = -20.0 + (np.arange(ny) + 0.5) * (40.0 / ny)
+
+    @staticmethod
+    def prim(y, t):
+        """(rho, u, v, p) of the inflow at heights y and time t."""
+        T0 = 30.0 / 2.68
+        v = sum(0.05 * np.cos(2.0 * np.pi * k * t / T0 + ph) * np.exp(-y * y / 10.0)
+                for k, ph in ((1, 0.0), (2, 0.5 * np.pi)))
+        rho = np.where(y > 0.0, 1.6374, 0.3626)
+        return rho, 2.5 + 0.5 * np.tanh(2.0 * y), v, np.full_like(y, 0.3327)
+
+    def inflow(self, t):
+        """Left-side profile (ny, 4) of primitive states at time t."""
+        return np.column_stack([np.broadcast_to(q, self.yc.shape) for q in self.prim(self.yc, t)])
+
+    def initial(self):
+        return project2d(lambda X, Y: self.prim(Y, 0.0), self.nx, self.ny, self.extent, self.gamma)
+
+
 def random_smooth_2d(nx, ny, seed, gamma=1.4, extent=(0.0, 1.0, 0.0, 1.0), noise=1e-4):
     """Smooth random periodic state (4 Fourier modes per field, Mach < 0.5)
     with small cell-level noise on the moments, for parity tests."""

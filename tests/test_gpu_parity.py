@@ -256,3 +256,37 @@ def test_gpu_residual_equivariance():
     assert dg['pp_cells'] > 0
     for a, b in zip(eg, eo):
         assert a < 10.0 * max(b, 1e-13)
+
+
+def test_time_dependent_inflow_steps_and_errors():
+    """Example 5.11's forced inflow: fixed steps with the left side's profile at
+    the three stage times (and the post-shock state on top) against the
+    oracle stepping with the same boundary data in time; refused inputs."""
+    m = workloads.ShockMixingLayer(50, 20)
+    g = 1.4
+    ph = dict(gamma=g, Pr=0.72, mu_ref=1.0 / 500.0)
+    s = hweno.Solver(m.nx, m.ny, extent=m.extent, bc=m.bc, inflow={0: m.top, 3: m.top}, **ph)
+    U = m.initial()
+    s.set_state(to_dev(U))
+    sc = Scheme2D(m.nx, m.ny, *m.extent, Physics(**ph), Options(), bc=m.bc,
+                  inflow={0: _cons(m.inflow(0.0), g), 3: _cons(np.array([m.top]), g)[:, 0]})
+    _, _, d0 = sc.residual(U)
+    dt = rk.trial_dt(sc, d0['alpha'], 0.0)
+    Uo, t = U, 0.0
+    for _ in range(4):
+        s.set_inflow_stages(0, m.inflow(t), m.inflow(t + dt), m.inflow(t + 0.5 * dt))
+        d = s.rk_step_inflow(dt)
+        Uo, _, _ = rk.rk3_step(sc, Uo, t, dt=dt, inflow=lambda tt: {0: _cons(m.inflow(tt), g)})
+        t += dt
+        assert d['restarts'] == 0 and abs(d['t'] - t) < 1e-12 * t
+    e = rel_err(fields2d(s.get_state()[0].cpu().numpy()), fields2d(Uo))
+    print('time-dependent inflow, 4 steps: state err %.2e' % e)
+    assert e < 1e-12
+    p = m.inflow(t)
+    with pytest.raises(hweno.HwenoError):
+        s.rk_step_inflow(0.0)
+    with pytest.raises(hweno.HwenoError):
+        s.set_inflow_stages(0, p[:-1], p[:-1], p[:-1])
+    with pytest.raises(hweno.HwenoError):
+        s.set_inflow_stages(1, p, p, p)                       # an outflow side
+    assert hweno.lib().hweno_set_inflow_stages(s._h, 0, None, None, None, 0) == 0

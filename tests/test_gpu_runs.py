@@ -277,3 +277,38 @@ def test_timing_records_selected_classes_only():
     s.rk_step(0.0)
     tm = s.timing()
     assert tm['ghost'][1] == 3 and tm['grad'][1] == 3 and tm['flux'][1] == 3
+
+
+def test_shock_mixing_layer_example_5_11():
+    """Example 5.11 on the paper's 500x100 grid to T = 120: the forced inflow
+    enters each stage at the stage's time (hweno_rk_step_inflow), the step
+    from the paper's rule on the step's initial state.  Every stage stays
+    admissible, the density stays within the range of the paper's contour
+    plot (0.3 .. 2.7), and the layer, thin upstream, has rolled up downstream
+    of the shock impingement."""
+    m = workloads.ShockMixingLayer(500, 100)
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1.0 / 500.0)
+    s = hweno.Solver(m.nx, m.ny, extent=m.extent, bc=m.bc, inflow={0: m.top, 3: m.top}, **ph)
+    s.set_state(to_dev(m.initial()))
+    t, steps, T, h = 0.0, 0, 120.0, 0.4
+    while t < T - 1e-9:
+        _, _, d = s.residual(s.get_state()[0])
+        dt = min(0.6 * h / d['alpha_star'], 0.001 * h * h / ph['mu_ref'], T - t)
+        s.set_inflow_stages(0, m.inflow(t), m.inflow(t + dt), m.inflow(t + 0.5 * dt))
+        d = s.rk_step_inflow(dt)
+        assert d['min_rho'] > 0.0 and d['min_p'] > 0.0
+        t += dt
+        steps += 1
+    rho = s.get_state()[0][0, 0].cpu().numpy()
+    xc = (np.arange(m.nx) + 0.5) * 200.0 / m.nx
+    band = np.abs(m.yc) < 10.0
+
+    def mixed(x0, x1):
+        cols = rho[:, (xc > x0) & (xc < x1)][band]
+        return float(np.mean((cols > 0.6) & (cols < 1.4)))
+    up, down = mixed(0.0, 60.0), mixed(140.0, 200.0)
+    print('Example 5.11: %d steps to T = %.1f, density %.3f .. %.3f, intermediate density '
+          'in |y| < 10: %.3f upstream (x < 60), %.3f downstream (x > 140)'
+          % (steps, t, rho.min(), rho.max(), up, down))
+    assert abs(t - T) < 1e-9 and 0.3 < rho.min() and rho.max() < 2.8
+    assert up < 0.08 and down > 2.5 * up

@@ -735,3 +735,32 @@ def test_inflow_profile_ghosts():
         assert np.array_equal(G[0, :, H + ny + k, H:H + nx], prof_y)
         assert np.array_equal(G[0, :, H + ny + k, :H], np.repeat(prof_y[:, :1], H, axis=1))
         assert not G[1:, :, H:H + ny, k].any() and not G[1:, :, H + ny + k, :].any()
+
+
+def test_time_dependent_inflow_stage_times():
+    """Boundary data that vary in time enter each stage at that stage's time
+    (t, t + dt, t + dt/2, eq. (2.12)), like the source; data constant in time
+    give the step of the static inflow bit for bit."""
+    from paper_2608_10569_amd import workloads
+    m = workloads.ShockMixingLayer(12, 8)
+    g = PH.gamma
+    r, u, v, p = m.top
+    top = np.array([r, r * u, r * v, p / (g - 1) + 0.5 * r * (u * u + v * v)])
+
+    def cons(P):
+        r, u, v, p = P.T
+        return np.stack([r, r * u, r * v, p / (g - 1) + 0.5 * r * (u * u + v * v)])
+    sc = Scheme2D(12, 8, *m.extent, PH, Options(), bc=m.bc, inflow={0: cons(m.inflow(0.0)), 3: top})
+    U = m.initial()
+    seen = []
+
+    def inflow(tt):
+        seen.append(tt)
+        return {0: cons(m.inflow(tt))}
+    t, dt = 3.0, 0.05
+    rk.rk3_step(sc, U, t, dt=dt, inflow=inflow)
+    assert seen == [t, t + dt, t + 0.5 * dt]
+    sc.inflow[0] = cons(m.inflow(0.0))
+    A, _, _ = rk.rk3_step(sc, U, t, dt=dt)
+    B, _, _ = rk.rk3_step(sc, U, t, dt=dt, inflow=lambda tt: {0: cons(m.inflow(0.0))})
+    assert np.array_equal(A, B)
