@@ -28,9 +28,13 @@ class InadmissibleError(RuntimeError):
     """More restarts than ``Options.max_halvings`` were needed."""
 
 
-def admissible(U, gamma):
-    """All cell averages finite with rho > 0 and p > 0 (strictly)."""
+def admissible(U, gamma, solid=None):
+    """All cell averages finite with rho > 0 and p > 0 (strictly); solid cells
+    of a masked domain are not checked."""
     Ub = np.real(U[0])
+    if solid is not None:
+        Ub = Ub[:, ~solid]
+        U = U[..., ~solid]
     if not np.all(np.isfinite(np.real(U))):
         return False
     return bool(np.min(Ub[0]) > 0.0 and np.min(pressure(Ub, gamma)) > 0.0)
@@ -72,6 +76,13 @@ def rk3_step(scheme, U, t, dt=None, rule='paper', source=None, inflow=None):
     """
     g = scheme.phys.gamma
     src = (lambda tt: None) if source is None else source
+    solid = getattr(scheme, 'solid', None)
+
+    def keep_solid(V):
+        """Solid cells of a masked domain keep U^n through the stages."""
+        if solid is not None:
+            V[..., solid] = U[..., solid]
+        return V
 
     def residual(V, tt):
         if inflow is not None:
@@ -84,17 +95,17 @@ def rk3_step(scheme, U, t, dt=None, rule='paper', source=None, inflow=None):
     info = dict(alpha=d0['alpha'], beta_max=d0['beta_max'], restarts=0, pp_cells=0)
     while True:
         pp = d0['pp_cells']
-        U1 = B0 + dt * F0
-        ok = admissible(U1, g)
+        U1 = keep_solid(B0 + dt * F0)
+        ok = admissible(U1, g, solid)
         if ok:
             F1, V1, d1 = residual(U1, t + dt)
-            U2 = 0.75 * B0 + 0.25 * (_base(U1, V1) + dt * F1)
-            ok = admissible(U2, g)
+            U2 = keep_solid(0.75 * B0 + 0.25 * (_base(U1, V1) + dt * F1))
+            ok = admissible(U2, g, solid)
             pp += d1['pp_cells']
         if ok:
             F2, V2, d2 = residual(U2, t + 0.5 * dt)
-            U3 = (1.0 / 3.0) * B0 + (2.0 / 3.0) * (_base(U2, V2) + dt * F2)
-            ok = admissible(U3, g)
+            U3 = keep_solid((1.0 / 3.0) * B0 + (2.0 / 3.0) * (_base(U2, V2) + dt * F2))
+            ok = admissible(U3, g, solid)
             pp += d2['pp_cells']
         if ok:
             info['pp_cells'] = pp

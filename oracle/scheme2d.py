@@ -57,7 +57,7 @@ class Scheme2D:
     """
 
     def __init__(self, nx, ny, x0, x1, y0, y1, phys=None, opts=None,
-                 bc=('periodic',) * 4, inflow=None):
+                 bc=('periodic',) * 4, inflow=None, solid=None, solid_wall='slip'):
         self.nx, self.ny = nx, ny
         self.dx = (x1 - x0) / nx
         self.dy = (y1 - y0) / ny
@@ -66,6 +66,48 @@ class Scheme2D:
         self.bc = tuple(bc)
         self.inflow = inflow or {}
         self.rec = Hweno2D()
+        # masked domain (Examples 5.8, 5.10): solid cells of the grid
+        self.solid = None if solid is None else np.asarray(solid, dtype=bool)
+        self.mirrors = [] if solid is None else self._mirror_map(solid_wall)
+
+    # -- walls inside the grid (masked domains) ------------------------------
+    def _mirror_map(self, wall):
+        """(dst (j, i), src (j, i), signs (3, 4)) for every solid cell within
+        HALO cells (in both directions) of a fluid cell: the mirror image, across
+        the nearest wall face along +x, -x, +y, -y (ties in that order), of a
+        fluid cell; reflective ('slip') or adiabatic no-slip wall signs as at
+        the box walls (Remark 4.1).  A mirror that leaves the grid or lands in
+        solid falls back to the first fluid cell in that direction."""
+        S = self.solid
+        ny, nx = S.shape
+        out = []
+        for j in range(ny):
+            for i in range(nx):
+                if not S[j, i]:
+                    continue
+                win = S[max(j - HALO, 0):j + HALO + 1, max(i - HALO, 0):i + HALO + 1]
+                if win.all():
+                    continue                      # deep inside the solid
+                best = None
+                for dj, di, axis in ((0, 1, 0), (0, -1, 0), (1, 0, 1), (-1, 0, 1)):
+                    k = 1
+                    while 0 <= j + k * dj < ny and 0 <= i + k * di < nx and S[j + k * dj, i + k * di]:
+                        k += 1
+                    if not (0 <= j + k * dj < ny and 0 <= i + k * di < nx):
+                        continue                  # no fluid this way
+                    if best is None or k < best[0]:
+                        best = (k, dj, di, axis)
+                k, dj, di, axis = best
+                js, is_ = j + (2 * k - 1) * dj, i + (2 * k - 1) * di
+                if not (0 <= js < ny and 0 <= is_ < nx) or S[js, is_]:
+                    js, is_ = j + k * dj, i + k * di
+                if wall == 'noslip':
+                    par = NOSLIP
+                else:
+                    par = SLIP_X if axis == 0 else SLIP_Y
+                mom = np.array([1.0, -1.0, 1.0]) if axis == 0 else np.array([1.0, 1.0, -1.0])
+                out.append(((j, i), (js, is_), mom[:, None] * par[None, :]))
+        return out
 
     # -- Remark 4.1 ---------------------------------------------------------
     def _fill(self, Ug, side, axis):
@@ -109,10 +151,13 @@ class Scheme2D:
                 raise ValueError(kind)
 
     def ghost(self, U):
-        """U[3, 4, ny, nx] -> Ug[3, 4, ny + 8, nx + 8]."""
+        """U[3, 4, ny, nx] -> Ug[3, 4, ny + 8, nx + 8].  Solid cells next to the
+        fluid are filled first (from fluid cells), then the box's halo."""
         H = HALO
         Ug = np.zeros(U.shape[:2] + (self.ny + 2 * H, self.nx + 2 * H), dtype=U.dtype)
         Ug[:, :, H:H + self.ny, H:H + self.nx] = U
+        for (j, i), (js, is_), sg in self.mirrors:
+            Ug[:, :, H + j, H + i] = sg * Ug[:, :, H + js, H + is_]
         for side in (0, 1):
             self._fill(Ug, side, 0)
         for side in (0, 1):
@@ -274,6 +319,9 @@ class Scheme2D:
             F = F + np.stack(source)
         inner = (Ellipsis, slice(3, 3 + ny), slice(3, 3 + nx))
         Vhat = r['vhat'][inner]
+        if self.solid is not None and self.solid.shape == (ny, nx):
+            F = np.where(self.solid, 0.0, F)            # solid cells carry no residual
+            Vhat = np.where(self.solid, 0.0, Vhat)
 
         # internals kept for the pin tests: gradients s[21 points, 6] of the
         # interior cells (x-face, y-face, volume points), weak moments

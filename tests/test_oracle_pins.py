@@ -764,3 +764,61 @@ def test_time_dependent_inflow_stage_times():
     A, _, _ = rk.rk3_step(sc, U, t, dt=dt)
     B, _, _ = rk.rk3_step(sc, U, t, dt=dt, inflow=lambda tt: {0: cons(m.inflow(0.0))})
     assert np.array_equal(A, B)
+
+
+@pytest.mark.parametrize('wall', ['slip', 'noslip'])
+@pytest.mark.parametrize('axis', [0, 1])
+def test_solid_cells_act_as_a_box_wall(wall, axis):
+    """Masked domains (Examples 5.8, 5.10): solid cells mirrored across the
+    nearest wall face reproduce the box wall's ghost rule, so a grid whose
+    last columns (rows) are solid gives the fluid cells exactly the residual of
+    the smaller box with that wall on its high side."""
+    nx, ny, k = 14, 14, 9                  # fluid: the first k columns (rows)
+    h = 0.125                              # the same cell size on both grids, exactly
+    PHv = Physics(mu_ref=0.02)
+    if axis == 0:
+        U = _random_state_2d(k, ny, 17)
+        big = np.zeros((3, 4, ny, nx))
+        big[..., :k] = U
+        big[0, 0, :, k:], big[0, 3, :, k:] = 1.0, 2.5       # any admissible filling
+        solid = np.zeros((ny, nx), bool)
+        solid[:, k:] = True
+        box = Scheme2D(k, ny, 0.0, k * h, 0.0, ny * h, PHv, Options(),
+                       bc=('outflow', wall, 'outflow', 'outflow'))
+        sc = Scheme2D(nx, ny, 0.0, nx * h, 0.0, ny * h, PHv, Options(),
+                      bc=('outflow', 'outflow', 'outflow', 'outflow'), solid=solid, solid_wall=wall)
+        Fb, Vb, _ = box.residual(U)
+        F, V, _ = sc.residual(big)
+        assert np.array_equal(F[..., :k], Fb) and np.array_equal(V[..., :k], Vb)
+        assert not F[..., k:].any()
+    else:
+        U = _random_state_2d(nx, k, 17)
+        big = np.zeros((3, 4, ny, nx))
+        big[:, :, :k] = U
+        big[0, 0, k:], big[0, 3, k:] = 1.0, 2.5
+        solid = np.zeros((ny, nx), bool)
+        solid[k:] = True
+        box = Scheme2D(nx, k, 0.0, nx * h, 0.0, k * h, PHv, Options(),
+                       bc=('outflow', 'outflow', 'outflow', wall))
+        sc = Scheme2D(nx, ny, 0.0, nx * h, 0.0, ny * h, PHv, Options(),
+                      bc=('outflow', 'outflow', 'outflow', 'outflow'), solid=solid, solid_wall=wall)
+        Fb, Vb, _ = box.residual(U)
+        F, V, _ = sc.residual(big)
+        assert np.array_equal(F[:, :, :k], Fb) and np.array_equal(V[:, :, :k], Vb)
+
+
+def test_gas_at_rest_around_a_step_stays_at_rest():
+    """A uniform gas at rest in an L-shaped domain (a solid block in a corner,
+    reflective walls): the residual vanishes in the fluid (mass and energy
+    exactly, momenta to rounding) and an RK step leaves the state unchanged."""
+    nx, ny = 16, 12
+    solid = np.zeros((ny, nx), bool)
+    solid[:5, :4] = True
+    U = np.zeros((3, 4, ny, nx))
+    U[0, 0], U[0, 3] = 1.4, 2.5
+    sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, PH, Options(), bc=('slip',) * 4, solid=solid)
+    F, V, _ = sc.residual(U)
+    assert not F[0, 0].any() and not F[0, 3].any()
+    assert np.abs(F).max() < 1e-13 and np.abs(V).max() < 1e-15
+    U1, dt, info = rk.rk3_step(sc, U, 0.0)
+    assert np.abs(U1 - U).max() < 1e-13 and info['restarts'] == 0
