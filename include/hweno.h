@@ -167,6 +167,22 @@ HWENO_API hweno_status hweno_set_inflow_stages(hweno_ctx* ctx, int side, const d
  * (HWENO_E_INVAL otherwise); diag as for hweno_rk_step. */
 HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* ctx, double dt, hweno_diag* diag);
 
+/* Masked domain (Examples 5.8 and 5.10: a non-rectangular domain inside the
+ * grid's rectangle).  mask: host array of ny x nx bytes, row-major (j * nx + i),
+ * nonzero = solid; copied before return.  Every solid cell within 4 cells of
+ * the fluid (in both directions) is filled before each residual as the
+ * mirror image, across the nearest wall face along +x, -x, +y, -y (ties in
+ * that order), of a fluid cell, with the parities of the box walls (Remark
+ * 4.1) for `wall` = HWENO_BC_SLIP (reflective) or HWENO_BC_NOSLIP (adiabatic
+ * no-slip); a mirror off the grid or in solid falls back to the first fluid
+ * cell in that direction.  Solid cells carry no residual (zeros from
+ * hweno_residual), keep their state through the RK stages, and are not
+ * checked for admissibility; their values in hweno_get_state are those of
+ * the last fill.  mask = NULL removes the mask.  Single 2D grids only; the
+ * reverse-mode calls refuse a masked grid.  Errors: HWENO_E_INVAL (batch or
+ * 1D context, another wall kind, no fluid cell). */
+HWENO_API hweno_status hweno_set_solid(hweno_ctx* ctx, const unsigned char* mask, int wall);
+
 /* Stream (hipStream_t) on which all later work of this context is ordered. */
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* ctx, void* hip_stream);
 

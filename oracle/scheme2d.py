@@ -97,6 +97,8 @@ class Scheme2D:
                         continue                  # no fluid this way
                     if best is None or k < best[0]:
                         best = (k, dj, di, axis)
+                if best is None:
+                    continue                      # fluid only diagonally: left as it is
                 k, dj, di, axis = best
                 js, is_ = j + (2 * k - 1) * dj, i + (2 * k - 1) * di
                 if not (0 <= js < ny and 0 <= is_ < nx) or S[js, is_]:

@@ -142,6 +142,28 @@ __device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N,
     for (int q = 0; q < 12; ++q) S[q * N + dst] = sd.sign[q] * S[q * N + src];
 }
 
+// Walls inside the grid (masked domains): solid cell = mirror image of a fluid
+// cell across the nearest wall face, with the box walls' parities (Remark 4.1).
+__global__ void k_solid2(const Grid2* gp, int sidx) {
+    const Grid2& g = *gp;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.nsolid) return;
+    double* S = g.S[sidx];
+    const long long N = g.ncell;
+    const long long d = g.sdst[t], s = g.ssrc[t];
+    const int dir = g.sdir[t];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool vel = g.solid_wall == 4 ? (c == 1 || c == 2) : (c == 1 + dir);
+            const bool mom = m == 1 + dir;
+            const double sg = (vel != mom) ? -1.0 : 1.0;
+            S[(m * 4 + c) * N + d] = sg * S[(m * 4 + c) * N + s];
+        }
+    }
+}
+
 __global__ void k_ghost2_x(Batch bt, int sidx, int stage) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
@@ -703,7 +725,23 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
     const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     double rmin = INFINITY, pmin = INFINITY;
     unsigned int bad = 0;
-    if (t < nint) {
+    const bool solid = t < nint && gsrc.solid && gsrc.solid[t];
+    if (solid) {
+        // solid cell of a masked domain: no residual, keeps the stage input,
+        // not checked
+        const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
+        const long long N = g.ncell;
+        const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
+        if (stage == 0) {
+#pragma unroll
+            for (int q = 0; q < 12; ++q) Rout[q * nint + t] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Vout[q * nint + t] = 0.0;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 12; ++q) Sout[q * N + cell] = Sin[q * N + cell];
+        }
+    } else if (t < nint) {
         const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
         const long long N = g.ncell;
         const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
@@ -814,7 +852,7 @@ __global__ __launch_bounds__(256) void k_check2(Batch bt, int si) {
     const long long nint = (long long)g.nx * g.ny;
     const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
     unsigned int bad = 0;
-    if (t < nint) {
+    if (t < nint && !(gsrc.solid && gsrc.solid[t])) {
         const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
         const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
         double q[12];
@@ -987,6 +1025,11 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
 
 hipError_t launch_check2(const BatchL& b, int si, hipStream_t st) {
     k_check2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), si);
+    return hipGetLastError();
+}
+
+hipError_t launch_solid2(const Grid2* g, int n, int si, hipStream_t st) {
+    if (n > 0) k_solid2<<<nblk(n, 256), 256, 0, st>>>(g, si);
     return hipGetLastError();
 }
 

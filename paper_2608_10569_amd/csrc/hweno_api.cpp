@@ -74,6 +74,14 @@ struct hweno_ctx {
     // inflow profiles of the three stages of the next fixed-step call, per side
     std::vector<double> stage_host[4];
     double* stage_dev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // masked domain (single 2D grid): interior mask and the mirror list
+    std::vector<unsigned char> solid_host;
+    std::vector<int> sdst_host, ssrc_host, sdir_host;
+    int solid_wall = 0;
+    unsigned char* solid_dev = nullptr;
+    int* sdst_dev = nullptr;
+    int* ssrc_dev = nullptr;
+    int* sdir_dev = nullptr;
     hw::Timer* tm() { return timer.on ? &timer : nullptr; }
     const Inst& i0() const { return in[0]; }
     int dim() const { return in[0].grid.dim; }
@@ -240,6 +248,10 @@ size_t layout(hweno_ctx* c, char* base) {
             c->prof_dev[sd] = take(4 * len);
             c->stage_dev[sd] = take(12 * len);
         }
+        c->solid_dev = reinterpret_cast<unsigned char*>(take_bytes(nint));
+        c->sdst_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
+        c->ssrc_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
+        c->sdir_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
     }
     c->red = reinterpret_cast<hw::Reduce*>(take_bytes(n * sizeof(hw::Reduce)));
     c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
@@ -323,6 +335,34 @@ hweno_status upload_profiles(hweno_ctx* c) {
     return dev(hipStreamSynchronize(c->stream));
 }
 
+// Mask and mirror list of a masked single grid into the workspace; the grid
+// descriptor points at them (or at nothing).
+hweno_status upload_solid(hweno_ctx* c) {
+    hw::Grid2& g = c->hg[0];
+    g.solid = nullptr;
+    g.sdst = g.ssrc = g.sdir = nullptr;
+    g.nsolid = 0;
+    g.solid_wall = c->solid_wall;
+    if (c->solid_host.empty()) return HWENO_OK;
+    TRY(dev(hipMemcpyAsync(c->solid_dev, c->solid_host.data(), c->solid_host.size(),
+                           hipMemcpyHostToDevice, c->stream)));
+    const size_t n = c->sdst_host.size();
+    if (n) {
+        TRY(dev(hipMemcpyAsync(c->sdst_dev, c->sdst_host.data(), n * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+        TRY(dev(hipMemcpyAsync(c->ssrc_dev, c->ssrc_host.data(), n * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+        TRY(dev(hipMemcpyAsync(c->sdir_dev, c->sdir_host.data(), n * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+    }
+    g.solid = c->solid_dev;
+    g.sdst = c->sdst_dev;
+    g.ssrc = c->ssrc_dev;
+    g.sdir = c->sdir_dev;
+    g.nsolid = (int)n;
+    return dev(hipStreamSynchronize(c->stream));
+}
+
 hweno_status upload_state(hweno_ctx* c) {
     TRY(dev(hipMemcpyAsync(c->dst, c->hst.data(), c->hst.size() * sizeof(hw::InstState),
                            hipMemcpyHostToDevice, c->stream)));
@@ -338,7 +378,11 @@ hweno_status download_state(hweno_ctx* c) {
 hw::Grid2& g2(hweno_ctx* c) { return c->hg[0]; }
 
 hweno_status ghost(hweno_ctx* c, int si, int stage = -1) {
-    if (c->dim() == 2) return dev(hw::launch_ghost2(c->bl, si, c->stream, c->tm(), stage));
+    if (c->dim() == 2) {
+        if (!c->batch && !c->sdst_host.empty())     // walls inside the grid first
+            TRY(dev(hw::launch_solid2(c->dg, (int)c->sdst_host.size(), si, c->stream)));
+        return dev(hw::launch_ghost2(c->bl, si, c->stream, c->tm(), stage));
+    }
     return dev(hw::launch_ghost1(c->g1, c->S1[si], c->stream, c->tm()));
 }
 
@@ -568,7 +612,10 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) 
             st.status = 0;
         }
         TRY(upload_state(c));
-        if (!c->batch) TRY(upload_profiles(c));
+        if (!c->batch) {
+            TRY(upload_profiles(c));
+            TRY(upload_solid(c));
+        }
         TRY(upload_grids(c));
     }
     return HWENO_OK;
@@ -599,6 +646,77 @@ HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* c, int side, const do
     c->prof_host[side] = std::move(cons);
     if (!c->ws) return HWENO_OK;
     TRY(upload_profiles(c));
+    return upload_grids(c);
+}
+
+namespace {
+// Mirror list of a mask (row-major ny x nx, nonzero = solid): every solid cell
+// with a fluid cell within HALO cells in both directions is the mirror image,
+// across the nearest wall face along +x, -x, +y, -y (ties in that order), of a
+// fluid cell; a mirror off the grid or in solid falls back to the first fluid
+// cell in that direction; a cell with fluid only diagonally is left as it is.
+void mirror_list(const unsigned char* m, int nx, int ny, int NX, std::vector<int>& dst,
+                 std::vector<int>& src, std::vector<int>& dir) {
+    auto solid = [&](int j, int i) { return m[(size_t)j * nx + i] != 0; };
+    auto in = [&](int j, int i) { return j >= 0 && j < ny && i >= 0 && i < nx; };
+    auto ghosted = [&](int j, int i) { return (j + HALO) * NX + i + HALO; };
+    const int DJ[4] = {0, 0, 1, -1}, DI[4] = {1, -1, 0, 0};
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            if (!solid(j, i)) continue;
+            bool near = false;
+            for (int jj = std::max(j - HALO, 0); jj <= std::min(j + HALO, ny - 1) && !near; ++jj)
+                for (int ii = std::max(i - HALO, 0); ii <= std::min(i + HALO, nx - 1); ++ii)
+                    if (!solid(jj, ii)) {
+                        near = true;
+                        break;
+                    }
+            if (!near) continue;
+            int bk = 0, bd = -1;
+            for (int d = 0; d < 4; ++d) {
+                int k = 1;
+                while (in(j + k * DJ[d], i + k * DI[d]) && solid(j + k * DJ[d], i + k * DI[d])) ++k;
+                if (!in(j + k * DJ[d], i + k * DI[d])) continue;
+                if (bd < 0 || k < bk) {
+                    bk = k;
+                    bd = d;
+                }
+            }
+            if (bd < 0) continue;
+            int js = j + (2 * bk - 1) * DJ[bd], is = i + (2 * bk - 1) * DI[bd];
+            if (!in(js, is) || solid(js, is)) {
+                js = j + bk * DJ[bd];
+                is = i + bk * DI[bd];
+            }
+            dst.push_back(ghosted(j, i));
+            src.push_back(ghosted(js, is));
+            dir.push_back(bd < 2 ? 0 : 1);
+        }
+    }
+}
+}  // namespace
+
+HWENO_API hweno_status hweno_set_solid(hweno_ctx* c, const unsigned char* mask, int wall) {
+    if (!c || c->batch || c->dim() != 2) return HWENO_E_INVAL;
+    const int nx = c->i0().grid.nx, ny = c->i0().grid.ny;
+    std::vector<unsigned char> m;
+    std::vector<int> dst, src, dir;
+    if (mask) {
+        if (wall != HWENO_BC_SLIP && wall != HWENO_BC_NOSLIP) return HWENO_E_INVAL;
+        m.assign(mask, mask + (size_t)nx * ny);
+        for (auto& v : m) v = v ? 1 : 0;
+        bool fluid = false;
+        for (auto v : m) fluid = fluid || v == 0;
+        if (!fluid) return HWENO_E_INVAL;
+        mirror_list(m.data(), nx, ny, nx + 2 * HALO, dst, src, dir);
+    }
+    c->solid_host = std::move(m);
+    c->sdst_host = std::move(dst);
+    c->ssrc_host = std::move(src);
+    c->sdir_host = std::move(dir);
+    c->solid_wall = wall;
+    if (!c->ws) return HWENO_OK;
+    TRY(upload_solid(c));
     return upload_grids(c);
 }
 
@@ -781,7 +899,8 @@ HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* c, double dt, hweno_diag*
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar) {
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
+        return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     const hw::Grid2& g = g2(c);
     TRY(dev(hw::launch_copy_in2(g, U, g.S[2], c->stream)));
@@ -807,7 +926,8 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
                                          const double* U3bar, double* U0bar, double* mu_bar) {
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0) return HWENO_E_INVAL;
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
+        return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     const hw::Grid2& g = g2(c);
     const long long nint = (long long)g.nx * g.ny;

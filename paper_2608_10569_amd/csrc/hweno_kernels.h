@@ -71,6 +71,15 @@ struct Grid2 {
     double* fx;   // 12: x-face fluxes at (j, i+1/2) (G*4 + c)
     double* fy;   // 12: y-face fluxes at (j+1/2, i)
     Reduce* red;
+    // masked domain (single grid): interior mask (1 = solid, j*nx + i) or null;
+    // solid cells next to the fluid: ghosted destination, ghosted mirror source
+    // and wall direction (0: x face, 1: y face); wall kind (slip or no-slip)
+    const unsigned char* solid;
+    const int* sdst;
+    const int* ssrc;
+    const int* sdir;
+    int nsolid;
+    int solid_wall;
 };
 
 struct Grid1 {
@@ -194,6 +203,9 @@ hipError_t launch_copy_in2(const Grid2& g, const double* U, double* S, hipStream
 hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStream_t st);
 // 2D pipeline over every instance of b; state buffers by index into Grid2::S
 hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int stage = -1);
+// Mirror fill of the solid cells next to the fluid of a single masked grid
+// (before the box halo); `g` is the device descriptor, n its nsolid.
+hipError_t launch_solid2(const Grid2* g, int n, int si, hipStream_t st);
 hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm);
 // stage 0: write R (12) and Vhat (8) in interior layout (single grid);
 // stage 1..3: RK update S[iout] from S[i0] (U^n) and S[iin] (stage input);

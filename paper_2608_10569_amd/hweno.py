@@ -17,7 +17,7 @@ BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_inflow_stages',
-           'hweno_rk_step_inflow', 'hweno_set_stream',
+           'hweno_rk_step_inflow', 'hweno_set_solid', 'hweno_set_stream',
            'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_rk_step', 'hweno_rk_step_source', 'hweno_residual_vjp',
            'hweno_rk_step_vjp',
@@ -102,6 +102,7 @@ def lib():
         L.hweno_set_inflow_profile.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
         L.hweno_set_inflow_stages.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
         L.hweno_rk_step_inflow.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
+        L.hweno_set_solid.argtypes = [vp, vp, ctypes.c_int]
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
@@ -224,6 +225,18 @@ class Solver:
         check(lib().hweno_set_inflow_stages(self._h, int(side),
                                             *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs],
                                             arrs[0].shape[0]))
+
+    def set_solid(self, mask, wall='slip'):
+        """Solid cells inside the grid (bool array (ny, nx)) with reflective
+        ('slip') or adiabatic no-slip ('noslip') walls; None removes the mask."""
+        import numpy as np
+        if mask is None:
+            check(lib().hweno_set_solid(self._h, None, 0))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.shape != (self.ny, self.nx):
+            raise ValueError('mask of shape (ny, nx) expected')
+        check(lib().hweno_set_solid(self._h, m.ctypes.data_as(ctypes.c_void_p), BC[wall]))
 
     def rk_step_inflow(self, dt):
         """One step of fixed dt with the stage inflow profiles; returns diag."""

@@ -191,6 +191,31 @@ def mach2000_jet(nx=640, ny=320, gamma=5.0 / 3.0):
     return U, prof
 
 
+def shock_diffraction(h=0.125, mach=5.09, gamma=1.4):
+    """Example 5.8: the domain [0,1]x[6,11] U [1,13]x[0,11] inside the grid of
+    [0,13]x[0,11] with square cells of size h (1/h integer, so the step's
+    faces are cell faces); a Mach-`mach` shock at x = 0.5 above the step
+    moving right into (rho, u, v, p) = (1.4, 0, 0, 1); the post-shock state
+    from the Rankine-Hugoniot relations.  Returns (U, solid mask (ny, nx),
+    post-shock primitive state)."""
+    nx, ny = int(round(13.0 / h)), int(round(11.0 / h))
+    m2 = mach * mach
+    r1, p1 = 1.4, 1.0
+    c1 = np.sqrt(gamma * p1 / r1)
+    r2 = r1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)
+    u2 = mach * c1 * (1.0 - r1 / r2)
+    xc = (np.arange(nx) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(xc, yc)
+    solid = (X < 1.0) & (Y < 6.0)
+    post = (X < 0.5) & ~solid
+    U = np.zeros((3, 4, ny, nx))
+    U[0] = np.where(post, _cons2(r2, u2, 0.0, p2, gamma)[:, None, None] * np.ones((4, ny, nx)),
+                    _cons2(r1, 0.0, 0.0, p1, gamma)[:, None, None] * np.ones((4, ny, nx)))
+    return U, solid, (r2, u2, 0.0, p2)
+
+
 class ShockMixingLayer:
     """Example 5.11 on [0, 200] x [-20, 20]: a mixing layer u = 2.5 +
     0.5 tanh(2y), rho = 1.6374 above y = 0 and 0.3626 below, p = 0.3327,

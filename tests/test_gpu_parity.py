@@ -5,6 +5,8 @@ Metric (per field = component x moment): max over cells of |gpu - oracle|
 divided by max over cells of |oracle|.
 """
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -290,3 +292,60 @@ def test_time_dependent_inflow_steps_and_errors():
     with pytest.raises(hweno.HwenoError):
         s.set_inflow_stages(1, p, p, p)                       # an outflow side
     assert hweno.lib().hweno_set_inflow_stages(s._h, 0, None, None, None, 0) == 0
+
+
+@pytest.mark.parametrize('wall', ['slip', 'noslip'])
+def test_masked_domain_residual_and_step(wall):
+    """Solid cells inside the grid (a block in a corner, and one away from the
+    box's sides so all four wall directions and the block's corners occur):
+    residual (zero in solid cells) and one RK step against the oracle's masked
+    domain; the step is compared on the fluid cells (the library keeps the
+    last mirror fill in solid cells)."""
+    nx, ny = 30, 24
+    U = workloads.random_smooth_2d(nx, ny, seed=31, noise=1e-3)
+    corner = np.zeros((ny, nx), bool)
+    corner[:10, :9] = True
+    inner = np.zeros((ny, nx), bool)
+    inner[8:15, 11:21] = True
+    for solid in (corner, inner):
+        bc = ('outflow',) * 4
+        s = hweno.Solver(nx, ny, mu_ref=0.01, bc=bc)
+        s.set_solid(solid, wall)
+        R, V, d = s.residual(to_dev(U))
+        R, V = R.cpu().numpy(), V.cpu().numpy()
+        sc = Scheme2D(nx, ny, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=0.01), Options(), bc=bc,
+                      solid=solid, solid_wall=wall)
+        Ro, Vo, do = sc.residual(U)
+        eR = rel_err(fields2d(R), fields2d(Ro))
+        eV = rel_err(fields2d(V), fields2d(Vo.reshape(8, ny, nx)))
+        assert not R[..., solid].any() and not V[..., solid].any()
+        s.set_state(to_dev(U))
+        dg = s.rk_step(0.0)
+        Uo, dto, _ = rk.rk3_step(sc, U, 0.0)
+        G = s.get_state()[0].cpu().numpy()
+        eS = rel_err(G[..., ~solid].reshape(12, -1), Uo[..., ~solid].reshape(12, -1))
+        print('%s block, %s wall: residual %.2e, V %.2e, step %.2e' %
+              ('corner' if solid is corner else 'inner', wall, eR, eV, eS))
+        assert eR < 1e-11 and eV < 1e-12 and eS < 1e-12
+        assert abs(dg['dt'] - dto) < 1e-13 * dto and abs(d['alpha_star'] - do['alpha']) < 1e-13 * do['alpha']
+
+
+def test_masked_domain_refusals():
+    nx, ny = 12, 10
+    s = hweno.Solver(nx, ny, mu_ref=0.01, bc=('outflow',) * 4)
+    m = np.zeros((ny, nx), bool)
+    m[:4, :4] = True
+    with pytest.raises(hweno.HwenoError):
+        s.set_solid(m, 'outflow')                 # walls are reflective or no-slip
+    with pytest.raises(hweno.HwenoError):
+        s.set_solid(np.ones((ny, nx), bool))      # no fluid
+    s.set_solid(m)
+    U = workloads.random_smooth_2d(nx, ny, seed=2, noise=1e-3)
+    z = torch.zeros((3, 4, ny, nx), dtype=torch.float64, device=DEV)
+    with pytest.raises(hweno.HwenoError):
+        s.residual_vjp(to_dev(U), z)             # no reverse mode on a masked grid
+    s.set_solid(None)
+    s.residual_vjp(to_dev(U), z)
+    b = hweno.Batch([dict(nx=8, ny=8)])
+    mm = np.zeros((8, 8), np.uint8)
+    assert hweno.lib().hweno_set_solid(b._h, mm.ctypes.data_as(ctypes.c_void_p), 3) == 1
