@@ -58,7 +58,11 @@ PEAK_HBM_GBS = 8000.0
 #   rbar:  interface averages, face moments, 18 weak moments.
 #   flux:  per face 6 point fluxes and PP speed bounds, 12 LF combinations.
 #   update: assembly of 12 residual entries and the stage combination.
-FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400}
+#   fluxup: the face fluxes formed inside the update kernel, per cell: the
+#          fluxes of two faces and the update (faces on tile edges, formed
+#          twice, counted once).
+FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400,
+         'fluxup': 2 * 560 + 400}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the factors a 1 GiB device copy gives in the same process
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid

@@ -256,7 +256,8 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, doubl
  * context's stream around every launch while timing is enabled.  Classes:
  * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative
  * moments, 3 gradient reconstruction + volume flux, 4 face fluxes, 5 stage
- * update / assembly, 6 a whole batched run (hweno_batch_run), 7 unused. */
+ * update / assembly, 6 a whole batched run (hweno_batch_run), 7 face fluxes
+ * fused with the stage update / assembly (tiles.flux = 0). */
 typedef struct hweno_timing {
     double ms[8];                       /* summed elapsed milliseconds */
     unsigned long long launches[8];     /* timed launches */
@@ -317,7 +318,9 @@ HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* ctx, int i, hweno_diag* o
 typedef struct hweno_tiles {
     int recon;      /* cells per block of the characteristic reconstruction: 16 or 32 */
     int grad;       /* cells per block of the gradient reconstruction: 32 or 64 */
-    int flux;       /* faces per block of the face fluxes: 64 or 128 */
+    int flux;       /* faces per block of the face-flux kernels: 64 or 128; 0: no
+                       separate flux kernels -- the update kernel forms the fluxes
+                       of each 32 x 8 tile of cells in LDS (same results) */
     int order;      /* batch schedule: 0 instances as given, 1 largest first */
     int xcd;        /* 1: each of the 8 XCDs (own L2) takes a contiguous range of a
                        launch's blocks, so neighbouring rows share an L2; 0: launch order */
@@ -327,9 +330,11 @@ typedef struct hweno_tiles {
 HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* ctx, hweno_tiles* out);
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* ctx, const hweno_tiles* tiles);
 
-/* Autotuner: times `reps` residual evaluations of the current state(s) for
- * each candidate tile of every tunable kernel, keeps the fastest per kernel,
- * then (batches) the faster instance order, and sets them; `chosen` may be
+/* Autotuner: times `reps` residual evaluations (each with a stage update) of
+ * the current state(s) for each candidate tile of every tunable kernel, keeps
+ * the fastest per kernel (for the face fluxes: split or fused into the
+ * update, by the time of fluxes plus update), then the faster block order
+ * and (batches) the faster instance order, and sets them; `chosen` may be
  * NULL.  Needs the state(s) set; leaves them unchanged.  Synchronises. */
 HWENO_API hweno_status hweno_autotune(hweno_ctx* ctx, int reps, hweno_tiles* chosen);
 

@@ -12,6 +12,8 @@
 //   flux_x, flux_y   : PP Lax-Friedrichs fluxes at face Gauss points (eq. (3.3))
 //   update           : assembly of eq. (3.2) and the stage combination of the
 //                      SSP-RK3 scheme with modified moments (eq. (2.12))
+//   fluxup           : flux_x + flux_y + update in one kernel per tile of
+//                      cells, the face fluxes kept in LDS (a tile choice)
 //
 // Every intermediate lives in HBM, laid out component-major over the ghosted
 // grid so that consecutive lanes touch consecutive cells.
@@ -52,20 +54,31 @@ __device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
 #pragma unroll
         for (int w = 1; w < NT / 64; ++w) v = fmax(v, sh[w]);
         const unsigned long long k = dkey(v);
-        if (v > -INFINITY && k > *(volatile unsigned long long*)slot) atomicMax(slot, k);
+        if (v > -INFINITY && k > *(volatile HW_GLOBAL unsigned long long*)slot) atomicMax(slot, k);
     }
 }
+// Two minima in one pass (one LDS array per value: a second red_min call
+// right after the first could overwrite slots thread 0 is still reading).
 template <int NT>
-__device__ __forceinline__ void red_min(unsigned long long* slot, double v) {
-    __shared__ double sh[NT / 64];
-    v = wave_min(v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+__device__ __forceinline__ void red_min2(unsigned long long* sa, double a, unsigned long long* sb,
+                                         double b) {
+    __shared__ double sh[2][NT / 64];
+    a = wave_min(a);
+    b = wave_min(b);
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = a;
+        sh[1][threadIdx.x >> 6] = b;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 1; w < NT / 64; ++w) v = fmin(v, sh[w]);
-        const unsigned long long k = dkey(v);
-        if (v < INFINITY && k < *(volatile unsigned long long*)slot) atomicMin(slot, k);
+        for (int w = 1; w < NT / 64; ++w) {
+            a = fmin(a, sh[0][w]);
+            b = fmin(b, sh[1][w]);
+        }
+        const unsigned long long ka = dkey(a), kb = dkey(b);
+        if (a < INFINITY && ka < *(volatile HW_GLOBAL unsigned long long*)sa) atomicMin(sa, ka);
+        if (b < INFINITY && kb < *(volatile HW_GLOBAL unsigned long long*)sb) atomicMin(sb, kb);
     }
 }
 template <int NT>
@@ -707,31 +720,29 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
 }
 
 // ---------------------------------------------------------------------------
-// Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form).
-// stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3 stage.
+// Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form) of interior
+// cell (ii, jj), t = jj * nx + ii.  ff(G, c, fl, fr, gb, gt) gives component c
+// of the fluxes at Gauss point G of the cell's left, right, bottom and top
+// faces.  stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3
+// stage.  rmin, pmin and bad receive the cell's share of the admissibility
+// reductions (stages 1..3; solid cells give none).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, int iin, int iout,
-                                                 double* __restrict__ Rout,
-                                                 double* __restrict__ Vout,
-                                                 const double* __restrict__ src) {
-    const Loc lc = locate(bt);
-    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
-    if (!gsrc.st->active) return;
-    const Grid2 g = gsrc;
+template <class FF>
+__device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, long long t, int jj,
+                                            int ii, int stage, int i0, int iin, int iout,
+                                            double* __restrict__ Rout,
+                                            double* __restrict__ Vout,
+                                            const double* __restrict__ src, const FF& ff,
+                                            double& rmin, double& pmin, unsigned int& bad) {
     const double* __restrict__ S0 = gsrc.S[i0];
     const double* __restrict__ Sin = gsrc.S[iin];
     double* __restrict__ Sout = gsrc.S[iout];
     const long long nint = (long long)g.nx * g.ny;
-    const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
-    double rmin = INFINITY, pmin = INFINITY;
-    unsigned int bad = 0;
-    const bool solid = t < nint && gsrc.solid && gsrc.solid[t];
-    if (solid) {
+    const long long N = g.ncell;
+    const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
+    if (gsrc.solid && gsrc.solid[t]) {
         // solid cell of a masked domain: no residual, keeps the stage input,
         // not checked
-        const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
-        const long long N = g.ncell;
-        const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
         if (stage == 0) {
 #pragma unroll
             for (int q = 0; q < 12; ++q) Rout[q * nint + t] = 0.0;
@@ -741,84 +752,217 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
 #pragma unroll
             for (int q = 0; q < 12; ++q) Sout[q * N + cell] = Sin[q * N + cell];
         }
-    } else if (t < nint) {
+        return;
+    }
+    const double idx = g.K.idx, idy = g.K.idy;
+    double Fm[3][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double dfx = 0.0, sfx = 0.0, dfxe = 0.0, dgy = 0.0, sgy = 0.0, dgyx = 0.0;
+#pragma unroll
+        for (int G = 0; G < 3; ++G) {
+            const double wg = G == 1 ? GW1 : GW0;
+            const double xg = G == 0 ? -GS : (G == 1 ? 0.0 : GS);
+            double fl, fr, gb, gt;
+            ff(G, c, fl, fr, gb, gt);
+            dfx += wg * (fr - fl);
+            sfx += wg * (fl + fr);
+            dfxe += wg * xg * (fr - fl);
+            dgy += wg * (gt - gb);
+            sgy += wg * (gb + gt);
+            dgyx += wg * xg * (gt - gb);
+        }
+        Fm[0][c] = -dfx * idx - dgy * idy;
+        Fm[1][c] = -sfx * (0.5 * idx) - dgyx * idy + g.vf[c * N + cell] * idx;
+        Fm[2][c] = -dfxe * idx - sgy * (0.5 * idy) + g.vf[(4 + c) * N + cell] * idy;
+    }
+    if (src) {   // prescribed source moments (layout of R; single grid)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Fm[m][c] += src[(m * 4 + c) * nint + t];
+    }
+    if (stage == 0) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Rout[(m * 4 + c) * nint + t] = Fm[m][c];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Vout[q * nint + t] = g.vk[q * N + cell];
+        return;
+    }
+    const double dt = g.red->dt;
+    double nw[12];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double in0 = Sin[c * N + cell];
+        const double in1 = g.vk[c * N + cell];
+        const double in2 = g.vk[(4 + c) * N + cell];
+        if (stage == 1) {
+            nw[c] = in0 + dt * Fm[0][c];
+            nw[4 + c] = in1 + dt * Fm[1][c];
+            nw[8 + c] = in2 + dt * Fm[2][c];
+            g.vn[c * N + cell] = in1;
+            g.vn[(4 + c) * N + cell] = in2;
+        } else {
+            const double a = stage == 2 ? 0.75 : 1.0 / 3.0;
+            const double bb = stage == 2 ? 0.25 : 2.0 / 3.0;
+            nw[c] = a * S0[c * N + cell] + bb * (in0 + dt * Fm[0][c]);
+            nw[4 + c] = a * g.vn[c * N + cell] + bb * (in1 + dt * Fm[1][c]);
+            nw[8 + c] = a * g.vn[(4 + c) * N + cell] + bb * (in2 + dt * Fm[2][c]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) Sout[q * N + cell] = nw[q];
+    const double p = pressure2(g.K, nw[0], nw[1], nw[2], nw[3]);
+    rmin = nw[0];
+    pmin = p;
+    bool ok = nw[0] > 0.0 && p > 0.0;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) ok = ok && isfinite(nw[q]);
+    bad = ok ? 0u : 1u;
+}
+
+// Split path: the face fluxes come from k_flux2 through HBM.
+__global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, int iin, int iout,
+                                                 double* __restrict__ Rout,
+                                                 double* __restrict__ Vout,
+                                                 const double* __restrict__ src) {
+    const Loc lc = locate(bt);
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)lc.b * blockDim.x + threadIdx.x;
+    double rmin = INFINITY, pmin = INFINITY;
+    unsigned int bad = 0;
+    if (t < nint) {
         const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
         const long long N = g.ncell;
         const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
-        const double idx = g.K.idx, idy = g.K.idy;
-        double Fm[3][4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double dfx = 0.0, sfx = 0.0, dfxe = 0.0, dgy = 0.0, sgy = 0.0, dgyx = 0.0;
-#pragma unroll
-            for (int G = 0; G < 3; ++G) {
-                const double wg = G == 1 ? GW1 : GW0;
-                const double xg = G == 0 ? -GS : (G == 1 ? 0.0 : GS);
-                const double fr = g.fx[(G * 4 + c) * N + cell];
-                const double fl = g.fx[(G * 4 + c) * N + cell - 1];
-                const double gt = g.fy[(G * 4 + c) * N + cell];
-                const double gb = g.fy[(G * 4 + c) * N + cell - g.NX];
-                dfx += wg * (fr - fl);
-                sfx += wg * (fl + fr);
-                dfxe += wg * xg * (fr - fl);
-                dgy += wg * (gt - gb);
-                sgy += wg * (gb + gt);
-                dgyx += wg * xg * (gt - gb);
-            }
-            Fm[0][c] = -dfx * idx - dgy * idy;
-            Fm[1][c] = -sfx * (0.5 * idx) - dgyx * idy + g.vf[c * N + cell] * idx;
-            Fm[2][c] = -dfxe * idx - sgy * (0.5 * idy) + g.vf[(4 + c) * N + cell] * idy;
-        }
-        if (src) {   // prescribed source moments (layout of R; single grid)
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Fm[m][c] += src[(m * 4 + c) * nint + t];
-        }
-        if (stage == 0) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Rout[(m * 4 + c) * nint + t] = Fm[m][c];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) Vout[q * nint + t] = g.vk[q * N + cell];
-        } else {
-            const double dt = g.red->dt;
-            double nw[12];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double in0 = Sin[c * N + cell];
-                const double in1 = g.vk[c * N + cell];
-                const double in2 = g.vk[(4 + c) * N + cell];
-                if (stage == 1) {
-                    nw[c] = in0 + dt * Fm[0][c];
-                    nw[4 + c] = in1 + dt * Fm[1][c];
-                    nw[8 + c] = in2 + dt * Fm[2][c];
-                    g.vn[c * N + cell] = in1;
-                    g.vn[(4 + c) * N + cell] = in2;
-                } else {
-                    const double a = stage == 2 ? 0.75 : 1.0 / 3.0;
-                    const double bb = stage == 2 ? 0.25 : 2.0 / 3.0;
-                    nw[c] = a * S0[c * N + cell] + bb * (in0 + dt * Fm[0][c]);
-                    nw[4 + c] = a * g.vn[c * N + cell] + bb * (in1 + dt * Fm[1][c]);
-                    nw[8 + c] = a * g.vn[(4 + c) * N + cell] + bb * (in2 + dt * Fm[2][c]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 12; ++q) Sout[q * N + cell] = nw[q];
-            const double p = pressure2(g.K, nw[0], nw[1], nw[2], nw[3]);
-            rmin = nw[0];
-            pmin = p;
-            bool ok = nw[0] > 0.0 && p > 0.0;
-#pragma unroll
-            for (int q = 0; q < 12; ++q) ok = ok && isfinite(nw[q]);
-            bad = ok ? 0u : 1u;
-        }
+        auto ff = [&](int G, int c, double& fl, double& fr, double& gb, double& gt) {
+            fr = g.fx[(G * 4 + c) * N + cell];
+            fl = g.fx[(G * 4 + c) * N + cell - 1];
+            gt = g.fy[(G * 4 + c) * N + cell];
+            gb = g.fy[(G * 4 + c) * N + cell - g.NX];
+        };
+        update_cell(g, gsrc, t, jj, ii, stage, i0, iin, iout, Rout, Vout, src, ff, rmin, pmin,
+                    bad);
     }
     if (stage > 0) {
-        red_min<256>(&g.red->min_rho_key, rmin);
-        red_min<256>(&g.red->min_p_key, pmin);
+        red_min2<256>(&g.red->min_rho_key, rmin, &g.red->min_p_key, pmin);
         red_add32<256>(&g.red->bad[stage], bad);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes fused with the assembly and the stage update.  A block of 256
+// threads owns FU_TX x FU_TY interior cells.  First the fluxes of every face
+// of the tile at its three Gauss points go to LDS: thread (tx, ty) forms the
+// x-face left of its cell and the y-face below it, and one more pass forms the
+// x-faces right of the tile and the y-faces above it.  Then each thread
+// assembles and updates its cell.  A face on a tile edge is formed by both
+// tiles that share it.  The arithmetic per face and per cell is that of
+// k_flux2 and k_update2, so the two paths give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int FU_TX = 32, FU_TY = 8;
+
+// Fluxes of the face between cells cm and cp (direction d) at its three
+// Gauss points into o[(G * 4 + c) * stride]; returns the LF coefficient
+// (max over the three points and both sides).
+template <int d>
+__device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long long cp,
+                                             double* o, int stride) {
+    const Consts& K = g.K;
+    const long long N = g.ncell;
+    const double* F = d == 0 ? g.xf : g.yf;
+    const int pg = d == 0 ? 0 : 6;
+    double fs[3][4], du[3][4], bg[3];
+#pragma unroll
+    for (int G = 0; G < 3; ++G) {
+        double Um[4], Up[4], sm[6], sp[6], fm[4], fp[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Um[c] = F[((3 + G) * 4 + c) * N + cm];
+            Up[c] = F[(G * 4 + c) * N + cp];
+        }
+#pragma unroll
+        for (int z = 0; z < 6; ++z) {
+            sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
+            sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
+        }
+        flux2<d>(K, Um, sm, fm);
+        flux2<d>(K, Up, sp, fp);
+        bg[G] = fmax(speed2<d>(K, Um, sm), speed2<d>(K, Up, sp));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            fs[G][c] = fm[c] + fp[c];
+            du[G][c] = Up[c] - Um[c];
+        }
+    }
+    const double beta = fmax(fmax(bg[0], bg[1]), bg[2]);
+#pragma unroll
+    for (int G = 0; G < 3; ++G)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[(G * 4 + c) * stride] = 0.5 * (fs[G][c] - beta * du[G][c]);
+    return beta;
+}
+
+__global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, int i0, int iin,
+                                                           int iout, double* __restrict__ Rout,
+                                                           double* __restrict__ Vout,
+                                                           const double* __restrict__ src) {
+    constexpr int RX = FU_TX + 1;                              // x-face columns per row
+    constexpr int SX = FU_TY * RX, SY = (FU_TY + 1) * FU_TX;   // plane sizes
+    __shared__ double lx[12 * SX];   // [G*4 + c][row][face column 0..FU_TX]
+    __shared__ double ly[12 * SY];   // [G*4 + c][face row 0..FU_TY][column]
+    const Loc lc = locate(bt);
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const int tiles_x = (g.nx + FU_TX - 1) / FU_TX;
+    const int ii0 = (lc.b % tiles_x) * FU_TX, jj0 = (lc.b / tiles_x) * FU_TY;
+    const int tx = threadIdx.x % FU_TX, ty = threadIdx.x / FU_TX;
+    double bmax = -INFINITY;
+    // x-face left of interior cell (ii0 + fc, jj0 + row); fc = FU_TX and
+    // ii = nx (the domain's right boundary face) included
+    auto xface = [&](int fc, int row) {
+        const int ii = ii0 + fc, jj = jj0 + row;
+        if (ii > g.nx || jj >= g.ny) return;
+        const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
+        bmax = fmax(bmax, face_flux3<0>(g, cp - 1, cp, lx + row * RX + fc, SX));
+    };
+    // y-face below interior cell (ii0 + col, jj0 + fr); fr = FU_TY and jj = ny
+    // included
+    auto yface = [&](int fr, int col) {
+        const int ii = ii0 + col, jj = jj0 + fr;
+        if (ii >= g.nx || jj > g.ny) return;
+        const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
+        bmax = fmax(bmax, face_flux3<1>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
+    };
+    xface(tx, ty);
+    yface(ty, tx);
+    if (threadIdx.x < FU_TX) yface(FU_TY, threadIdx.x);                  // wavefront 0
+    else if (threadIdx.x >= 64 && threadIdx.x < 64 + FU_TY) xface(FU_TX, threadIdx.x - 64);
+    __syncthreads();
+    const int ii = ii0 + tx, jj = jj0 + ty;
+    double rmin = INFINITY, pmin = INFINITY;
+    unsigned int bad = 0;
+    if (ii < g.nx && jj < g.ny) {
+        auto ff = [&](int G, int c, double& fl, double& fr, double& gb, double& gt) {
+            const int q = G * 4 + c;
+            fl = lx[q * SX + ty * RX + tx];
+            fr = lx[q * SX + ty * RX + tx + 1];
+            gb = ly[q * SY + ty * FU_TX + tx];
+            gt = ly[q * SY + (ty + 1) * FU_TX + tx];
+        };
+        update_cell(g, gsrc, (long long)jj * g.nx + ii, jj, ii, stage, i0, iin, iout, Rout, Vout,
+                    src, ff, rmin, pmin, bad);
+    }
+    red_max<FU_TX * FU_TY>(&g.red->beta_key, bmax);
+    if (stage > 0) {
+        red_min2<FU_TX * FU_TY>(&g.red->min_rho_key, rmin, &g.red->min_p_key, pmin);
+        red_add32<FU_TX * FU_TY>(&g.red->bad[stage], bad);
     }
 }
 
@@ -1014,8 +1158,18 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                     per = 1;
                     break;
                 case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
-                case KB_FLUX0: work = (long long)(g.nx + 1) * g.ny; per = t.flux; break;
-                case KB_FLUX1: work = (long long)g.nx * (g.ny + 1); per = t.flux; break;
+                case KB_FLUX0:   // none when the update kernel forms the fluxes
+                    work = t.flux ? (long long)(g.nx + 1) * g.ny : 0;
+                    per = t.flux ? t.flux : 1;
+                    break;
+                case KB_FLUX1:
+                    work = t.flux ? (long long)g.nx * (g.ny + 1) : 0;
+                    per = t.flux ? t.flux : 1;
+                    break;
+                case KB_FLUXUP:  // tiles of FU_TX x FU_TY interior cells
+                    work = (long long)((g.nx + FU_TX - 1) / FU_TX) * ((g.ny + FU_TY - 1) / FU_TY);
+                    per = 1;
+                    break;
                 default: work = (long long)g.nx * g.ny; break;
             }
             st[p + 1] = st[p] + (int)nblk(work, per);
@@ -1065,6 +1219,7 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
     if (b.tiles.grad == 64) k_grad2<64><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
     else k_grad2<32><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
     tend(tm, st);
+    if (b.tiles.flux == 0) return hipGetLastError();   // fluxes formed by the update kernel
     tbeg(tm, KC_FLUX, st);
     if (b.tiles.flux == 128) {
         k_flux2<0, 128><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
@@ -1079,9 +1234,15 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
 
 hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
                           double* Vhat, hipStream_t st, Timer* tm, const double* src) {
-    tbeg(tm, KC_UPDATE, st);
-    k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R, Vhat,
-                                                  src);
+    if (b.tiles.flux == 0) {
+        tbeg(tm, KC_FLUXUP, st);
+        k_fluxup2<<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(b.arg(KB_FLUXUP), stage, i0, iin,
+                                                                 iout, R, Vhat, src);
+    } else {
+        tbeg(tm, KC_UPDATE, st);
+        k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R,
+                                                      Vhat, src);
+    }
     tend(tm, st);
     return hipGetLastError();
 }

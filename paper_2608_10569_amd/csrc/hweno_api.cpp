@@ -173,8 +173,8 @@ void rule(const Inst& c, double* cfl_h, double* visc_dt) {
 // Carves the workspace into the grids' arrays (or just sizes it if base == nullptr).
 size_t layout(hweno_ctx* c, char* base) {
     size_t off = 0;
-    auto take = [&](size_t ndouble) -> double* {
-        double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    auto take = [&](size_t ndouble) -> hw::gdouble* {
+        hw::gdouble* p = base ? (hw::gdouble*)(base + off) : nullptr;
         off += up(ndouble * sizeof(double));
         return p;
     };
@@ -199,7 +199,7 @@ size_t layout(hweno_ctx* c, char* base) {
         g.fh = take(3 * m);
         g.vf = take(3 * m);
         c->red = reinterpret_cast<hw::Reduce*>(take_bytes(sizeof(hw::Reduce)));
-        g.red = c->red;
+        g.red = (HW_GLOBAL hw::Reduce*)c->red;
         return off;
     }
     for (int p = 0; p < n; ++p) {
@@ -258,8 +258,8 @@ size_t layout(hweno_ctx* c, char* base) {
     c->dg = reinterpret_cast<hw::Grid2*>(take_bytes(n * sizeof(hw::Grid2)));
     c->dstart = reinterpret_cast<int*>(take_bytes(hw::KB_COUNT * (n + 1) * sizeof(int)));
     for (int p = 0; p < n; ++p) {
-        c->hg[p].red = c->red ? c->red + p : nullptr;
-        c->hg[p].st = c->dst ? c->dst + p : nullptr;
+        c->hg[p].red = (HW_GLOBAL hw::Reduce*)(c->red ? c->red + p : nullptr);
+        c->hg[p].st = (HW_GLOBAL hw::InstState*)(c->dst ? c->dst + p : nullptr);
     }
     return off;
 }
@@ -322,14 +322,14 @@ hweno_status upload_profiles(hweno_ctx* c) {
         if (!h.empty()) {
             TRY(dev(hipMemcpyAsync(c->prof_dev[sd], h.data(), h.size() * sizeof(double),
                                    hipMemcpyHostToDevice, c->stream)));
-            c->hg[0].side[sd].prof = c->prof_dev[sd];
+            c->hg[0].side[sd].prof = (const hw::gdouble*)c->prof_dev[sd];
         }
         const std::vector<double>& q = c->stage_host[sd];
         c->hg[0].side[sd].prof_stage = nullptr;
         if (!q.empty()) {
             TRY(dev(hipMemcpyAsync(c->stage_dev[sd], q.data(), q.size() * sizeof(double),
                                    hipMemcpyHostToDevice, c->stream)));
-            c->hg[0].side[sd].prof_stage = c->stage_dev[sd];
+            c->hg[0].side[sd].prof_stage = (const hw::gdouble*)c->stage_dev[sd];
         }
     }
     return dev(hipStreamSynchronize(c->stream));
@@ -355,10 +355,10 @@ hweno_status upload_solid(hweno_ctx* c) {
         TRY(dev(hipMemcpyAsync(c->sdir_dev, c->sdir_host.data(), n * sizeof(int),
                                hipMemcpyHostToDevice, c->stream)));
     }
-    g.solid = c->solid_dev;
-    g.sdst = c->sdst_dev;
-    g.ssrc = c->ssrc_dev;
-    g.sdir = c->sdir_dev;
+    g.solid = (const HW_GLOBAL unsigned char*)c->solid_dev;
+    g.sdst = (const HW_GLOBAL int*)c->sdst_dev;
+    g.ssrc = (const HW_GLOBAL int*)c->ssrc_dev;
+    g.sdir = (const HW_GLOBAL int*)c->sdir_dev;
     g.nsolid = (int)n;
     return dev(hipStreamSynchronize(c->stream));
 }
@@ -1090,7 +1090,7 @@ HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
     if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
     if ((t->recon != 16 && t->recon != 32) || (t->grad != 32 && t->grad != 64) ||
-        (t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1) ||
+        (t->flux != 0 && t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1) ||
         (t->xcd != 0 && t->xcd != 1))
         return HWENO_E_INVAL;
     c->tiles.recon = t->recon;
@@ -1121,21 +1121,24 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         for (auto& st : c->hst) st.active = 1;
         TRY(upload_state(c));
     }
-    // `reps` residual evaluations of the current states; ms per kernel class
-    auto measure = [&](double* ms) -> hweno_status {
+    // `reps` residual evaluations of the current states, each followed by a
+    // stage-1 update into the scratch state S[2] (the fluxes may be formed
+    // there); ms per kernel class
+    auto one = [&]() -> hweno_status {
         TRY(reset(c));
         TRY(ghost(c, si));
-        TRY(residual(c, si));                        // warm-up
+        TRY(residual(c, si));
+        TRY(dev(hw::launch_dt2(c->bl, c->stream)));
+        return update(c, 1, si, si, 2, nullptr, nullptr);
+    };
+    auto measure = [&](double* ms) -> hweno_status {
+        TRY(one());                                  // warm-up
         TRY(dev(hipStreamSynchronize(c->stream)));
         c->timer.collect();
         c->timer.reset();
         c->timer.on = true;
         c->timer.mask = (1u << hw::KC_COUNT) - 1u;
-        for (int r = 0; r < reps; ++r) {
-            TRY(reset(c));
-            TRY(ghost(c, si));
-            TRY(residual(c, si));
-        }
+        for (int r = 0; r < reps; ++r) TRY(one());
         TRY(dev(hipStreamSynchronize(c->stream)));
         c->timer.collect();
         for (int k = 0; k < hw::KC_COUNT; ++k) ms[k] = c->timer.ms[k];
@@ -1144,17 +1147,23 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         c->timer.reset();
         return HWENO_OK;
     };
-    const hw::Tiles cand[2] = {{16, 32, 64, 1}, {32, 64, 128, 1}};
-    double ms[2][hw::KC_COUNT];
-    for (int q = 0; q < 2; ++q) {
+    // candidate 2 differs in the flux path only: fused into the update
+    const hw::Tiles cand[3] = {{16, 32, 64, 1}, {32, 64, 128, 1}, {16, 32, 0, 1}};
+    double ms[3][hw::KC_COUNT];
+    for (int q = 0; q < 3; ++q) {
         c->tiles = cand[q];
         TRY(upload_grids(c));
         TRY(measure(ms[q]));
     }
+    // face fluxes + update: split (two flux kernels, then the update) or fused
+    double fu[3];
+    for (int q = 0; q < 3; ++q)
+        fu[q] = ms[q][hw::KC_FLUX] + ms[q][hw::KC_UPDATE] + ms[q][hw::KC_FLUXUP];
     hw::Tiles best;
     best.recon = ms[0][hw::KC_RECON] <= ms[1][hw::KC_RECON] ? cand[0].recon : cand[1].recon;
     best.grad = ms[0][hw::KC_GRAD] <= ms[1][hw::KC_GRAD] ? cand[0].grad : cand[1].grad;
-    best.flux = ms[0][hw::KC_FLUX] <= ms[1][hw::KC_FLUX] ? cand[0].flux : cand[1].flux;
+    const int fq = fu[2] < std::min(fu[0], fu[1]) ? 2 : (fu[0] <= fu[1] ? 0 : 1);
+    best.flux = cand[fq].flux;
     c->tiles = best;
     {
         // block order: XCD-aware or as launched

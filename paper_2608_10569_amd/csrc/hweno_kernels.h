@@ -7,6 +7,20 @@
 
 namespace hw {
 
+// Pointers into the workspace are read by the kernels from device memory
+// (the grid descriptors), where the compiler cannot tell their address space
+// and would access them with flat instructions.  In the device pass they are
+// typed as global-memory pointers, so the kernels use global loads and
+// stores, whose completion is tracked per instruction (flat accesses also
+// count against the LDS counter, which forces coarser waits).  Host code sees
+// plain pointers; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HW_GLOBAL __attribute__((address_space(1)))
+#else
+#define HW_GLOBAL
+#endif
+using gdouble = HW_GLOBAL double;
+
 // Device-side reduction slots, one set per grid.  Doubles are stored as
 // order-preserving keys (dkey) so that atomicMax / atomicMin work for any sign.
 struct Reduce {
@@ -26,10 +40,10 @@ struct Side {
     int kind;             // HWENO_BC_* value
     double sign[12];      // multiplier per (moment, component) for walls
     double inflow[4];     // conservative inflow state
-    const double* prof;   // inflow profile: conservative state of boundary cell k at
+    const gdouble* prof;   // inflow profile: conservative state of boundary cell k at
                           // prof[4 k .. 4 k + 3] (rows of an x side, columns of a y
                           // side); null: the constant state above
-    const double* prof_stage;   // profiles of the three RK stages, n cells each
+    const gdouble* prof_stage;   // profiles of the three RK stages, n cells each
                                 // (stage s, cell k at 4 (s n + k)); used only by
                                 // ghost fills that name a stage
 };
@@ -56,28 +70,28 @@ struct Grid2 {
     long long ncell;          // NX * NY
     Consts K;
     Side side[4];
-    double* S[4];  // 12 each: ghosted states (current, stage outputs, scratch)
-    InstState* st;
-    double* xf;   // 24: x-face traces (p*4 + c), p 0..2 left face, 3..5 right face
-    double* yf;   // 24: y-face traces, p 0..2 bottom face, 3..5 top face
-    double* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g
-    double* yv;   // 36: y-basis volume values
-    double* wb;   // 6:  wbar of (u, v, e) from x-basis, then from y-basis
-    double* vk;   // 8:  modified moments of the current input (hat-v 0..3, hat-w 4..7)
-    double* vn;   // 8:  modified moments of U^n (kept for stages 2 and 3)
-    double* rb;   // 18: weak moments ((l*3 + w)*3 + mom)
-    double* gf;   // 72: gradients at face points ((p*6 + s)), p 0..5 x-face, 6..11 y-face
-    double* vf;   // 8:  volume flux quadratures (sum f, sum g)
-    double* fx;   // 12: x-face fluxes at (j, i+1/2) (G*4 + c)
-    double* fy;   // 12: y-face fluxes at (j+1/2, i)
-    Reduce* red;
+    gdouble* S[4];  // 12 each: ghosted states (current, stage outputs, scratch)
+    HW_GLOBAL InstState* st;
+    gdouble* xf;   // 24: x-face traces (p*4 + c), p 0..2 left face, 3..5 right face
+    gdouble* yf;   // 24: y-face traces, p 0..2 bottom face, 3..5 top face
+    gdouble* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g
+    gdouble* yv;   // 36: y-basis volume values
+    gdouble* wb;   // 6:  wbar of (u, v, e) from x-basis, then from y-basis
+    gdouble* vk;   // 8:  modified moments of the current input (hat-v 0..3, hat-w 4..7)
+    gdouble* vn;   // 8:  modified moments of U^n (kept for stages 2 and 3)
+    gdouble* rb;   // 18: weak moments ((l*3 + w)*3 + mom)
+    gdouble* gf;   // 72: gradients at face points ((p*6 + s)), p 0..5 x-face, 6..11 y-face
+    gdouble* vf;   // 8:  volume flux quadratures (sum f, sum g)
+    gdouble* fx;   // 12: x-face fluxes at (j, i+1/2) (G*4 + c)
+    gdouble* fy;   // 12: y-face fluxes at (j+1/2, i)
+    HW_GLOBAL Reduce* red;
     // masked domain (single grid): interior mask (1 = solid, j*nx + i) or null;
     // solid cells next to the fluid: ghosted destination, ghosted mirror source
     // and wall direction (0: x face, 1: y face); wall kind (slip or no-slip)
-    const unsigned char* solid;
-    const int* sdst;
-    const int* ssrc;
-    const int* sdir;
+    const HW_GLOBAL unsigned char* solid;
+    const HW_GLOBAL int* sdst;
+    const HW_GLOBAL int* ssrc;
+    const HW_GLOBAL int* sdir;
     int nsolid;
     int solid_wall;
 };
@@ -86,20 +100,22 @@ struct Grid1 {
     int nx, NX;               // interior and ghosted (halo 4) sizes
     Consts K;
     Side side[2];
-    double* pts;  // 12: limited LGL point values (p*3 + c)
-    double* wb;   // 2: wbar of (u, e)
-    double* vk;   // 3: modified moment of the current input
-    double* vn;   // 3: modified moment of U^n
-    double* rb;   // 4: weak moments (w*2 + mom)
-    double* gr;   // 8: gradients at the LGL points (p*2 + w)
-    double* fh;   // 3: face flux at i+1/2
-    double* vf;   // 3: volume flux quadrature
-    Reduce* red;
+    gdouble* pts;  // 12: limited LGL point values (p*3 + c)
+    gdouble* wb;   // 2: wbar of (u, e)
+    gdouble* vk;   // 3: modified moment of the current input
+    gdouble* vn;   // 3: modified moment of U^n
+    gdouble* rb;   // 4: weak moments (w*2 + mom)
+    gdouble* gr;   // 8: gradients at the LGL points (p*2 + w)
+    gdouble* fh;   // 3: face flux at i+1/2
+    gdouble* vf;   // 3: volume flux quadrature
+    HW_GLOBAL Reduce* red;
 };
 
 // Optional per-kernel timing with HIP events on the launch stream.  Kernel
-// classes: 0 ghost, 1 recon, 2 rbar, 3 grad, 4 flux, 5 update, 6 other.
-enum { KC_GHOST = 0, KC_RECON, KC_RBAR, KC_GRAD, KC_FLUX, KC_UPDATE, KC_OTHER, KC_COUNT = 8 };
+// classes: 0 ghost, 1 recon, 2 rbar, 3 grad, 4 flux, 5 update, 6 other,
+// 7 face fluxes fused with the update.
+enum { KC_GHOST = 0, KC_RECON, KC_RBAR, KC_GRAD, KC_FLUX, KC_UPDATE, KC_OTHER, KC_FLUXUP,
+       KC_COUNT };
 
 struct Timer {
     static constexpr int CAP = 1024;
@@ -166,7 +182,7 @@ inline void tend(Timer* t, hipStream_t st) { if (t) t->end(st); }
 // block of the instance in slot p (start[n] = the launch's block count).
 // ---------------------------------------------------------------------------
 enum { KB_GHOSTX = 0, KB_GHOSTY, KB_RECON, KB_RBAR, KB_GRAD, KB_FLUX0, KB_FLUX1, KB_CELLS,
-       KB_COUNT };
+       KB_FLUXUP, KB_COUNT };
 
 struct Batch {
     const Grid2* g;
@@ -179,7 +195,7 @@ struct Batch {
 struct Tiles {
     int recon = 32;   // 16 or 32
     int grad = 32;    // 32 or 64
-    int flux = 64;    // 64 or 128
+    int flux = 64;    // 64 or 128; 0: face fluxes formed inside the update kernel
     int xcd = 1;      // 1: each XCD takes a contiguous range of a launch's blocks
 };
 

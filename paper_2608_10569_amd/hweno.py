@@ -26,8 +26,9 @@ EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_work
            'hweno_batch_run', 'hweno_batch_get_diag', 'hweno_get_tiles', 'hweno_set_tiles',
            'hweno_autotune')
 
-#: kernel classes of hweno_timing ('batch' = a whole hweno_batch_run graph)
-KERNEL_CLASSES = ('ghost', 'recon', 'rbar', 'grad', 'flux', 'update', 'batch')
+#: kernel classes of hweno_timing ('batch' = a whole hweno_batch_run graph,
+#: 'fluxup' = face fluxes fused with the update, tiles flux = 0)
+KERNEL_CLASSES = ('ghost', 'recon', 'rbar', 'grad', 'flux', 'update', 'batch', 'fluxup')
 
 
 class Grid(ctypes.Structure):
