@@ -66,11 +66,12 @@ FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400,
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the factors a 1 GiB device copy gives in the same process
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
-# and for the kernels as they are now: e.g. recon with 16-cell tiles reads
-# 64.1 MB and writes 554.7 MB per launch.
-TRAFFIC_BYTES = {('recon', 16): 618803036, ('recon', 32): 604279657,
-                 ('grad', 32): 744265548, ('grad', 64): 701270401,
-                 ('rbar', None): 327999173, ('update', None): 272461195}
+# and for the kernels as they are now: e.g. recon with 32-cell tiles reads
+# 53.2 MB and writes 553.0 MB per launch.
+TRAFFIC_BYTES = {('recon', 16): 605453715, ('recon', 32): 606145510,
+                 ('grad', 32): 745109657, ('grad', 64): 702618293,
+                 ('rbar', None): 309232508, ('update', None): 263533906,
+                 ('fluxup', None): 740175254}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).

@@ -488,8 +488,10 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
     const Grid2 g = gsrc;
-    const int tiles_x = (g.NX - 4 + RB_TX - 1) / RB_TX;
-    const int i0 = 2 + (lc.b % tiles_x) * RB_TX;
+    // tiles start at multiples of RB_TX columns of the ghosted grid (whole
+    // cache lines per row segment); columns 0 and 1 are outside the region
+    const int tiles_x = (g.NX - 2 + RB_TX - 1) / RB_TX;
+    const int i0 = (lc.b % tiles_x) * RB_TX;
     const int j0 = 2 + (lc.b / tiles_x) * RB_TY;
     const long long N = g.ncell;
     for (int t = threadIdx.x; t < NXF + NYF; t += RB_TX * RB_TY) {
@@ -502,13 +504,13 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
             j = j0 + q / (RB_TX + 1);
             ilo = i - 1;
             jlo = j;
-            if (j > g.NY - 3 || i > g.NX - 2) continue;
+            if (j > g.NY - 3 || i > g.NX - 2 || i < 2) continue;
         } else {
             i = i0 + q % RB_TX;
             j = j0 + q / RB_TX;
             ilo = i;
             jlo = j - 1;
-            if (i > g.NX - 3 || j > g.NY - 2) continue;
+            if (i > g.NX - 3 || j > g.NY - 2 || i < 2) continue;
         }
         const double* F = xd ? g.xf : g.yf;
         const long long lo = (long long)jlo * g.NX + ilo, hi = (long long)j * g.NX + i;
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
     __syncthreads();
     const int tx = threadIdx.x % RB_TX, ty = threadIdx.x / RB_TX;
     const int i = i0 + tx, j = j0 + ty;
-    if (i > g.NX - 3 || j > g.NY - 3) return;
+    if (i < 2 || i > g.NX - 3 || j > g.NY - 3) return;
     const long long cell = (long long)j * g.NX + i;
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
@@ -920,15 +922,18 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
     const Grid2 g = gsrc;
-    const int tiles_x = (g.nx + FU_TX - 1) / FU_TX;
-    const int ii0 = (lc.b % tiles_x) * FU_TX, jj0 = (lc.b / tiles_x) * FU_TY;
+    // tiles start at multiples of FU_TX columns of the ghosted grid, so that
+    // their row segments are whole cache lines; the first tile's leading
+    // columns are ghost cells and stay idle
+    const int tiles_x = (g.nx + HALO + FU_TX - 1) / FU_TX;
+    const int ii0 = (lc.b % tiles_x) * FU_TX - HALO, jj0 = (lc.b / tiles_x) * FU_TY;
     const int tx = threadIdx.x % FU_TX, ty = threadIdx.x / FU_TX;
     double bmax = -INFINITY;
     // x-face left of interior cell (ii0 + fc, jj0 + row); fc = FU_TX and
     // ii = nx (the domain's right boundary face) included
     auto xface = [&](int fc, int row) {
         const int ii = ii0 + fc, jj = jj0 + row;
-        if (ii > g.nx || jj >= g.ny) return;
+        if (ii < 0 || ii > g.nx || jj >= g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
         bmax = fmax(bmax, face_flux3<0>(g, cp - 1, cp, lx + row * RX + fc, SX));
     };
@@ -936,7 +941,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
     // included
     auto yface = [&](int fr, int col) {
         const int ii = ii0 + col, jj = jj0 + fr;
-        if (ii >= g.nx || jj > g.ny) return;
+        if (ii < 0 || ii >= g.nx || jj > g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
         bmax = fmax(bmax, face_flux3<1>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
     };
@@ -948,7 +953,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
     const int ii = ii0 + tx, jj = jj0 + ty;
     double rmin = INFINITY, pmin = INFINITY;
     unsigned int bad = 0;
-    if (ii < g.nx && jj < g.ny) {
+    if (ii >= 0 && ii < g.nx && jj < g.ny) {
         auto ff = [&](int G, int c, double& fl, double& fr, double& gb, double& gt) {
             const int q = G * 4 + c;
             fl = lx[q * SX + ty * RX + tx];
@@ -1152,8 +1157,8 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                     work = (long long)(g.NY - 2) * ((g.NX - 2 + t.recon - 1) / t.recon);
                     per = 1;
                     break;
-                case KB_RBAR:    // tiles of RB_TX x RB_TY cells
-                    work = (long long)((g.NX - 4 + RB_TX - 1) / RB_TX) *
+                case KB_RBAR:    // tiles of RB_TX x RB_TY cells, aligned to ghosted columns
+                    work = (long long)((g.NX - 2 + RB_TX - 1) / RB_TX) *
                            ((g.NY - 4 + RB_TY - 1) / RB_TY);
                     per = 1;
                     break;
@@ -1166,8 +1171,9 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                     work = t.flux ? (long long)g.nx * (g.ny + 1) : 0;
                     per = t.flux ? t.flux : 1;
                     break;
-                case KB_FLUXUP:  // tiles of FU_TX x FU_TY interior cells
-                    work = (long long)((g.nx + FU_TX - 1) / FU_TX) * ((g.ny + FU_TY - 1) / FU_TY);
+                case KB_FLUXUP:  // tiles of FU_TX x FU_TY cells, aligned to ghosted columns
+                    work = (long long)((g.nx + HALO + FU_TX - 1) / FU_TX) *
+                           ((g.ny + FU_TY - 1) / FU_TY);
                     per = 1;
                     break;
                 default: work = (long long)g.nx * g.ny; break;
