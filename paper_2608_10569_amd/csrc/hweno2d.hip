@@ -859,13 +859,14 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
 
 // ---------------------------------------------------------------------------
 // Face fluxes fused with the assembly and the stage update.  A block of 256
-// threads owns FU_TX x FU_TY interior cells.  First the fluxes of every face
-// of the tile at its three Gauss points go to LDS: thread (tx, ty) forms the
-// x-face left of its cell and the y-face below it, and one more pass forms the
-// x-faces right of the tile and the y-faces above it.  Then each thread
-// assembles and updates its cell.  A face on a tile edge is formed by both
-// tiles that share it.  The arithmetic per face and per cell is that of
-// k_flux2 and k_update2, so the two paths give the same bits.
+// threads owns a tile of FU_TX x FU_TY cells (columns aligned to multiples of
+// FU_TX in the ghosted grid; ghost cells in it stay idle).  First the fluxes
+// of every face of the tile at its three Gauss points go to LDS: thread
+// (tx, ty) forms the x-face left of its cell and the y-face below it, and one
+// more pass forms the x-faces right of the tile and the y-faces above it.
+// Then each thread assembles and updates its cell.  A face on a tile edge is
+// formed by both tiles that share it.  The arithmetic per face and per cell
+// is that of k_flux2 and k_update2, so the two paths give the same bits.
 // ---------------------------------------------------------------------------
 constexpr int FU_TX = 32, FU_TY = 8;
 
