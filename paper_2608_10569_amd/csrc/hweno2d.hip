@@ -1,7 +1,7 @@
 // 2D HWENO-GR residual and SSP-RK3 stage update (Sec. 3 of arXiv 2608.10569)
 // as a pipeline of HIP kernels over a ghosted structure-of-arrays grid.
 //
-//   ghost_x, ghost_y : halo of width 4 (Remark 4.1)
+//   ghost            : halo of width 4 (Remark 4.1)
 //   recon            : characteristic HWENO in the x- and y-bases (eq. (3.4)),
 //                      positivity limiter on the face values, wbar, hat-v/w,
 //                      CFL wave speed                 [cells of halo ring 3]
@@ -134,25 +134,48 @@ __device__ __forceinline__ Loc locate(const Batch& B) {
 }
 
 // ---------------------------------------------------------------------------
-// Ghost cells (Remark 4.1).  x sweep on interior rows, then y sweep on every
-// column, so corner cells compose the two rules.
+// Ghost cells (Remark 4.1).  The x rule fills the ghost columns of interior
+// rows and the y rule every column of the ghost rows; a corner cell takes the
+// y rule applied to the value the x rule gives the ghost cell of its source
+// row (what an x sweep followed by a y sweep would leave), so one launch
+// fills the whole halo.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void fill_one(const Side& sd, double* S, long long N, long long dst,
-                                         long long src, int k, int n, int stage) {
-    if (sd.kind == 2) {   // inflow: prescribed average (of boundary cell k), zero moments
-        const double* st = (stage >= 0 && sd.prof_stage) ? sd.prof_stage + 4 * (stage * n + k)
-                           : sd.prof                      ? sd.prof + 4 * k
-                                                          : sd.inflow;
+// Source of ghost index gi (0..HALO-1 below the interior, HALO+n.. above)
+// along a direction with n interior cells: the periodic image, the boundary
+// cell (outflow) or the mirror cell (walls).
+__device__ __forceinline__ int ghost_src(int kind, int gi, int n) {
+    if (gi < HALO) {
+        const int d = HALO - gi;   // distance from the boundary
+        return kind == 0 ? HALO + n - d : (kind == 1 ? HALO : HALO + d - 1);
+    }
+    const int d = gi - (HALO + n - 1);
+    return kind == 0 ? HALO + d - 1 : (kind == 1 ? HALO + n - 1 : HALO + n - d);
+}
+
+// Inflow: the prescribed average of boundary cell k (of n along the side;
+// the stage's profile when the fill names a stage), zero moments.
+__device__ __forceinline__ void inflow_values(const Side& sd, int k, int n, int stage, double* v) {
+    const double* st = (stage >= 0 && sd.prof_stage) ? sd.prof_stage + 4 * (stage * n + k)
+                       : sd.prof                      ? sd.prof + 4 * k
+                                                      : sd.inflow;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            S[c * N + dst] = st[c];
-            S[(4 + c) * N + dst] = 0.0;
-            S[(8 + c) * N + dst] = 0.0;
-        }
+    for (int c = 0; c < 4; ++c) {
+        v[c] = st[c];
+        v[4 + c] = 0.0;
+        v[8 + c] = 0.0;
+    }
+}
+
+// Value the x rule of side sd gives ghost column i of interior row j.
+__device__ __forceinline__ void x_ghost(const Grid2& g, const Side& sd, const double* S, int j,
+                                        int i, int stage, double* v) {
+    if (sd.kind == 2) {
+        inflow_values(sd, j - HALO, g.ny, stage, v);
         return;
     }
+    const long long src = (long long)j * g.NX + ghost_src(sd.kind, i, g.nx);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) S[q * N + dst] = sd.sign[q] * S[q * N + src];
+    for (int q = 0; q < 12; ++q) v[q] = sd.sign[q] * S[q * g.ncell + src];
 }
 
 // Walls inside the grid (masked domains): solid cell = mirror image of a fluid
@@ -177,55 +200,49 @@ __global__ void k_solid2(const Grid2* gp, int sidx) {
     }
 }
 
-__global__ void k_ghost2_x(Batch bt, int sidx, int stage) {
+// Threads 0 .. 2 HALO ny - 1: ghost columns of the interior rows; then the
+// 2 HALO ghost rows, every column.
+__global__ void k_ghost2(Batch bt, int sidx, int stage) {
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
     const Grid2 g = gsrc;
     double* S = gsrc.S[sidx];
     const int t = lc.b * blockDim.x + threadIdx.x;
-    if (t >= g.ny * 2 * HALO) return;
-    const int j = HALO + t / (2 * HALO);
-    const int gi = t % (2 * HALO);
-    const int right = gi >= HALO;
-    const int d = (gi % HALO) + 1;                      // distance from the boundary
-    const Side& sd = gsrc.side[right];
-    int di, si;
-    if (!right) {
-        di = HALO - d;
-        si = sd.kind == 0 ? HALO + g.nx - d : (sd.kind == 1 ? HALO : HALO + d - 1);
+    const int nxg = g.ny * 2 * HALO;
+    if (t >= nxg + g.NX * 2 * HALO) return;
+    double v[12];
+    long long dst;
+    if (t < nxg) {
+        const int j = HALO + t / (2 * HALO);
+        const int gi = t % (2 * HALO);
+        const int i = gi < HALO ? gi : g.nx + gi;
+        x_ghost(g, gsrc.side[gi >= HALO], S, j, i, stage, v);
+        dst = (long long)j * g.NX + i;
     } else {
-        di = HALO + g.nx - 1 + d;
-        si = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.nx - 1 : HALO + g.nx - d);
+        const int u = t - nxg;
+        const int i = u % g.NX;
+        const int gj = u / g.NX;
+        const int j = gj < HALO ? gj : g.ny + gj;
+        const Side& sd = gsrc.side[2 + (gj >= HALO)];
+        if (sd.kind == 2) {
+            // ghost columns take the profile's end states
+            inflow_values(sd, min(max(i - HALO, 0), g.nx - 1), g.nx, stage, v);
+        } else {
+            const int sj = ghost_src(sd.kind, j, g.ny);
+            if (i < HALO || i >= HALO + g.nx) {
+                x_ghost(g, gsrc.side[i >= HALO], S, sj, i, stage, v);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 12; ++q) v[q] = S[q * g.ncell + (long long)sj * g.NX + i];
+            }
+#pragma unroll
+            for (int q = 0; q < 12; ++q) v[q] = sd.sign[q] * v[q];
+        }
+        dst = (long long)j * g.NX + i;
     }
-    const long long row = (long long)j * g.NX;
-    fill_one(sd, S, g.ncell, row + di, row + si, j - HALO, g.ny, stage);
-}
-
-__global__ void k_ghost2_y(Batch bt, int sidx, int stage) {
-    const Loc lc = locate(bt);
-    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
-    if (!gsrc.st->active) return;
-    const Grid2 g = gsrc;
-    double* S = gsrc.S[sidx];
-    const int t = lc.b * blockDim.x + threadIdx.x;
-    if (t >= g.NX * 2 * HALO) return;
-    const int i = t % g.NX;
-    const int gj = t / g.NX;
-    const int top = gj >= HALO;
-    const int d = (gj % HALO) + 1;
-    const Side& sd = gsrc.side[2 + top];
-    int dj, sj;
-    if (!top) {
-        dj = HALO - d;
-        sj = sd.kind == 0 ? HALO + g.ny - d : (sd.kind == 1 ? HALO : HALO + d - 1);
-    } else {
-        dj = HALO + g.ny - 1 + d;
-        sj = sd.kind == 0 ? HALO + d - 1 : (sd.kind == 1 ? HALO + g.ny - 1 : HALO + g.ny - d);
-    }
-    // ghost columns take the profile's end states
-    const int k = min(max(i - HALO, 0), g.nx - 1);
-    fill_one(sd, S, g.ncell, (long long)dj * g.NX + i, (long long)sj * g.NX + i, k, g.nx, stage);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) S[q * g.ncell + dst] = v[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,8 +1169,7 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
             long long work = 0;
             int per = 256;
             switch (k) {
-                case KB_GHOSTX: work = (long long)g.ny * 2 * HALO; break;
-                case KB_GHOSTY: work = (long long)g.NX * 2 * HALO; break;
+                case KB_GHOST: work = (long long)(g.ny + g.NX) * 2 * HALO; break;
                 case KB_RECON:   // row segments of t.recon cells
                     work = (long long)(g.NY - 2) * ((g.NX - 2 + t.recon - 1) / t.recon);
                     per = 1;
@@ -1208,8 +1224,7 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
 
 hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int stage) {
     tbeg(tm, KC_GHOST, st);
-    k_ghost2_x<<<b.blocks(KB_GHOSTX), 256, 0, st>>>(b.arg(KB_GHOSTX), si, stage);
-    k_ghost2_y<<<b.blocks(KB_GHOSTY), 256, 0, st>>>(b.arg(KB_GHOSTY), si, stage);
+    k_ghost2<<<b.blocks(KB_GHOST), 256, 0, st>>>(b.arg(KB_GHOST), si, stage);
     tend(tm, st);
     return hipGetLastError();
 }

@@ -60,6 +60,7 @@ struct hweno_ctx {
     double* X2 = nullptr;
     double t = 0.0;
     bool has_state = false;
+    bool state_checked = false;        // the current state passed the admissibility check
     std::vector<char> have;            // batch: state set, per instance
     // batched run: graphs of `gsteps` steps and of one step
     hipGraphExec_t gexec = nullptr;
@@ -604,6 +605,7 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) 
     c->ws = static_cast<char*>(p);
     layout(c, c->ws);
     c->has_state = false;
+    c->state_checked = false;
     c->cur = 0;
     std::fill(c->have.begin(), c->have.end(), 0);
     if (c->dim() == 2) {
@@ -733,6 +735,7 @@ HWENO_API hweno_status hweno_set_state(hweno_ctx* c, const double* U, double t) 
     else TRY(dev(hw::launch_copy_in1(c->g1, U, c->S1[0], c->stream)));
     c->t = t;
     c->has_state = true;
+    c->state_checked = false;
     return HWENO_OK;
 }
 
@@ -801,7 +804,9 @@ hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag*
     hw::Reduce r;
     for (;;) {
         TRY(reset(c));
-        if (restarts == 0) {
+        // the input state is checked once: the output of an accepted step
+        // already passed the same test in the stage-3 update
+        if (restarts == 0 && !c->state_checked) {
             if (two) TRY(dev(hw::launch_check2(c->bl, a, c->stream)));
             else TRY(dev(hw::launch_check1(c->g1, c->S1[0], c->stream)));
         }
@@ -828,6 +833,7 @@ hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag*
     }
     if (two) c->cur = b;
     else std::swap(c->S1[0], c->S1[1]);
+    c->state_checked = true;
     c->t += r.dt;
     fill_diag(c->t, r, diag, restarts, true);
     return HWENO_OK;

@@ -181,7 +181,7 @@ inline void tend(Timer* t, hipStream_t st) { if (t) t->end(st); }
 // array g holds the instances in schedule order and start[p] is the first
 // block of the instance in slot p (start[n] = the launch's block count).
 // ---------------------------------------------------------------------------
-enum { KB_GHOSTX = 0, KB_GHOSTY, KB_RECON, KB_RBAR, KB_GRAD, KB_FLUX0, KB_FLUX1, KB_CELLS,
+enum { KB_GHOST = 0, KB_RECON, KB_RBAR, KB_GRAD, KB_FLUX0, KB_FLUX1, KB_CELLS,
        KB_FLUXUP, KB_COUNT };
 
 struct Batch {
