@@ -581,7 +581,7 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
 // (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also form
 // the volume-flux quadratures of eq. (3.2).
 // ---------------------------------------------------------------------------
-template <int GR_CELLS>
+template <int GR_CELLS, bool VarMu>
 __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     __shared__ double shv[6 * 9 * GR_CELLS];
     const Loc lc = locate(bt);
@@ -655,7 +655,7 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
             double sq[6], f[4];
 #pragma unroll
             for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
-            flux2_dir(K, Uv[qq], sq, dy, f);
+            flux2_dir<VarMu>(K, Uv[qq], sq, dy, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
         }
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
 // last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
 // max over the face's three Gauss points and both sides.
 // ---------------------------------------------------------------------------
-template <int d, int FX_FACES>   // block = 3 Gauss points x FX_FACES faces
+template <int d, int FX_FACES, bool VarMu>   // block = 3 Gauss points x FX_FACES faces
 __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __shared__ double shb[3 * FX_FACES];
     const Loc lc = locate(bt);
@@ -717,9 +717,9 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
             sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
             sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
         }
-        flux2<d>(K, Um, sm, fm);
-        flux2<d>(K, Up, sp, fp);
-        beta = fmax(speed2<d>(K, Um, sm), speed2<d>(K, Up, sp));
+        flux2<d, VarMu>(K, Um, sm, fm);
+        flux2<d, VarMu>(K, Up, sp, fp);
+        beta = fmax(speed2<d, VarMu>(K, Um, sm), speed2<d, VarMu>(K, Up, sp));
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             fs[c] = fm[c] + fp[c];
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     if (valid) {
         double* out = d == 0 ? g.fx : g.fy;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) out[(G * 4 + c) * N + cm] = 0.5 * (fs[c] - beta * du[c]);
+        for (int c = 0; c < 4; ++c) out[(G * 4 + c) * N + cm] = 0.5 * fma(-beta, du[c], fs[c]);
     }
     red_max<3 * FX_FACES>(&g.red->beta_key, valid && G == 0 ? beta : -INFINITY);
 }
@@ -753,6 +753,9 @@ __device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, l
                                             double* __restrict__ Vout,
                                             const double* __restrict__ src, const FF& ff,
                                             double& rmin, double& pmin, unsigned int& bad) {
+    // explicit fused multiply-adds, no automatic contraction: the same
+    // rounding whichever kernel inlines this
+#pragma clang fp contract(off)
     const double* __restrict__ S0 = gsrc.S[i0];
     const double* __restrict__ Sin = gsrc.S[iin];
     double* __restrict__ Sout = gsrc.S[iout];
@@ -781,19 +784,19 @@ __device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, l
 #pragma unroll
         for (int G = 0; G < 3; ++G) {
             const double wg = G == 1 ? GW1 : GW0;
-            const double xg = G == 0 ? -GS : (G == 1 ? 0.0 : GS);
+            const double wx = G == 0 ? -GW0 * GS : (G == 1 ? 0.0 : GW0 * GS);   // wg * x_G
             double fl, fr, gb, gt;
             ff(G, c, fl, fr, gb, gt);
-            dfx += wg * (fr - fl);
-            sfx += wg * (fl + fr);
-            dfxe += wg * xg * (fr - fl);
-            dgy += wg * (gt - gb);
-            sgy += wg * (gb + gt);
-            dgyx += wg * xg * (gt - gb);
+            dfx = fma(wg, fr - fl, dfx);
+            sfx = fma(wg, fl + fr, sfx);
+            dfxe = fma(wx, fr - fl, dfxe);
+            dgy = fma(wg, gt - gb, dgy);
+            sgy = fma(wg, gb + gt, sgy);
+            dgyx = fma(wx, gt - gb, dgyx);
         }
-        Fm[0][c] = -dfx * idx - dgy * idy;
-        Fm[1][c] = -sfx * (0.5 * idx) - dgyx * idy + g.vf[c * N + cell] * idx;
-        Fm[2][c] = -dfxe * idx - sgy * (0.5 * idy) + g.vf[(4 + c) * N + cell] * idy;
+        Fm[0][c] = fma(-dfx, idx, -dgy * idy);
+        Fm[1][c] = fma(g.vf[c * N + cell], idx, fma(-sfx, 0.5 * idx, -dgyx * idy));
+        Fm[2][c] = fma(g.vf[(4 + c) * N + cell], idy, fma(-dfxe, idx, -sgy * (0.5 * idy)));
     }
     if (src) {   // prescribed source moments (layout of R; single grid)
 #pragma unroll
@@ -818,17 +821,17 @@ __device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, l
         const double in1 = g.vk[c * N + cell];
         const double in2 = g.vk[(4 + c) * N + cell];
         if (stage == 1) {
-            nw[c] = in0 + dt * Fm[0][c];
-            nw[4 + c] = in1 + dt * Fm[1][c];
-            nw[8 + c] = in2 + dt * Fm[2][c];
+            nw[c] = fma(dt, Fm[0][c], in0);
+            nw[4 + c] = fma(dt, Fm[1][c], in1);
+            nw[8 + c] = fma(dt, Fm[2][c], in2);
             g.vn[c * N + cell] = in1;
             g.vn[(4 + c) * N + cell] = in2;
         } else {
             const double a = stage == 2 ? 0.75 : 1.0 / 3.0;
             const double bb = stage == 2 ? 0.25 : 2.0 / 3.0;
-            nw[c] = a * S0[c * N + cell] + bb * (in0 + dt * Fm[0][c]);
-            nw[4 + c] = a * g.vn[c * N + cell] + bb * (in1 + dt * Fm[1][c]);
-            nw[8 + c] = a * g.vn[(4 + c) * N + cell] + bb * (in2 + dt * Fm[2][c]);
+            nw[c] = fma(a, S0[c * N + cell], bb * fma(dt, Fm[0][c], in0));
+            nw[4 + c] = fma(a, g.vn[c * N + cell], bb * fma(dt, Fm[1][c], in1));
+            nw[8 + c] = fma(a, g.vn[(4 + c) * N + cell], bb * fma(dt, Fm[2][c], in2));
         }
     }
 #pragma unroll
@@ -890,7 +893,7 @@ constexpr int FU_TX = 32, FU_TY = 8;
 // Fluxes of the face between cells cm and cp (direction d) at its three
 // Gauss points into o[(G * 4 + c) * stride]; returns the LF coefficient
 // (max over the three points and both sides).
-template <int d>
+template <int d, bool VarMu>
 __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long long cp,
                                              double* o, int stride) {
     const Consts& K = g.K;
@@ -911,9 +914,9 @@ __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long 
             sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
             sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
         }
-        flux2<d>(K, Um, sm, fm);
-        flux2<d>(K, Up, sp, fp);
-        bg[G] = fmax(speed2<d>(K, Um, sm), speed2<d>(K, Up, sp));
+        flux2<d, VarMu>(K, Um, sm, fm);
+        flux2<d, VarMu>(K, Up, sp, fp);
+        bg[G] = fmax(speed2<d, VarMu>(K, Um, sm), speed2<d, VarMu>(K, Up, sp));
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             fs[G][c] = fm[c] + fp[c];
@@ -924,10 +927,11 @@ __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long 
 #pragma unroll
     for (int G = 0; G < 3; ++G)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[(G * 4 + c) * stride] = 0.5 * (fs[G][c] - beta * du[G][c]);
+        for (int c = 0; c < 4; ++c) o[(G * 4 + c) * stride] = 0.5 * fma(-beta, du[G][c], fs[G][c]);
     return beta;
 }
 
+template <bool VarMu>
 __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, int i0, int iin,
                                                            int iout, double* __restrict__ Rout,
                                                            double* __restrict__ Vout,
@@ -953,7 +957,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
         const int ii = ii0 + fc, jj = jj0 + row;
         if (ii < 0 || ii > g.nx || jj >= g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
-        bmax = fmax(bmax, face_flux3<0>(g, cp - 1, cp, lx + row * RX + fc, SX));
+        bmax = fmax(bmax, face_flux3<0, VarMu>(g, cp - 1, cp, lx + row * RX + fc, SX));
     };
     // y-face below interior cell (ii0 + col, jj0 + fr); fr = FU_TY and jj = ny
     // included
@@ -961,7 +965,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
         const int ii = ii0 + col, jj = jj0 + fr;
         if (ii < 0 || ii >= g.nx || jj > g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
-        bmax = fmax(bmax, face_flux3<1>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
+        bmax = fmax(bmax, face_flux3<1, VarMu>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
     };
     xface(tx, ty);
     yface(ty, tx);
@@ -1238,17 +1242,32 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
     k_rbar2<<<b.blocks(KB_RBAR), RB_TX * RB_TY, 0, st>>>(b.arg(KB_RBAR));
     tend(tm, st);
     tbeg(tm, KC_GRAD, st);
-    if (b.tiles.grad == 64) k_grad2<64><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
-    else k_grad2<32><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
+    if (b.tiles.grad == 64) {
+        if (b.var_mu) k_grad2<64, true><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
+        else k_grad2<64, false><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
+    } else {
+        if (b.var_mu) k_grad2<32, true><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
+        else k_grad2<32, false><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
+    }
     tend(tm, st);
     if (b.tiles.flux == 0) return hipGetLastError();   // fluxes formed by the update kernel
     tbeg(tm, KC_FLUX, st);
     if (b.tiles.flux == 128) {
-        k_flux2<0, 128><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
-        k_flux2<1, 128><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
+        if (b.var_mu) {
+            k_flux2<0, 128, true><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
+            k_flux2<1, 128, true><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
+        } else {
+            k_flux2<0, 128, false><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
+            k_flux2<1, 128, false><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
+        }
     } else {
-        k_flux2<0, 64><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
-        k_flux2<1, 64><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
+        if (b.var_mu) {
+            k_flux2<0, 64, true><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
+            k_flux2<1, 64, true><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
+        } else {
+            k_flux2<0, 64, false><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
+            k_flux2<1, 64, false><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
+        }
     }
     tend(tm, st);
     return hipGetLastError();
@@ -1258,8 +1277,12 @@ hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout,
                           double* Vhat, hipStream_t st, Timer* tm, const double* src) {
     if (b.tiles.flux == 0) {
         tbeg(tm, KC_FLUXUP, st);
-        k_fluxup2<<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(b.arg(KB_FLUXUP), stage, i0, iin,
-                                                                 iout, R, Vhat, src);
+        if (b.var_mu)
+            k_fluxup2<true><<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(
+                b.arg(KB_FLUXUP), stage, i0, iin, iout, R, Vhat, src);
+        else
+            k_fluxup2<false><<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(
+                b.arg(KB_FLUXUP), stage, i0, iin, iout, R, Vhat, src);
     } else {
         tbeg(tm, KC_UPDATE, st);
         k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R,

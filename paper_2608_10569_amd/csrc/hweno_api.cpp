@@ -310,6 +310,8 @@ hweno_status upload_grids(hweno_ctx* c) {
     c->bl.hstart = c->hstart.data();
     c->bl.n = n;
     c->bl.tiles = c->tiles;
+    c->bl.var_mu = false;
+    for (const Inst& in : c->in) c->bl.var_mu = c->bl.var_mu || in.phys.mu_exp != 0.0;
     drop_graphs(c);
     return HWENO_OK;
 }

@@ -62,8 +62,12 @@ __device__ __forceinline__ Consts grad_consts(const Consts& K) {
     return G;
 }
 
+// mu(T) = mu_ref (T / T_ref)^mu_exp.  VarMu = false builds code that serves
+// constant viscosity only (mu_exp = 0 in every instance of a launch): the
+// power law, and the registers its code needs, stay out of such kernels.
+template <bool VarMu = true>
 __device__ __forceinline__ double viscosity(const Consts& K, double rho, double p) {
-    if (K.mu_exp == 0.0) return K.mu_ref;
+    if (!VarMu || K.mu_exp == 0.0) return K.mu_ref;
     return K.mu_ref * pow((p / rho) / K.T_ref, K.mu_exp);
 }
 
@@ -278,7 +282,8 @@ __device__ __forceinline__ double pressure1(const Consts& K, double r, double m,
 }
 __device__ __forceinline__ double pressure2(const Consts& K, double r, double m, double n,
                                             double E) {
-    return K.gm1 * (E - 0.5 * (m * m + n * n) * rcp(r));
+#pragma clang fp contract(off)   // same rounding in every kernel (see the 2D fluxes)
+    return K.gm1 * fma(-0.5 * fma(m, m, n * n), rcp(r), E);
 }
 
 // 1D total flux f = f^a - f^d with tau = (4/3) mu u_x, q = -gamma mu e_x / Pr.
@@ -311,50 +316,59 @@ __device__ __forceinline__ double speed1(const Consts& K, const double* U, doubl
     return ac >= bpp ? ac : bpp;
 }
 
+// The 2D flux and speed-bound arithmetic below is written with explicit
+// fused multiply-adds and no automatic contraction, so that it rounds the
+// same way in every kernel it is inlined into (the face fluxes are formed
+// by more than one kernel, and their results must agree bit for bit).
+
 // 2D stresses divided by Re (mu(T) in place of 1/Re).
 struct Stress { double xx, xy, yy; };
 __device__ __forceinline__ Stress stresses(double mu, const double* s) {
+#pragma clang fp contract(off)
     Stress t;
-    t.xx = mu * ((4.0 / 3.0) * s[0] - (2.0 / 3.0) * s[3]);
+    t.xx = mu * fma(4.0 / 3.0, s[0], -(2.0 / 3.0) * s[3]);
     t.xy = mu * (s[1] + s[2]);
-    t.yy = mu * ((4.0 / 3.0) * s[3] - (2.0 / 3.0) * s[0]);
+    t.yy = mu * fma(4.0 / 3.0, s[3], -(2.0 / 3.0) * s[0]);
     return t;
 }
 
 // 2D total flux in direction d (0: f, 1: g); s = (u_x,u_y,v_x,v_y,e_x,e_y).
-template <int d>
+template <int d, bool VarMu = true>
 __device__ __forceinline__ void flux2(const Consts& K, const double* U, const double* s,
                                       double* f) {
+#pragma clang fp contract(off)
     const double r = U[0], m = U[1], n = U[2], E = U[3];
     const double ir = rcp(r);
     const double u = m * ir, v = n * ir;
-    const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
-    const double mu = viscosity(K, r, p);
+    const double p = K.gm1 * fma(-0.5, fma(m, u, n * v), E);
+    const double mu = viscosity<VarMu>(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gPr * mu;
     if (d == 0) {
         f[0] = m;
-        f[1] = m * u + p - t.xx;
-        f[2] = n * u - t.xy;
-        f[3] = (E + p) * u - (t.xx * u + t.xy * v + kq * s[4]);
+        f[1] = fma(m, u, p) - t.xx;
+        f[2] = fma(n, u, -t.xy);
+        f[3] = fma(E + p, u, -fma(t.xx, u, fma(t.xy, v, kq * s[4])));
     } else {
         f[0] = n;
-        f[1] = m * v - t.xy;
-        f[2] = n * v + p - t.yy;
-        f[3] = (E + p) * v - (t.xy * u + t.yy * v + kq * s[5]);
+        f[1] = fma(m, v, -t.xy);
+        f[2] = fma(n, v, p) - t.yy;
+        f[3] = fma(E + p, v, -fma(t.xy, u, fma(t.yy, v, kq * s[5])));
     }
 }
 
 // The same flux with the direction a run-time value (dy: g instead of f);
 // selects instead of branches, so lanes of one wave may take different
 // directions without diverging.
+template <bool VarMu = true>
 __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, const double* s,
                                           bool dy, double* f) {
+#pragma clang fp contract(off)
     const double r = U[0], m = U[1], n = U[2], E = U[3];
     const double ir = rcp(r);
     const double u = m * ir, v = n * ir;
-    const double p = K.gm1 * (E - 0.5 * (m * u + n * v));
-    const double mu = viscosity(K, r, p);
+    const double p = K.gm1 * fma(-0.5, fma(m, u, n * v), E);
+    const double mu = viscosity<VarMu>(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gPr * mu;
     const double un = dy ? v : u;           // velocity along the direction
@@ -362,27 +376,28 @@ __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, cons
     const double tny = dy ? t.yy : t.xy;    // stress (y, direction)
     const double qd = dy ? s[5] : s[4];
     f[0] = dy ? n : m;
-    f[1] = m * un + (dy ? 0.0 : p) - tnx;
-    f[2] = n * un + (dy ? p : 0.0) - tny;
-    f[3] = (E + p) * un - (tnx * u + tny * v + kq * qd);
+    f[1] = fma(m, un, (dy ? 0.0 : p)) - tnx;
+    f[2] = fma(n, un, (dy ? p : 0.0)) - tny;
+    f[3] = fma(E + p, un, -fma(tnx, u, fma(tny, v, kq * qd)));
 }
 
 // PP wave-speed bound of eq. (3.3) in direction d, no smaller than |u_d| + c.
-template <int d>
+template <int d, bool VarMu = true>
 __device__ __forceinline__ double speed2(const Consts& K, const double* U, const double* s) {
+#pragma clang fp contract(off)
     const double r = U[0], m = U[1], n = U[2], E = U[3];
     const double ir = rcp(r);
-    const double p = K.gm1 * (E - 0.5 * (m * m + n * n) * ir);
-    const double mu = viscosity(K, r, p);
+    const double p = K.gm1 * fma(-0.5 * fma(m, m, n * n), ir, E);
+    const double mu = viscosity<VarMu>(K, r, p);
     const Stress t = stresses(mu, s);
     const double kq = K.gPr * mu;
     const double un = (d == 0 ? m : n) * ir;
     const double q = kq * s[4 + d];
-    const double t2 = d == 0 ? (t.xx - p) * (t.xx - p) + t.xy * t.xy
-                             : t.xy * t.xy + (t.yy - p) * (t.yy - p);
+    const double tp = (d == 0 ? t.xx : t.yy) - p;
+    const double t2 = fma(tp, tp, t.xy * t.xy);
     const double r2e = r * p * K.igm1;      // rho^2 e with e = p / ((gamma - 1) rho)
-    const double root = sqrt(r * r * q * q + 2.0 * r2e * t2);
-    const double bpp = fabs(un) + (root + r * fabs(q)) * (0.5 * rcp(r2e));
+    const double root = sqrt(fma(r * r, q * q, 2.0 * r2e * t2));
+    const double bpp = fma(fma(r, fabs(q), root), 0.5 * rcp(r2e), fabs(un));
     const double ac = fabs(un) + sqrt(K.gamma * p * ir);
     return ac >= bpp ? ac : bpp;
 }

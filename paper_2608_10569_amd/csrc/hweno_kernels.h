@@ -205,6 +205,7 @@ struct BatchL {
     const int* hstart = nullptr;   // host copy of dstart
     int n = 0;
     Tiles tiles;
+    bool var_mu = true;            // some instance has a temperature-dependent mu
     Batch arg(int k) const { return Batch{dg, dstart + k * (n + 1), n, tiles.xcd}; }
     unsigned blocks(int k) const { return (unsigned)hstart[k * (n + 1) + n]; }
 };
