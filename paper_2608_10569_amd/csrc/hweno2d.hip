@@ -675,6 +675,16 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     }
 }
 
+// The two Gauss moments of a face flux that the assembly of eq. (3.2) takes
+// from a face, per component: A = sum_G w_G F_G and B = sum_G w_G x_G F_G
+// (x_G = -s, 0, s in face units).  One definition for every kernel.
+__device__ __forceinline__ void face_moments(double F0, double F1, double F2, double& A,
+                                             double& B) {
+#pragma clang fp contract(off)
+    A = fma(GW0, F2, fma(GW1, F1, GW0 * F0));
+    B = (GW0 * GS) * (F2 - F0);
+}
+
 // ---------------------------------------------------------------------------
 // Face fluxes (eq. (3.3)): x-faces (j, i+1/2) for interior rows, i from the
 // last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
@@ -683,6 +693,7 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
 template <int d, int FX_FACES, bool VarMu>   // block = 3 Gauss points x FX_FACES faces
 __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __shared__ double shb[3 * FX_FACES];
+    __shared__ double shf[4][3 * FX_FACES];
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -730,19 +741,28 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __syncthreads();
     // LF coefficient: max over the face's three Gauss points and both sides
     beta = fmax(fmax(shb[fl], shb[FX_FACES + fl]), shb[2 * FX_FACES + fl]);
-    if (valid) {
+    // the face's Gauss moments: the three points meet in LDS
+#pragma unroll
+    for (int c = 0; c < 4; ++c) shf[c][threadIdx.x] = 0.5 * fma(-beta, du[c], fs[c]);
+    __syncthreads();
+    if (valid && G == 0) {
         double* out = d == 0 ? g.fx : g.fy;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) out[(G * 4 + c) * N + cm] = 0.5 * fma(-beta, du[c], fs[c]);
+        for (int c = 0; c < 4; ++c) {
+            double A, B;
+            face_moments(shf[c][fl], shf[c][FX_FACES + fl], shf[c][2 * FX_FACES + fl], A, B);
+            out[c * N + cm] = A;
+            out[(4 + c) * N + cm] = B;
+        }
     }
     red_max<3 * FX_FACES>(&g.red->beta_key, valid && G == 0 ? beta : -INFINITY);
 }
 
 // ---------------------------------------------------------------------------
 // Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form) of interior
-// cell (ii, jj), t = jj * nx + ii.  ff(G, c, fl, fr, gb, gt) gives component c
-// of the fluxes at Gauss point G of the cell's left, right, bottom and top
-// faces.  stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3
+// cell (ii, jj), t = jj * nx + ii.  ff(c, L, R, Bo, T) gives the Gauss
+// moments (A, B) of component c of the fluxes of the cell's left, right,
+// bottom and top faces (L[0] = A, L[1] = B, ...).  stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3
 // stage.  rmin, pmin and bad receive the cell's share of the admissibility
 // reductions (stages 1..3; solid cells give none).
 // ---------------------------------------------------------------------------
@@ -780,20 +800,10 @@ __device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, l
     double Fm[3][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        double dfx = 0.0, sfx = 0.0, dfxe = 0.0, dgy = 0.0, sgy = 0.0, dgyx = 0.0;
-#pragma unroll
-        for (int G = 0; G < 3; ++G) {
-            const double wg = G == 1 ? GW1 : GW0;
-            const double wx = G == 0 ? -GW0 * GS : (G == 1 ? 0.0 : GW0 * GS);   // wg * x_G
-            double fl, fr, gb, gt;
-            ff(G, c, fl, fr, gb, gt);
-            dfx = fma(wg, fr - fl, dfx);
-            sfx = fma(wg, fl + fr, sfx);
-            dfxe = fma(wx, fr - fl, dfxe);
-            dgy = fma(wg, gt - gb, dgy);
-            sgy = fma(wg, gb + gt, sgy);
-            dgyx = fma(wx, gt - gb, dgyx);
-        }
+        double L[2], R[2], Bo[2], T[2];
+        ff(c, L, R, Bo, T);
+        const double dfx = R[0] - L[0], sfx = L[0] + R[0], dfxe = R[1] - L[1];
+        const double dgy = T[0] - Bo[0], sgy = Bo[0] + T[0], dgyx = T[1] - Bo[1];
         Fm[0][c] = fma(-dfx, idx, -dgy * idy);
         Fm[1][c] = fma(g.vf[c * N + cell], idx, fma(-sfx, 0.5 * idx, -dgyx * idy));
         Fm[2][c] = fma(g.vf[(4 + c) * N + cell], idy, fma(-dfxe, idx, -sgy * (0.5 * idy)));
@@ -862,11 +872,14 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
         const int jj = (int)(t / g.nx), ii = (int)(t % g.nx);
         const long long N = g.ncell;
         const long long cell = (long long)(jj + HALO) * g.NX + ii + HALO;
-        auto ff = [&](int G, int c, double& fl, double& fr, double& gb, double& gt) {
-            fr = g.fx[(G * 4 + c) * N + cell];
-            fl = g.fx[(G * 4 + c) * N + cell - 1];
-            gt = g.fy[(G * 4 + c) * N + cell];
-            gb = g.fy[(G * 4 + c) * N + cell - g.NX];
+        auto ff = [&](int c, double* L, double* R, double* Bo, double* T) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                R[m] = g.fx[(4 * m + c) * N + cell];
+                L[m] = g.fx[(4 * m + c) * N + cell - 1];
+                T[m] = g.fy[(4 * m + c) * N + cell];
+                Bo[m] = g.fy[(4 * m + c) * N + cell - g.NX];
+            }
         };
         update_cell(g, gsrc, t, jj, ii, stage, i0, iin, iout, Rout, Vout, src, ff, rmin, pmin,
                     bad);
@@ -880,8 +893,8 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
 // ---------------------------------------------------------------------------
 // Face fluxes fused with the assembly and the stage update.  A block of 256
 // threads owns a tile of FU_TX x FU_TY cells (columns aligned to multiples of
-// FU_TX in the ghosted grid; ghost cells in it stay idle).  First the fluxes
-// of every face of the tile at its three Gauss points go to LDS: thread
+// FU_TX in the ghosted grid; ghost cells in it stay idle).  First the two
+// Gauss moments of the flux of every face of the tile go to LDS: thread
 // (tx, ty) forms the x-face left of its cell and the y-face below it, and one
 // more pass forms the x-faces right of the tile and the y-faces above it.
 // Then each thread assembles and updates its cell.  A face on a tile edge is
@@ -890,9 +903,9 @@ __global__ __launch_bounds__(256) void k_update2(Batch bt, int stage, int i0, in
 // ---------------------------------------------------------------------------
 constexpr int FU_TX = 32, FU_TY = 8;
 
-// Fluxes of the face between cells cm and cp (direction d) at its three
-// Gauss points into o[(G * 4 + c) * stride]; returns the LF coefficient
-// (max over the three points and both sides).
+// Gauss moments (A into o[c * stride], B into o[(4 + c) * stride]) of the
+// flux of the face between cells cm and cp (direction d); returns the LF
+// coefficient (max over the three points and both sides).
 template <int d, bool VarMu>
 __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long long cp,
                                              double* o, int stride) {
@@ -924,10 +937,14 @@ __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long 
         }
     }
     const double beta = fmax(fmax(bg[0], bg[1]), bg[2]);
+    double Fg[3][4];   // the flux at each Gauss point
 #pragma unroll
     for (int G = 0; G < 3; ++G)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[(G * 4 + c) * stride] = 0.5 * fma(-beta, du[G][c], fs[G][c]);
+        for (int c = 0; c < 4; ++c) Fg[G][c] = 0.5 * fma(-beta, du[G][c], fs[G][c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        face_moments(Fg[0][c], Fg[1][c], Fg[2][c], o[c * stride], o[(4 + c) * stride]);
     return beta;
 }
 
@@ -938,8 +955,8 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
                                                            const double* __restrict__ src) {
     constexpr int RX = FU_TX + 1;                              // x-face columns per row
     constexpr int SX = FU_TY * RX, SY = (FU_TY + 1) * FU_TX;   // plane sizes
-    __shared__ double lx[12 * SX];   // [G*4 + c][row][face column 0..FU_TX]
-    __shared__ double ly[12 * SY];   // [G*4 + c][face row 0..FU_TY][column]
+    __shared__ double lx[8 * SX];    // [moment*4 + c][row][face column 0..FU_TX]
+    __shared__ double ly[8 * SY];    // [moment*4 + c][face row 0..FU_TY][column]
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -976,12 +993,15 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
     double rmin = INFINITY, pmin = INFINITY;
     unsigned int bad = 0;
     if (ii >= 0 && ii < g.nx && jj < g.ny) {
-        auto ff = [&](int G, int c, double& fl, double& fr, double& gb, double& gt) {
-            const int q = G * 4 + c;
-            fl = lx[q * SX + ty * RX + tx];
-            fr = lx[q * SX + ty * RX + tx + 1];
-            gb = ly[q * SY + ty * FU_TX + tx];
-            gt = ly[q * SY + (ty + 1) * FU_TX + tx];
+        auto ff = [&](int c, double* L, double* R, double* Bo, double* T) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int q = 4 * m + c;
+                L[m] = lx[q * SX + ty * RX + tx];
+                R[m] = lx[q * SX + ty * RX + tx + 1];
+                Bo[m] = ly[q * SY + ty * FU_TX + tx];
+                T[m] = ly[q * SY + (ty + 1) * FU_TX + tx];
+            }
         };
         update_cell(g, gsrc, (long long)jj * g.nx + ii, jj, ii, stage, i0, iin, iout, Rout, Vout,
                     src, ff, rmin, pmin, bad);

@@ -218,8 +218,8 @@ size_t layout(hweno_ctx* c, char* base) {
         g.rb = take(18 * m);
         g.gf = take(72 * m);
         g.vf = take(8 * m);
-        g.fx = take(12 * m);
-        g.fy = take(12 * m);
+        g.fx = take(8 * m);
+        g.fy = take(8 * m);
     }
     if (!c->batch) {
         // reverse-mode workspace (zero-filled at the start of every adjoint call)

@@ -82,8 +82,8 @@ struct Grid2 {
     gdouble* rb;   // 18: weak moments ((l*3 + w)*3 + mom)
     gdouble* gf;   // 72: gradients at face points ((p*6 + s)), p 0..5 x-face, 6..11 y-face
     gdouble* vf;   // 8:  volume flux quadratures (sum f, sum g)
-    gdouble* fx;   // 12: x-face fluxes at (j, i+1/2) (G*4 + c)
-    gdouble* fy;   // 12: y-face fluxes at (j+1/2, i)
+    gdouble* fx;   // 8: x-face flux moments at (j, i+1/2): sum_G w_G F (c), sum_G w_G x_G F (4 + c)
+    gdouble* fy;   // 8: y-face flux moments at (j+1/2, i)
     HW_GLOBAL Reduce* red;
     // masked domain (single grid): interior mask (1 = solid, j*nx + i) or null;
     // solid cells next to the fluid: ghosted destination, ghosted mirror source
