@@ -68,10 +68,10 @@ FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400,
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
 # and for the kernels as they are now: e.g. recon with 32-cell tiles reads
 # 53.2 MB and writes 553.0 MB per launch.
-TRAFFIC_BYTES = {('recon', 16): 605453715, ('recon', 32): 606145510,
-                 ('grad', 32): 745109657, ('grad', 64): 702618293,
-                 ('rbar', None): 309232508, ('update', None): 263533906,
-                 ('fluxup', None): 740175254}
+TRAFFIC_BYTES = {('recon', 16): 605898255, ('recon', 32): 606225963,
+                 ('grad', 32): 737347035, ('grad', 64): 715785806,
+                 ('rbar', None): 309259384, ('update', None): 228053671,
+                 ('fluxup', None): 733103288}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).
@@ -222,6 +222,12 @@ def bench_adjoint(nsteps=200, every=20):
         s.rk_step(dt)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    # untimed warm-up: one checkpoint segment forward and backward (first
+    # launches of the reverse-mode kernels, autograd set-up)
+    r = rho.clone().requires_grad_(True)
+    m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
+    adjoint.kinetic_energy(adjoint.rollout(s, adjoint.project_fields(r, u, v, f[3], gamma), m,
+                                           dt, every, every), s.dx, s.dy).backward()
     r = rho.clone().requires_grad_(True)
     m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
     torch.cuda.synchronize()
