@@ -72,6 +72,26 @@ def test_batch_equals_single_grids():
         assert torch.equal(got, ref)
 
 
+def test_batch_mixed_viscosity_laws_equal_single_grids():
+    """One instance with mu(T) makes the whole launch use the kernels built
+    with the power law; the constant-viscosity instances beside it must still
+    match their single-grid runs (which use the constant-viscosity build)
+    bit for bit, with the face fluxes split and fused."""
+    probs, states = mixed_problems()
+    probs = probs[:3]
+    states = states[:3]
+    probs[1] = dict(probs[1], mu_exp=0.7, T_ref=1.0 / 1.4)
+    for tiles in (dict(recon=32, grad=64, flux=0, order=0, xcd=1),
+                  dict(recon=32, grad=32, flux=64, order=0, xcd=1)):
+        b = run_batch(probs, states, 4, tiles)
+        for i, (p, U) in enumerate(zip(probs, states)):
+            ref, t, steps, _ = single_run(p, U, 4)
+            got, tb = b.get_state(i)
+            print('flux %d, instance %d (mu_exp %s): equal %s'
+                  % (tiles['flux'], i, p.get('mu_exp', 0.0), torch.equal(got, ref)), flush=True)
+            assert tb == t and torch.equal(got, ref)
+
+
 @pytest.mark.parametrize('tiles', [dict(recon=16, grad=64, flux=128, order=1, xcd=1),
                                    dict(recon=32, grad=32, flux=64, order=1, xcd=0),
                                    dict(recon=16, grad=32, flux=128, order=0, xcd=0),
