@@ -499,8 +499,10 @@ constexpr int RB_TX = 32, RB_TY = 8;
 
 __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
     constexpr int NXF = RB_TY * (RB_TX + 1), NYF = (RB_TY + 1) * RB_TX;
-    __shared__ double hx[9][RB_TY][RB_TX + 1];   // [3 G + w][row][face i - 1/2]
-    __shared__ double hy[9][RB_TY + 1][RB_TX];   // [3 G + w][face j - 1/2][column]
+    // per face and variable w: the Gauss average W0 = sum_G w_G h_G and the
+    // first moment W1 = sum_G w_G x_G h_G of the interface average h
+    __shared__ double hx[6][RB_TY][RB_TX + 1];   // [3 m + w][row][face i - 1/2]
+    __shared__ double hy[6][RB_TY + 1][RB_TX];   // [3 m + w][face j - 1/2][column]
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -531,16 +533,26 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
         }
         const double* F = xd ? g.xf : g.yf;
         const long long lo = (long long)jlo * g.NX + ilo, hi = (long long)j * g.NX + i;
+        double h[3][3];   // [G][w]
 #pragma unroll
         for (int G = 0; G < 3; ++G) {
             double a[3], c[3];
             prim3(F, N, lo, 3 + G, a);
             prim3(F, N, hi, G, c);
 #pragma unroll
-            for (int w = 0; w < 3; ++w) {
-                const double h = 0.5 * (a[w] + c[w]);
-                if (xd) hx[3 * G + w][j - j0][i - i0] = h;
-                else hy[3 * G + w][j - j0][i - i0] = h;
+            for (int w = 0; w < 3; ++w) h[G][w] = 0.5 * (a[w] + c[w]);
+        }
+        // mirror-symmetric forms (outer points exchanged: same W0, -W1)
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            const double W0 = fma(GW0, h[0][w] + h[2][w], GW1 * h[1][w]);
+            const double W1 = (GW0 * GS) * (h[2][w] - h[0][w]);
+            if (xd) {
+                hx[w][j - j0][i - i0] = W0;
+                hx[3 + w][j - j0][i - i0] = W1;
+            } else {
+                hy[w][j - j0][i - i0] = W0;
+                hy[3 + w][j - j0][i - i0] = W1;
             }
         }
     }
@@ -554,16 +566,10 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
         const double ih = l ? g.K.idy : g.K.idx;
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
-            double hlo[3], hhi[3];
-#pragma unroll
-            for (int G = 0; G < 3; ++G) {
-                hlo[G] = l ? hy[3 * G + w][ty][tx] : hx[3 * G + w][ty][tx];
-                hhi[G] = l ? hy[3 * G + w][ty + 1][tx] : hx[3 * G + w][ty][tx + 1];
-            }
-            const double W0lo = GW0 * hlo[0] + GW1 * hlo[1] + GW0 * hlo[2];
-            const double W0hi = GW0 * hhi[0] + GW1 * hhi[1] + GW0 * hhi[2];
-            const double W1lo = GW0 * GS * (hlo[2] - hlo[0]);
-            const double W1hi = GW0 * GS * (hhi[2] - hhi[0]);
+            const double W0lo = l ? hy[w][ty][tx] : hx[w][ty][tx];
+            const double W0hi = l ? hy[w][ty + 1][tx] : hx[w][ty][tx + 1];
+            const double W1lo = l ? hy[3 + w][ty][tx] : hx[3 + w][ty][tx];
+            const double W1hi = l ? hy[3 + w][ty + 1][tx] : hx[3 + w][ty][tx + 1];
             const double wbl = g.wb[(l * 3 + w) * N + cell];
             const double d0 = (W0hi - W0lo) * ih;                    // moment 0
             const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
@@ -678,10 +684,12 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
 // The two Gauss moments of a face flux that the assembly of eq. (3.2) takes
 // from a face, per component: A = sum_G w_G F_G and B = sum_G w_G x_G F_G
 // (x_G = -s, 0, s in face units).  One definition for every kernel.
+// Both are written so that exchanging the outer points (a mirror image of
+// the face) gives the same A and the negated B bit for bit.
 __device__ __forceinline__ void face_moments(double F0, double F1, double F2, double& A,
                                              double& B) {
 #pragma clang fp contract(off)
-    A = fma(GW0, F2, fma(GW1, F1, GW0 * F0));
+    A = fma(GW0, F0 + F2, GW1 * F1);
     B = (GW0 * GS) * (F2 - F0);
 }
 
