@@ -330,7 +330,7 @@ class Solver:
         check(lib().hweno_get_tiles(self._h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tiles(self, recon=32, grad=32, flux=64, order=0, xcd=1):
+    def set_tiles(self, recon=32, grad=64, flux=0, order=0, xcd=1):
         t = TilesC(recon, grad, flux, order, xcd)
         check(lib().hweno_set_tiles(self._h, ctypes.byref(t)))
 
