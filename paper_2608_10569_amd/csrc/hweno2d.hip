@@ -770,9 +770,10 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
 // Assembly (eq. (3.2)) and stage update (eq. (2.12) in 2D form) of interior
 // cell (ii, jj), t = jj * nx + ii.  ff(c, L, R, Bo, T) gives the Gauss
 // moments (A, B) of component c of the fluxes of the cell's left, right,
-// bottom and top faces (L[0] = A, L[1] = B, ...).  stage 0: R and Vhat out (interior layout); stage 1..3: SSP-RK3
-// stage.  rmin, pmin and bad receive the cell's share of the admissibility
-// reductions (stages 1..3; solid cells give none).
+// bottom and top faces (L[0] = A, L[1] = B, ...).  stage 0: R and Vhat out
+// (interior layout); stage 1..3: SSP-RK3 stage.  rmin, pmin and bad receive
+// the cell's share of the admissibility reductions (stages 1..3; solid cells
+// give none).
 // ---------------------------------------------------------------------------
 template <class FF>
 __device__ __forceinline__ void update_cell(const Grid2& g, const Grid2& gsrc, long long t, int jj,
