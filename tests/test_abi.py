@@ -93,6 +93,30 @@ def test_workspace_and_state_errors_without_device():
     assert L.hweno_status_string(4).decode().startswith('stage inadmissible')
 
 
+def test_tile_defaults_and_validation_without_device():
+    """A new 2D context uses the fused face-flux path; tile values outside the
+    documented sets are refused (checked on the host, before any upload)."""
+    g, ph, b, o = _args()
+    h = ctypes.c_void_p()
+    L = hweno.lib()
+    assert L.hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                          ctypes.byref(h)) == 0
+    t = hweno.TilesC()
+    assert L.hweno_get_tiles(h, ctypes.byref(t)) == 0
+    base = t.as_dict()
+    assert base == dict(recon=32, grad=64, flux=0, order=0, xcd=1)
+    for change, code in ((dict(flux=64), 0), (dict(flux=128), 0), (dict(recon=16, grad=32), 0),
+                         (dict(order=1, xcd=0), 0), (dict(recon=64), 1), (dict(grad=16), 1),
+                         (dict(flux=32), 1), (dict(order=2), 1), (dict(xcd=2), 1)):
+        v = dict(base, **change)
+        tt = hweno.TilesC(v['recon'], v['grad'], v['flux'], v['order'], v['xcd'])
+        assert L.hweno_set_tiles(h, ctypes.byref(tt)) == code, change
+        if code == 0:
+            got = hweno.TilesC()
+            assert L.hweno_get_tiles(h, ctypes.byref(got)) == 0 and got.as_dict() == v
+    assert L.hweno_destroy(h) == 0
+
+
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hweno, 'LIB_PATH', str(tmp_path / 'missing.so'))
     monkeypatch.setattr(hweno, '_lib', None)
