@@ -78,6 +78,24 @@ TRAFFIC_BYTES = {('recon', 16): 617946138, ('recon', 32): 604370813,
 ALGO_BYTES_PER_CELL_STAGE = 277.0
 
 
+def pipeline_hbm(tiles, value):
+    """HBM bytes the whole stage pipeline moves per cell-stage (the counter
+    table above, for the tiles in use; ghost fill and reductions left out) and
+    the rate they imply at the measured throughput."""
+    if tiles.get('flux') != 0:   # split face-flux kernels have no entry in the table
+        return None
+    parts = [('recon', tiles.get('recon')), ('rbar', None), ('grad', tiles.get('grad')),
+             ('fluxup', None)]
+    if any(p not in TRAFFIC_BYTES for p in parts):
+        return None
+    per_cell = sum(TRAFFIC_BYTES[p] for p in parts) / (NX * NY)
+    rate = per_cell * value
+    return {'bytes_per_cell_stage': per_cell, 'GB/s': rate / 1e9,
+            'frac': rate / (PEAK_HBM_GBS * 1e9),
+            'note': 'rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated), summed over the '
+                    'kernels of one stage, times the measured cell-stage rate'}
+
+
 def log(msg):
     print('[bench] ' + msg, file=sys.stderr, flush=True)
 
@@ -341,6 +359,7 @@ def main():
                      'flops_per_unit': FLOPS[dom], 'units_per_launch': units_per_launch(dom),
                      'us_per_launch': avg_s * 1e6, 'launches_timed': n},
         'hbm_frac_algorithmic': value * ALGO_BYTES_PER_CELL_STAGE / (PEAK_HBM_GBS * 1e9),
+        'hbm_pipeline': pipeline_hbm(tiles, value),
         'path_fp64_tflops_algorithmic': value * path_flops / 1e12,
         'kernels': kern,
         'kernels_note': 'every class timed over 5 untimed steps before the timed region',
