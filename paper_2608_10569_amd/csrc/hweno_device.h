@@ -436,26 +436,35 @@ __device__ __forceinline__ void eig2_rows(const Consts& K, const double* Ub, int
     const double un = b ? v : u;       // normal velocity
     const double ut = b ? u : v;       // tangential velocity
     // In (rho, m_n, m_t, E) ordering the two Jacobians have identical
-    // eigenvectors; map to (rho, m, n, E) by placing n/t slots.
-    const int in = b ? 2 : 1, it = b ? 1 : 2;
-    double Lr[4], Rr[4];
-    // L rows in normal/tangential ordering
+    // eigenvectors; (rho, m, n, E) puts the normal momentum in slot 1 for
+    // b = 0 and in slot 2 for b = 1.  Row k of L in the normal/tangential
+    // ordering:
+    double L0, Ln, Lt, L3;
     switch (k) {
-        case 0: Lr[0] = 0.5 * (b2 + un * ic); Lr[in] = -0.5 * (b1 * un + ic);
-                Lr[it] = -0.5 * b1 * ut;      Lr[3] = 0.5 * b1; break;
-        case 1: Lr[0] = 1.0 - b2; Lr[in] = b1 * un; Lr[it] = b1 * ut; Lr[3] = -b1; break;
-        case 2: Lr[0] = -ut; Lr[in] = 0.0; Lr[it] = 1.0; Lr[3] = 0.0; break;
-        default: Lr[0] = 0.5 * (b2 - un * ic); Lr[in] = 0.5 * (ic - b1 * un);
-                 Lr[it] = -0.5 * b1 * ut;     Lr[3] = 0.5 * b1; break;
+        case 0: L0 = 0.5 * (b2 + un * ic); Ln = -0.5 * (b1 * un + ic);
+                Lt = -0.5 * b1 * ut;       L3 = 0.5 * b1; break;
+        case 1: L0 = 1.0 - b2; Ln = b1 * un; Lt = b1 * ut; L3 = -b1; break;
+        case 2: L0 = -ut; Ln = 0.0; Lt = 1.0; L3 = 0.0; break;
+        default: L0 = 0.5 * (b2 - un * ic); Ln = 0.5 * (ic - b1 * un);
+                 Lt = -0.5 * b1 * ut;       L3 = 0.5 * b1; break;
     }
-    // R row for conserved component k (columns: fields 0..3)
-    // columns: (1, un-c, ut, H-un c), (1, un, ut, q2/2), (0, 0, 1, ut), (1, un+c, ut, H+un c)
-    if (k == 0) { Rr[0] = 1.0; Rr[1] = 1.0; Rr[2] = 0.0; Rr[3] = 1.0; }
-    else if (k == in) { Rr[0] = un - c; Rr[1] = un; Rr[2] = 0.0; Rr[3] = un + c; }
-    else if (k == it) { Rr[0] = ut; Rr[1] = ut; Rr[2] = 1.0; Rr[3] = ut; }
-    else { Rr[0] = H - un * c; Rr[1] = 0.5 * q2; Rr[2] = ut; Rr[3] = H + un * c; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { Lrow[i] = Lr[i]; Rrow[i] = Rr[i]; }
+    Lrow[0] = L0;
+    Lrow[1] = b ? Lt : Ln;
+    Lrow[2] = b ? Ln : Lt;
+    Lrow[3] = L3;
+    // Row of R for conserved component k; columns (fields 0..3):
+    // (1, un-c, ut, H-un c), (1, un, ut, q2/2), (0, 0, 1, ut), (1, un+c, ut, H+un c)
+    if (k == 0) {
+        Rrow[0] = 1.0; Rrow[1] = 1.0; Rrow[2] = 0.0; Rrow[3] = 1.0;
+    } else if (k == 3) {
+        Rrow[0] = H - un * c; Rrow[1] = 0.5 * q2; Rrow[2] = ut; Rrow[3] = H + un * c;
+    } else {
+        const bool nrm = (k == 1) == (b == 0);   // the normal momentum's row
+        Rrow[0] = nrm ? un - c : ut;
+        Rrow[1] = nrm ? un : ut;
+        Rrow[2] = nrm ? 0.0 : 1.0;
+        Rrow[3] = nrm ? un + c : ut;
+    }
 }
 
 // ---------------------------------------------------------------------------
