@@ -221,14 +221,15 @@ def bench_developed(nsteps, t_dev=0.3):
 
 
 def bench_adjoint(nsteps=200, every=20):
-    """Double shear layer: forward + checkpointed backward vs plain forward."""
+    """Double shear layer: forward + checkpointed backward vs plain forward
+    (the stage intermediates kept for the step adjoints)."""
     import numpy as np
     import torch
     from paper_2608_10569_amd import adjoint, hweno
     n, mu, gamma = 256, 1e-3, 1.4
     f = adjoint.shear_layer_fields(n)
     rho, u, v = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in f[:3]]
-    s = hweno.Solver(n, n, mu_ref=mu)
+    s = hweno.Solver(n, n, mu_ref=mu, keep_stages=1)
     U0 = adjoint.project_fields(rho, u, v, f[3], gamma)
     s.set_state(U0)
     dt = s.rk_step(0.0)['dt']

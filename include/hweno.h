@@ -100,6 +100,10 @@ typedef struct hweno_options {
     int max_halvings;           /* restarts with dt/2 allowed per step (>= 0) */
     int linear_gradients;       /* 1: omega = gamma in the gradient reconstruction only
                                    (the linear counterpart of Remark 3.1); 0: paper */
+    int keep_stages;            /* 2D single grid: 1 keeps the residual intermediates of the
+                                   three RK stages apart (2 x 248 doubles more workspace per
+                                   ghosted cell), so that hweno_rk_step_vjp evaluates three
+                                   residuals instead of five; 0 (default): one set */
 } hweno_options;
 
 /* Diagnostics of the last call (Sec. 5 preamble; Table 5.3 PP activity). */
@@ -245,7 +249,11 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const
  * dt is held constant (the time-step rule is not differentiated).  The two
  * intermediate stages are recomputed from U0 with the forward kernels; the
  * three stage residual adjoints then run in reverse, branch and tie rules as
- * in hweno_residual_vjp, bitwise reproducible.  U3bar must not overlap U0.
+ * in hweno_residual_vjp, bitwise reproducible.  Each adjoint needs the
+ * intermediates of its stage residual: with keep_stages = 0 they are
+ * recomputed (five residual evaluations per call), with keep_stages = 1 the
+ * second and third stage keep theirs (three); the results are the same bits.
+ * U3bar must not overlap U0.
  * Uses the workspace; leaves the context state alone; with a non-NULL
  * mu_bar the call synchronises.  HWENO_E_INVAL for dt <= 0, dim = 1 or
  * mu_exp != 0. */

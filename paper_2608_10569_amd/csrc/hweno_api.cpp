@@ -55,6 +55,12 @@ struct hweno_ctx {
     hw::Grid1 g1{};
     // reverse mode (single 2D grid)
     hw::AdjWs adj{};
+    // keep_stages (single 2D grid): residual intermediates of RK stages 2 and 3
+    // in arrays of their own, described by stage[k] (host) / dstage + k
+    // (device) and launched through blstage[k]
+    hw::Grid2 stage[2]{};
+    hw::Grid2* dstage = nullptr;
+    hw::BatchL blstage[2];
     double* mu_dev = nullptr;
     double* X1 = nullptr;              // interior stage cotangents (12 per cell)
     double* X2 = nullptr;
@@ -253,6 +259,23 @@ size_t layout(hweno_ctx* c, char* base) {
         c->sdst_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
         c->ssrc_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
         c->sdir_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
+        if (c->i0().opt.keep_stages) {
+            for (int k = 0; k < 2; ++k) {
+                hw::Grid2& st = c->stage[k];
+                st.xf = take(24 * m);
+                st.yf = take(24 * m);
+                st.xv = take(36 * m);
+                st.yv = take(36 * m);
+                st.wb = take(6 * m);
+                st.vk = take(8 * m);
+                st.rb = take(18 * m);
+                st.gf = take(72 * m);
+                st.vf = take(8 * m);
+                st.fx = take(8 * m);
+                st.fy = take(8 * m);
+            }
+            c->dstage = reinterpret_cast<hw::Grid2*>(take_bytes(2 * sizeof(hw::Grid2)));
+        }
     }
     c->red = reinterpret_cast<hw::Reduce*>(take_bytes(n * sizeof(hw::Reduce)));
     c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
@@ -312,6 +335,33 @@ hweno_status upload_grids(hweno_ctx* c) {
     c->bl.tiles = c->tiles;
     c->bl.var_mu = false;
     for (const Inst& in : c->in) c->bl.var_mu = c->bl.var_mu || in.phys.mu_exp != 0.0;
+    if (!c->batch && c->dstage) {
+        // descriptors of the stage intermediates: the grid's own, with the
+        // intermediate arrays of set k
+        hw::Grid2 d[2];
+        for (int k = 0; k < 2; ++k) {
+            const hw::Grid2& st = c->stage[k];
+            d[k] = c->hg[0];
+            d[k].xf = st.xf;
+            d[k].yf = st.yf;
+            d[k].xv = st.xv;
+            d[k].yv = st.yv;
+            d[k].wb = st.wb;
+            d[k].vk = st.vk;
+            d[k].rb = st.rb;
+            d[k].gf = st.gf;
+            d[k].vf = st.vf;
+            d[k].fx = st.fx;
+            d[k].fy = st.fy;
+        }
+        TRY(dev(hipMemcpyAsync(c->dstage, d, sizeof d, hipMemcpyHostToDevice, c->stream)));
+        TRY(dev(hipStreamSynchronize(c->stream)));
+        for (int k = 0; k < 2; ++k) {
+            c->stage[k] = d[k];
+            c->blstage[k] = c->bl;
+            c->blstage[k].dg = c->dstage + k;
+        }
+    }
     drop_graphs(c);
     return HWENO_OK;
 }
@@ -389,15 +439,17 @@ hweno_status ghost(hweno_ctx* c, int si, int stage = -1) {
     return dev(hw::launch_ghost1(c->g1, c->S1[si], c->stream, c->tm()));
 }
 
-hweno_status residual(hweno_ctx* c, int si) {
-    if (c->dim() == 2) return dev(hw::launch_residual2(c->bl, si, c->stream, c->tm()));
+// b: the 2D launch list to use (the stage sets of keep_stages); default the grid's
+hweno_status residual(hweno_ctx* c, int si, const hw::BatchL* b = nullptr) {
+    if (c->dim() == 2) return dev(hw::launch_residual2(b ? *b : c->bl, si, c->stream, c->tm()));
     return dev(hw::launch_residual1(c->g1, c->S1[si], c->stream, c->tm()));
 }
 
 hweno_status update(hweno_ctx* c, int stage, int i0, int iin, int iout, double* R, double* V,
-                    const double* src = nullptr) {
+                    const double* src = nullptr, const hw::BatchL* b = nullptr) {
     if (c->dim() == 2)
-        return dev(hw::launch_update2(c->bl, stage, i0, iin, iout, R, V, c->stream, c->tm(), src));
+        return dev(hw::launch_update2(b ? *b : c->bl, stage, i0, iin, iout, R, V, c->stream,
+                                      c->tm(), src));
     return dev(hw::launch_update1(c->g1, stage, c->S1[i0], c->S1[iin], c->S1[iout], R, V,
                                   c->stream, c->tm(), src));
 }
@@ -439,7 +491,7 @@ hweno_status validate(const hweno_grid* grid, const hweno_physics* phys, const h
         !(phys->T_ref > 0.0) || !std::isfinite(phys->mu_exp))
         return HWENO_E_INVAL;
     if (!(opt->cfl > 0.0) || !(opt->eps_pp > 0.0) || !(opt->eps_weno > 0.0) ||
-        opt->max_halvings < 0)
+        opt->max_halvings < 0 || (opt->keep_stages != 0 && opt->keep_stages != 1))
         return HWENO_E_INVAL;
     const int nsides = 2 * grid->dim;
     for (int s = 0; s < nsides; ++s) {
@@ -554,6 +606,7 @@ HWENO_API hweno_status hweno_default_options(hweno_options* o) {
     o->linear_weights = 0;
     o->max_halvings = 64;
     o->linear_gradients = 0;
+    o->keep_stages = 0;
     return HWENO_OK;
 }
 
@@ -944,30 +997,42 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     TRY(dev(hw::launch_copy_in2(g, U0, g.S[ia], c->stream)));
     TRY(reset(c));
     TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
+    // with keep_stages the residual intermediates of U0 stay in the grid's
+    // set, those of U1 go to stage set 0 and those of U2 to stage set 1, so
+    // the adjoints of stages 2 and 1 need no recomputation
+    const bool keep = c->dstage != nullptr;
+    const hw::BatchL* b1 = keep ? &c->blstage[0] : nullptr;
     TRY(ghost(c, ia));
     TRY(residual(c, ia));
     TRY(update(c, 1, ia, ia, ib, nullptr, nullptr));
     TRY(ghost(c, ib));
-    TRY(residual(c, ib));
-    TRY(update(c, 2, ia, ib, ic, nullptr, nullptr));
-    auto vjp_at = [&](int si, const double* Rb, const double* Vb, double rs, double vs,
-                      double* out, int acc) {
-        TRY(reset(c));
-        TRY(ghost(c, si));
-        TRY(residual(c, si));
+    TRY(residual(c, ib, b1));
+    TRY(update(c, 2, ia, ib, ic, nullptr, nullptr, nullptr, b1));
+    // adjoint at stage input si with the intermediates described by gi
+    // (launched through bi when they are formed first)
+    auto vjp_at = [&](int si, const hw::Grid2& gi, const hw::BatchL* bi, bool form,
+                      const double* Rb, const double* Vb, double rs, double vs, double* out,
+                      int acc) {
+        if (form) {
+            TRY(reset(c));
+            TRY(ghost(c, si));
+            TRY(residual(c, si, bi));
+        }
         hw::AdjIn A{Rb, Vb, rs, vs};
-        return dev(hw::launch_vjp2(g, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream));
+        return dev(hw::launch_vjp2(gi, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream));
     };
     // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified moments)
-    TRY(vjp_at(ic, U3bar, U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
+    TRY(vjp_at(ic, keep ? c->stage[1] : g, keep ? &c->blstage[1] : nullptr, true, U3bar,
+               U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
     TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
     // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar
-    TRY(vjp_at(ib, c->X2, c->X2 + 4 * nint, 0.25 * dt, 0.25, c->X1, 1));
+    TRY(vjp_at(ib, keep ? c->stage[0] : g, nullptr, !keep, c->X2, c->X2 + 4 * nint, 0.25 * dt,
+               0.25, c->X1, 1));
     TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
     // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar
-    TRY(vjp_at(ia, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
+    TRY(vjp_at(ia, g, nullptr, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
     TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,

@@ -50,7 +50,8 @@ class OptionsC(ctypes.Structure):
     _fields_ = [('cfl', ctypes.c_double), ('b_visc', ctypes.c_double),
                 ('eps_pp', ctypes.c_double), ('eps_weno', ctypes.c_double),
                 ('t_final', ctypes.c_double), ('linear_weights', ctypes.c_int),
-                ('max_halvings', ctypes.c_int), ('linear_gradients', ctypes.c_int)]
+                ('max_halvings', ctypes.c_int), ('linear_gradients', ctypes.c_int),
+                ('keep_stages', ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -155,7 +156,7 @@ class Solver:
     ``bc`` = kinds for (xlo, xhi[, ylo, yhi]); ``inflow`` = {side: primitive
     state (rho, u, [v,] p)}; ``options`` = keyword overrides of the paper's
     defaults (cfl, b_visc, eps_pp, eps_weno, t_final, linear_weights,
-    max_halvings).
+    max_halvings, linear_gradients, keep_stages).
     """
 
     def __init__(self, nx, ny=None, extent=(0.0, 1.0, 0.0, 1.0), gamma=1.4, Pr=0.72,

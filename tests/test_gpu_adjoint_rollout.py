@@ -142,6 +142,35 @@ def test_rollout_checkpointing_is_exact():
     assert torch.equal(U.grad, grads[0][0]) and mu.grad.item() == grads[0][1]
 
 
+def test_kept_stage_intermediates_give_the_same_bits():
+    """keep_stages: the RK-step adjoint reuses the intermediates of the stage
+    residuals instead of recomputing them.  The step adjoint (periodic, and
+    walls with outflow) and a checkpointed rollout gradient must not change
+    by a bit."""
+    rng = np.random.default_rng([2608, 78])
+    for seed, bc in ((29, ('periodic',) * 4), (30, ('noslip', 'outflow', 'slip', 'outflow'))):
+        U = workloads.random_smooth_2d(24, 20, seed=seed, noise=1e-3)
+        a = hweno.Solver(24, 20, bc=bc, mu_ref=0.01)
+        b = hweno.Solver(24, 20, bc=bc, mu_ref=0.01, keep_stages=1)
+        dt = rule_dt(a, U)
+        Wb = to_dev(rng.standard_normal(U.shape))
+        Ua, ma = a.rk_step_vjp(to_dev(U), dt, Wb)
+        Ub, mb = b.rk_step_vjp(to_dev(U), dt, Wb)
+        print('%s: step adjoint equal %s, mu %r %r' % (bc[0], torch.equal(Ua, Ub), ma, mb))
+        assert torch.equal(Ua, Ub) and ma == mb
+    U0 = to_dev(workloads.random_smooth_2d(16, 16, seed=31, noise=1e-3))
+    grads = []
+    for keep in (0, 1):
+        s = hweno.Solver(16, 16, mu_ref=0.01, keep_stages=keep)
+        dt = rule_dt(s, U0.cpu().numpy())
+        U = U0.clone().requires_grad_(True)
+        mu = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
+        J = adjoint.kinetic_energy(adjoint.rollout(s, U, mu, dt, 6, 3), s.dx, s.dy)
+        J.backward()
+        grads.append((U.grad.clone(), mu.grad.item(), J.item()))
+    assert torch.equal(grads[0][0], grads[1][0]) and grads[0][1:] == grads[1][1:]
+
+
 def rollout_gradient(n, nsteps, every, mu, fields):
     """J and its gradient w.r.t. the node fields (rho, u, v) and mu."""
     gamma = 1.4
