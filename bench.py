@@ -283,8 +283,8 @@ def main():
                          'kernel of known size, for calibrating HBM byte counters)')
     args = ap.parse_args()
     if args.gpus != 1:
-        print('bench.py measures one GPU only: this build has no multi-GPU path '
-              '(the grid would be split into slabs with halo exchange; see the design notes).',
+        print('bench.py measures one GPU only: the library has no multi-GPU path (a grid '
+              'would be split into y-slabs with a 4-row halo exchange per RK stage).',
               file=sys.stderr)
         sys.exit(2)
 

@@ -12,7 +12,7 @@ dense linear solve in FP64 on a monomial basis of the scaled coordinates
 (xi, eta) of the target cell, with the moment integrals computed by a
 Gauss-Legendre rule that is exact for them.  Nothing is tabulated by hand.
 
-Readings where the paper is silent (also listed in the design notes):
+Readings where the paper is silent:
 
 * Smoothness indicators (the paper defers them to its reference on unified
   stencils): the Sobolev form in scaled coordinates,
