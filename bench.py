@@ -68,10 +68,10 @@ FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400,
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
 # and for the kernels as they are now: e.g. recon with 32-cell tiles reads
 # 53.2 MB and writes 553.0 MB per launch.
-TRAFFIC_BYTES = {('recon', 16): 606896130, ('recon', 32): 606213750,
-                 ('grad', 32): 737598675, ('grad', 64): 715730572,
-                 ('rbar', None): 307858239, ('update', None): 227459678,
-                 ('fluxup', None): 732806729}
+TRAFFIC_BYTES = {('recon', 16): 606967035, ('recon', 32): 606181404,
+                 ('grad', 32): 737965288, ('grad', 64): 715948182,
+                 ('rbar', None): 318119878, ('update', None): 227934447,
+                 ('fluxup', None): 748826092}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).

@@ -109,12 +109,14 @@ __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
 // The hardware hands a launch's blocks to the 8 XCDs round-robin, and each
 // XCD has its own L2.  With xcd set, XCD x takes the contiguous range x of the
 // logical blocks, so blocks of neighbouring rows (which share stencil rows)
-// run on the same XCD.  A bijection of [0, nb).
+// run on the same XCD; with rev each XCD takes its range last first.  A
+// bijection of [0, nb).
 constexpr int NUM_XCD = 8;
-__device__ __forceinline__ int xcd_block(int b, int nb) {
+__device__ __forceinline__ int xcd_block(int b, int nb, bool rev) {
     const int q = nb / NUM_XCD, r = nb % NUM_XCD;
     const int x = b % NUM_XCD, k = b / NUM_XCD;
-    return x * q + (x < r ? x : r) + k;
+    const int len = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + (rev ? len - 1 - k : k);
 }
 
 // Slot of the instance that owns this block and the block's index within it
@@ -123,7 +125,9 @@ struct Loc {
     int p, b;
 };
 __device__ __forceinline__ Loc locate(const Batch& B) {
-    const int bid = B.xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int nb = (int)gridDim.x;
+    const int bid = B.xcd ? xcd_block((int)blockIdx.x, nb, B.rev)
+                          : (B.rev ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x);
     int lo = 0, hi = B.n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;

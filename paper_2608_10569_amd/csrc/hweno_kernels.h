@@ -189,6 +189,7 @@ struct Batch {
     const int* start;
     int n;
     int xcd;          // 1: XCD-aware order of the launch's blocks
+    int rev;          // 1: each XCD (or the launch) takes its range of blocks last first
 };
 
 // Work per block of the tunable kernels (cells, cells, faces).
@@ -206,7 +207,15 @@ struct BatchL {
     int n = 0;
     Tiles tiles;
     bool var_mu = true;            // some instance has a temperature-dependent mu
-    Batch arg(int k) const { return Batch{dg, dstart + k * (n + 1), n, tiles.xcd}; }
+    // bit k: kernel class k runs its blocks last first.  The weak-moment and
+    // face-flux kernels run in the opposite order of the kernel that wrote
+    // most of their input just before them (reconstruction, gradients), so
+    // their first blocks read what is still in L2 and the memory-side cache;
+    // the next stage's reconstruction then again runs opposite to them.
+    unsigned rev = (1u << KB_RBAR) | (1u << KB_FLUX0) | (1u << KB_FLUX1) | (1u << KB_FLUXUP);
+    Batch arg(int k) const {
+        return Batch{dg, dstart + k * (n + 1), n, tiles.xcd, (int)((rev >> k) & 1u)};
+    }
     unsigned blocks(int k) const { return (unsigned)hstart[k * (n + 1) + n]; }
 };
 
