@@ -260,8 +260,11 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar);
 
-/* Per-kernel-class GPU time, measured with HIP events recorded on the
- * context's stream around every launch while timing is enabled.  Classes:
+/* Per-kernel-class GPU time, measured with HIP events while timing is
+ * enabled.  A class of one kernel has the kernel record the events at the
+ * start and end of its execution (hipExtLaunchKernel: the dispatch is not
+ * counted); classes 4 and 6 record them on the stream around their launches.
+ * Classes:
  * 0 ghost fill, 1 characteristic reconstruction + limiter, 2 weak-derivative
  * moments, 3 gradient reconstruction + volume flux, 4 face fluxes, 5 stage
  * update / assembly, 6 a whole batched run (hweno_batch_run), 7 face fluxes

@@ -18,6 +18,8 @@
 // Every intermediate lives in HBM, laid out component-major over the ghosted
 // grid so that consecutive lanes touch consecutive cells.
 
+#include <hip/hip_ext.h>
+
 #include "hweno_kernels.h"
 
 namespace hw {
@@ -1259,30 +1261,36 @@ hipError_t launch_copy_out2(const Grid2& g, const double* S, double* U, hipStrea
     return hipGetLastError();
 }
 
+// Launch of a kernel that is a timing class of its own: when the class is
+// timed, the kernel records the two events itself at the start and end of
+// its execution; otherwise a plain launch (the one graphs record).
+template <typename F, typename... Args>
+void tlaunch(Timer* tm, int k, F kern, unsigned grid, unsigned block, hipStream_t st,
+             Args... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) tm->ext(k, &e0, &e1);
+    if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, args...);
+}
+
 hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int stage) {
-    tbeg(tm, KC_GHOST, st);
-    k_ghost2<<<b.blocks(KB_GHOST), 256, 0, st>>>(b.arg(KB_GHOST), si, stage);
-    tend(tm, st);
+    tlaunch(tm, KC_GHOST, k_ghost2, b.blocks(KB_GHOST), 256, st, b.arg(KB_GHOST), si, stage);
     return hipGetLastError();
 }
 
 hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) {
-    tbeg(tm, KC_RECON, st);
-    if (b.tiles.recon == 16) k_recon2<16><<<b.blocks(KB_RECON), 128, 0, st>>>(b.arg(KB_RECON), si);
-    else k_recon2<32><<<b.blocks(KB_RECON), 256, 0, st>>>(b.arg(KB_RECON), si);
-    tend(tm, st);
-    tbeg(tm, KC_RBAR, st);
-    k_rbar2<<<b.blocks(KB_RBAR), RB_TX * RB_TY, 0, st>>>(b.arg(KB_RBAR));
-    tend(tm, st);
-    tbeg(tm, KC_GRAD, st);
+    const unsigned nr = b.blocks(KB_RECON), ng = b.blocks(KB_GRAD);
+    if (b.tiles.recon == 16) tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, b.arg(KB_RECON), si);
+    else tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, b.arg(KB_RECON), si);
+    tlaunch(tm, KC_RBAR, k_rbar2, b.blocks(KB_RBAR), RB_TX * RB_TY, st, b.arg(KB_RBAR));
+    const Batch ag = b.arg(KB_GRAD);
     if (b.tiles.grad == 64) {
-        if (b.var_mu) k_grad2<64, true><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
-        else k_grad2<64, false><<<b.blocks(KB_GRAD), 384, 0, st>>>(b.arg(KB_GRAD));
+        if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<64, true>, ng, 384, st, ag);
+        else tlaunch(tm, KC_GRAD, k_grad2<64, false>, ng, 384, st, ag);
     } else {
-        if (b.var_mu) k_grad2<32, true><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
-        else k_grad2<32, false><<<b.blocks(KB_GRAD), 192, 0, st>>>(b.arg(KB_GRAD));
+        if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<32, true>, ng, 192, st, ag);
+        else tlaunch(tm, KC_GRAD, k_grad2<32, false>, ng, 192, st, ag);
     }
-    tend(tm, st);
     if (b.tiles.flux == 0) return hipGetLastError();   // fluxes formed by the update kernel
     tbeg(tm, KC_FLUX, st);
     if (b.tiles.flux == 128) {
@@ -1309,19 +1317,17 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
 hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout, double* R,
                           double* Vhat, hipStream_t st, Timer* tm, const double* src) {
     if (b.tiles.flux == 0) {
-        tbeg(tm, KC_FLUXUP, st);
+        const unsigned nb = b.blocks(KB_FLUXUP);
         if (b.var_mu)
-            k_fluxup2<true><<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(
-                b.arg(KB_FLUXUP), stage, i0, iin, iout, R, Vhat, src);
+            tlaunch(tm, KC_FLUXUP, k_fluxup2<true>, nb, FU_TX * FU_TY, st, b.arg(KB_FLUXUP), stage,
+                    i0, iin, iout, R, Vhat, src);
         else
-            k_fluxup2<false><<<b.blocks(KB_FLUXUP), FU_TX * FU_TY, 0, st>>>(
-                b.arg(KB_FLUXUP), stage, i0, iin, iout, R, Vhat, src);
+            tlaunch(tm, KC_FLUXUP, k_fluxup2<false>, nb, FU_TX * FU_TY, st, b.arg(KB_FLUXUP),
+                    stage, i0, iin, iout, R, Vhat, src);
     } else {
-        tbeg(tm, KC_UPDATE, st);
-        k_update2<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS), stage, i0, iin, iout, R,
-                                                      Vhat, src);
+        tlaunch(tm, KC_UPDATE, k_update2, b.blocks(KB_CELLS), 256, st, b.arg(KB_CELLS), stage, i0,
+                iin, iout, R, Vhat, src);
     }
-    tend(tm, st);
     return hipGetLastError();
 }
 

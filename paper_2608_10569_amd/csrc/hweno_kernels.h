@@ -148,6 +148,17 @@ struct Timer {
         (void)hipEventRecord(a[n], st);
         open = true;
     }
+    // events for a launch that records them itself (hipExtLaunchKernel): the
+    // interval then spans the kernel's execution, without its dispatch
+    void ext(int k, hipEvent_t* e0, hipEvent_t* e1) {
+        *e0 = *e1 = nullptr;
+        open = false;
+        if (!on || !((mask >> k) & 1u) || n >= CAP) return;
+        cls[n] = k;
+        *e0 = a[n];
+        *e1 = b[n];
+        ++n;
+    }
     void end(hipStream_t st) {
         if (!open) return;
         (void)hipEventRecord(b[n], st);
