@@ -108,19 +108,6 @@ __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
     }
 }
 
-// The hardware hands a launch's blocks to the 8 XCDs round-robin, and each
-// XCD has its own L2.  With xcd set, XCD x takes the contiguous range x of the
-// logical blocks, so blocks of neighbouring rows (which share stencil rows)
-// run on the same XCD; with rev each XCD takes its range last first.  A
-// bijection of [0, nb).
-constexpr int NUM_XCD = 8;
-__device__ __forceinline__ int xcd_block(int b, int nb, bool rev) {
-    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
-    const int x = b % NUM_XCD, k = b / NUM_XCD;
-    const int len = q + (x < r ? 1 : 0);
-    return x * q + (x < r ? x : r) + (rev ? len - 1 - k : k);
-}
-
 // Slot of the instance that owns this block and the block's index within it
 // (uniform per block: binary search of the launch's block prefix table).
 struct Loc {

@@ -40,7 +40,14 @@ __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, in
     return A.rs * A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
 }
 
-// fixed-order block sum of the mu adjoint: one partial per block
+// Logical index of this block: XCD-aware (each XCD takes a contiguous range
+// of the launch, so neighbouring rows of a stencil share an L2).  The mu
+// partials are stored by it, so their fixed summation order is unchanged.
+__device__ __forceinline__ int lblock() {
+    return xcd_block((int)blockIdx.x, (int)gridDim.x, false);
+}
+
+// fixed-order block sum of the mu adjoint: one partial per (logical) block
 template <int NT>
 __device__ __forceinline__ void mu_partial(double v, double* part) {
     __shared__ double sh[NT];
@@ -49,7 +56,7 @@ __device__ __forceinline__ void mu_partial(double v, double* part) {
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int t = 0; t < NT; ++t) s += sh[t];
-        part[blockIdx.x] = s;
+        part[lblock()] = s;
     }
 }
 
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
     const int nfj = d == 0 ? g.ny : g.ny + 1;
     const int G = threadIdx.x / AF;
     const int fl = threadIdx.x % AF;
-    const long long t = (long long)blockIdx.x * AF + fl;
+    const long long t = (long long)lblock() * AF + fl;
     const bool valid = t < (long long)nfi * nfj;
     const long long N = g.ncell;
     int j = HALO, i = HALO;
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
     const int w = s >> 1, l = s & 1;
     const int wc = g.NX - 6;
     const long long nreg = (long long)wc * (g.NY - 6);
-    const long long cid = (long long)blockIdx.x * AG + cl;
+    const long long cid = (long long)lblock() * AG + cl;
     const bool valid = cid < nreg;
     int j = 3, i = 3;
     if (valid) {
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
 __global__ void k_adj_rgather(Grid2 g, AdjWs W) {
     const int wc = g.NX - 4;
     const long long nreg = (long long)wc * (g.NY - 4);
-    const long long cid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long cid = (long long)lblock() * blockDim.x + threadIdx.x;
     if (cid >= nreg) return;
     const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
     const int task = threadIdx.x / WM_CELLS;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)blockIdx.x * WM_CELLS + threadIdx.x % WM_CELLS;
+    const long long cid = (long long)lblock() * WM_CELLS + threadIdx.x % WM_CELLS;
     if (cid >= nreg) return;
     const int j = 1 + (int)(cid / wc), i = 1 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     const int b = bk >> 2, k = bk & 3;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)blockIdx.x * AC + cl;
+    const long long cid = (long long)lblock() * AC + cl;
     const bool valid = cid < nreg;
     int j = 1, i = 1;
     if (valid) {
@@ -734,7 +741,7 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
 // cell X - off(k) (averages: all 9 slots; moments: the 4 edge slots).
 // ---------------------------------------------------------------------------
 __global__ void k_adj_ugather(Grid2 g, AdjWs W) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)lblock() * blockDim.x + threadIdx.x;
     if (t >= g.ncell) return;
     const int j = (int)(t / g.NX), i = (int)(t % g.NX);
     const long long N = g.ncell;

@@ -10,6 +10,19 @@
 
 namespace hw {
 
+// The hardware hands a launch's blocks to the 8 XCDs round-robin, and each
+// XCD has its own L2.  With xcd set, XCD x takes the contiguous range x of the
+// logical blocks, so blocks of neighbouring rows (which share stencil rows)
+// run on the same XCD; with rev each XCD takes its range last first.  A
+// bijection of [0, nb).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb, bool rev) {
+    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int x = b % NUM_XCD, k = b / NUM_XCD;
+    const int len = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + (rev ? len - 1 - k : k);
+}
+
 // ---------------------------------------------------------------------------
 // Quadrature (Sec. 2.1: 4-point Legendre-Gauss-Lobatto; Sec. 3.1: 3-point
 // Gauss per direction), scaled to the unit cell [-1/2, 1/2].
