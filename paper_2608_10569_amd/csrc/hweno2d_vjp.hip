@@ -41,22 +41,25 @@ __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, in
 }
 
 // Logical index of this block: XCD-aware (each XCD takes a contiguous range
-// of the launch, so neighbouring rows of a stencil share an L2).  The mu
-// partials are stored by it, so their fixed summation order is unchanged.
-__device__ __forceinline__ int lblock() {
-    return xcd_block((int)blockIdx.x, (int)gridDim.x, false);
+// of the launch, so neighbouring rows of a stencil share an L2), last first
+// where bit k of W.rev is set (k: 0, 1 face fluxes x, y; 2 gradients; 3
+// weak-moment gather; 4 weak moments; 5 reconstruction; 6 state gather).
+// The mu partials are stored by it, so their fixed summation order is
+// unchanged.
+__device__ __forceinline__ int lblock(const AdjWs& W, int k) {
+    return xcd_block((int)blockIdx.x, (int)gridDim.x, (W.rev >> k) & 1u);
 }
 
 // fixed-order block sum of the mu adjoint: one partial per (logical) block
 template <int NT>
-__device__ __forceinline__ void mu_partial(double v, double* part) {
+__device__ __forceinline__ void mu_partial(double v, double* part, int lb) {
     __shared__ double sh[NT];
     sh[threadIdx.x] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int t = 0; t < NT; ++t) s += sh[t];
-        part[lblock()] = s;
+        part[lb] = s;
     }
 }
 
@@ -76,7 +79,8 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
     const int nfj = d == 0 ? g.ny : g.ny + 1;
     const int G = threadIdx.x / AF;
     const int fl = threadIdx.x % AF;
-    const long long t = (long long)lblock() * AF + fl;
+    const int lb = lblock(W, d);
+    const long long t = (long long)lb * AF + fl;
     const bool valid = t < (long long)nfi * nfj;
     const long long N = g.ncell;
     int j = HALO, i = HALO;
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
             W.gfb[((pg + G) * 6 + z) * N + cp] = spb[z];
         }
     }
-    mu_partial<3 * AF>(valid ? mub : 0.0, W.mupart + (d == 0 ? 0 : W.mu_off1));
+    mu_partial<3 * AF>(valid ? mub : 0.0, W.mupart + (d == 0 ? 0 : W.mu_off1), lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,7 +200,8 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
     const int w = s >> 1, l = s & 1;
     const int wc = g.NX - 6;
     const long long nreg = (long long)wc * (g.NY - 6);
-    const long long cid = (long long)lblock() * AG + cl;
+    const int lb = lblock(W, 2);
+    const long long cid = (long long)lb * AG + cl;
     const bool valid = cid < nreg;
     int j = 3, i = 3;
     if (valid) {
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
 #pragma unroll
         for (int k = 0; k < 17; ++k) W.rbc[(s * 17 + k) * N + cell] = ab[k];
     }
-    mu_partial<6 * AG>(mub, W.mupart + W.mu_off2);
+    mu_partial<6 * AG>(mub, W.mupart + W.mu_off2, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
 __global__ void k_adj_rgather(Grid2 g, AdjWs W) {
     const int wc = g.NX - 4;
     const long long nreg = (long long)wc * (g.NY - 4);
-    const long long cid = (long long)lblock() * blockDim.x + threadIdx.x;
+    const long long cid = (long long)lblock(W, 3) * blockDim.x + threadIdx.x;
     if (cid >= nreg) return;
     const int j = 2 + (int)(cid / wc), i = 2 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
     const int task = threadIdx.x / WM_CELLS;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)lblock() * WM_CELLS + threadIdx.x % WM_CELLS;
+    const long long cid = (long long)lblock(W, 4) * WM_CELLS + threadIdx.x % WM_CELLS;
     if (cid >= nreg) return;
     const int j = 1 + (int)(cid / wc), i = 1 + (int)(cid % wc);
     const long long N = g.ncell;
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     const int b = bk >> 2, k = bk & 3;
     const int wc = g.NX - 2;
     const long long nreg = (long long)wc * (g.NY - 2);
-    const long long cid = (long long)lblock() * AC + cl;
+    const long long cid = (long long)lblock(W, 5) * AC + cl;
     const bool valid = cid < nreg;
     int j = 1, i = 1;
     if (valid) {
@@ -741,7 +746,7 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
 // cell X - off(k) (averages: all 9 slots; moments: the 4 edge slots).
 // ---------------------------------------------------------------------------
 __global__ void k_adj_ugather(Grid2 g, AdjWs W) {
-    const long long t = (long long)lblock() * blockDim.x + threadIdx.x;
+    const long long t = (long long)lblock(W, 6) * blockDim.x + threadIdx.x;
     if (t >= g.ncell) return;
     const int j = (int)(t / g.NX), i = (int)(t % g.NX);
     const long long N = g.ncell;
@@ -876,6 +881,10 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     const unsigned bg = nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
     W.mu_off1 = bx;
     W.mu_off2 = bx + by;
+    // the reconstruction adjoint walks its blocks last first, opposite to the
+    // weak-moment adjoint before it (1.5 % of a step adjoint on 256^2; the
+    // other kernels showed no gain)
+    W.rev = 1u << 5;
     k_adj_flux<0><<<bx, 3 * AF, 0, st>>>(g, A, W);
     k_adj_flux<1><<<by, 3 * AF, 0, st>>>(g, A, W);
     k_adj_grad<<<bg, 6 * AG, 0, st>>>(g, A, W);

@@ -28,6 +28,7 @@ struct AdjWs {
     double* ubb;        // 12 / 6: gathered state adjoint (ghosted)
     double* mupart;     // block partials of the mu adjoint
     int mu_off1, mu_off2;
+    unsigned rev;       // bit k: adjoint kernel k takes its blocks last first (per XCD)
 };
 
 __device__ __forceinline__ double g_ld(const double* p, long long idx) { return p[idx]; }
