@@ -21,7 +21,8 @@
  *
  * Conventions
  *  - Every function returns hweno_status; nothing throws or aborts across
- *    the ABI.  hweno_status_string() names a status.
+ *    the ABI (a failed host allocation inside a call is reported as
+ *    HWENO_E_NOMEM).  hweno_status_string() names a status.
  *  - Array arguments documented as "device" are GPU pointers (HIP device
  *    memory of the device current when the context was created).  The
  *    caller owns every pointer it passes; the library keeps none after a
@@ -55,7 +56,9 @@ typedef enum hweno_status {
     HWENO_E_WORKSPACE = 3,      /* no workspace set, or too small / misaligned */
     HWENO_E_INADMISSIBLE = 4,   /* restart cap reached: a stage kept nonpositive rho or p */
     HWENO_E_NONFINITE = 5,      /* input state with non-finite values or rho<=0 / p<=0 */
-    HWENO_E_STATE = 6           /* no state set yet */
+    HWENO_E_STATE = 6,          /* no state set yet */
+    HWENO_E_NOMEM = 7           /* host memory allocation failed (the context is unchanged
+                                   when the failure precedes any change; otherwise recreate it) */
 } hweno_status;
 
 /* Ghost-cell rules of Remark 4.1. */
@@ -92,7 +95,8 @@ typedef struct hweno_bcs {
 /* Scheme constants (Sec. 5 preamble and Appendix A). */
 typedef struct hweno_options {
     double cfl;                 /* CFL number of the time-step rule (paper: 0.6) */
-    double b_visc;              /* viscous time-step constant b (paper: 0.001); <= 0 disables */
+    double b_visc;              /* viscous time-step constant b (paper: 0.001); <= 0 or +inf
+                                   turns the viscous bound b*h^2/mu_ref off; NaN is invalid */
     double eps_pp;              /* positivity floor (paper: 1e-12) */
     double eps_weno;            /* nonlinear-weight epsilon (paper: 1e-8) */
     double t_final;             /* steps are clipped to end at t_final; <= 0: no clipping */
@@ -119,14 +123,16 @@ typedef struct hweno_diag {
 } hweno_diag;
 
 /* Fills the paper's constants: cfl 0.6, b 0.001, eps_pp 1e-12, eps_weno 1e-8,
- * no clipping, nonlinear weights, 40 halvings. */
+ * no clipping, nonlinear weights, 64 halvings (the 1D Sedov start of
+ * Example 5.5 needs 51 in its first step), keep_stages 0. */
 HWENO_API hweno_status hweno_default_options(hweno_options* opt);
 
 /* Validates the problem and creates a context (host memory only).
  * Errors: HWENO_E_INVAL for a NULL argument, dim not 1/2, nx/ny < 4,
  * empty domain, gamma <= 1, Pr <= 0, mu_ref < 0, T_ref <= 0, unknown BC
  * kind, a periodic side paired with a non-periodic one, inflow density or
- * pressure <= 0, cfl <= 0, eps_pp <= 0, eps_weno <= 0, max_halvings < 0. */
+ * pressure <= 0, cfl <= 0, eps_pp <= 0, eps_weno <= 0, max_halvings < 0,
+ * b_visc or t_final NaN, keep_stages not 0/1. */
 HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
                                     const hweno_bcs* bcs, const hweno_options* opt,
                                     hweno_ctx** out);

@@ -98,7 +98,7 @@ class Options:
     """Scheme constants (Sec. 5 preamble and Appendix A)."""
 
     cfl: float = 0.6            #: CFL number (0.3 for Example 5.12)
-    b_visc: float = 0.001       #: viscous time-step constant b
+    b_visc: float = 0.001       #: viscous time-step constant b (<= 0 or inf: no bound)
     eps_pp: float = 1e-12       #: positivity-limiter floor
     eps_weno: float = 1e-8      #: epsilon of the nonlinear weights
     t_final: float = math.inf   #: last step is clipped to reach t_final

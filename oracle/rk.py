@@ -54,7 +54,7 @@ def trial_dt(scheme, alpha, t, rule='paper'):
     h = grid_h(scheme)
     if rule == 'paper':
         dt = op.cfl * h / alpha
-        if ph.mu_ref > 0.0:
+        if ph.mu_ref > 0.0 and op.b_visc > 0.0:   # b <= 0 (or inf): no viscous bound
             dt = min(dt, op.b_visc * h * h / ph.mu_ref)
     elif rule == 'h53':
         dt = op.cfl * h ** (5.0 / 3.0) / alpha

@@ -1137,7 +1137,8 @@ __global__ __launch_bounds__(256) void k_commit_copy(Batch bt) {
     for (int q = 0; q < 12; ++q) g.S[0][q * g.ncell + cell] = g.S[1][q * g.ncell + cell];
 }
 
-__global__ void k_commit_state(const Grid2* __restrict__ gs, int n, int code_inadmissible) {
+__global__ void k_commit_state(const Grid2* __restrict__ gs, int n, int code_inadmissible,
+                               int code_nonfinite) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const Grid2& g = gs[p];
@@ -1148,6 +1149,13 @@ __global__ void k_commit_state(const Grid2* __restrict__ gs, int n, int code_ina
     st->beta_max = dkey_inv(r->beta_key);
     st->min_rho = dkey_inv(r->min_rho_key);
     st->min_p = dkey_inv(r->min_p_key);
+    if (!(r->dt > 0.0) || !isfinite(r->dt)) {
+        // no usable step size (a non-finite wave speed): stop the instance
+        // as the single-grid driver stops, instead of halving a NaN
+        st->status = code_nonfinite;
+        st->active = 0;
+        return;
+    }
     if (accepted(g)) {
         st->t += r->dt;
         st->dt_last = r->dt;
@@ -1330,7 +1338,7 @@ hipError_t launch_dt2(const BatchL& b, hipStream_t st) {
 
 hipError_t launch_commit2(const BatchL& b, hipStream_t st) {
     k_commit_copy<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS));
-    k_commit_state<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n, 4);
+    k_commit_state<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n, 4, 5);
     return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <utility>
 #include <vector>
@@ -302,6 +303,18 @@ hweno_status dev(hipError_t e) {
         if (s_ != HWENO_OK) return s_;           \
     } while (0)
 
+// Every exported function runs its body inside GUARD_BEGIN / GUARD_END, so no
+// C++ exception crosses the C ABI.  The only ones the host code can raise are
+// the standard containers' allocation failures (std::bad_alloc,
+// std::length_error), reported as HWENO_E_NOMEM; the context is left as it
+// was before the call wherever the failing allocation precedes any change.
+#define GUARD_BEGIN try {
+#define GUARD_END                                \
+    }                                            \
+    catch (...) {                                \
+        return HWENO_E_NOMEM;                    \
+    }
+
 void drop_graphs(hweno_ctx* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gexec1) (void)hipGraphExecDestroy(c->gexec1);
@@ -491,7 +504,8 @@ hweno_status validate(const hweno_grid* grid, const hweno_physics* phys, const h
         !(phys->T_ref > 0.0) || !std::isfinite(phys->mu_exp))
         return HWENO_E_INVAL;
     if (!(opt->cfl > 0.0) || !(opt->eps_pp > 0.0) || !(opt->eps_weno > 0.0) ||
-        opt->max_halvings < 0 || (opt->keep_stages != 0 && opt->keep_stages != 1))
+        opt->max_halvings < 0 || (opt->keep_stages != 0 && opt->keep_stages != 1) ||
+        std::isnan(opt->b_visc) || std::isnan(opt->t_final))
         return HWENO_E_INVAL;
     const int nsides = 2 * grid->dim;
     for (int s = 0; s < nsides; ++s) {
@@ -513,7 +527,8 @@ hweno_status validate(const hweno_grid* grid, const hweno_physics* phys, const h
 // Builds the context of n validated instances (host side only).
 hweno_ctx* make_ctx(int n, const hweno_grid* grids, const hweno_physics* phys,
                     const hweno_bcs* bcs, const hweno_options* opts, bool batch) {
-    hweno_ctx* c = new (std::nothrow) hweno_ctx;
+    std::unique_ptr<hweno_ctx> owner(new (std::nothrow) hweno_ctx);
+    hweno_ctx* c = owner.get();
     if (!c) return nullptr;
     c->batch = batch;
     c->in.resize(n);
@@ -543,7 +558,7 @@ hweno_ctx* make_ctx(int n, const hweno_grid* grids, const hweno_physics* phys,
         for (int s = 0; s < 2; ++s) make_side(c->in[0], s, c->g1.side[s]);
     }
     c->ws_bytes = layout(c, nullptr);
-    return c;
+    return owner.release();
 }
 
 // One step of every active instance of a batch (eq. (2.12) with the step rule
@@ -597,6 +612,7 @@ hweno_status capture(hweno_ctx* c, int nsteps, hipGraphExec_t* out) {
 extern "C" {
 
 HWENO_API hweno_status hweno_default_options(hweno_options* o) {
+    GUARD_BEGIN
     if (!o) return HWENO_E_INVAL;
     o->cfl = 0.6;
     o->b_visc = 0.001;
@@ -608,23 +624,27 @@ HWENO_API hweno_status hweno_default_options(hweno_options* o) {
     o->linear_gradients = 0;
     o->keep_stages = 0;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
                                     const hweno_bcs* bcs, const hweno_options* opt,
                                     hweno_ctx** out) {
+    GUARD_BEGIN
     if (!out) return HWENO_E_INVAL;
     *out = nullptr;
     TRY(validate(grid, phys, bcs, opt));
     hweno_ctx* c = make_ctx(1, grid, phys, bcs, opt, false);
-    if (!c) return HWENO_E_INVAL;
+    if (!c) return HWENO_E_NOMEM;
     *out = c;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
                                           const hweno_physics* phys, const hweno_bcs* bcs,
                                           const hweno_options* opts, hweno_ctx** out) {
+    GUARD_BEGIN
     if (!out) return HWENO_E_INVAL;
     *out = nullptr;
     if (n < 1 || n > HWENO_BATCH_MAX || !grids || !phys || !bcs || !opts) return HWENO_E_INVAL;
@@ -633,27 +653,33 @@ HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
         if (grids[p].dim != 2) return HWENO_E_INVAL;
     }
     hweno_ctx* c = make_ctx(n, grids, phys, bcs, opts, true);
-    if (!c) return HWENO_E_INVAL;
+    if (!c) return HWENO_E_NOMEM;
     *out = c;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_destroy(hweno_ctx* c) {
+    GUARD_BEGIN
     if (!c) return HWENO_E_INVAL;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->timer.destroy();
     delete c;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_workspace_bytes(const hweno_ctx* c, size_t* bytes) {
+    GUARD_BEGIN
     if (!c || !bytes) return HWENO_E_INVAL;
     *bytes = c->ws_bytes;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) {
+    GUARD_BEGIN
     if (!c || !p) return HWENO_E_INVAL;
     if (bytes < c->ws_bytes || (reinterpret_cast<uintptr_t>(p) % ALIGN) != 0)
         return HWENO_E_WORKSPACE;
@@ -676,10 +702,12 @@ HWENO_API hweno_status hweno_set_workspace(hweno_ctx* c, void* p, size_t bytes) 
         TRY(upload_grids(c));
     }
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* c, int side, const double* prim,
                                                 int n) {
+    GUARD_BEGIN
     if (!c || c->batch || c->dim() != 2 || side < 0 || side > 3) return HWENO_E_INVAL;
     const Inst& in = c->i0();
     if (in.bcs.kind[side] != HWENO_BC_INFLOW) return HWENO_E_INVAL;
@@ -704,6 +732,7 @@ HWENO_API hweno_status hweno_set_inflow_profile(hweno_ctx* c, int side, const do
     if (!c->ws) return HWENO_OK;
     TRY(upload_profiles(c));
     return upload_grids(c);
+    GUARD_END
 }
 
 namespace {
@@ -754,6 +783,7 @@ void mirror_list(const unsigned char* m, int nx, int ny, int NX, std::vector<int
 }  // namespace
 
 HWENO_API hweno_status hweno_set_solid(hweno_ctx* c, const unsigned char* mask, int wall) {
+    GUARD_BEGIN
     if (!c || c->batch || c->dim() != 2) return HWENO_E_INVAL;
     const int nx = c->i0().grid.nx, ny = c->i0().grid.ny;
     std::vector<unsigned char> m;
@@ -775,15 +805,19 @@ HWENO_API hweno_status hweno_set_solid(hweno_ctx* c, const unsigned char* mask, 
     if (!c->ws) return HWENO_OK;
     TRY(upload_solid(c));
     return upload_grids(c);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* c, void* s) {
+    GUARD_BEGIN
     if (!c) return HWENO_E_INVAL;
     c->stream = static_cast<hipStream_t>(s);
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_state(hweno_ctx* c, const double* U, double t) {
+    GUARD_BEGIN
     if (!c || !U || !std::isfinite(t) || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (c->dim() == 2) TRY(dev(hw::launch_copy_in2(g2(c), U, g2(c).S[c->cur], c->stream)));
@@ -792,9 +826,11 @@ HWENO_API hweno_status hweno_set_state(hweno_ctx* c, const double* U, double t) 
     c->has_state = true;
     c->state_checked = false;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_get_state(hweno_ctx* c, double* U, double* t) {
+    GUARD_BEGIN
     if (!c || !U || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
@@ -802,10 +838,12 @@ HWENO_API hweno_status hweno_get_state(hweno_ctx* c, double* U, double* t) {
     else TRY(dev(hw::launch_copy_out1(c->g1, c->S1[0], U, c->stream)));
     if (t) *t = c->t;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, double* V,
                                       hweno_diag* diag) {
+    GUARD_BEGIN
     if (!c || !U || !R || !V || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (c->dim() == 2) TRY(dev(hw::launch_copy_in2(g2(c), U, g2(c).S[2], c->stream)));
@@ -822,6 +860,7 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
         diag->min_rho = diag->min_p = NAN;
     }
     return HWENO_OK;
+    GUARD_END
 }
 
 }  // extern "C"
@@ -899,25 +938,30 @@ hweno_status step(hweno_ctx* c, double dt, const double* const* src, hweno_diag*
 extern "C" {
 
 HWENO_API hweno_status hweno_rk_step(hweno_ctx* c, double dt, hweno_diag* diag) {
+    GUARD_BEGIN
     if (!c || std::isnan(dt) || c->batch) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
     return step(c, dt, nullptr, diag);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* c, double dt, const double* src1,
                                             const double* src2, const double* src3,
                                             hweno_diag* diag) {
+    GUARD_BEGIN
     if (!c || !(dt > 0.0) || !std::isfinite(dt) || c->batch || !src1 || !src2 || !src3)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
     const double* src[3] = {src1, src2, src3};
     return step(c, dt, src, diag);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_inflow_stages(hweno_ctx* c, int side, const double* prim1,
                                                const double* prim2, const double* prim3, int n) {
+    GUARD_BEGIN
     if (!c || c->batch || c->dim() != 2 || side < 0 || side > 3) return HWENO_E_INVAL;
     const Inst& in = c->i0();
     if (in.bcs.kind[side] != HWENO_BC_INFLOW) return HWENO_E_INVAL;
@@ -947,18 +991,22 @@ HWENO_API hweno_status hweno_set_inflow_stages(hweno_ctx* c, int side, const dou
     if (!c->ws) return HWENO_OK;
     TRY(upload_profiles(c));
     return upload_grids(c);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* c, double dt, hweno_diag* diag) {
+    GUARD_BEGIN
     if (!c || !(dt > 0.0) || !std::isfinite(dt) || c->batch || c->dim() != 2)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->has_state) return HWENO_E_STATE;
     return step(c, dt, nullptr, diag, true);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar) {
+    GUARD_BEGIN
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
     if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
         return HWENO_E_INVAL;
@@ -976,6 +1024,7 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
         TRY(dev(hipStreamSynchronize(c->stream)));
     }
     return HWENO_OK;
+    GUARD_END
 }
 
 // Reverse mode of one SSP-RK3 step with the step size frozen (eq. (2.12)):
@@ -985,6 +1034,7 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
 // residual adjoints run in reverse with the stage cotangents as seeds.
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar) {
+    GUARD_BEGIN
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
     if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
@@ -1040,12 +1090,14 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
         TRY(dev(hipStreamSynchronize(c->stream)));
     }
     return HWENO_OK;
+    GUARD_END
 }
 
 // ---------------------------------------------------------------------------
 // Batches
 // ---------------------------------------------------------------------------
 HWENO_API hweno_status hweno_batch_set_state(hweno_ctx* c, int i, const double* U, double t) {
+    GUARD_BEGIN
     if (!c || !c->batch || !U || i < 0 || i >= (int)c->in.size() || !std::isfinite(t))
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
@@ -1058,9 +1110,11 @@ HWENO_API hweno_status hweno_batch_set_state(hweno_ctx* c, int i, const double* 
     TRY(upload_state(c));
     c->have[i] = 1;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_batch_get_state(hweno_ctx* c, int i, double* U, double* t) {
+    GUARD_BEGIN
     if (!c || !c->batch || !U || i < 0 || i >= (int)c->in.size()) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (!c->have[i]) return HWENO_E_STATE;
@@ -1068,9 +1122,11 @@ HWENO_API hweno_status hweno_batch_get_state(hweno_ctx* c, int i, double* U, dou
     TRY(dev(hw::launch_copy_out2(g, g.S[0], U, c->stream)));
     if (t) *t = c->hst[i].t;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_batch_run(hweno_ctx* c, int nsteps) {
+    GUARD_BEGIN
     if (!c || !c->batch || nsteps < 1) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     const int n = (int)c->in.size();
@@ -1130,9 +1186,11 @@ HWENO_API hweno_status hweno_batch_run(hweno_ctx* c, int nsteps) {
     for (auto& st : c->hst)
         if (st.status != 0) return (hweno_status)st.status;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* c, int i, hweno_diag* d) {
+    GUARD_BEGIN
     if (!c || !c->batch || !d || i < 0 || i >= (int)c->in.size()) return HWENO_E_INVAL;
     const hw::InstState& st = c->hst[i];
     d->t = st.t;
@@ -1145,12 +1203,14 @@ HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* c, int i, hweno_diag* d) 
     d->restarts = (int)st.restarts;
     d->pad = st.steps;
     return HWENO_OK;
+    GUARD_END
 }
 
 // ---------------------------------------------------------------------------
 // Tiles and the autotuner (2D contexts)
 // ---------------------------------------------------------------------------
 HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
+    GUARD_BEGIN
     if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
     t->recon = c->tiles.recon;
     t->grad = c->tiles.grad;
@@ -1158,9 +1218,11 @@ HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
     t->order = c->order_mode;
     t->xcd = c->tiles.xcd;
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
+    GUARD_BEGIN
     if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
     if ((t->recon != 16 && t->recon != 32) || (t->grad != 32 && t->grad != 64) ||
         (t->flux != 0 && t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1) ||
@@ -1173,9 +1235,11 @@ HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
     c->order_mode = t->order;
     if (!c->ws) return HWENO_OK;
     return upload_grids(c);
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chosen) {
+    GUARD_BEGIN
     if (!c || c->dim() != 2 || reps < 1) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (c->batch) {
@@ -1271,9 +1335,11 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
     }
     if (chosen) TRY(hweno_get_tiles(c, chosen));
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_set_timing(hweno_ctx* c, int enable) {
+    GUARD_BEGIN
     if (!c) return HWENO_E_INVAL;
     if (enable) {
         if (!c->timer.init()) return HWENO_E_DEVICE;
@@ -1283,9 +1349,11 @@ HWENO_API hweno_status hweno_set_timing(hweno_ctx* c, int enable) {
         c->timer.on = false;
     }
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API hweno_status hweno_get_timing(hweno_ctx* c, hweno_timing* out, int reset) {
+    GUARD_BEGIN
     if (!c || !out) return HWENO_E_INVAL;
     if (c->timer.ready) {
         TRY(dev(hipStreamSynchronize(c->stream)));
@@ -1297,6 +1365,7 @@ HWENO_API hweno_status hweno_get_timing(hweno_ctx* c, hweno_timing* out, int res
     }
     if (reset && c->timer.ready) c->timer.reset();
     return HWENO_OK;
+    GUARD_END
 }
 
 HWENO_API const char* hweno_status_string(hweno_status s) {
@@ -1308,6 +1377,7 @@ HWENO_API const char* hweno_status_string(hweno_status s) {
         case HWENO_E_INADMISSIBLE: return "stage inadmissible after the maximum number of halvings";
         case HWENO_E_NONFINITE: return "state not finite or not positive";
         case HWENO_E_STATE: return "no state set";
+        case HWENO_E_NOMEM: return "host memory allocation failed";
     }
     return "unknown status";
 }

@@ -62,7 +62,8 @@ def test_create_validates_arguments():
     assert _create(*_args()) == 0
     for kw in (dict(dim=3), dict(nx=3), dict(ny=2), dict(gamma=1.0), dict(Pr=0.0),
                dict(mu_ref=-1e-3), dict(T_ref=0.0), dict(cfl=0.0), dict(eps_pp=0.0),
-               dict(eps_weno=-1.0), dict(max_halvings=-1), dict(x1=0.0)):
+               dict(eps_weno=-1.0), dict(max_halvings=-1), dict(x1=0.0),
+               dict(b_visc=float('nan')), dict(t_final=float('nan'))):
         assert _create(*_args(**kw)) == 1, kw
     g, ph, b, o = _args()
     b.kind[0] = 0          # periodic paired with a wall
@@ -91,6 +92,7 @@ def test_workspace_and_state_errors_without_device():
     assert L.hweno_set_workspace(h, ctypes.c_void_p(4096 + 8), n.value) == 3   # misaligned
     assert L.hweno_destroy(h) == 0
     assert L.hweno_status_string(4).decode().startswith('stage inadmissible')
+    assert L.hweno_status_string(7).decode() == 'host memory allocation failed'
 
 
 def test_tile_defaults_and_validation_without_device():
@@ -122,3 +124,47 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hweno, '_lib', None)
     with pytest.raises(ImportError):
         hweno.lib()
+
+
+_ALLOC_FAIL_SCRIPT = r'''
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2608_10569_amd import hweno
+L = hweno.lib()
+ny = 40_000_000                       # one inflow state per boundary row: 1.28 GB
+g = hweno.Grid(2, 8, ny, 0.0, 1.0, 0.0, 1.0)
+ph = hweno.PhysicsC(1.4, 0.72, 1e-3, 0.0, 1.0)
+b = hweno.Bcs()
+for s, k in enumerate((2, 1, 3, 3)):
+    b.kind[s] = k
+b.inflow[0][0], b.inflow[0][3] = 1.0, 1.0
+o = hweno.default_options()
+h = ctypes.c_void_p()
+assert L.hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                      ctypes.byref(h)) == 0
+prim = np.zeros(4 * ny)               # untouched pages: address space only
+vm = [l for l in open('/proc/self/status') if l.startswith('VmSize')][0]
+cur = int(vm.split()[1]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (cur + (256 << 20), resource.RLIM_INFINITY))
+code = L.hweno_set_inflow_profile(h, 0, prim.ctypes.data_as(ctypes.c_void_p), ny)
+resource.setrlimit(resource.RLIMIT_AS, (resource.RLIM_INFINITY, resource.RLIM_INFINITY))
+print('status', code, L.hweno_status_string(code).decode())
+# the context is still usable and the side keeps its constant state
+assert L.hweno_set_inflow_profile(h, 0, None, ny) == 0
+assert L.hweno_destroy(h) == 0
+sys.exit(0 if code == 7 else 1)
+'''
+
+
+def test_host_allocation_failure_is_a_status():
+    """A failed host allocation inside a call comes back as HWENO_E_NOMEM
+    instead of an exception crossing the C ABI (which would abort the
+    process): the library's copy of a 40M-row inflow profile is made to fail
+    by capping the address space of a child process."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, '-c', _ALLOC_FAIL_SCRIPT, ROOT], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert 'status 7 host memory allocation failed' in r.stdout
