@@ -105,6 +105,10 @@ class Options:
     linear_weights: bool = False  #: test mode: omega = gamma (no nonlinearity)
     #: Remark 3.1 ablation: omega = gamma in the gradient reconstruction only
     linear_gradients: bool = False
+    #: viscous gradients: 'GR' (weak-derivative moments reconstructed, Sec. 2.2
+    #: and 3.2) or 'DR' (the comparison scheme: derivatives of the convective
+    #: reconstruction with its weights reused, eqs. (2.5) and (3.5))
+    gradients: str = 'GR'
     max_halvings: int = 64      #: restarts allowed per step before giving up
     #: linear weights gamma_m (1D: eq. (A.3); 2D: eq. (A.6))
     gamma1d: tuple = field(default=(199.0 / 200.0, 1.0 / 400.0, 1.0 / 400.0))

@@ -118,6 +118,14 @@ class Hweno1D:
         """Values of the polynomial with coefficients C at scaled points."""
         return np.stack([sum(C[k] * (x ** k) for k in range(C.shape[0])) for x in pts])
 
+    @staticmethod
+    def derivative(C, pts):
+        """d/dxi of the polynomial with coefficients C at scaled points: with C
+        the nonlinear combination of eq. (2.4), the combination of the
+        candidates' derivatives with the same weights (eq. (2.5))."""
+        return np.stack([sum(k * C[k] * (x ** (k - 1)) for k in range(1, C.shape[0]))
+                         for x in pts])
+
     def moment(self, C):
         """Scaled first moment int u xi over the own cell (the hat-v of eq. (2.4))."""
         return np.tensordot(self.own_moment, C, axes=1)
@@ -232,6 +240,23 @@ class Hweno2D:
                 acc = acc + C[k] * (x ** px) * (y ** py)
             out.append(acc)
         return np.stack(out)
+
+    def derivatives(self, C, pts):
+        """(d/dxi, d/deta) at scaled points pts = [(xi, eta), ...], each
+        (npts, ...): for the nonlinear combination C of eq. (3.4), the
+        derivatives of eq. (3.5) (candidates differentiated, weights reused)."""
+        dxi, deta = [], []
+        for (x, y) in pts:
+            ax = 0.0
+            ay = 0.0
+            for k, (px, py) in enumerate(self.MONOS):
+                if px:
+                    ax = ax + C[k] * px * (x ** (px - 1)) * (y ** py)
+                if py:
+                    ay = ay + C[k] * py * (x ** px) * (y ** (py - 1))
+            dxi.append(ax)
+            deta.append(ay)
+        return np.stack(dxi), np.stack(deta)
 
     def moments(self, C):
         """Scaled first moments (int u xi, int u eta) over the own cell."""

@@ -12,7 +12,9 @@ One call of :meth:`Scheme1D.residual` performs, in the paper's order
 3. positivity limiter on the four LGL values (Sec. 2.1, last paragraph before
    the HWENO-DR description);
 4. interface averages and weak-derivative moments (eqs. (2.6)-(2.8));
-5. gradient reconstruction with the same scalar routine (eq. (2.9));
+5. gradient reconstruction with the same scalar routine (eq. (2.9)); with
+   ``Options.gradients = 'DR'`` steps 4-5 are replaced by the comparison
+   scheme's derivatives of the convective reconstruction (eq. (2.5));
 6. PP local Lax-Friedrichs fluxes (eq. (2.3)) and the volume term;
 7. the residual F^1, F^2 of eq. (2.2).
 """
@@ -131,17 +133,31 @@ class Scheme1D:
         # 3. positivity limiter on all four LGL values
         Ulim, th1, th2 = pp_limit(ubar, Upts, g, op.eps_pp)
 
-        # 4. weak-derivative moments on cells 2 .. NG-3 (indices in region c)
-        w_pts = np.stack(primitives(np.moveaxis(Ulim, 0, 1)))   # (2, 4, n)
-        wbar = np.tensordot(w_pts, LGL_WEIGHTS, axes=([1], [0]))  # (2, n)
-        what = 0.5 * (w_pts[:, 3, :-1] + w_pts[:, 0, 1:])      # faces between n, n+1
-        rb0 = (what[:, 1:] - what[:, :-1]) / dx                 # cells 1..n-2 of c
-        rb1 = (0.5 * (what[:, 1:] + what[:, :-1]) - wbar[:, 1:-1]) / dx
+        if op.gradients == 'DR':
+            # 4'-5'. HWENO-DR (eq. (2.5)): d/dx of each field's nonlinear
+            # combination, weights reused, transformed back to (rho, m, E)_x
+            # and converted to (u_x, e_x) with the point values entering the
+            # flux there (the limited LGL values)
+            dvals = rec.derivative(C, LGL_NODES) / dx          # (4, k, n)
+            dU = np.einsum('ckn,pkn->pcn', R, dvals)           # (4, c, n)
+            rho, mom, E = Ulim[:, 0], Ulim[:, 1], Ulim[:, 2]
+            u = mom / rho
+            ux = (dU[:, 1] - u * dU[:, 0]) / rho
+            ex = (dU[:, 2] - (E / rho) * dU[:, 0]) / rho - u * ux
+            grads = np.stack([ux, ex], axis=1)[:, :, 2:-2]     # cells 3..NG-4
+            rb0 = rb1 = None
+        else:
+            # 4. weak-derivative moments on cells 2 .. NG-3 (indices in region c)
+            w_pts = np.stack(primitives(np.moveaxis(Ulim, 0, 1)))   # (2, 4, n)
+            wbar = np.tensordot(w_pts, LGL_WEIGHTS, axes=([1], [0]))  # (2, n)
+            what = 0.5 * (w_pts[:, 3, :-1] + w_pts[:, 0, 1:])      # faces between n, n+1
+            rb0 = (what[:, 1:] - what[:, :-1]) / dx                 # cells 1..n-2 of c
+            rb1 = (0.5 * (what[:, 1:] + what[:, :-1]) - wbar[:, 1:-1]) / dx
 
-        # 5. gradient reconstruction on cells 3 .. NG-4
-        ar = np.stack([rb0[:, :-2], rb0[:, 1:-1], rb0[:, 2:], rb1[:, :-2], rb1[:, 2:]])
-        Cg = rec.combined(ar, op, gradient=True)           # (5, 2, m)
-        grads = rec.evaluate(Cg, LGL_NODES)                # (4, 2, m) m: cells 3..NG-4
+            # 5. gradient reconstruction on cells 3 .. NG-4
+            ar = np.stack([rb0[:, :-2], rb0[:, 1:-1], rb0[:, 2:], rb1[:, :-2], rb1[:, 2:]])
+            Cg = rec.combined(ar, op, gradient=True)           # (5, 2, m)
+            grads = rec.evaluate(Cg, LGL_NODES)                # (4, 2, m) m: cells 3..NG-4
         # align region-c arrays with gradient cells: c index = ghosted - 1
         Ug_c = Ulim[:, :, 2:-2]                            # (4, c, m)
 
@@ -173,7 +189,7 @@ class Scheme1D:
         # internals kept for the pin tests: gradients (u_x, e_x) at the LGL
         # points of the interior cells, limited point values, weak moments
         self.last = dict(grads=grads[:, :, inner], points=Ug_c[:, :, inner],
-                         rbar=np.stack([rb0, rb1])[:, :, 2:2 + nx])
+                         rbar=None if rb0 is None else np.stack([rb0, rb1])[:, :, 2:2 + nx])
 
         # diagnostics: CFL wave speed from interior face traces, PP activity
         Uint = Ulim[:, :, 3:3 + nx]

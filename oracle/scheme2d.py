@@ -17,7 +17,9 @@ Order of one residual evaluation (flowchart of Sec. 4):
 4. face moments and weak-derivative moments (eqs. (3.6)-(3.8)) from the
    limited face traces and the unlimited volume values;
 5. gradient reconstruction, componentwise, same routine (eq. (3.9)), at the
-   12 face and 9 volume points;
+   12 face and 9 volume points (with ``Options.gradients = 'DR'`` steps 4-5
+   are the comparison scheme's derivatives of the convective reconstruction,
+   eq. (3.5), each basis serving its own points and fluxes);
 6. PP local Lax-Friedrichs fluxes at the face Gauss points (eq. (3.3)) and
    the volume fluxes;
 7. the residual F^1, F^2, F^3 of eq. (3.2).
@@ -199,11 +201,20 @@ class Scheme2D:
             out['face%d' % b] = U[:6]
             out['vol%d' % b] = U[6:]
             out['mom%d' % b] = np.einsum('ck...,k...->c...', R, mxi if b == 0 else meta)
+            if op.gradients == 'DR':
+                # eq. (3.5): derivatives of the same combination, back in
+                # conservative variables, per unit length
+                dxi, deta = rec.derivatives(C, pts_sets[b] + VOL)
+                out['d%d' % b] = (np.einsum('ck...,pk...->pc...', R, dxi) / self.dx,
+                                  np.einsum('ck...,pk...->pc...', R, deta) / self.dy)
         allpts = np.concatenate([out['face0'], out['face1'], out['vol0'], out['vol1']])
         Ulim, th1, th2 = pp_limit(ubar, allpts, g, op.eps_pp)
-        return dict(xface=Ulim[:6], yface=Ulim[6:12], xvol=out['vol0'], yvol=out['vol1'],
-                    vhat=np.stack([out['mom0'], out['mom1']]), theta1=th1, theta2=th2,
-                    ubar=ubar)
+        res = dict(xface=Ulim[:6], yface=Ulim[6:12], xvol=out['vol0'], yvol=out['vol1'],
+                   vhat=np.stack([out['mom0'], out['mom1']]), theta1=th1, theta2=th2,
+                   ubar=ubar)
+        if op.gradients == 'DR':
+            res['dU'] = (out['d0'], out['d1'])
+        return res
 
     def residual(self, U, source=None):
         """Semi-discrete residual of eq. (3.2) and the modified moments.
@@ -226,6 +237,45 @@ class Scheme2D:
         ny, nx = Ug.shape[2] - 2 * HALO, Ug.shape[3] - 2 * HALO
         r = self.reconstruct(Ug)             # region c: ghosted index - 1
 
+        # region-c arrays aligned to r1 (the cells whose gradients are
+        # reconstructed; region c shrunk by 2)
+        def c2r1(A):
+            return A[..., 2:-2, 2:-2]
+
+        if op.gradients == 'DR':
+            s_xf, s_yf, s_volf, s_volg, s_last = self._dr_gradients(r, c2r1)
+            rbar = None
+        else:
+            s_xf, s_yf, s_volf, s_volg, s_last, rbar = self._gr_gradients(r, dx, dy)
+        return self._fluxes(r, c2r1, s_xf, s_yf, s_volf, s_volg, s_last, rbar, source, nx, ny)
+
+    def _dr_gradients(self, r, c2r1):
+        """HWENO-DR (eq. (3.5)): the conservative derivatives of each basis's
+        reconstruction converted to s = (u_x, u_y, v_x, v_y, e_x, e_y) with the
+        point values that enter the flux there: the limited face traces, and
+        the (unlimited) volume values of the basis whose flux they feed."""
+        def prim_grads(P, dU):
+            rho, m, n, E = P[:, 0], P[:, 1], P[:, 2], P[:, 3]
+            u, v = m / rho, n / rho
+            comp = []
+            for D in dU:                         # d/dx, then d/dy
+                ul = (D[:, 1] - u * D[:, 0]) / rho
+                vl = (D[:, 2] - v * D[:, 0]) / rho
+                el = (D[:, 3] - (E / rho) * D[:, 0]) / rho - u * ul - v * vl
+                comp.append((ul, vl, el))
+            (ux, vx, ex), (uy, vy, ey) = comp
+            return np.stack([ux, uy, vx, vy, ex, ey], axis=1)    # (P, 6, ...)
+        d0, d1 = r['dU']
+        s_xf = c2r1(prim_grads(r['xface'], (d0[0][:6], d0[1][:6])))
+        s_yf = c2r1(prim_grads(r['yface'], (d1[0][:6], d1[1][:6])))
+        s_volf = c2r1(prim_grads(r['xvol'], (d0[0][6:], d0[1][6:])))
+        s_volg = c2r1(prim_grads(r['yvol'], (d1[0][6:], d1[1][6:])))
+        return s_xf, s_yf, s_volf, s_volg, np.concatenate([s_xf, s_yf, s_volf])
+
+    def _gr_gradients(self, r, dx, dy):
+        """Steps 4-5 of HWENO-GR: weak-derivative moments and their
+        reconstruction; gradients at the 12 face and 9 volume points of r1."""
+        op, rec = self.opts, self.rec
         # 4. weak-derivative moments (eqs. (3.6)-(3.8)) on region c shrunk by 1
         wxf = np.stack(primitives(np.moveaxis(r['xface'], 0, 1)))   # (3, 6, ...)
         wyf = np.stack(primitives(np.moveaxis(r['yface'], 0, 1)))
@@ -263,12 +313,13 @@ class Scheme2D:
         gv = rec.evaluate(Cg, XFACE + YFACE + VOL)                    # (21, l, w, ...)
         # s = (u_x, u_y, v_x, v_y, e_x, e_y): index 2*w + l
         s = np.stack([gv[:, l, w] for w in range(3) for l in range(2)], axis=1)  # (21, 6, ...)
-        s_xf, s_yf, s_vol = s[0:6], s[6:12], s[12:21]
+        return s[0:6], s[6:12], s[12:21], s[12:21], s, rbar
 
-        # region-c arrays aligned to r1: offset 2
-        def c2r1(A):
-            return A[..., 2:-2, 2:-2]
-
+    def _fluxes(self, r, c2r1, s_xf, s_yf, s_volf, s_volg, s_last, rbar, source, nx, ny):
+        """Steps 6-7: fluxes at the face Gauss points, volume fluxes, assembly."""
+        ph = self.phys
+        g = ph.gamma
+        dx, dy = self.dx, self.dy
         xf, yf = c2r1(r['xface']), c2r1(r['yface'])
         xv, yv = c2r1(r['xvol']), c2r1(r['yvol'])
 
@@ -309,9 +360,9 @@ class Scheme2D:
         def gsum(A, wts):
             return np.tensordot(wts, A, axes=([0], [0]))
 
-        fvol = sum(WVOL[q] * flux2d(xv[q][:, rows, cols], s_vol[q][:, rows, cols], ph, 0)
+        fvol = sum(WVOL[q] * flux2d(xv[q][:, rows, cols], s_volf[q][:, rows, cols], ph, 0)
                    for q in range(9))
-        gvol = sum(WVOL[q] * flux2d(yv[q][:, rows, cols], s_vol[q][:, rows, cols], ph, 1)
+        gvol = sum(WVOL[q] * flux2d(yv[q][:, rows, cols], s_volg[q][:, rows, cols], ph, 1)
                    for q in range(9))
         F1 = -gsum(fR - fL, W3) / dx - gsum(gT - gB, W3) / dy
         F2 = (-gsum(fL + fR, W3) / (2.0 * dx) - gsum(gT - gB, W3 * G3) / dy + fvol / dx)
@@ -327,8 +378,8 @@ class Scheme2D:
 
         # internals kept for the pin tests: gradients s[21 points, 6] of the
         # interior cells (x-face, y-face, volume points), weak moments
-        self.last = dict(grads=s[..., rows, cols],
-                         rbar=rbar[..., 2:2 + ny, 2:2 + nx])
+        self.last = dict(grads=s_last[..., rows, cols],
+                         rbar=None if rbar is None else rbar[..., 2:2 + ny, 2:2 + nx])
 
         # diagnostics
         fx = r['xface'][inner]
