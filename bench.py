@@ -21,7 +21,9 @@ grid.  Three more measurements ride along in the same line:
   the single-grid path;
 * ``adjoint``: the double shear layer on 256^2 (Re 1000), 200 steps with dt
   frozen, forward plus checkpointed backward (every 20 steps) against the
-  plain forward.
+  plain forward;
+* ``dr``: the same grid with the comparison scheme HWENO-DR (gradients by
+  differentiating the convective reconstruction), and T_GR / T_DR.
 """
 
 import argparse
@@ -112,28 +114,114 @@ def units_per_launch(kind):
     return NX * NY
 
 
-def cpu_baseline(rows=64):
-    """The oracle on a bounded sample: three stage residual evaluations (one
-    RK3 step's spatial work) on a 1000 x ``rows`` window of the same grid,
-    with its true neighbours as halo, on one thread."""
+def cpu_model():
+    try:
+        with open('/proc/cpuinfo') as f:
+            for line in f:
+                if line.startswith('model name'):
+                    return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return 'unknown'
+
+
+def _c3_window_rate(rows, j0, reps):
+    """Oracle cell-stages/s of ``reps`` stage residuals on a 1000 x rows window
+    (true neighbours as halo) of the 1000x500 shock tube at t = 0, one thread."""
     from threadpoolctl import threadpool_limits
     from oracle.common import Options, Physics
     from oracle.scheme2d import Scheme2D
     from paper_2608_10569_amd import workloads
     U = workloads.viscous_shock_tube_2d(NX, NY)
     sc = Scheme2D(NX, NY, *EXTENT, Physics(**PHYS), Options(cfl=0.3), bc=BCS)
-    Ug = sc.ghost(U)
-    j0 = (NY - rows) // 2
-    W = Ug[:, :, j0:j0 + rows + 8, :]
+    W = sc.ghost(U)[:, :, j0:j0 + rows + 8, :]
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        for _ in range(3):
+        for _ in range(reps):
             sc.residual_ghosted(W)
         el = time.perf_counter() - t0
-    return {'value': 3 * rows * NX / el, 'unit': UNIT, 'cores': 1, 'kind': 'oracle',
-            'sample': '3 residual evaluations on a %dx%d-cell window (rows %d..%d) of the '
-                      '1000x500 shock tube at t=0, numpy, 1 thread, %.1f s'
-                      % (NX, rows, j0, j0 + rows - 1, el)}
+    return reps * rows * NX, el
+
+
+def _c3_worker(args):
+    return _c3_window_rate(*args)
+
+
+def cpu_baseline(rows=64, reps=3):
+    """The oracle (as it stands) on bounded samples of the benchmark's
+    workloads, on this host: the 1000x500 shock tube as 1000 x ``rows``
+    windows (three stage residuals = one RK step's spatial work each) on one
+    thread (median of three) and on every core the process may use (one
+    window per worker process, up to 16); plus short samples of the 1D
+    configurations and of the batched instances, one thread each."""
+    import statistics
+    from concurrent.futures import ProcessPoolExecutor
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle import rk
+    from oracle.common import Options, Physics
+    from oracle.scheme1d import Scheme1D
+    from oracle.scheme2d import Scheme2D
+    from paper_2608_10569_amd import workloads
+    nproc = os.cpu_count()
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else nproc
+    workers = max(1, min(usable, 16))
+    j0 = (NY - rows) // 2
+    one = []
+    for _ in range(3):
+        n, el = _c3_window_rate(rows, j0, reps)
+        one.append(n / el)
+    rate1 = statistics.median(one)
+    # all cores: the grid's rows split into windows, one per worker process
+    starts = [min(k * rows, NY - rows) for k in range(workers)]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        t0 = time.perf_counter()
+        res = list(ex.map(_c3_worker, [(rows, j, reps) for j in starts]))
+        wall = time.perf_counter() - t0
+    rate_all = sum(n for n, _ in res) / wall
+    extra = {}
+    with threadpool_limits(1):
+        # C2: Sod at N = 2000, paper rule, 100 steps
+        sc = Scheme1D(2000, 0.0, 1.0, Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3),
+                      Options(cfl=0.3), bc=('outflow', 'outflow'))
+        U, t = workloads.sod_1d(2000), 0.0
+        t0 = time.perf_counter()
+        for _ in range(100):
+            U, dt, _ = rk.rk3_step(sc, U, t)
+            t += dt
+        el = time.perf_counter() - t0
+        extra['c2_sod_n2000'] = {'value': 100 * 3 * 2000 / el, 'sample': '100 steps', 's': el}
+        # C1: smooth wave at N = 200, the first 300 steps of the run to t = 1
+        sc = Scheme1D(200, 0.0, 2 * np.pi, Physics(gamma=1.4, Pr=0.72, mu_ref=0.01),
+                      Options(cfl=0.3, b_visc=0.001, t_final=1.0))
+        U, t = workloads.smooth_wave_1d(200), 0.0
+        t0 = time.perf_counter()
+        for _ in range(300):
+            U, dt, _ = rk.rk3_step(sc, U, t)
+            t += dt
+        el = time.perf_counter() - t0
+        extra['c1_smooth_n200'] = {'value': 300 * 3 * 200 / el, 'sample': '300 steps', 's': el}
+        # C4: one step of the batch's four smallest instances
+        inst = sorted(workloads.batched_periodic_2d(), key=lambda x: x[0])[:4]
+        cells = 0
+        t0 = time.perf_counter()
+        for n, Re, U in inst:
+            sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=1.0 / Re), Options())
+            rk.rk3_step(sc, U, 0.0)
+            cells += n * n
+        el = time.perf_counter() - t0
+        extra['c4_four_smallest'] = {'value': 3 * cells / el,
+                                     'sample': 'one step of %s instances' %
+                                               '+'.join('%d^2' % n for n, _, _ in inst), 's': el}
+    return {'value': rate_all, 'unit': UNIT, 'cores': workers, 'kind': 'oracle',
+            'sample': '%d worker processes, each %d stage residuals on a 1000x%d-cell window of '
+                      'the 1000x500 shock tube at t=0 (true neighbours as halo), numpy, one '
+                      'thread per process, %.1f s wall' % (workers, reps, rows, wall),
+            'one_thread': {'value': rate1, 'unit': UNIT, 'median_of': 3,
+                           'sample': '%d stage residuals on rows %d..%d' % (reps, j0,
+                                                                             j0 + rows - 1)},
+            'cpu_model': cpu_model(), 'nproc': nproc, 'usable_cpus': usable,
+            'other_workloads_one_thread': extra}
 
 
 def bench_batched(nsteps, sequential=True):
@@ -180,6 +268,31 @@ def bench_batched(nsteps, sequential=True):
         out['sequential_value'] = cells * 3 * nsteps / el2
         out['speedup_vs_sequential'] = el2 / el
     return out
+
+
+def bench_dr(nsteps, tiles, ms_gr):
+    """The comparison scheme HWENO-DR on the same grid, rule and tiles: time
+    per step and T_GR / T_DR (the paper's cost ratio of Table 5.3)."""
+    import torch
+    from paper_2608_10569_amd import hweno, workloads
+    s = hweno.Solver(NX, NY, extent=EXTENT, bc=BCS, cfl=0.3, t_final=1.0, gradients='DR',
+                     **PHYS)
+    s.set_tiles(**tiles)
+    s.set_state(torch.from_numpy(workloads.viscous_shock_tube_2d(NX, NY)).cuda())
+    for _ in range(5):
+        s.rk_step(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        s.rk_step(0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    ms = 1e3 * el / nsteps
+    return {'workload': 'the same 1000x500 shock tube and step rule, viscous gradients by '
+                        'HWENO-DR (convective reconstruction differentiated, weights reused)',
+            'steps': nsteps, 'ms_per_step': ms, 'value': nsteps * 3 * NX * NY / el,
+            'unit': UNIT, 't_gr_over_t_dr': ms_gr / ms}
 
 
 def bench_developed(nsteps, t_dev=0.3):
@@ -271,12 +384,13 @@ def main():
     ap.add_argument('--steps', type=int, default=100)
     ap.add_argument('--warmup', type=int, default=10)
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-rows', type=int, default=192)
+    ap.add_argument('--cpu-rows', type=int, default=64)
     ap.add_argument('--batch-steps', type=int, default=100)
     ap.add_argument('--no-batched', action='store_true')
     ap.add_argument('--no-sequential', action='store_true')
     ap.add_argument('--no-adjoint', action='store_true')
     ap.add_argument('--no-developed', action='store_true')
+    ap.add_argument('--no-dr', action='store_true')
     ap.add_argument('--no-autotune', action='store_true')
     ap.add_argument('--calib-copy-mib', type=int, default=0,
                     help='first run one device-to-device copy of this many MiB (a plain copy '
@@ -369,6 +483,10 @@ def main():
     del s
     torch.cuda.empty_cache()
     log('single grid: %.3e %s, %.3f ms/step' % (value, UNIT, 1e3 * el / args.steps))
+    if not args.no_dr:
+        out['dr'] = bench_dr(args.steps, tiles, 1e3 * el / args.steps)
+        log('HWENO-DR: %.3f ms/step, T_GR/T_DR = %.2f' % (out['dr']['ms_per_step'],
+                                                           out['dr']['t_gr_over_t_dr']))
     if not args.no_developed:
         out['developed'] = bench_developed(args.steps)
         log('developed state: %.3e %s' % (out['developed']['value'], UNIT))

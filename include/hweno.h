@@ -108,6 +108,12 @@ typedef struct hweno_options {
                                    three RK stages apart (2 x 248 doubles more workspace per
                                    ghosted cell), so that hweno_rk_step_vjp evaluates three
                                    residuals instead of five; 0 (default): one set */
+    int gradients;              /* viscous gradients: 0 (default) HWENO-GR, the paper's scheme
+                                   (weak-derivative moments reconstructed, Sec. 2.2 / 3.2);
+                                   1 HWENO-DR, its comparison scheme (the convective
+                                   reconstruction differentiated with its weights kept,
+                                   eqs. (2.5) / (3.5)); the reverse-mode calls refuse DR and a
+                                   batch needs one value for all its instances */
 } hweno_options;
 
 /* Diagnostics of the last call (Sec. 5 preamble; Table 5.3 PP activity). */
@@ -132,7 +138,7 @@ HWENO_API hweno_status hweno_default_options(hweno_options* opt);
  * empty domain, gamma <= 1, Pr <= 0, mu_ref < 0, T_ref <= 0, unknown BC
  * kind, a periodic side paired with a non-periodic one, inflow density or
  * pressure <= 0, cfl <= 0, eps_pp <= 0, eps_weno <= 0, max_halvings < 0,
- * b_visc or t_final NaN, keep_stages not 0/1. */
+ * b_visc or t_final NaN, keep_stages or gradients not 0/1. */
 HWENO_API hweno_status hweno_create(const hweno_grid* grid, const hweno_physics* phys,
                                     const hweno_bcs* bcs, const hweno_options* opt,
                                     hweno_ctx** out);
@@ -243,7 +249,8 @@ HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* ctx, double dt, const dou
  * Uses the workspace (the forward intermediates are recomputed); with a
  * non-NULL mu_bar the call synchronises.  HWENO_E_INVAL for dim = 1 or
  * mu_exp != 0.  Reverse-mode part of the differentiable rollout (the paper's
- * scheme of eq. (3.2); adjoint of its Sec. 3 residual). */
+ * scheme of eq. (3.2); adjoint of its Sec. 3 residual).  HWENO_E_INVAL also
+ * for a context with options.gradients = 1 (DR) or a solid mask. */
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar);
 
@@ -307,7 +314,8 @@ HWENO_API const char* hweno_status_string(hweno_status s);
 #define HWENO_BATCH_MAX 4096
 
 /* n instances (1 <= n <= HWENO_BATCH_MAX); grids[i].dim must be 2; each
- * instance is validated as by hweno_create.  Arrays of length n. */
+ * instance is validated as by hweno_create, and all must have the same
+ * options.gradients.  Arrays of length n. */
 HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
                                           const hweno_physics* phys, const hweno_bcs* bcs,
                                           const hweno_options* opts, hweno_ctx** out);

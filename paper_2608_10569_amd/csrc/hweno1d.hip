@@ -3,6 +3,8 @@
 //   ghost -> recon (eq. (2.4), characteristic fields, PP limiter on the four
 //   LGL values) -> rbar (eqs. (2.6)-(2.8)) -> grad (eq. (2.9), volume-flux
 //   quadrature) -> flux (eq. (2.3)) -> update (eqs. (2.2), (2.12)).
+// The comparison scheme HWENO-DR (eq. (2.5)) takes its gradients and volume
+// fluxes from the reconstruction kernel and skips rbar and grad.
 
 #include "hweno_kernels.h"
 
@@ -55,7 +57,13 @@ __global__ void k_ghost1(Grid1 g, double* S) {
     for (int q = 0; q < 6; ++q) S[q * N + di] = sd.sign[q] * S[q * N + si];
 }
 
-// Characteristic reconstruction + PP limiter on cells 1 .. NX-2.
+// Characteristic reconstruction + PP limiter on cells 1 .. NX-2.  DR: the
+// comparison scheme's viscous gradients as well (eq. (2.5)): each field's
+// combination differentiated with its weights kept, transformed back to
+// (rho, m, E)_x and converted to (u_x, e_x) with the limited point values,
+// which enter the flux there; then the volume-flux quadrature, so that the
+// weak-moment and gradient kernels are not needed.
+template <bool DR>
 __global__ void k_recon1(Grid1 g, const double* __restrict__ S) {
     const Consts& K = g.K;
     const long long N = g.NX;
@@ -70,6 +78,7 @@ __global__ void k_recon1(Grid1 g, const double* __restrict__ S) {
         Eig1 e;
         eig1(K, ub, e);
         double P[4][3] = {{0.0}}, vh[3] = {0.0, 0.0, 0.0};
+        double dP[4][3] = {{0.0}};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -91,6 +100,14 @@ __global__ void k_recon1(Grid1 g, const double* __restrict__ S) {
 #pragma unroll
                 for (int p = 0; p < 4; ++p) P[p][c] += e.R[c][k] * v[p];
                 vh[c] += e.R[c][k] * mo;
+            }
+            if constexpr (DR) {
+                double dv[4];
+                deval1d(C, dv);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) dP[p][c] += e.R[c][k] * (dv[p] * K.idx);
             }
         }
         // positivity limiter on the four LGL values (all four are rescaled)
@@ -124,6 +141,26 @@ __global__ void k_recon1(Grid1 g, const double* __restrict__ S) {
         g.wb[0 * N + i] = su;
         g.wb[1 * N + i] = se;
         const bool inter = i >= HALO && i < HALO + g.nx;
+        if constexpr (DR) {
+            double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const double r = P[p][0], u = P[p][1] / r;
+                const double ux = (dP[p][1] - u * dP[p][0]) / r;
+                const double ex = (dP[p][2] - (P[p][2] / r) * dP[p][0]) / r - u * ux;
+                g.gr[(p * 2 + 0) * N + i] = ux;
+                g.gr[(p * 2 + 1) * N + i] = ex;
+                double f[3];
+                flux1(K, P[p], ux, ex, f);
+                const double wq = (p == 0 || p == 3) ? LGL_W0 : LGL_W1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] += wq * f[c];
+            }
+            if (inter) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) g.vf[c * N + i] = acc[c];
+            }
+        }
         if (inter) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) g.vk[c * N + i] = vh[c];
@@ -366,8 +403,15 @@ hipError_t launch_ghost1(const Grid1& g, double* S, hipStream_t st, Timer* tm) {
 
 hipError_t launch_residual1(const Grid1& g, const double* S, hipStream_t st, Timer* tm) {
     tbeg(tm, KC_RECON, st);
-    k_recon1<<<nb(g.NX - 2, 128), 128, 0, st>>>(g, S);
+    if (g.K.dr) k_recon1<true><<<nb(g.NX - 2, 128), 128, 0, st>>>(g, S);
+    else k_recon1<false><<<nb(g.NX - 2, 128), 128, 0, st>>>(g, S);
     tend(tm, st);
+    if (g.K.dr) {   // the gradients and volume fluxes came with the reconstruction
+        tbeg(tm, KC_FLUX, st);
+        k_flux1<<<nb(g.nx + 1, 128), 128, 0, st>>>(g);
+        tend(tm, st);
+        return hipGetLastError();
+    }
     tbeg(tm, KC_RBAR, st);
     k_rbar1<<<nb(g.NX - 4, 128), 128, 0, st>>>(g);
     tend(tm, st);

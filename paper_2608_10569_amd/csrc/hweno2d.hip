@@ -243,8 +243,17 @@ __global__ void k_ghost2(Batch bt, int sidx, int stage) {
 // Block: 32 cells x 8 threads; thread (b, k) projects onto characteristic
 // field k of basis b (0: x-Jacobian, 1: y-Jacobian), reconstructs it, and
 // after an LDS exchange owns conservative component k of basis b.
+// DR (the comparison scheme HWENO-DR, eq. (3.5)): the thread also
+// differentiates its field's combination in xi and eta at the basis's face
+// and volume points (weights kept), the derivatives go back to conservative
+// variables through the same exchange, and the viscous gradients
+// s = (u_x, u_y, v_x, v_y, e_x, e_y) are formed with the point values that
+// enter the flux there (limited face traces; each basis's unlimited volume
+// values for its own volume flux).  The kernel then writes the face
+// gradients and the volume-flux quadratures itself, in place of the
+// weak-moment and gradient kernels.
 // ---------------------------------------------------------------------------
-template <int RC_CELLS>
+template <int RC_CELLS, bool DR = false, bool VarMu = false>
 __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     // one block = RC_CELLS consecutive cells of one row; the 3-row stencil
     // tile of all 12 fields is staged in LDS first, then the same memory holds
@@ -463,6 +472,120 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
             amax = fmax(amax, sp);
         }
     }
+    if constexpr (DR) {
+        // thread k converts the points o = k, k+4, k+8, k+12 of basis b:
+        // gather the four components of the point values (limited on the
+        // faces) and of their two derivatives from the exchange
+        double P[4][4], Dx[4][4], Dy[4][4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int o = k + 4 * s4;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (o < 15) {
+                    const double x = comp(b, c, o);
+                    const double ut = c == 0 ? rbar + th1 * (x - rbar) : x;
+                    P[s4][c] = o < 6 ? ub[c] + th2 * (ut - ub[c]) : x;
+                } else {
+                    P[s4][c] = 1.0;
+                }
+            }
+        }
+        // the derivatives of this field's combination in xi, then eta, at the
+        // 15 points; back to conservative component k through the exchange
+        // (as the values), then a second exchange hands each thread the four
+        // components at its points
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            double dv[15];
+            {
+                double D[15];
+                if (dir == 0) dxi_coeffs(C, D);
+                else deta_coeffs(C, D);
+                if (b == 0) eval_xface(D, dv);
+                else eval_yface(D, dv);
+                eval_vol(D, dv + 6);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int o = 0; o < 15; ++o) sh[(bk * 16 + o) * RC_CELLS + cl] = dv[o];
+            __syncthreads();
+            const double h = dir == 0 ? K.idx : K.idy;
+#pragma unroll
+            for (int o = 0; o < 15; ++o) {
+                double acc = 0.0;
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    acc += Rr[f] * sh[((b * 4 + f) * 16 + o) * RC_CELLS + cl];
+                dv[o] = acc * h;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int o = 0; o < 15; ++o) sh[(bk * 16 + o) * RC_CELLS + cl] = dv[o];
+            __syncthreads();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int o = min(k + 4 * s4, 14);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double x = sh[((b * 4 + c) * 16 + o) * RC_CELLS + cl];
+                    if (dir == 0) Dx[s4][c] = x;
+                    else Dy[s4][c] = x;
+                }
+            }
+        }
+        // faces of interior cells read the gradients of the cells on both
+        // sides; volume fluxes are needed in interior cells only
+        const bool ring = valid && j >= HALO - 1 && j <= HALO + g.ny && i >= HALO - 1 &&
+                          i <= HALO + g.nx;
+        double vfs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int o = k + 4 * s4;
+            if (o >= 15 || !ring) continue;
+            const double ir = rcp(P[s4][0]);
+            const double u = P[s4][1] * ir, v = P[s4][2] * ir, eo = P[s4][3] * ir;
+            double sg[6];
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir) {
+                const double* D = dir == 0 ? Dx[s4] : Dy[s4];
+                const double ul = (D[1] - u * D[0]) * ir;
+                const double vl = (D[2] - v * D[0]) * ir;
+                const double el = (D[3] - eo * D[0]) * ir - u * ul - v * vl;
+                sg[0 + dir] = ul;
+                sg[2 + dir] = vl;
+                sg[4 + dir] = el;
+            }
+            if (o < 6) {
+                const int p = b * 6 + o;
+                double dc[3];
+                if (b == 0) stress_combos<0>(sg, dc);
+                else stress_combos<1>(sg, dc);
+#pragma unroll
+                for (int z = 0; z < 3; ++z) g.gf[(p * 3 + z) * N + cell] = dc[z];
+            } else {
+                const int q = o - 6;
+                const double w = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
+                double f[4];
+                flux2_dir<VarMu>(K, P[s4], sg, b == 1, f);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) vfs[c] += w * f[c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[(bk * 16 + c) * RC_CELLS + cl] = vfs[c];
+        __syncthreads();
+        if (inter && k == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc += sh[((b * 4 + f) * 16 + c) * RC_CELLS + cl];
+                g.vf[(b * 4 + c) * N + cell] = acc;
+            }
+        }
+    }
     red_max<8 * RC_CELLS>(&g.red->alpha_key, amax);
     red_add<8 * RC_CELLS>(&g.red->pp_cells,
                           (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
@@ -580,7 +703,7 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
 // (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also form
 // the volume-flux quadratures of eq. (3.2).
 // ---------------------------------------------------------------------------
-template <int GR_CELLS, bool VarMu>
+template <int GR_CELLS, bool VarMu, bool FULL>
 __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     __shared__ double shv[6 * 9 * GR_CELLS];
     const Loc lc = locate(bt);
@@ -623,9 +746,35 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     eval_xface(C, fo);
     eval_yface(C, fo + 6);
     eval_vol(C, vo);
-    if (valid) {
+    if constexpr (FULL) {
+        if (valid) {
 #pragma unroll
-        for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
+            for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
+        }
+    } else {
+        // the face fluxes need three combinations of the six gradients per
+        // face point (stress_combos): the x-face points, then the y-face
+        // points, meet in LDS, and thread s forms outputs s, s + 6, s + 12 of
+        // the 18 of each half
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) shv[(s * 6 + q) * GR_CELLS + cl] = fo[half * 6 + q];
+            __syncthreads();
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int o = s + 6 * r, q = o / 3, z = o % 3;
+                    double sq[6], dc[3];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) sq[c] = shv[(c * 6 + q) * GR_CELLS + cl];
+                    if (half == 0) stress_combos<0>(sq, dc);
+                    else stress_combos<1>(sq, dc);
+                    g.gf[((half * 6 + q) * 3 + z) * N + cell] = dc[z];
+                }
+            }
+            __syncthreads();
+        }
     }
     const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
     // volume-flux quadratures of interior cells: 2 directions x 9 points over
@@ -686,12 +835,29 @@ __device__ __forceinline__ void face_moments(double F0, double F1, double F2, do
     B = (GW0 * GS) * (F2 - F0);
 }
 
+// The three gradient combinations of face point p (0..5 x-face, 6..11
+// y-face; direction d of that face) of a cell: read as stored, or formed from
+// the six gradients of the full layout.
+template <int d, bool FULL>
+__device__ __forceinline__ void face_grad(const Grid2& g, int p, long long cell, double* dc) {
+    const long long N = g.ncell;
+    if constexpr (FULL) {
+        double sq[6];
+#pragma unroll
+        for (int z = 0; z < 6; ++z) sq[z] = g.gf[(p * 6 + z) * N + cell];
+        stress_combos<d>(sq, dc);
+    } else {
+#pragma unroll
+        for (int z = 0; z < 3; ++z) dc[z] = g.gf[(p * 3 + z) * N + cell];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Face fluxes (eq. (3.3)): x-faces (j, i+1/2) for interior rows, i from the
 // last ghost column; y-faces (j+1/2, i) likewise.  The LF coefficient is the
 // max over the face's three Gauss points and both sides.
 // ---------------------------------------------------------------------------
-template <int d, int FX_FACES, bool VarMu>   // block = 3 Gauss points x FX_FACES faces
+template <int d, int FX_FACES, bool VarMu, bool FULL>   // block = 3 Gauss points x FX_FACES faces
 __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
     __shared__ double shb[3 * FX_FACES];
     __shared__ double shf[4][3 * FX_FACES];
@@ -718,20 +884,17 @@ __global__ __launch_bounds__(3 * FX_FACES) void k_flux2(Batch bt) {
         cp = d == 0 ? cm + 1 : cm + g.NX;
         const double* F = d == 0 ? g.xf : g.yf;
         const int pg = d == 0 ? 0 : 6;
-        double Um[4], Up[4], sm[6], sp[6], fm[4], fp[4];
+        double Um[4], Up[4], sm[3], sp[3], fm[4], fp[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             Um[c] = F[((3 + G) * 4 + c) * N + cm];
             Up[c] = F[(G * 4 + c) * N + cp];
         }
-#pragma unroll
-        for (int z = 0; z < 6; ++z) {
-            sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
-            sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
-        }
-        flux2<d, VarMu>(K, Um, sm, fm);
-        flux2<d, VarMu>(K, Up, sp, fp);
-        beta = fmax(speed2<d, VarMu>(K, Um, sm), speed2<d, VarMu>(K, Up, sp));
+        face_grad<d, FULL>(g, pg + 3 + G, cm, sm);
+        face_grad<d, FULL>(g, pg + G, cp, sp);
+        flux2c<d, VarMu>(K, Um, sm, fm);
+        flux2c<d, VarMu>(K, Up, sp, fp);
+        beta = fmax(speed2c<d, VarMu>(K, Um, sm), speed2c<d, VarMu>(K, Up, sp));
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             fs[c] = fm[c] + fp[c];
@@ -908,7 +1071,7 @@ constexpr int FU_TX = 32, FU_TY = 8;
 // Gauss moments (A into o[c * stride], B into o[(4 + c) * stride]) of the
 // flux of the face between cells cm and cp (direction d); returns the LF
 // coefficient (max over the three points and both sides).
-template <int d, bool VarMu>
+template <int d, bool VarMu, bool FULL>
 __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long long cp,
                                              double* o, int stride) {
     const Consts& K = g.K;
@@ -918,20 +1081,17 @@ __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long 
     double fs[3][4], du[3][4], bg[3];
 #pragma unroll
     for (int G = 0; G < 3; ++G) {
-        double Um[4], Up[4], sm[6], sp[6], fm[4], fp[4];
+        double Um[4], Up[4], sm[3], sp[3], fm[4], fp[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             Um[c] = F[((3 + G) * 4 + c) * N + cm];
             Up[c] = F[(G * 4 + c) * N + cp];
         }
-#pragma unroll
-        for (int z = 0; z < 6; ++z) {
-            sm[z] = g.gf[((pg + 3 + G) * 6 + z) * N + cm];
-            sp[z] = g.gf[((pg + G) * 6 + z) * N + cp];
-        }
-        flux2<d, VarMu>(K, Um, sm, fm);
-        flux2<d, VarMu>(K, Up, sp, fp);
-        bg[G] = fmax(speed2<d, VarMu>(K, Um, sm), speed2<d, VarMu>(K, Up, sp));
+        face_grad<d, FULL>(g, pg + 3 + G, cm, sm);
+        face_grad<d, FULL>(g, pg + G, cp, sp);
+        flux2c<d, VarMu>(K, Um, sm, fm);
+        flux2c<d, VarMu>(K, Up, sp, fp);
+        bg[G] = fmax(speed2c<d, VarMu>(K, Um, sm), speed2c<d, VarMu>(K, Up, sp));
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             fs[G][c] = fm[c] + fp[c];
@@ -950,7 +1110,7 @@ __device__ __forceinline__ double face_flux3(const Grid2& g, long long cm, long 
     return beta;
 }
 
-template <bool VarMu>
+template <bool VarMu, bool FULL>
 __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, int i0, int iin,
                                                            int iout, double* __restrict__ Rout,
                                                            double* __restrict__ Vout,
@@ -976,7 +1136,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
         const int ii = ii0 + fc, jj = jj0 + row;
         if (ii < 0 || ii > g.nx || jj >= g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
-        bmax = fmax(bmax, face_flux3<0, VarMu>(g, cp - 1, cp, lx + row * RX + fc, SX));
+        bmax = fmax(bmax, face_flux3<0, VarMu, FULL>(g, cp - 1, cp, lx + row * RX + fc, SX));
     };
     // y-face below interior cell (ii0 + col, jj0 + fr); fr = FU_TY and jj = ny
     // included
@@ -984,7 +1144,7 @@ __global__ __launch_bounds__(FU_TX * FU_TY) void k_fluxup2(Batch bt, int stage, 
         const int ii = ii0 + col, jj = jj0 + fr;
         if (ii < 0 || ii >= g.nx || jj > g.ny) return;
         const long long cp = (long long)(jj + HALO) * g.NX + ii + HALO;
-        bmax = fmax(bmax, face_flux3<1, VarMu>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
+        bmax = fmax(bmax, face_flux3<1, VarMu, FULL>(g, cp - g.NX, cp, ly + fr * FU_TX + col, SY));
     };
     xface(tx, ty);
     yface(ty, tx);
@@ -1273,38 +1433,69 @@ hipError_t launch_ghost2(const BatchL& b, int si, hipStream_t st, Timer* tm, int
     return hipGetLastError();
 }
 
+// The split face-flux kernels of both directions for the launch's tiles.
+template <bool FULL>
+void launch_flux2(const BatchL& b, hipStream_t st) {
+    const Batch a0 = b.arg(KB_FLUX0), a1 = b.arg(KB_FLUX1);
+    const unsigned n0 = b.blocks(KB_FLUX0), n1 = b.blocks(KB_FLUX1);
+    if (b.tiles.flux == 128) {
+        if (b.var_mu) {
+            k_flux2<0, 128, true, FULL><<<n0, 384, 0, st>>>(a0);
+            k_flux2<1, 128, true, FULL><<<n1, 384, 0, st>>>(a1);
+        } else {
+            k_flux2<0, 128, false, FULL><<<n0, 384, 0, st>>>(a0);
+            k_flux2<1, 128, false, FULL><<<n1, 384, 0, st>>>(a1);
+        }
+    } else {
+        if (b.var_mu) {
+            k_flux2<0, 64, true, FULL><<<n0, 192, 0, st>>>(a0);
+            k_flux2<1, 64, true, FULL><<<n1, 192, 0, st>>>(a1);
+        } else {
+            k_flux2<0, 64, false, FULL><<<n0, 192, 0, st>>>(a0);
+            k_flux2<1, 64, false, FULL><<<n1, 192, 0, st>>>(a1);
+        }
+    }
+}
+
 hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) {
     const unsigned nr = b.blocks(KB_RECON), ng = b.blocks(KB_GRAD);
-    if (b.tiles.recon == 16) tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, b.arg(KB_RECON), si);
-    else tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, b.arg(KB_RECON), si);
-    tlaunch(tm, KC_RBAR, k_rbar2, b.blocks(KB_RBAR), RB_TX * RB_TY, st, b.arg(KB_RBAR));
-    const Batch ag = b.arg(KB_GRAD);
-    if (b.tiles.grad == 64) {
-        if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<64, true>, ng, 384, st, ag);
-        else tlaunch(tm, KC_GRAD, k_grad2<64, false>, ng, 384, st, ag);
+    const Batch ar = b.arg(KB_RECON);
+    if (b.dr) {   // HWENO-DR: gradients and volume fluxes come with the reconstruction
+        if (b.tiles.recon == 16) {
+            if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<16, true, true>, nr, 128, st, ar, si);
+            else tlaunch(tm, KC_RECON, k_recon2<16, true, false>, nr, 128, st, ar, si);
+        } else {
+            if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, true, true>, nr, 256, st, ar, si);
+            else tlaunch(tm, KC_RECON, k_recon2<32, true, false>, nr, 256, st, ar, si);
+        }
+    } else if (b.tiles.recon == 16) {
+        tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, ar, si);
     } else {
-        if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<32, true>, ng, 192, st, ag);
-        else tlaunch(tm, KC_GRAD, k_grad2<32, false>, ng, 192, st, ag);
+        tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, ar, si);
+    }
+    if (!b.dr) {   // HWENO-GR: weak-derivative moments, then their reconstruction
+        tlaunch(tm, KC_RBAR, k_rbar2, b.blocks(KB_RBAR), RB_TX * RB_TY, st, b.arg(KB_RBAR));
+        const Batch ag = b.arg(KB_GRAD);
+        if (b.full_grad) {   // the reverse mode reads all six gradients
+            if (b.tiles.grad == 64) {
+                if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<64, true, true>, ng, 384, st, ag);
+                else tlaunch(tm, KC_GRAD, k_grad2<64, false, true>, ng, 384, st, ag);
+            } else {
+                if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<32, true, true>, ng, 192, st, ag);
+                else tlaunch(tm, KC_GRAD, k_grad2<32, false, true>, ng, 192, st, ag);
+            }
+        } else if (b.tiles.grad == 64) {
+            if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<64, true, false>, ng, 384, st, ag);
+            else tlaunch(tm, KC_GRAD, k_grad2<64, false, false>, ng, 384, st, ag);
+        } else {
+            if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<32, true, false>, ng, 192, st, ag);
+            else tlaunch(tm, KC_GRAD, k_grad2<32, false, false>, ng, 192, st, ag);
+        }
     }
     if (b.tiles.flux == 0) return hipGetLastError();   // fluxes formed by the update kernel
     tbeg(tm, KC_FLUX, st);
-    if (b.tiles.flux == 128) {
-        if (b.var_mu) {
-            k_flux2<0, 128, true><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
-            k_flux2<1, 128, true><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
-        } else {
-            k_flux2<0, 128, false><<<b.blocks(KB_FLUX0), 384, 0, st>>>(b.arg(KB_FLUX0));
-            k_flux2<1, 128, false><<<b.blocks(KB_FLUX1), 384, 0, st>>>(b.arg(KB_FLUX1));
-        }
-    } else {
-        if (b.var_mu) {
-            k_flux2<0, 64, true><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
-            k_flux2<1, 64, true><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
-        } else {
-            k_flux2<0, 64, false><<<b.blocks(KB_FLUX0), 192, 0, st>>>(b.arg(KB_FLUX0));
-            k_flux2<1, 64, false><<<b.blocks(KB_FLUX1), 192, 0, st>>>(b.arg(KB_FLUX1));
-        }
-    }
+    if (b.full_grad) launch_flux2<true>(b, st);
+    else launch_flux2<false>(b, st);
     tend(tm, st);
     return hipGetLastError();
 }
@@ -1313,12 +1504,22 @@ hipError_t launch_update2(const BatchL& b, int stage, int i0, int iin, int iout,
                           double* Vhat, hipStream_t st, Timer* tm, const double* src) {
     if (b.tiles.flux == 0) {
         const unsigned nb = b.blocks(KB_FLUXUP);
-        if (b.var_mu)
-            tlaunch(tm, KC_FLUXUP, k_fluxup2<true>, nb, FU_TX * FU_TY, st, b.arg(KB_FLUXUP), stage,
-                    i0, iin, iout, R, Vhat, src);
-        else
-            tlaunch(tm, KC_FLUXUP, k_fluxup2<false>, nb, FU_TX * FU_TY, st, b.arg(KB_FLUXUP),
-                    stage, i0, iin, iout, R, Vhat, src);
+        const Batch a = b.arg(KB_FLUXUP);
+        constexpr unsigned NT = FU_TX * FU_TY;
+        if (b.full_grad) {
+            if (b.var_mu)
+                tlaunch(tm, KC_FLUXUP, k_fluxup2<true, true>, nb, NT, st, a, stage, i0, iin, iout,
+                        R, Vhat, src);
+            else
+                tlaunch(tm, KC_FLUXUP, k_fluxup2<false, true>, nb, NT, st, a, stage, i0, iin,
+                        iout, R, Vhat, src);
+        } else if (b.var_mu) {
+            tlaunch(tm, KC_FLUXUP, k_fluxup2<true, false>, nb, NT, st, a, stage, i0, iin, iout, R,
+                    Vhat, src);
+        } else {
+            tlaunch(tm, KC_FLUXUP, k_fluxup2<false, false>, nb, NT, st, a, stage, i0, iin, iout,
+                    R, Vhat, src);
+        }
     } else {
         tlaunch(tm, KC_UPDATE, k_update2, b.blocks(KB_CELLS), 256, st, b.arg(KB_CELLS), stage, i0,
                 iin, iout, R, Vhat, src);

@@ -116,6 +116,7 @@ hw::Consts make_consts(const Inst& c) {
     K.eps_weno = c.opt.eps_weno;
     K.linear = c.opt.linear_weights ? 1 : 0;
     K.linear_grad = c.opt.linear_gradients ? 1 : 0;
+    K.dr = c.opt.gradients ? 1 : 0;
     K.dx = (c.grid.x1 - c.grid.x0) / c.grid.nx;
     K.idx = 1.0 / K.dx;
     if (c.grid.dim == 2) {
@@ -223,7 +224,7 @@ size_t layout(hweno_ctx* c, char* base) {
         g.vk = take(8 * m);
         g.vn = take(8 * m);
         g.rb = take(18 * m);
-        g.gf = take(72 * m);
+        g.gf = take((c->batch ? 36 : 72) * m);   // batches never need the reverse mode's six
         g.vf = take(8 * m);
         g.fx = take(8 * m);
         g.fy = take(8 * m);
@@ -348,6 +349,7 @@ hweno_status upload_grids(hweno_ctx* c) {
     c->bl.tiles = c->tiles;
     c->bl.var_mu = false;
     for (const Inst& in : c->in) c->bl.var_mu = c->bl.var_mu || in.phys.mu_exp != 0.0;
+    c->bl.dr = c->i0().opt.gradients != 0;   // the same for every instance (checked)
     if (!c->batch && c->dstage) {
         // descriptors of the stage intermediates: the grid's own, with the
         // intermediate arrays of set k
@@ -505,6 +507,7 @@ hweno_status validate(const hweno_grid* grid, const hweno_physics* phys, const h
         return HWENO_E_INVAL;
     if (!(opt->cfl > 0.0) || !(opt->eps_pp > 0.0) || !(opt->eps_weno > 0.0) ||
         opt->max_halvings < 0 || (opt->keep_stages != 0 && opt->keep_stages != 1) ||
+        (opt->gradients != 0 && opt->gradients != 1) ||
         std::isnan(opt->b_visc) || std::isnan(opt->t_final))
         return HWENO_E_INVAL;
     const int nsides = 2 * grid->dim;
@@ -623,6 +626,7 @@ HWENO_API hweno_status hweno_default_options(hweno_options* o) {
     o->max_halvings = 64;
     o->linear_gradients = 0;
     o->keep_stages = 0;
+    o->gradients = 0;
     return HWENO_OK;
     GUARD_END
 }
@@ -651,6 +655,8 @@ HWENO_API hweno_status hweno_batch_create(int n, const hweno_grid* grids,
     for (int p = 0; p < n; ++p) {
         TRY(validate(grids + p, phys + p, bcs + p, opts + p));
         if (grids[p].dim != 2) return HWENO_E_INVAL;
+        // one launch serves every instance: one gradient scheme per batch
+        if (opts[p].gradients != opts[0].gradients) return HWENO_E_INVAL;
     }
     hweno_ctx* c = make_ctx(n, grids, phys, bcs, opts, true);
     if (!c) return HWENO_E_NOMEM;
@@ -1008,14 +1014,17 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
                                           const double* Vbar, double* Ubar, double* mu_bar) {
     GUARD_BEGIN
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty() ||
+        c->i0().opt.gradients != 0)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     const hw::Grid2& g = g2(c);
+    hw::BatchL full = c->bl;   // the adjoint kernels read all six face gradients
+    full.full_grad = true;
     TRY(dev(hw::launch_copy_in2(g, U, g.S[2], c->stream)));
     TRY(reset(c));
     TRY(ghost(c, 2));
-    TRY(residual(c, 2));
+    TRY(residual(c, 2, &full));
     hw::AdjIn A{Rbar, Vbar, 1.0, 1.0};
     TRY(dev(hw::launch_vjp2(g, A, c->adj, g.S[2], Ubar, c->mu_dev, 0, c->stream)));
     if (mu_bar) {
@@ -1037,7 +1046,8 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     GUARD_BEGIN
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty())
+    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty() ||
+        c->i0().opt.gradients != 0)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     const hw::Grid2& g = g2(c);
@@ -1051,10 +1061,13 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     // set, those of U1 go to stage set 0 and those of U2 to stage set 1, so
     // the adjoints of stages 2 and 1 need no recomputation
     const bool keep = c->dstage != nullptr;
-    const hw::BatchL* b1 = keep ? &c->blstage[0] : nullptr;
+    // every residual here feeds an adjoint, which reads all six face gradients
+    hw::BatchL full = c->bl, full_st[2] = {c->blstage[0], c->blstage[1]};
+    full.full_grad = full_st[0].full_grad = full_st[1].full_grad = true;
+    const hw::BatchL* b1 = keep ? &full_st[0] : &full;
     TRY(ghost(c, ia));
-    TRY(residual(c, ia));
-    TRY(update(c, 1, ia, ia, ib, nullptr, nullptr));
+    TRY(residual(c, ia, &full));
+    TRY(update(c, 1, ia, ia, ib, nullptr, nullptr, nullptr, &full));
     TRY(ghost(c, ib));
     TRY(residual(c, ib, b1));
     TRY(update(c, 2, ia, ib, ic, nullptr, nullptr, nullptr, b1));
@@ -1072,17 +1085,17 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
         return dev(hw::launch_vjp2(gi, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream));
     };
     // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified moments)
-    TRY(vjp_at(ic, keep ? c->stage[1] : g, keep ? &c->blstage[1] : nullptr, true, U3bar,
+    TRY(vjp_at(ic, keep ? c->stage[1] : g, keep ? &full_st[1] : &full, true, U3bar,
                U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
     TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
     // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar
-    TRY(vjp_at(ib, keep ? c->stage[0] : g, nullptr, !keep, c->X2, c->X2 + 4 * nint, 0.25 * dt,
+    TRY(vjp_at(ib, keep ? c->stage[0] : g, &full, !keep, c->X2, c->X2 + 4 * nint, 0.25 * dt,
                0.25, c->X1, 1));
     TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
     // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar
-    TRY(vjp_at(ia, g, nullptr, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
+    TRY(vjp_at(ia, g, &full, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
     TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,

@@ -51,6 +51,7 @@ struct Consts {
     double eps_pp, eps_weno;
     int linear;                 // 1: omega = gamma (test mode)
     int linear_grad;            // 1: omega = gamma in the gradient reconstruction only
+    int dr;                     // 1: viscous gradients by the comparison scheme (HWENO-DR)
     double dx, dy, idx, idy;    // cell sizes and inverses
 };
 
@@ -132,6 +133,19 @@ __device__ __forceinline__ void eval1d(const double* __restrict__ C, double* __r
 }
 __device__ __forceinline__ double moment1d(const double* __restrict__ C) {
     return C[1] * (1.0 / 12.0) + C[3] * (1.0 / 80.0);
+}
+// d/dxi at the four LGL points: with C the combination of eq. (2.4), the
+// derivative of eq. (2.5) (the candidates differentiated, the weights kept).
+__device__ __forceinline__ void deval1d(const double* __restrict__ C, double* __restrict__ v) {
+    const double t2 = LGL_T * LGL_T;
+    const double eh = C[1] + 0.75 * C[3];           // even part of p' at |xi| = 1/2
+    const double oh = C[2] + 0.5 * C[4];            // odd part
+    const double et = C[1] + 3.0 * t2 * C[3];
+    const double ot = LGL_T * (2.0 * C[2] + 4.0 * t2 * C[4]);
+    v[0] = eh - oh;
+    v[1] = et - ot;
+    v[2] = et + ot;
+    v[3] = eh + oh;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,6 +293,26 @@ __device__ __forceinline__ void eval_vol(const double* __restrict__ C, double* _
     }
 }
 
+// Coefficients (same monomial layout, degree-4 slots zero) of d/dxi and
+// d/deta of the quartic C: with C the combination of eq. (3.4), the
+// derivatives of eq. (3.5), so the value evaluators above apply to them.
+__device__ __forceinline__ void dxi_coeffs(const double* __restrict__ C, double* __restrict__ D) {
+#pragma unroll
+    for (int q = 0; q < 15; ++q) D[q] = 0.0;
+#pragma unroll
+    for (int a = 1; a <= 4; ++a)
+#pragma unroll
+        for (int b = 0; b <= 4 - a; ++b) D[MI(a - 1, b)] = (double)a * C[MI(a, b)];
+}
+__device__ __forceinline__ void deta_coeffs(const double* __restrict__ C, double* __restrict__ D) {
+#pragma unroll
+    for (int q = 0; q < 15; ++q) D[q] = 0.0;
+#pragma unroll
+    for (int b = 1; b <= 4; ++b)
+#pragma unroll
+        for (int a = 0; a <= 4 - b; ++a) D[MI(a, b - 1)] = (double)b * C[MI(a, b)];
+}
+
 // Scaled first moments over the own cell: int p xi, int p eta.
 __device__ __forceinline__ double moment_xi(const double* __restrict__ C) {
     return C[MI(1, 0)] * (1.0 / 12.0) + C[MI(1, 2)] * (1.0 / 144.0) + C[MI(3, 0)] * (1.0 / 80.0);
@@ -368,6 +402,66 @@ __device__ __forceinline__ void flux2(const Consts& K, const double* U, const do
         f[2] = fma(n, v, p) - t.yy;
         f[3] = fma(E + p, v, -fma(t.xy, u, fma(t.yy, v, kq * s[5])));
     }
+}
+
+// The face fluxes need the six gradients only through three combinations per
+// face point: the normal stress and the shear stress divided by mu, and the
+// normal derivative of e.  d = 0 (x-face): (4/3 u_x - 2/3 v_y, u_y + v_x,
+// e_x); d = 1 (y-face): (4/3 v_y - 2/3 u_x, u_y + v_x, e_y).  Rounded as
+// stresses() rounds them, so fluxes from the combinations are the same bits.
+template <int d>
+__device__ __forceinline__ void stress_combos(const double* s, double* dc) {
+#pragma clang fp contract(off)
+    dc[0] = d == 0 ? fma(4.0 / 3.0, s[0], -(2.0 / 3.0) * s[3])
+                   : fma(4.0 / 3.0, s[3], -(2.0 / 3.0) * s[0]);
+    dc[1] = s[1] + s[2];
+    dc[2] = s[4 + d];
+}
+
+// flux2 at a face point from the three combinations dc of stress_combos.
+template <int d, bool VarMu = true>
+__device__ __forceinline__ void flux2c(const Consts& K, const double* U, const double* dc,
+                                       double* f) {
+#pragma clang fp contract(off)
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double ir = rcp(r);
+    const double u = m * ir, v = n * ir;
+    const double p = K.gm1 * fma(-0.5, fma(m, u, n * v), E);
+    const double mu = viscosity<VarMu>(K, r, p);
+    const double tnn = mu * dc[0], txy = mu * dc[1];
+    const double kq = K.gPr * mu;
+    if (d == 0) {
+        f[0] = m;
+        f[1] = fma(m, u, p) - tnn;
+        f[2] = fma(n, u, -txy);
+        f[3] = fma(E + p, u, -fma(tnn, u, fma(txy, v, kq * dc[2])));
+    } else {
+        f[0] = n;
+        f[1] = fma(m, v, -txy);
+        f[2] = fma(n, v, p) - tnn;
+        f[3] = fma(E + p, v, -fma(txy, u, fma(tnn, v, kq * dc[2])));
+    }
+}
+
+// speed2 from the three combinations.
+template <int d, bool VarMu = true>
+__device__ __forceinline__ double speed2c(const Consts& K, const double* U, const double* dc) {
+#pragma clang fp contract(off)
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double ir = rcp(r);
+    const double p = K.gm1 * fma(-0.5 * fma(m, m, n * n), ir, E);
+    const double mu = viscosity<VarMu>(K, r, p);
+    const double tnn = mu * dc[0], txy = mu * dc[1];
+    const double kq = K.gPr * mu;
+    const double un = (d == 0 ? m : n) * ir;
+    const double q = kq * dc[2];
+    const double tp = tnn - p;
+    const double t2 = fma(tp, tp, txy * txy);
+    const double r2e = r * p * K.igm1;
+    const double root = sqrt(fma(r * r, q * q, 2.0 * r2e * t2));
+    const double bpp = fma(fma(r, fabs(q), root), 0.5 * rcp(r2e), fabs(un));
+    const double ac = fabs(un) + sqrt(K.gamma * p * ir);
+    return ac >= bpp ? ac : bpp;
 }
 
 // The same flux with the direction a run-time value (dy: g instead of f);

@@ -80,7 +80,9 @@ struct Grid2 {
     gdouble* vk;   // 8:  modified moments of the current input (hat-v 0..3, hat-w 4..7)
     gdouble* vn;   // 8:  modified moments of U^n (kept for stages 2 and 3)
     gdouble* rb;   // 18: weak moments ((l*3 + w)*3 + mom)
-    gdouble* gf;   // 72: gradients at face points ((p*6 + s)), p 0..5 x-face, 6..11 y-face
+    gdouble* gf;   // gradients at the face points, p 0..5 x-face, 6..11 y-face: 36, the
+                   // three combinations of stress_combos (p*3 + z), or with the
+                   // reverse mode's full_grad 72, the six gradients (p*6 + s)
     gdouble* vf;   // 8:  volume flux quadratures (sum f, sum g)
     gdouble* fx;   // 8: x-face flux moments at (j, i+1/2): sum_G w_G F (c), sum_G w_G x_G F (4 + c)
     gdouble* fy;   // 8: y-face flux moments at (j+1/2, i)
@@ -218,6 +220,10 @@ struct BatchL {
     int n = 0;
     Tiles tiles;
     bool var_mu = true;            // some instance has a temperature-dependent mu
+    bool dr = false;               // HWENO-DR gradients (every instance of the launch)
+    bool full_grad = false;        // face gradients stored as all six (the reverse mode
+                                   // reads them); else as the three combinations the
+                                   // face fluxes use
     // bit k: kernel class k runs its blocks last first.  The weak-moment and
     // face-flux kernels run in the opposite order of the kernel that wrote
     // most of their input just before them (reconstruction, gradients), so

@@ -51,7 +51,7 @@ class OptionsC(ctypes.Structure):
                 ('eps_pp', ctypes.c_double), ('eps_weno', ctypes.c_double),
                 ('t_final', ctypes.c_double), ('linear_weights', ctypes.c_int),
                 ('max_halvings', ctypes.c_int), ('linear_gradients', ctypes.c_int),
-                ('keep_stages', ctypes.c_int)]
+                ('keep_stages', ctypes.c_int), ('gradients', ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -138,10 +138,15 @@ def check(code):
         raise HwenoError(code, lib().hweno_status_string(code).decode())
 
 
+GRADIENTS = {'GR': 0, 'DR': 1}
+
+
 def default_options(**kw):
     o = OptionsC()
     check(lib().hweno_default_options(ctypes.byref(o)))
     for k, v in kw.items():
+        if k == 'gradients' and isinstance(v, str):
+            v = GRADIENTS[v]
         setattr(o, k, v)
     return o
 
@@ -156,7 +161,8 @@ class Solver:
     ``bc`` = kinds for (xlo, xhi[, ylo, yhi]); ``inflow`` = {side: primitive
     state (rho, u, [v,] p)}; ``options`` = keyword overrides of the paper's
     defaults (cfl, b_visc, eps_pp, eps_weno, t_final, linear_weights,
-    max_halvings, linear_gradients, keep_stages).
+    max_halvings, linear_gradients, keep_stages, gradients: 'GR' (default)
+    or 'DR', or 0 / 1).
     """
 
     def __init__(self, nx, ny=None, extent=(0.0, 1.0, 0.0, 1.0), gamma=1.4, Pr=0.72,

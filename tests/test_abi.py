@@ -168,3 +168,4 @@ def test_host_allocation_failure_is_a_status():
                        text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert 'status 7 host memory allocation failed' in r.stdout
+
