@@ -217,6 +217,28 @@ HWENO_API hweno_status hweno_get_state(hweno_ctx* ctx, double* U, double* t);
 HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R, double* Vhat,
                                       hweno_diag* diag);
 
+/* For callers that cannot allocate device memory or hand the library a
+ * workspace -- code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc: hweno_residual with every intermediate in a
+ * library-owned static device buffer of HWENO_NOALLOC_BYTES (256 MiB) per
+ * device, which each device the library runs on holds until the process
+ * ends.  Same arguments, results and diag as hweno_residual (the same
+ * kernels, so the same bits); no hweno_set_workspace is needed and the
+ * context's workspace and state are left alone.  The call allocates nothing
+ * (no hipMalloc/hipFree, no host allocation); its first call on a device
+ * looks up the buffer's device address once.
+ * Size limit: 2D needs 1856 * (nx + 8) * (ny + 8) bytes plus about 3 KiB
+ * (e.g. up to 372 x 372 cells), 1D 352 * (nx + 8) plus 512 bytes; larger
+ * grids return HWENO_E_WORKSPACE.  Single grids without inflow profiles,
+ * stage profiles or a solid mask (those live in the workspace): otherwise
+ * HWENO_E_INVAL.  All calls on one device share the buffer and it keeps the
+ * last call's contents (every value a call reads it has written itself
+ * first): calls that overlap on one device -- concurrent streams, threads
+ * or contexts -- race and must be serialised by the caller. */
+#define HWENO_NOALLOC_BYTES ((size_t)256 << 20)
+HWENO_API hweno_status hweno_residual_noalloc(hweno_ctx* ctx, const double* U, double* R,
+                                              double* Vhat, hweno_diag* diag);
+
 /* One SSP-RK3 step of eq. (2.12) on the context state.  dt > 0: that step;
  * dt <= 0: dt = min(cfl*h/alpha*, b*h^2/mu_ref, t_final - t) with alpha*
  * from the stage-1 face traces (Sec. 5 preamble).  A stage with a cell of

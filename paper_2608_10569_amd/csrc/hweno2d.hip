@@ -20,6 +20,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "hweno_kernels.h"
 
 namespace hw {
@@ -1541,6 +1543,36 @@ hipError_t launch_commit2(const BatchL& b, hipStream_t st) {
     k_commit_copy<<<b.blocks(KB_CELLS), 256, 0, st>>>(b.arg(KB_CELLS));
     k_commit_state<<<nblk(b.n, 64), 64, 0, st>>>(b.dg, b.n, 4, 5);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free residual: a file-scope array in device
+// memory, one per device the library runs on.  Host code never passes the
+// array's name to a kernel (on the host it only names a stand-in); it takes
+// the device address from hipGetSymbolAddress, once per device with that
+// device current, and hands that pointer on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    *out = nullptr;
+    int d = 0;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[d]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[d] = p;
+    }
+    *out = addr[d];
+    return hipSuccess;
 }
 
 }  // namespace hw

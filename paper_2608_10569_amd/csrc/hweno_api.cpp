@@ -90,6 +90,12 @@ struct hweno_ctx {
     int* sdst_dev = nullptr;
     int* ssrc_dev = nullptr;
     int* sdir_dev = nullptr;
+    // allocation-free residual (hweno_residual_noalloc): the descriptors it
+    // copies into the library's static scratch, kept here so that the copies
+    // read host memory that outlives the call
+    hw::Grid2 sgrid{};
+    hw::InstState sstate{};
+    int sstart[2 * hw::KB_COUNT] = {};
     hw::Timer* tm() { return timer.on ? &timer : nullptr; }
     const Inst& i0() const { return in[0]; }
     int dim() const { return in[0].grid.dim; }
@@ -861,6 +867,153 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* c, const double* U, double* R, 
     if (diag) {
         hw::Reduce r;
         TRY(read_reduce(c, &r));
+        fill_diag(c->t, r, diag, 0, false);
+        diag->dt = 0.0;
+        diag->min_rho = diag->min_p = NAN;
+    }
+    return HWENO_OK;
+    GUARD_END
+}
+
+}  // extern "C"
+
+namespace {
+
+static_assert(hw::STATIC_SCRATCH_BYTES == HWENO_NOALLOC_BYTES,
+              "the static scratch and its documented size differ");
+
+// Residual-only carve of the static scratch for a 2D grid: descriptor,
+// instance state, reduction slots, block table, one ghosted state and the
+// intermediates of one residual (no RK buffers, reverse-mode or profile
+// arrays).  base == nullptr: size only.
+size_t static_layout2(hw::Grid2& g, char* base, hw::Grid2** dgrid, hw::InstState** dst,
+                      int** dstart) {
+    size_t off = 0;
+    auto take_bytes = [&](size_t nb) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += up(nb);
+        return p;
+    };
+    auto take = [&](size_t nd) -> hw::gdouble* {
+        return (hw::gdouble*)take_bytes(nd * sizeof(double));
+    };
+    const size_t m = (size_t)g.ncell;
+    *dgrid = reinterpret_cast<hw::Grid2*>(take_bytes(sizeof(hw::Grid2)));
+    *dst = reinterpret_cast<hw::InstState*>(take_bytes(sizeof(hw::InstState)));
+    g.st = (HW_GLOBAL hw::InstState*)*dst;
+    g.red = (HW_GLOBAL hw::Reduce*)take_bytes(sizeof(hw::Reduce));
+    *dstart = reinterpret_cast<int*>(take_bytes(2 * hw::KB_COUNT * sizeof(int)));
+    hw::gdouble* S = take(12 * m);
+    for (int k = 0; k < 4; ++k) g.S[k] = S;
+    g.xf = take(24 * m);
+    g.yf = take(24 * m);
+    g.xv = take(36 * m);
+    g.yv = take(36 * m);
+    g.wb = take(6 * m);
+    g.vk = take(8 * m);
+    g.vn = take(8 * m);
+    g.rb = take(18 * m);
+    g.gf = take(36 * m);
+    g.vf = take(8 * m);
+    g.fx = take(8 * m);
+    g.fy = take(8 * m);
+    g.solid = nullptr;
+    g.sdst = g.ssrc = g.sdir = nullptr;
+    g.nsolid = 0;
+    for (int sd = 0; sd < 4; ++sd) g.side[sd].prof = g.side[sd].prof_stage = nullptr;
+    return off;
+}
+
+// The same for a 1D grid: reduction slots, one ghosted state, intermediates.
+size_t static_layout1(hw::Grid1& g, char* base, double** S) {
+    size_t off = 0;
+    auto take_bytes = [&](size_t nb) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += up(nb);
+        return p;
+    };
+    auto take = [&](size_t nd) -> hw::gdouble* {
+        return (hw::gdouble*)take_bytes(nd * sizeof(double));
+    };
+    const size_t m = (size_t)g.NX;
+    g.red = (HW_GLOBAL hw::Reduce*)take_bytes(sizeof(hw::Reduce));
+    *S = (double*)take(6 * m);
+    g.pts = take(12 * m);
+    g.wb = take(2 * m);
+    g.vk = take(3 * m);
+    g.vn = take(3 * m);
+    g.rb = take(4 * m);
+    g.gr = take(8 * m);
+    g.fh = take(3 * m);
+    g.vf = take(3 * m);
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+HWENO_API hweno_status hweno_residual_noalloc(hweno_ctx* c, const double* U, double* R,
+                                              double* V, hweno_diag* diag) {
+    GUARD_BEGIN
+    if (!c || !U || !R || !V || c->batch) return HWENO_E_INVAL;
+    // inflow profiles and masks live in the context's workspace
+    if (!c->solid_host.empty()) return HWENO_E_INVAL;
+    for (int sd = 0; sd < 4; ++sd)
+        if (!c->prof_host[sd].empty() || !c->stage_host[sd].empty()) return HWENO_E_INVAL;
+    hipStream_t st = c->stream;
+    hw::Reduce* red = nullptr;
+    if (c->dim() == 2) {
+        hw::Grid2 g = c->hg[0];
+        hw::Grid2* dg = nullptr;
+        hw::InstState* dst = nullptr;
+        int* dstart = nullptr;
+        if (static_layout2(g, nullptr, &dg, &dst, &dstart) > hw::STATIC_SCRATCH_BYTES)
+            return HWENO_E_WORKSPACE;
+        void* base = nullptr;
+        TRY(dev(hw::static_scratch(&base)));
+        static_layout2(g, static_cast<char*>(base), &dg, &dst, &dstart);
+        c->sgrid = g;
+        c->sstate = hw::InstState{};
+        c->sstate.active = 1;
+        hw::batch_blocks(&c->sgrid, 1, c->tiles, c->sstart);
+        TRY(dev(hipMemcpyAsync(dg, &c->sgrid, sizeof(hw::Grid2), hipMemcpyHostToDevice, st)));
+        TRY(dev(hipMemcpyAsync(dst, &c->sstate, sizeof(hw::InstState), hipMemcpyHostToDevice,
+                               st)));
+        TRY(dev(hipMemcpyAsync(dstart, c->sstart, sizeof(c->sstart), hipMemcpyHostToDevice,
+                               st)));
+        hw::BatchL bl;
+        bl.dg = dg;
+        bl.dstart = dstart;
+        bl.hstart = c->sstart;
+        bl.n = 1;
+        bl.tiles = c->tiles;
+        bl.var_mu = c->i0().phys.mu_exp != 0.0;
+        bl.dr = c->i0().opt.gradients != 0;
+        TRY(dev(hw::launch_copy_in2(g, U, g.S[0], st)));
+        TRY(dev(hw::launch_reset2(bl, st)));
+        TRY(dev(hw::launch_ghost2(bl, 0, st, nullptr)));
+        TRY(dev(hw::launch_residual2(bl, 0, st, nullptr)));
+        TRY(dev(hw::launch_update2(bl, 0, 0, 0, 0, R, V, st, nullptr)));
+        red = (hw::Reduce*)g.red;
+    } else {
+        hw::Grid1 g = c->g1;
+        double* S = nullptr;
+        if (static_layout1(g, nullptr, &S) > hw::STATIC_SCRATCH_BYTES) return HWENO_E_WORKSPACE;
+        void* base = nullptr;
+        TRY(dev(hw::static_scratch(&base)));
+        static_layout1(g, static_cast<char*>(base), &S);
+        red = (hw::Reduce*)g.red;
+        TRY(dev(hw::launch_copy_in1(g, U, S, st)));
+        TRY(dev(hw::launch_reset(red, st)));
+        TRY(dev(hw::launch_ghost1(g, S, st, nullptr)));
+        TRY(dev(hw::launch_residual1(g, S, st, nullptr)));
+        TRY(dev(hw::launch_update1(g, 0, S, S, S, R, V, st, nullptr)));
+    }
+    if (diag) {
+        hw::Reduce r;
+        TRY(dev(hipMemcpyAsync(&r, red, sizeof(hw::Reduce), hipMemcpyDeviceToHost, st)));
+        TRY(dev(hipStreamSynchronize(st)));
         fill_diag(c->t, r, diag, 0, false);
         diag->dt = 0.0;
         diag->min_rho = diag->min_p = NAN;

@@ -274,4 +274,11 @@ hipError_t launch_update1(const Grid1& g, int stage, const double* S0, const dou
                           const double* src = nullptr);
 hipError_t launch_check1(const Grid1& g, const double* S, hipStream_t st);
 
+// Library-owned device scratch of the allocation-free residual entry point:
+// one file-scope array per device (its size is fixed at build time and it
+// lives until the process ends).  static_scratch returns its device address
+// on the current device, looked up once per device.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(256) << 20;
+hipError_t static_scratch(void** ptr);
+
 }  // namespace hw

@@ -14,12 +14,16 @@ LIB_PATH = os.path.join(HERE, 'libhweno.so')
 
 BC = {'periodic': 0, 'outflow': 1, 'inflow': 2, 'slip': 3, 'noslip': 4}
 
+#: size of the library's static device buffer used by hweno_residual_noalloc
+NOALLOC_BYTES = 256 << 20
+
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_inflow_stages',
            'hweno_rk_step_inflow', 'hweno_set_solid', 'hweno_set_stream',
            'hweno_set_state', 'hweno_get_state',
-           'hweno_residual', 'hweno_rk_step', 'hweno_rk_step_source', 'hweno_residual_vjp',
+           'hweno_residual', 'hweno_residual_noalloc', 'hweno_rk_step', 'hweno_rk_step_source',
+           'hweno_residual_vjp',
            'hweno_rk_step_vjp',
            'hweno_set_timing', 'hweno_get_timing', 'hweno_status_string',
            'hweno_batch_create', 'hweno_batch_set_state', 'hweno_batch_get_state',
@@ -108,6 +112,7 @@ def lib():
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
+        L.hweno_residual_noalloc.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_rk_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
         L.hweno_rk_step_source.argtypes = [vp, ctypes.c_double, vp, vp, vp, ctypes.POINTER(Diag)]
         L.hweno_residual_vjp.argtypes = [vp, vp, vp, vp, vp, dp]
@@ -279,6 +284,18 @@ class Solver:
         d = Diag()
         check(lib().hweno_residual(self._h, _ptr(U), _ptr(R), _ptr(V),
                                    ctypes.byref(d) if diag else None))
+        return R, V, (d.as_dict() if diag else None)
+
+    def residual_noalloc(self, U, diag=True):
+        """hweno_residual_noalloc: the residual with the library's static
+        device buffer in place of the workspace (same results)."""
+        import torch
+        self._dev(U)
+        R = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        V = torch.empty(self.vhat_shape, dtype=torch.float64, device=self.device)
+        d = Diag()
+        check(lib().hweno_residual_noalloc(self._h, _ptr(U), _ptr(R), _ptr(V),
+                                           ctypes.byref(d) if diag else None))
         return R, V, (d.as_dict() if diag else None)
 
     def residual_vjp(self, U, Rbar, Vbar=None, want_mu=True):

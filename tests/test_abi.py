@@ -169,3 +169,34 @@ def test_host_allocation_failure_is_a_status():
     assert r.returncode == 0, r.stdout + r.stderr
     assert 'status 7 host memory allocation failed' in r.stdout
 
+
+def test_noalloc_residual_host_checks_without_device():
+    """The allocation-free residual refuses, before touching a device, a grid
+    whose residual does not fit its static buffer (1856 bytes per ghosted
+    cell in 2D), a batch context and NULL arrays."""
+    L = hweno.lib()
+    dummy = ctypes.c_void_p(4096)     # never dereferenced: the checks come first
+    big = hweno.Grid(2, 400, 400, 0.0, 1.0, 0.0, 1.0)
+    fits = hweno.Grid(2, 300, 300, 0.0, 1.0, 0.0, 1.0)
+    assert 1856 * 408 * 408 > hweno.NOALLOC_BYTES > 1856 * 308 * 308
+    ph = hweno.PhysicsC(1.4, 0.72, 0.01, 0.0, 1.0)
+    b = hweno.Bcs()
+    o = hweno.default_options()
+    h = ctypes.c_void_p()
+    assert L.hweno_create(ctypes.byref(big), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                          ctypes.byref(h)) == 0
+    assert L.hweno_residual_noalloc(h, dummy, dummy, dummy, None) == 3
+    assert L.hweno_residual_noalloc(h, None, dummy, dummy, None) == 1
+    assert L.hweno_destroy(h) == 0
+    g1 = hweno.Grid(1, 800000, 1, 0.0, 1.0, 0.0, 1.0)      # 1D: 352 bytes per ghosted cell
+    assert L.hweno_create(ctypes.byref(g1), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                          ctypes.byref(h)) == 0
+    assert L.hweno_residual_noalloc(h, dummy, dummy, dummy, None) == 3
+    assert L.hweno_destroy(h) == 0
+    gs = (hweno.Grid * 2)(fits, fits)
+    phs = (hweno.PhysicsC * 2)(ph, ph)
+    bs = (hweno.Bcs * 2)(b, b)
+    os_ = (hweno.OptionsC * 2)(o, o)
+    assert L.hweno_batch_create(2, gs, phs, bs, os_, ctypes.byref(h)) == 0
+    assert L.hweno_residual_noalloc(h, dummy, dummy, dummy, None) == 1
+    assert L.hweno_destroy(h) == 0

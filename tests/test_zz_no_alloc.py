@@ -1,0 +1,105 @@
+"""The allocation-free residual entry point (library-owned static scratch)
+against the workspace entry point hweno_residual, through the C ABI: the
+same kernels, so the same bits, over consecutive calls of decreasing size
+that share the one static buffer."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2608_10569_amd import hweno, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _noalloc(s, U):
+    import torch
+    R = torch.empty(s.state_shape, dtype=torch.float64, device=s.device)
+    V = torch.empty(s.vhat_shape, dtype=torch.float64, device=s.device)
+    d = hweno.Diag()
+    code = hweno.lib().hweno_residual_noalloc(s._h, hweno._ptr(U), hweno._ptr(R), hweno._ptr(V),
+                                              ctypes.byref(d))
+    assert code == 0, hweno.lib().hweno_status_string(code).decode()
+    return R, V, d.as_dict()
+
+
+def _trough(U):
+    U[0, 0, 6:9, 5:10] = 2e-3
+    U[0, 3, 6:9, 5:10] = 0.5 * (U[0, 1, 6:9, 5:10] ** 2 + U[0, 2, 6:9, 5:10] ** 2) / 2e-3 + 2e-3
+    return U
+
+
+def _cases():
+    """(name, solver kwargs, state) in call order: each call smaller than the
+    one before it, so later calls run on a buffer holding a larger grid's data."""
+    return [
+        ('2d periodic 96x80', dict(nx=96, ny=80, mu_ref=0.01),
+         workloads.random_smooth_2d(96, 80, seed=7)),
+        ('2d walls 40x24', dict(nx=40, ny=24, extent=(0.0, 1.0, 0.0, 0.5), mu_ref=1 / 200,
+                                Pr=0.73, bc=['noslip', 'noslip', 'noslip', 'slip']),
+         workloads.viscous_shock_tube_2d(40, 24, seed=1, amp=0.05)),
+        ('2d trough 16x16 (limiter active)', dict(nx=16, ny=16, mu_ref=1e-3),
+         _trough(workloads.random_smooth_2d(16, 16, seed=3))),
+        ('2d DR 30x20 (comparison scheme)', dict(nx=30, ny=20, mu_ref=0.01, gradients='DR'),
+         workloads.random_smooth_2d(30, 20, seed=9)),
+        ('1d periodic 300', dict(nx=300, mu_ref=0.01), workloads.random_smooth_1d(300, seed=2)),
+        ('1d DR 200', dict(nx=200, mu_ref=0.01, gradients='DR'),
+         workloads.random_smooth_1d(200, seed=4)),
+        ('1d outflow 64', dict(nx=64, mu_ref=1e-3, bc=['outflow', 'outflow']),
+         workloads.riemann_1d((7.0, -1.0, 0.2), (7.0, 1.0, 0.2), 64)),
+    ]
+
+
+def test_noalloc_residual_equals_workspace_residual():
+    import torch
+    dev = torch.device('cuda:0')
+    for name, kw, U in _cases():
+        print('case', name, flush=True)
+        s = hweno.Solver(device=dev, **kw)
+        Ut = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
+        R0, V0, d0 = s.residual(Ut)
+        R1, V1, d1 = _noalloc(s, Ut)
+        torch.cuda.synchronize()
+        assert torch.equal(R0, R1), name
+        assert torch.equal(V0, V1), name
+        for k in ('alpha_star', 'beta_max', 'pp_cells'):
+            assert d0[k] == d1[k], (name, k, d0[k], d1[k])
+        if 'limiter' in name:
+            assert d1['pp_cells'] > 0
+        # a second call on the same buffer: the same bits again
+        R2, V2, _ = _noalloc(s, Ut)
+        assert torch.equal(R1, R2) and torch.equal(V1, V2), name
+
+
+def test_noalloc_needs_no_workspace_and_refuses_what_it_cannot_hold():
+    """A context without a workspace works; grids beyond the buffer, masked
+    grids and batches are refused before any device work."""
+    import torch
+    dev = torch.device('cuda:0')
+    L = hweno.lib()
+    U = workloads.random_smooth_2d(32, 32, seed=5)
+    ref = hweno.Solver(32, 32, mu_ref=0.01, device=dev)
+    Ut = torch.from_numpy(U).to(dev)
+    R0, V0, _ = ref.residual(Ut, diag=False)
+    # a bare context: created, never given a workspace
+    g = hweno.Grid(2, 32, 32, 0.0, 1.0, 0.0, 1.0)
+    ph = hweno.PhysicsC(1.4, 0.72, 0.01, 0.0, 1.0)
+    b = hweno.Bcs()
+    o = hweno.default_options()
+    h = ctypes.c_void_p()
+    assert L.hweno_create(ctypes.byref(g), ctypes.byref(ph), ctypes.byref(b), ctypes.byref(o),
+                          ctypes.byref(h)) == 0
+    assert L.hweno_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)) == 0
+    R = torch.empty_like(R0)
+    V = torch.empty_like(V0)
+    assert L.hweno_residual_noalloc(h, hweno._ptr(Ut), hweno._ptr(R), hweno._ptr(V), None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(R, R0) and torch.equal(V, V0)
+    assert L.hweno_destroy(h) == 0
+    # masked grid: refused
+    m = np.zeros((32, 32), dtype=bool)
+    m[10:14, 10:14] = True
+    ref.set_solid(m)
+    assert L.hweno_residual_noalloc(ref._h, hweno._ptr(Ut), hweno._ptr(R), hweno._ptr(V),
+                                    None) == 1
