@@ -147,15 +147,10 @@ def _c3_worker(args):
     return _c3_window_rate(*args)
 
 
-def cpu_baseline(rows=64, reps=3):
-    """The oracle (as it stands) on bounded samples of the benchmark's
-    workloads, on this host: the 1000x500 shock tube as 1000 x ``rows``
-    windows (three stage residuals = one RK step's spatial work each) on one
-    thread (median of three) and on every core the process may use (one
-    window per worker process, up to 16); plus short samples of the 1D
-    configurations and of the batched instances, one thread each."""
-    import statistics
-    from concurrent.futures import ProcessPoolExecutor
+def _cpu_task(task):
+    """One single-threaded oracle sample in a worker process: ('c1',) the
+    smooth-wave run to t = 1; ('c2', nsteps) Sod at N = 2000; ('c4', n, Re, U)
+    one step of a batched instance.  Returns (kind, cell-stages, seconds)."""
     from threadpoolctl import threadpool_limits
     import numpy as np
     from oracle import rk
@@ -163,12 +158,49 @@ def cpu_baseline(rows=64, reps=3):
     from oracle.scheme1d import Scheme1D
     from oracle.scheme2d import Scheme2D
     from paper_2608_10569_amd import workloads
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        if task[0] == 'c1':
+            sc = Scheme1D(200, 0.0, 2 * np.pi, Physics(gamma=1.4, Pr=0.72, mu_ref=0.01),
+                          Options(cfl=0.3, b_visc=0.001, t_final=1.0))
+            U, t, steps = workloads.smooth_wave_1d(200), 0.0, 0
+            while t < 1.0 - 1e-12:
+                U, dt, _ = rk.rk3_step(sc, U, t)
+                t += dt
+                steps += 1
+            return 'c1', 3 * 200 * steps, time.perf_counter() - t0
+        if task[0] == 'c2':
+            sc = Scheme1D(2000, 0.0, 1.0, Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3),
+                          Options(cfl=0.3), bc=('outflow', 'outflow'))
+            U, t = workloads.sod_1d(2000), 0.0
+            for _ in range(task[1]):
+                U, dt, _ = rk.rk3_step(sc, U, t)
+                t += dt
+            return 'c2', 3 * 2000 * task[1], time.perf_counter() - t0
+        _, n, Re, U = task
+        sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=1.0 / Re), Options())
+        rk.rk3_step(sc, U, 0.0)
+        return 'c4', 3 * n * n, time.perf_counter() - t0
+
+
+def cpu_baseline(rows=64, reps=3, c2_steps=1000):
+    """The oracle (as it stands) on bounded samples of the benchmark's
+    workloads, on this host: the 1000x500 shock tube as 1000 x ``rows``
+    windows (three stage residuals = one RK step's spatial work each) on one
+    thread (median of five) and on every core the process may use (one
+    window per worker process, up to 16); then, over the same worker pool,
+    one single-threaded task each: the 1D smooth-wave run to t = 1, Sod at
+    N = 2000 for ``c2_steps`` steps, and one step of every batched
+    instance."""
+    import statistics
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2608_10569_amd import workloads
     nproc = os.cpu_count()
     usable = len(os.sched_getaffinity(0)) if hasattr(os, 'sched_getaffinity') else nproc
     workers = max(1, min(usable, 16))
     j0 = (NY - rows) // 2
     one = []
-    for _ in range(3):
+    for _ in range(5):
         n, el = _c3_window_rate(rows, j0, reps)
         one.append(n / el)
     rate1 = statistics.median(one)
@@ -179,49 +211,38 @@ def cpu_baseline(rows=64, reps=3):
         res = list(ex.map(_c3_worker, [(rows, j, reps) for j in starts]))
         wall = time.perf_counter() - t0
     rate_all = sum(n for n, _ in res) / wall
-    extra = {}
-    with threadpool_limits(1):
-        # C2: Sod at N = 2000, paper rule, 100 steps
-        sc = Scheme1D(2000, 0.0, 1.0, Physics(gamma=1.4, Pr=0.72, mu_ref=1e-3),
-                      Options(cfl=0.3), bc=('outflow', 'outflow'))
-        U, t = workloads.sod_1d(2000), 0.0
+    # the other workloads: the two 1D tasks first, then the batched instances
+    # largest first (longest-processing-time order)
+    inst = sorted(workloads.batched_periodic_2d(), key=lambda x: -x[0])
+    tasks = [('c1',), ('c2', c2_steps)] + [('c4', n, Re, U) for n, Re, U in inst]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
         t0 = time.perf_counter()
-        for _ in range(100):
-            U, dt, _ = rk.rk3_step(sc, U, t)
-            t += dt
-        el = time.perf_counter() - t0
-        extra['c2_sod_n2000'] = {'value': 100 * 3 * 2000 / el, 'sample': '100 steps', 's': el}
-        # C1: smooth wave at N = 200, the first 300 steps of the run to t = 1
-        sc = Scheme1D(200, 0.0, 2 * np.pi, Physics(gamma=1.4, Pr=0.72, mu_ref=0.01),
-                      Options(cfl=0.3, b_visc=0.001, t_final=1.0))
-        U, t = workloads.smooth_wave_1d(200), 0.0
-        t0 = time.perf_counter()
-        for _ in range(300):
-            U, dt, _ = rk.rk3_step(sc, U, t)
-            t += dt
-        el = time.perf_counter() - t0
-        extra['c1_smooth_n200'] = {'value': 300 * 3 * 200 / el, 'sample': '300 steps', 's': el}
-        # C4: one step of the batch's four smallest instances
-        inst = sorted(workloads.batched_periodic_2d(), key=lambda x: x[0])[:4]
-        cells = 0
-        t0 = time.perf_counter()
-        for n, Re, U in inst:
-            sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=1.0 / Re), Options())
-            rk.rk3_step(sc, U, 0.0)
-            cells += n * n
-        el = time.perf_counter() - t0
-        extra['c4_four_smallest'] = {'value': 3 * cells / el,
-                                     'sample': 'one step of %s instances' %
-                                               '+'.join('%d^2' % n for n, _, _ in inst), 's': el}
+        out = list(ex.map(_cpu_task, tasks))
+        wall4 = time.perf_counter() - t0
+    by = {k: [(n, el) for kk, n, el in out if kk == k] for k in ('c1', 'c2', 'c4')}
+    c4n = sum(n for n, _ in by['c4'])
+    c4s = sum(el for _, el in by['c4'])
+    extra = {
+        'c1_smooth_n200': {'value': by['c1'][0][0] / by['c1'][0][1], 'threads': 1,
+                           'sample': 'the whole run to t = 1 (%d cell-stages)' % by['c1'][0][0],
+                           's': by['c1'][0][1]},
+        'c2_sod_n2000': {'value': by['c2'][0][0] / by['c2'][0][1], 'threads': 1,
+                         'sample': '%d steps' % c2_steps, 's': by['c2'][0][1]},
+        'c4_batched': {'value_one_thread': c4n / c4s, 'value_all_threads': c4n / wall4,
+                       'threads': workers,
+                       'sample': 'one step of each of the %d instances (%d cells), one '
+                                 'process per instance; all-thread rate over the pool\'s wall '
+                                 'time, which also ran the two 1D tasks' % (len(inst), c4n // 3),
+                       's_one_thread_sum': c4s, 's_wall': wall4}}
     return {'value': rate_all, 'unit': UNIT, 'cores': workers, 'kind': 'oracle',
             'sample': '%d worker processes, each %d stage residuals on a 1000x%d-cell window of '
                       'the 1000x500 shock tube at t=0 (true neighbours as halo), numpy, one '
                       'thread per process, %.1f s wall' % (workers, reps, rows, wall),
-            'one_thread': {'value': rate1, 'unit': UNIT, 'median_of': 3,
+            'one_thread': {'value': rate1, 'unit': UNIT, 'median_of': len(one),
                            'sample': '%d stage residuals on rows %d..%d' % (reps, j0,
                                                                              j0 + rows - 1)},
             'cpu_model': cpu_model(), 'nproc': nproc, 'usable_cpus': usable,
-            'other_workloads_one_thread': extra}
+            'other_workloads': extra}
 
 
 def bench_batched(nsteps, sequential=True):

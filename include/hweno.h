@@ -227,8 +227,8 @@ HWENO_API hweno_status hweno_residual(hweno_ctx* ctx, const double* U, double* R
  * context's workspace and state are left alone.  The call allocates nothing
  * (no hipMalloc/hipFree, no host allocation); its first call on a device
  * looks up the buffer's device address once.
- * Size limit: 2D needs 1856 * (nx + 8) * (ny + 8) bytes plus about 3 KiB
- * (e.g. up to 372 x 372 cells), 1D 352 * (nx + 8) plus 512 bytes; larger
+ * Size limit: 2D needs 1776 * (nx + 8) * (ny + 8) bytes plus about 3 KiB
+ * (e.g. up to 380 x 380 cells), 1D 352 * (nx + 8) plus 512 bytes; larger
  * grids return HWENO_E_WORKSPACE.  Single grids without inflow profiles,
  * stage profiles or a solid mask (those live in the workspace): otherwise
  * HWENO_E_INVAL.  All calls on one device share the buffer and it keeps the

@@ -48,9 +48,10 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 // Block-level reductions: wave shuffles, then LDS across the block's waves;
 // thread 0 issues at most one atomic, and only when it can change the slot.
+// (red_max / red_add with a scratch pointer use the caller's LDS, NT / 64
+// free slots no thread reads or writes until the block ends.)
 template <int NT>
-__device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
-    __shared__ double sh[NT / 64];
+__device__ __forceinline__ void red_max(unsigned long long* slot, double v, double* sh) {
     v = wave_max(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -60,6 +61,11 @@ __device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
         const unsigned long long k = dkey(v);
         if (v > -INFINITY && k > *(volatile HW_GLOBAL unsigned long long*)slot) atomicMax(slot, k);
     }
+}
+template <int NT>
+__device__ __forceinline__ void red_max(unsigned long long* slot, double v) {
+    __shared__ double sh[NT / 64];
+    red_max<NT>(slot, v, sh);
 }
 // Two minima in one pass (one LDS array per value: a second red_min call
 // right after the first could overwrite slots thread 0 is still reading).
@@ -86,8 +92,8 @@ __device__ __forceinline__ void red_min2(unsigned long long* sa, double a, unsig
     }
 }
 template <int NT>
-__device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long long v) {
-    __shared__ unsigned long long sh[NT / 64];
+__device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long long v,
+                                        unsigned long long* sh) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -96,6 +102,11 @@ __device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long 
         for (int w = 1; w < NT / 64; ++w) v += sh[w];
         if (v) atomicAdd(slot, v);
     }
+}
+template <int NT>
+__device__ __forceinline__ void red_add(unsigned long long* slot, unsigned long long v) {
+    __shared__ unsigned long long sh[NT / 64];
+    red_add<NT>(slot, v, sh);
 }
 template <int NT>
 __device__ __forceinline__ void red_add32(unsigned int* slot, unsigned int v) {
@@ -255,7 +266,7 @@ __global__ void k_ghost2(Batch bt, int sidx, int stage) {
 // gradients and the volume-flux quadratures itself, in place of the
 // weak-moment and gradient kernels.
 // ---------------------------------------------------------------------------
-template <int RC_CELLS, bool DR = false, bool VarMu = false>
+template <int RC_CELLS, bool DR = false, bool VarMu = false, bool FULL = false>
 __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     // one block = RC_CELLS consecutive cells of one row; the 3-row stencil
     // tile of all 12 fields is staged in LDS first, then the same memory holds
@@ -264,8 +275,9 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     constexpr int TILE = 12 * 3 * TW;
     constexpr int SH = 8 * 16 * RC_CELLS;
     __shared__ double sh[SH > TILE ? SH : TILE];
-    __shared__ double redA[8 * RC_CELLS];
-    __shared__ double redB[8 * RC_CELLS];
+    // the per-thread reductions use the exchange's moment slots (o = 15),
+    // which are never read back
+    double* const red = sh + 15 * RC_CELLS;
     const Loc lc = locate(bt);
     const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
     if (!gsrc.st->active) return;
@@ -386,11 +398,11 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
     auto comp = [&](int bb, int c, int o) { return sh[((bb * 4 + c) * 16 + o) * RC_CELLS + cl]; };
     double rmin = INFINITY;
     for (int o = k; o < 15; o += 4) rmin = fmin(rmin, comp(b, 0, o));
-    redA[bk * RC_CELLS + cl] = rmin;
+    red[bk * 16 * RC_CELLS + cl] = rmin;
     __syncthreads();
-    rmin = redA[cl];
+    rmin = red[cl];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) rmin = fmin(rmin, redA[q * RC_CELLS + cl]);
+    for (int q = 1; q < 8; ++q) rmin = fmin(rmin, red[q * 16 * RC_CELLS + cl]);
     const double rbar = ub[0];
     const double pbar = pressure2(K, ub[0], ub[1], ub[2], ub[3]);
     const double eps = fmin(fmin(K.eps_pp, rbar), pbar);
@@ -401,11 +413,12 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
         const double pt = pressure2(K, rt, comp(b, 1, o), comp(b, 2, o), comp(b, 3, o));
         if (pt < eps) tmin = fmin(tmin, (pbar - eps) / (pbar - pt));
     }
-    redB[bk * RC_CELLS + cl] = tmin;
+    __syncthreads();   // every thread has read the rho minima
+    red[bk * 16 * RC_CELLS + cl] = tmin;
     __syncthreads();
-    double th2 = redB[cl];
+    double th2 = red[cl];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) th2 = fmin(th2, redB[q * RC_CELLS + cl]);
+    for (int q = 1; q < 8; ++q) th2 = fmin(th2, red[q * 16 * RC_CELLS + cl]);
 
     const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
     if (valid) {
@@ -416,43 +429,71 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
             F[o * 4 * N] = ub[k] + th2 * (ut - ub[k]);
         }
     }
-    // wbar of (u, v, e) from this basis' unlimited volume values: thread k
-    // sums the volume points q = k, k+4, k+8, then the four partial sums meet
-    // in LDS
-    {
+    // HWENO-GR: wbar of (u, v, e) from this basis' unlimited volume values,
+    // and the compact volume data of the gradient kernel's volume flux: the
+    // Gauss sum of this basis' convective flux and the velocities (and
+    // viscosities) at the points.  Thread k takes the volume points q = k,
+    // k+4, k+8; the partial sums meet in LDS.  (HWENO-DR forms its volume
+    // fluxes below and needs none of this.)
+    if constexpr (!DR) {
         double su = 0.0, sv = 0.0, se = 0.0;
+        double fs[4] = {0.0, 0.0, 0.0, 0.0};
+        double* VC = g.vc + (long long)b * VC_B * N + cell;
         for (int q = k; q < 9; q += 4) {
             const int o = 6 + q;
             const double w = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
-            const double ir = rcp(comp(b, 0, o));
-            const double u = comp(b, 1, o) * ir, v = comp(b, 2, o) * ir;
-            const double e = comp(b, 3, o) * ir - 0.5 * (u * u + v * v);
+            const double r = comp(b, 0, o), m = comp(b, 1, o), n = comp(b, 2, o);
+            const double E = comp(b, 3, o);
+            const double ir = rcp(r);
+            const double u = m * ir, v = n * ir;
+            const double e = E * ir - 0.5 * (u * u + v * v);
             su += w * u;
             sv += w * v;
             se += w * e;
+            double fc[4], mu;
+            conv2_dir<VarMu>(K, r, m, n, E, u, v, b == 1, fc, mu);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fs[c] += w * fc[c];
+            if (valid) {
+                VC[(4 + q) * N] = u;
+                VC[(13 + q) * N] = v;
+                if constexpr (VarMu) VC[(22 + q) * N] = mu;
+            }
         }
-        __syncthreads();   // redA / redB reads above are complete
-        redA[bk * RC_CELLS + cl] = su;
-        redB[bk * RC_CELLS + cl] = sv;
-        sh[(bk * 16 + 15) * RC_CELLS + cl] = se;   // moment slots are not read back
+        __syncthreads();   // theta2 and the volume slots of sh are read
+        // the partial sums go to the thread's own volume slots 6..12
+        sh[(bk * 16 + 10) * RC_CELLS + cl] = su;
+        sh[(bk * 16 + 11) * RC_CELLS + cl] = sv;
+        sh[(bk * 16 + 12) * RC_CELLS + cl] = se;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[(bk * 16 + 6 + c) * RC_CELLS + cl] = fs[c];
         __syncthreads();
         if (valid && k == 0) {
             double tu = 0.0, tv = 0.0, te = 0.0;
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                tu += redA[(b * 4 + f) * RC_CELLS + cl];
-                tv += redB[(b * 4 + f) * RC_CELLS + cl];
-                te += sh[((b * 4 + f) * 16 + 15) * RC_CELLS + cl];
+                tu += sh[((b * 4 + f) * 16 + 10) * RC_CELLS + cl];
+                tv += sh[((b * 4 + f) * 16 + 11) * RC_CELLS + cl];
+                te += sh[((b * 4 + f) * 16 + 12) * RC_CELLS + cl];
             }
             g.wb[(b * 3 + 0) * N + cell] = tu;
             g.wb[(b * 3 + 1) * N + cell] = tv;
             g.wb[(b * 3 + 2) * N + cell] = te;
-        }
-    }
-    if (valid) {
-        double* V = (b == 0 ? g.xv : g.yv) + k * N + cell;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) V[q * 4 * N] = U[6 + q];
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc += sh[((b * 4 + f) * 16 + 6 + c) * RC_CELLS + cl];
+                VC[c * N] = acc;
+            }
+        }
+        if constexpr (FULL) {   // the reverse mode reads the full volume values
+            if (valid) {
+                double* V = (b == 0 ? g.xv : g.yv) + k * N + cell;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) V[q * 4 * N] = U[6 + q];
+            }
+        }
     }
     if (inter) g.vk[(b * 4 + k) * N + cell] = U[15];
     // CFL wave speed over the limited face traces of interior cells; thread k
@@ -588,9 +629,12 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
             }
         }
     }
-    red_max<8 * RC_CELLS>(&g.red->alpha_key, amax);
+    // the block reductions use moment slots of the exchange: past the
+    // barriers above, no thread reads or writes them any more
+    red_max<8 * RC_CELLS>(&g.red->alpha_key, amax, red);
     red_add<8 * RC_CELLS>(&g.red->pp_cells,
-                          (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull);
+                          (inter && bk == 0 && (th1 < 1.0 || th2 < 1.0)) ? 1ull : 0ull,
+                          reinterpret_cast<unsigned long long*>(red + 8));
 }
 
 // ---------------------------------------------------------------------------
@@ -779,48 +823,54 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
         }
     }
     const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
-    // volume-flux quadratures of interior cells: 2 directions x 9 points over
-    // the cell's 6 threads, 3 points each (thread s: direction s / 3, points
-    // 3 (s % 3) .. 3 (s % 3) + 2); partial sums meet in LDS.  The state at the
-    // thread's points is loaded before the barrier.
+    // volume-flux quadratures of interior cells: the reconstruction kernel
+    // left the Gauss sum of the convective flux and the velocities (and
+    // viscosities) at the points; the viscous part is summed here over the
+    // cell's 6 threads, 2 directions x 9 points, 3 points each (thread s:
+    // direction s / 3, points 3 (s % 3) .. 3 (s % 3) + 2), and the partial
+    // sums meet in LDS.  The point data are loaded before the barrier.
     const bool dy = s >= 3;
     const int q0 = 3 * (s % 3);
-    double Uv[3][4];
+    const double* VC = g.vc + (long long)(dy ? VC_B : 0) * N + cell;
+    double pu[3], pv[3], pm[3];
     if (inter) {
-        const double* V = (dy ? g.yv : g.xv) + cell;
 #pragma unroll
-        for (int qq = 0; qq < 3; ++qq)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) Uv[qq][c] = V[((q0 + qq) * 4 + c) * N];
+        for (int qq = 0; qq < 3; ++qq) {
+            pu[qq] = VC[(4 + q0 + qq) * N];
+            pv[qq] = VC[(13 + q0 + qq) * N];
+            pm[qq] = VarMu ? VC[(22 + q0 + qq) * N] : K.mu_ref;
+        }
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * GR_CELLS + cl] = vo[q];
     __syncthreads();
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     if (inter) {
 #pragma unroll
         for (int qq = 0; qq < 3; ++qq) {
             const int q = q0 + qq;
             const double wq = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
-            double sq[6], f[4];
+            double sq[6], f[3];
 #pragma unroll
             for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
-            flux2_dir<VarMu>(K, Uv[qq], sq, dy, f);
+            visc2_dir(K, pu[qq], pv[qq], pm[qq], sq, dy, f);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] += wq * f[c];
+            for (int c = 0; c < 3; ++c) acc[c] += wq * f[c];
         }
     }
     __syncthreads();   // every read of the gradient values is done
 #pragma unroll
-    for (int c = 0; c < 4; ++c) shv[(s * 4 + c) * GR_CELLS + cl] = acc[c];
+    for (int c = 0; c < 3; ++c) shv[(s * 3 + c) * GR_CELLS + cl] = acc[c];
     __syncthreads();
     if (inter && s < 2) {
+        const double* VS = g.vc + (long long)s * VC_B * N + cell;
+        g.vf[(s * 4) * N + cell] = VS[0];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double t0 = shv[((3 * s + 0) * 4 + c) * GR_CELLS + cl];
-            const double t1 = shv[((3 * s + 1) * 4 + c) * GR_CELLS + cl];
-            const double t2 = shv[((3 * s + 2) * 4 + c) * GR_CELLS + cl];
-            g.vf[(s * 4 + c) * N + cell] = t0 + t1 + t2;
+        for (int c = 0; c < 3; ++c) {
+            const double t0 = shv[((3 * s + 0) * 3 + c) * GR_CELLS + cl];
+            const double t1 = shv[((3 * s + 1) * 3 + c) * GR_CELLS + cl];
+            const double t2 = shv[((3 * s + 2) * 3 + c) * GR_CELLS + cl];
+            g.vf[(s * 4 + 1 + c) * N + cell] = VS[(1 + c) * N] + (t0 + t1 + t2);
         }
     }
 }
@@ -1470,10 +1520,18 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
             if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, true, true>, nr, 256, st, ar, si);
             else tlaunch(tm, KC_RECON, k_recon2<32, true, false>, nr, 256, st, ar, si);
         }
+    } else if (b.full_grad) {
+        // the reverse mode (constant viscosity only) also stores the full
+        // volume values
+        if (b.var_mu) return hipErrorInvalidValue;
+        if (b.tiles.recon == 16) tlaunch(tm, KC_RECON, k_recon2<16, false, false, true>, nr, 128, st, ar, si);
+        else tlaunch(tm, KC_RECON, k_recon2<32, false, false, true>, nr, 256, st, ar, si);
     } else if (b.tiles.recon == 16) {
-        tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, ar, si);
+        if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<16, false, true>, nr, 128, st, ar, si);
+        else tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, ar, si);
     } else {
-        tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, ar, si);
+        if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, false, true>, nr, 256, st, ar, si);
+        else tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, ar, si);
     }
     if (!b.dr) {   // HWENO-GR: weak-derivative moments, then their reconstruction
         tlaunch(tm, KC_RBAR, k_rbar2, b.blocks(KB_RBAR), RB_TX * RB_TY, st, b.arg(KB_RBAR));

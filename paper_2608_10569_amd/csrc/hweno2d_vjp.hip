@@ -14,7 +14,8 @@
 //   k_adj_grad     volume-flux + gradient-reconstruction adjoint (eq. (3.9))
 //   k_adj_rgather  gather of the weak-moment adjoints from the 3x3 stencils
 //   k_adj_wmom     weak-moment adjoint (eqs. (3.6)-(3.8)) -> trace / volume adjoints
-//   k_adj_recon    limiter, back-transform, scalar HWENO, projection, bases
+//   k_adj_recon_a  forward recompute; limiter and back-transform adjoints
+//   k_adj_recon_b  scalar HWENO, eigen-system and projection adjoints
 //   k_adj_ugather  gather of the state adjoint from the 3x3 stencils
 //   k_adj_ghost_*  adjoint of the ghost fill (Remark 4.1)
 
@@ -43,7 +44,8 @@ __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, in
 // Logical index of this block: XCD-aware (each XCD takes a contiguous range
 // of the launch, so neighbouring rows of a stencil share an L2), last first
 // where bit k of W.rev is set (k: 0, 1 face fluxes x, y; 2 gradients; 3
-// weak-moment gather; 4 weak moments; 5 reconstruction; 6 state gather).
+// weak-moment gather; 4 weak moments; 5, 7 the two reconstruction kernels;
+// 6 state gather).
 // The mu partials are stored by it, so their fixed summation order is
 // unchanged.
 __device__ __forceinline__ int lblock(const AdjWs& W, int k) {
@@ -412,21 +414,29 @@ __global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
 }
 
 // ---------------------------------------------------------------------------
-// Characteristic reconstruction adjoint.  Block: 16 cells x 8 threads
-// (b = basis, k = characteristic field / conservative component).
+// Characteristic reconstruction adjoint, in two kernels over the same cells.
+// Block: 16 cells x 8 threads (b = basis, k = characteristic field /
+// conservative component).
+//   k_adj_recon_a: forward recompute (scalar HWENO, back-transform, limiter),
+//     adjoint of the limiter and of the back-transform: the cotangents of
+//     the 16 characteristic outputs of every (cell, b, k), the R-bar rows and
+//     the limiter's share of the cell-average adjoint go to the workspace;
+//   k_adj_recon_b: the scalar HWENO adjoint, the eigen-system adjoint and the
+//     projection adjoint.
+// Split, each kernel keeps fewer values live and less LDS per block than the
+// one kernel before it (256 VGPRs plus spill space, 75 KB of LDS, one wave
+// per SIMD).
 // ---------------------------------------------------------------------------
 constexpr int AC = 16;
 
 __device__ __forceinline__ int pt_index(int b, int o) { return o < 6 ? b * 6 + o : 12 + b * 9 + (o - 6); }
 
-__global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
-                                                      const double* __restrict__ S) {
+__global__ __launch_bounds__(8 * AC) void k_adj_recon_a(Grid2 g, AdjIn A, AdjWs W,
+                                                        const double* __restrict__ S) {
     __shared__ double shc[8 * 16 * AC];   // characteristic point values (b, f, o)
-    __shared__ double shu[8 * 16 * AC];   // conservative point values   (b, c, o)
-    __shared__ double shb[8 * 16 * AC];   // adjoints of conservative values
-    __shared__ double sha[8 * 17 * AC];   // adjoints of the projected inputs (b, k, s)
-    __shared__ double shR[8 * 4 * AC];    // rows of R (b, c, f)
-    __shared__ double shL[8 * 4 * AC];    // rows of L (b, k, c)
+    // conservative point values (b, c, o); once the limiter adjoint has read
+    // them, the adjoints of the conservative values
+    __shared__ double shu[8 * 16 * AC];
     __shared__ double shr[8 * AC];        // reductions (value)
     __shared__ int shi[8 * AC];           // reductions (index)
     __shared__ double shx[8 * AC];        // second reduction value
@@ -452,7 +462,7 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     const long long cell = (long long)j * g.NX + i;
     auto C_ = [&](int bb, int f, int o) -> double& { return shc[((bb * 4 + f) * 16 + o) * AC + cl]; };
     auto U_ = [&](int bb, int c, int o) -> double& { return shu[((bb * 4 + c) * 16 + o) * AC + cl]; };
-    auto B_ = [&](int bb, int c, int o) -> double& { return shb[((bb * 4 + c) * 16 + o) * AC + cl]; };
+    auto B_ = [&](int bb, int c, int o) -> double& { return shu[((bb * 4 + c) * 16 + o) * AC + cl]; };
 
     // ---- forward recompute (as the forward reconstruction kernel) ----
     double ub[4];
@@ -496,11 +506,6 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
         out[15] = b == 0 ? moment_xi(C) : moment_eta(C);
 #pragma unroll
         for (int o = 0; o < 16; ++o) C_(b, k, o) = out[o];
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        shR[(bk * 4 + f) * AC + cl] = Rr[f];
-        shL[(bk * 4 + f) * AC + cl] = Lr[f];
     }
     __syncthreads();
 #pragma unroll
@@ -666,14 +671,71 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
 #pragma unroll
         for (int f = 0; f < 4; ++f) Rb[f] += Ub[o] * C_(b, f, o);
     }
+    // column k of R (eigenvector of field k), formed from the cell average
+    double Rk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double Lt[4], Rt[4];
+        eig2_rows(K, ub, b, c, Lt, Rt);
+        Rk[c] = Rt[k];
+    }
     double cb[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc += shR[((b * 4 + c) * 4 + k) * AC + cl] * B_(b, c, o);
+        for (int c = 0; c < 4; ++c) acc += Rk[c] * B_(b, c, o);
         cb[o] = acc;
     }
+    // ---- to the workspace: cotangents of the characteristic outputs, the
+    // R-bar row, and (thread b = 0, k = c) the limiter's cell-average part
+    // of component c ----
+    if (valid) {
+#pragma unroll
+        for (int o = 0; o < 16; ++o) W.rcb[(bk * 16 + o) * N + cell] = cb[o];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) W.rrb[(bk * 4 + f) * N + cell] = Rb[f];
+        if (b == 0)
+            W.rlim[k * N + cell] = shp[(0 * 4 + k) * AC + cl] + shp[(1 * 4 + k) * AC + cl] +
+                                   shp[(13 + k) * AC + cl];
+    }
+}
+
+// Scalar HWENO, eigen-system and projection adjoints of (cell, b, k), from
+// the cotangents k_adj_recon_a left in the workspace.
+__global__ __launch_bounds__(8 * AC, 2) void k_adj_recon_b(Grid2 g, AdjWs W,
+                                                        const double* __restrict__ S) {
+    __shared__ double sha[8 * 17 * AC];   // adjoints of the projected inputs (b, k, s)
+    __shared__ double shL[8 * 4 * AC];    // rows of L (b, k, c)
+    __shared__ double shq[8 * 4 * AC];    // eigen-system part of the cell-average adjoint
+    const Consts& K = g.K;
+    const int tid = threadIdx.x;
+    const int cl = tid % AC;
+    const int bk = tid / AC;
+    const int b = bk >> 2, k = bk & 3;
+    const int wc = g.NX - 2;
+    const long long nreg = (long long)wc * (g.NY - 2);
+    const long long cid = (long long)lblock(W, 7) * AC + cl;
+    const bool valid = cid < nreg;
+    int j = 1, i = 1;
+    if (valid) {
+        j = 1 + (int)(cid / wc);
+        i = 1 + (int)(cid % wc);
+    }
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    double ub[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ub[c] = S[c * N + cell];
+    double Lr[4], Rr[4];
+    eig2_rows(K, ub, b, k, Lr, Rr);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) shL[(bk * 4 + f) * AC + cl] = Lr[f];
+    double cb[16], Rb[4];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) cb[o] = valid ? W.rcb[(bk * 16 + o) * N + cell] : 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) Rb[f] = valid ? W.rrb[(bk * 4 + f) * N + cell] : 0.0;
     // ---- scalar reconstruction adjoint ----
     double Cb[15];
 #pragma unroll
@@ -685,10 +747,28 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     else moment_eta_T(cb[15], Cb);
     double ab[17];
     {
-        double Lk[4], a[17];
+        double a[17];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Lk[c] = shL[(bk * 4 + c) * AC + cl];
-        project(Lk, a);
+        for (int s = 0; s < 9; ++s) {
+            const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc += Lr[c] * S[c * N + nb];
+            a[s] = acc;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int s = 2 * e + 1;
+            const long long nb = cell + (long long)(s / 3 - 1) * g.NX + (s % 3 - 1);
+            double ax = 0.0, ay = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ax += Lr[c] * S[(4 + c) * N + nb];
+                ay += Lr[c] * S[(8 + c) * N + nb];
+            }
+            a[9 + e] = ax;
+            a[13 + e] = ay;
+        }
         hweno2d_vjp(a, K, Cb, ab);
     }
 #pragma unroll
@@ -712,10 +792,9 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
     double ubp[4] = {0.0, 0.0, 0.0, 0.0};
     if (b == 0) adj::eig2_vjp_0(K, ub, k, Lb, Rb, ubp);
     else adj::eig2_vjp_1(K, ub, k, Lb, Rb, ubp);
-    __syncthreads();
     // cell-average adjoint of this thread: eigen part (4 comps) -> LDS for the owner threads
 #pragma unroll
-    for (int c = 0; c < 4; ++c) shb[((b * 4 + k) * 16 + c) * AC + cl] = ubp[c];
+    for (int c = 0; c < 4; ++c) shq[((b * 4 + k) * 4 + c) * AC + cl] = ubp[c];
     __syncthreads();
     // ---- projection adjoint, thread (b, c): sum_k L[k][c] ab_k[s] ----
     if (valid) {
@@ -729,12 +808,9 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon(Grid2 g, AdjIn A, AdjWs W,
             if (s == 4) {
                 // own cell average: eigenvector dependence (both fields' rows of this basis)
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc += shb[((b * 4 + f) * 16 + c) * AC + cl];
+                for (int f = 0; f < 4; ++f) acc += shq[((b * 4 + f) * 4 + c) * AC + cl];
                 // limiter: per-component pass-through of theta and the cell-level part
-                if (b == 0) {
-                    acc += shp[(0 * 4 + c) * AC + cl] + shp[(1 * 4 + c) * AC + cl];
-                    acc += shp[(13 + c) * AC + cl];
-                }
+                if (b == 0) acc += W.rlim[c * N + cell];
             }
             UC[(s * 4 + c) * N + cell] = acc;
         }
@@ -890,7 +966,9 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     k_adj_grad<<<bg, 6 * AG, 0, st>>>(g, A, W);
     k_adj_rgather<<<nb2((long long)(g.NX - 4) * (g.NY - 4), 256), 256, 0, st>>>(g, W);
     k_adj_wmom<<<nb2((long long)(g.NX - 2) * (g.NY - 2), WM_CELLS), 6 * WM_CELLS, 0, st>>>(g, W);
-    k_adj_recon<<<nb2((long long)(g.NX - 2) * (g.NY - 2), AC), 8 * AC, 0, st>>>(g, A, W, S);
+    const unsigned brec = nb2((long long)(g.NX - 2) * (g.NY - 2), AC);
+    k_adj_recon_a<<<brec, 8 * AC, 0, st>>>(g, A, W, S);
+    k_adj_recon_b<<<brec, 8 * AC, 0, st>>>(g, W, S);
     k_adj_ugather<<<nb2(g.ncell, 256), 256, 0, st>>>(g, W);
     k_adj_ghost_y<<<nb2((long long)g.ny * g.NX, 256), 256, 0, st>>>(g, W);
     k_adj_ghost_x<<<nb2((long long)g.ny * g.nx, 256), 256, 0, st>>>(g, W);

@@ -224,13 +224,16 @@ size_t layout(hweno_ctx* c, char* base) {
         g.S[3] = c->batch ? nullptr : take(12 * m);   // reverse-mode recomputation
         g.xf = take(24 * m);
         g.yf = take(24 * m);
-        g.xv = take(36 * m);
-        g.yv = take(36 * m);
+        // the full volume values and the six face gradients are the reverse
+        // mode's, which batches never run
+        g.xv = c->batch ? nullptr : take(36 * m);
+        g.yv = c->batch ? nullptr : take(36 * m);
+        g.vc = take(2 * hw::VC_B * m);
         g.wb = take(6 * m);
         g.vk = take(8 * m);
         g.vn = take(8 * m);
         g.rb = take(18 * m);
-        g.gf = take((c->batch ? 36 : 72) * m);   // batches never need the reverse mode's six
+        g.gf = take((c->batch ? 36 : 72) * m);
         g.vf = take(8 * m);
         g.fx = take(8 * m);
         g.fy = take(8 * m);
@@ -252,6 +255,9 @@ size_t layout(hweno_ctx* c, char* base) {
         A.rbc = take(102 * m);
         A.rbb = take(18 * m);
         A.uc = take(136 * m);
+        A.rcb = take(128 * m);
+        A.rrb = take(32 * m);
+        A.rlim = take(4 * m);
         A.ubb = take(12 * m);
         A.mupart = take((size_t)hw::adj_mu_partials2(c->hg[0]));
         c->mu_dev = take(1);
@@ -274,6 +280,7 @@ size_t layout(hweno_ctx* c, char* base) {
                 st.yf = take(24 * m);
                 st.xv = take(36 * m);
                 st.yv = take(36 * m);
+                st.vc = take(2 * hw::VC_B * m);
                 st.wb = take(6 * m);
                 st.vk = take(8 * m);
                 st.rb = take(18 * m);
@@ -367,6 +374,7 @@ hweno_status upload_grids(hweno_ctx* c) {
             d[k].yf = st.yf;
             d[k].xv = st.xv;
             d[k].yv = st.yv;
+            d[k].vc = st.vc;
             d[k].wb = st.wb;
             d[k].vk = st.vk;
             d[k].rb = st.rb;
@@ -907,8 +915,8 @@ size_t static_layout2(hw::Grid2& g, char* base, hw::Grid2** dgrid, hw::InstState
     for (int k = 0; k < 4; ++k) g.S[k] = S;
     g.xf = take(24 * m);
     g.yf = take(24 * m);
-    g.xv = take(36 * m);
-    g.yv = take(36 * m);
+    g.xv = g.yv = nullptr;   // the full volume values are the reverse mode's
+    g.vc = take(2 * hw::VC_B * m);
     g.wb = take(6 * m);
     g.vk = take(8 * m);
     g.vn = take(8 * m);

@@ -488,6 +488,38 @@ __device__ __forceinline__ void flux2_dir(const Consts& K, const double* U, cons
     f[3] = fma(E + p, un, -fma(tnx, u, fma(tny, v, kq * qd)));
 }
 
+// The two parts of flux2_dir at a volume point, for a volume quadrature
+// split between two kernels: the convective flux (and the point's
+// viscosity) from the reconstructed state, given u = m / rho and v = n / rho
+// as flux2_dir forms them; and the viscous part of components 1..3 from the
+// velocities, that viscosity and the six gradients s.  Their sum is
+// flux2_dir's flux up to rounding.
+template <bool VarMu>
+__device__ __forceinline__ void conv2_dir(const Consts& K, double r, double m, double n, double E,
+                                          double u, double v, bool dy, double* f, double& mu) {
+#pragma clang fp contract(off)
+    const double p = K.gm1 * fma(-0.5, fma(m, u, n * v), E);
+    mu = viscosity<VarMu>(K, r, p);
+    const double un = dy ? v : u;
+    f[0] = dy ? n : m;
+    f[1] = fma(m, un, (dy ? 0.0 : p));
+    f[2] = fma(n, un, (dy ? p : 0.0));
+    f[3] = (E + p) * un;
+}
+
+__device__ __forceinline__ void visc2_dir(const Consts& K, double u, double v, double mu,
+                                          const double* s, bool dy, double* f) {
+#pragma clang fp contract(off)
+    const Stress t = stresses(mu, s);
+    const double kq = K.gPr * mu;
+    const double tnx = dy ? t.xy : t.xx;
+    const double tny = dy ? t.yy : t.xy;
+    const double qd = dy ? s[5] : s[4];
+    f[0] = -tnx;
+    f[1] = -tny;
+    f[2] = -fma(tnx, u, fma(tny, v, kq * qd));
+}
+
 // PP wave-speed bound of eq. (3.3) in direction d, no smaller than |u_d| + c.
 template <int d, bool VarMu = true>
 __device__ __forceinline__ double speed2(const Consts& K, const double* U, const double* s) {

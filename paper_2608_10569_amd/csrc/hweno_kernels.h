@@ -63,6 +63,10 @@ struct InstState {
     int status;               // 0, or the hweno_status that stopped the instance
 };
 
+// Compact volume data per basis: the convective flux sum and the point
+// velocities and viscosities the gradient kernel's viscous volume flux needs.
+constexpr int VC_B = 31;
+
 // Pointers and sizes of one 2D grid's workspace (all arrays SoA over the
 // ghosted grid NX x NY, component-major: a[q * ncell + j * NX + i]).
 struct Grid2 {
@@ -74,8 +78,12 @@ struct Grid2 {
     HW_GLOBAL InstState* st;
     gdouble* xf;   // 24: x-face traces (p*4 + c), p 0..2 left face, 3..5 right face
     gdouble* yf;   // 24: y-face traces, p 0..2 bottom face, 3..5 top face
-    gdouble* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g
-    gdouble* yv;   // 36: y-basis volume values
+    gdouble* xv;   // 36: x-basis volume values (q*4 + c), q = 3*h + g; written only
+                   // for the reverse mode (full_grad), which reads them
+    gdouble* yv;   // 36: y-basis volume values (likewise)
+    gdouble* vc;   // 2 * VC_B: per basis b (x for f, y for g), at b * VC_B: the
+                   // Gauss sum of the convective flux (4), then u, v and mu at
+                   // the nine volume points (9 each; mu only with mu(T))
     gdouble* wb;   // 6:  wbar of (u, v, e) from x-basis, then from y-basis
     gdouble* vk;   // 8:  modified moments of the current input (hat-v 0..3, hat-w 4..7)
     gdouble* vn;   // 8:  modified moments of U^n (kept for stages 2 and 3)

@@ -25,6 +25,9 @@ struct AdjWs {
     double* rbc;        // 102 / 10: weak-moment contributions to the 3x3 stencil
     double* rbb;        // 18 / 4: gathered weak-moment adjoints
     double* uc;         // 136 / 15: state contributions to the stencil
+    double* rcb;        // 128: cotangents of the 16 characteristic outputs per (b, k)
+    double* rrb;        // 32: R-bar rows per (b, k)
+    double* rlim;       // 4: the limiter's share of the cell-average adjoint
     double* ubb;        // 12 / 6: gathered state adjoint (ghosted)
     double* mupart;     // block partials of the mu adjoint
     int mu_off1, mu_off2;

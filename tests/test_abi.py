@@ -172,13 +172,13 @@ def test_host_allocation_failure_is_a_status():
 
 def test_noalloc_residual_host_checks_without_device():
     """The allocation-free residual refuses, before touching a device, a grid
-    whose residual does not fit its static buffer (1856 bytes per ghosted
-    cell in 2D), a batch context and NULL arrays."""
+    whose residual does not fit its static buffer (1776 bytes per ghosted
+    cell in 2D: up to 380 x 380 cells), a batch context and NULL arrays."""
     L = hweno.lib()
     dummy = ctypes.c_void_p(4096)     # never dereferenced: the checks come first
-    big = hweno.Grid(2, 400, 400, 0.0, 1.0, 0.0, 1.0)
+    big = hweno.Grid(2, 381, 381, 0.0, 1.0, 0.0, 1.0)
     fits = hweno.Grid(2, 300, 300, 0.0, 1.0, 0.0, 1.0)
-    assert 1856 * 408 * 408 > hweno.NOALLOC_BYTES > 1856 * 308 * 308
+    assert 1776 * 389 * 389 > hweno.NOALLOC_BYTES > 1776 * 388 * 388 + 4096
     ph = hweno.PhysicsC(1.4, 0.72, 0.01, 0.0, 1.0)
     b = hweno.Bcs()
     o = hweno.default_options()

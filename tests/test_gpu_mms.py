@@ -1,6 +1,7 @@
 """Manufactured solutions on the GPU (Examples 5.1 and 5.2): the source hook
 against the oracle step by step, and the accuracy tables at the paper's mesh
-sizes run through the HIP path.  Sources and exact moments come from the
+sizes run through the HIP path, for HWENO-GR and its comparison scheme
+HWENO-DR.  Sources and exact moments come from the
 oracle's symbolic fields (6-point Gauss moments); the GPU adds them in every
 stage through hweno_rk_step_source."""
 
@@ -174,3 +175,57 @@ def test_table_5_2_on_gpu():
     for a, b in ((80, 160), (160, 280)):
         for k in range(2):
             assert _rate(res[a][k], res[b][k], a, b) > 4.5, (a, b, k)
+
+
+def test_table_5_1_dr_on_gpu():
+    """The comparison scheme HWENO-DR (eq. (2.5)) on Example 5.1 from N = 80
+    to 280: density errors within 1.5x of Table 5.1's DR column (measured
+    1.07-1.18x), rates above 4 between consecutive meshes (printed 4.2-5.0),
+    and GR more accurate than DR on every mesh, as printed."""
+    tab = load_table('table_5_1_dr.txt')
+    res = {}
+    for n in (80, 120, 160, 200, 240, 280):
+        sc = Scheme1D(n, 0.0, 1.0, Physics(**PH), Options(cfl=CFL))
+        m = MMS1D(sc)
+        src = PolySource(m)
+        for gm in ('DR', 'GR'):
+            s = hweno.Solver(n, extent=(0.0, 1.0), gradients=gm, **PH)
+            U, t, steps = gpu_mms_run(s, to_dev(m.exact(0.0)), src, 1.0 / n, T_END)
+            err = U.cpu().numpy()[0, 0] - m.exact(t)[0, 0]
+            res[gm, n] = (np.abs(err).max(), np.abs(err).mean())
+        print('1D DR N=%d: %d steps, Linf %.3e (paper %.3e)  L1 %.3e (paper %.3e); GR %.3e %.3e'
+              % (n, steps, res['DR', n][0], tab[n][0], res['DR', n][1], tab[n][1],
+                 *res['GR', n]))
+    ns = sorted(n for gm, n in res if gm == 'DR')
+    for n in ns:
+        for k in range(2):
+            assert tab[n][k] / 1.5 < res['DR', n][k] < 1.5 * tab[n][k], (n, k, res['DR', n])
+            assert res['GR', n][k] < res['DR', n][k]
+    for a, b in zip(ns, ns[1:]):
+        for k in range(2):
+            assert _rate(res['DR', a][k], res['DR', b][k], a, b) > 4.0, (a, b, k)
+
+
+def test_table_5_2_dr_on_gpu():
+    """HWENO-DR (eq. (3.5)) on Example 5.2 at 200^2 and 280^2: density errors
+    within 1.5x of Table 5.2's DR column (measured 1.00-1.07x), rate above 4
+    (printed 4.5).  On coarser meshes the printed DR errors carry a large
+    pre-asymptotic part that ours lacks (40^2: printed 4.1e-4, ours 6e-6), so
+    there only 'not worse than printed' is asserted (at 80^2)."""
+    tab = load_table('table_5_2_dr.txt')
+    res = {}
+    for n in (80, 200, 280):
+        sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(**PH), Options(cfl=CFL))
+        m = MMS2D(sc)
+        s = hweno.Solver(n, n, gradients='DR', **PH)
+        src = PolySource(m)
+        U, t, steps = gpu_mms_run(s, to_dev(m.exact(0.0)), src, 1.0 / n, T_END)
+        err = U.cpu().numpy()[0, 0] - m.exact(t)[0, 0]
+        res[n] = (np.abs(err).max(), np.abs(err).mean())
+        print('2D DR N=%d: %d steps, Linf %.3e (paper %.3e)  L1 %.3e (paper %.3e)'
+              % (n, steps, res[n][0], tab[n][0], res[n][1], tab[n][1]))
+    for k in range(2):
+        assert res[80][k] < tab[80][k]
+        for n in (200, 280):
+            assert tab[n][k] / 1.5 < res[n][k] < 1.5 * tab[n][k], (n, k, res[n], tab[n])
+        assert _rate(res[200][k], res[280][k], 200, 280) > 4.0, k
