@@ -54,26 +54,27 @@ PEAK_HBM_GBS = 8000.0
 #   recon: 8 scalar reconstructions (projection 136, quartic candidate 138,
 #          smoothness indicator 87, weights 45, combination 35, 15 point values
 #          135, moment 5) = 4648; characteristic bases 75; back-transform 1024;
-#          limiter on 30 points 420; wbar 240; wave speed 300.
-#   grad:  6 scalar reconstructions at 21 points (495 each) = 2970; volume
-#          fluxes at 18 points 792.
+#          limiter on 30 points 420; wbar 240; wave speed 300; convective
+#          volume fluxes and their Gauss sums at 18 points 342.
+#   grad:  6 scalar reconstructions at 21 points (495 each) = 2970; viscous
+#          volume fluxes at 18 points and the sums 458.
 #   rbar:  interface averages, face moments, 18 weak moments.
 #   flux:  per face 6 point fluxes and PP speed bounds, 12 LF combinations.
 #   update: assembly of 12 residual entries and the stage combination.
 #   fluxup: the face fluxes formed inside the update kernel, per cell: the
 #          fluxes of two faces and the update (faces on tile edges, formed
 #          twice, counted once).
-FLOPS = {'recon': 6707, 'grad': 3762, 'rbar': 414, 'flux': 560, 'update': 400,
+FLOPS = {'recon': 7049, 'grad': 3428, 'rbar': 414, 'flux': 560, 'update': 400,
          'fluxup': 2 * 560 + 400}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the factors a 1 GiB device copy gives in the same process
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
 # and for the kernels as they are now: e.g. recon with 32-cell tiles reads
-# 53.2 MB and writes 553.0 MB per launch.
-TRAFFIC_BYTES = {('recon', 16): 606967035, ('recon', 32): 606181404,
-                 ('grad', 32): 737965288, ('grad', 64): 715948182,
-                 ('rbar', None): 318119878, ('update', None): 227934447,
-                 ('fluxup', None): 748826092}
+# 53.0 MB and writes 436.8 MB per launch.
+TRAFFIC_BYTES = {('recon', 16): 485793001, ('recon', 32): 489850960,
+                 ('grad', 32): 452673258, ('grad', 64): 431288905,
+                 ('rbar', None): 317537487, ('update', None): 228200086,
+                 ('fluxup', None): 618917909}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).
@@ -494,9 +495,16 @@ def main():
                      'traffic_gbs': traffic / avg_s / 1e9 if traffic else None,
                      'flops_per_unit': FLOPS[dom], 'units_per_launch': units_per_launch(dom),
                      'us_per_launch': avg_s * 1e6, 'launches_timed': n},
-        'hbm_frac_algorithmic': value * ALGO_BYTES_PER_CELL_STAGE / (PEAK_HBM_GBS * 1e9),
-        'hbm_pipeline': pipeline_hbm(tiles, value),
-        'path_fp64_tflops_algorithmic': value * path_flops / 1e12,
+        # the whole residual pipeline (every kernel of a stage) against both
+        # roofs: its algorithmic FP64 work and HBM bytes at the measured rate,
+        # and the HBM bytes the counters measured for its kernels
+        'path': {'fp64_tflops_algorithmic': value * path_flops / 1e12,
+                 'fp64_frac': value * path_flops / 1e12 / PEAK_FP64_TFLOPS,
+                 'flops_per_cell_stage': path_flops,
+                 'hbm_bytes_per_cell_stage_algorithmic': ALGO_BYTES_PER_CELL_STAGE,
+                 'hbm_frac_algorithmic':
+                     value * ALGO_BYTES_PER_CELL_STAGE / (PEAK_HBM_GBS * 1e9),
+                 'hbm_measured': pipeline_hbm(tiles, value)},
         'kernels': kern,
         'kernels_note': 'every class timed over 5 untimed steps before the timed region',
     }
