@@ -467,6 +467,15 @@ def main():
     ms, n = s.timing()[dom]
     s.set_timing(False)
     _, t_end = s.get_state()
+    # four more runs of the same length, untimed by events, for the spread
+    reps = [1e3 * el / args.steps]
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            s.rk_step(0.0)
+        torch.cuda.synchronize()
+        reps.append(1e3 * (time.perf_counter() - t1) / args.steps)
 
     cell_stages = args.steps * 3 * NX * NY
     value = cell_stages / el
@@ -507,6 +516,12 @@ def main():
                  'hbm_measured': pipeline_hbm(tiles, value)},
         'kernels': kern,
         'kernels_note': 'every class timed over 5 untimed steps before the timed region',
+        'kernel_only_ms_per_step': sum(v[0] for v in tm.values()) / 5.0,
+        'repeats_ms_per_step': reps,
+        'median_ms_per_step': sorted(reps)[len(reps) // 2],
+        'repeats_note': 'the timed run first, then four more runs of the same number of steps '
+                        'continuing from its state',
+
     }
     s.close()
     del s

@@ -374,7 +374,7 @@ typedef struct hweno_tiles {
 } hweno_tiles;
 
 /* 2D contexts (single grid or batch).  Results do not depend on the tiles.
- * A new context uses recon 32, grad 64, flux 0, order 0, xcd 1. */
+ * A new context uses recon 32, grad 32, flux 0, order 0, xcd 1. */
 HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* ctx, hweno_tiles* out);
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* ctx, const hweno_tiles* tiles);
 

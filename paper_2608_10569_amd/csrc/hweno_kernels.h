@@ -216,7 +216,7 @@ struct Batch {
 // Work per block of the tunable kernels (cells, cells, faces).
 struct Tiles {
     int recon = 32;   // 16 or 32
-    int grad = 64;    // 32 or 64
+    int grad = 32;    // 32 or 64
     int flux = 0;     // 64 or 128; 0: face fluxes formed inside the update kernel
     int xcd = 1;      // 1: each XCD takes a contiguous range of a launch's blocks
 };

@@ -106,7 +106,7 @@ def test_tile_defaults_and_validation_without_device():
     t = hweno.TilesC()
     assert L.hweno_get_tiles(h, ctypes.byref(t)) == 0
     base = t.as_dict()
-    assert base == dict(recon=32, grad=64, flux=0, order=0, xcd=1)
+    assert base == dict(recon=32, grad=32, flux=0, order=0, xcd=1)
     for change, code in ((dict(flux=64), 0), (dict(flux=128), 0), (dict(recon=16, grad=32), 0),
                          (dict(order=1, xcd=0), 0), (dict(recon=64), 1), (dict(grad=16), 1),
                          (dict(flux=32), 1), (dict(order=2), 1), (dict(xcd=2), 1)):
