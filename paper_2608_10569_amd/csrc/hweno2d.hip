@@ -1520,12 +1520,14 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
             if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, true, true>, nr, 256, st, ar, si);
             else tlaunch(tm, KC_RECON, k_recon2<32, true, false>, nr, 256, st, ar, si);
         }
-    } else if (b.full_grad) {
-        // the reverse mode (constant viscosity only) also stores the full
-        // volume values
-        if (b.var_mu) return hipErrorInvalidValue;
-        if (b.tiles.recon == 16) tlaunch(tm, KC_RECON, k_recon2<16, false, false, true>, nr, 128, st, ar, si);
-        else tlaunch(tm, KC_RECON, k_recon2<32, false, false, true>, nr, 256, st, ar, si);
+    } else if (b.full_grad) {   // the reverse mode also stores the full volume values
+        if (b.tiles.recon == 16) {
+            if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<16, false, true, true>, nr, 128, st, ar, si);
+            else tlaunch(tm, KC_RECON, k_recon2<16, false, false, true>, nr, 128, st, ar, si);
+        } else {
+            if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, false, true, true>, nr, 256, st, ar, si);
+            else tlaunch(tm, KC_RECON, k_recon2<32, false, false, true>, nr, 256, st, ar, si);
+        }
     } else if (b.tiles.recon == 16) {
         if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<16, false, true>, nr, 128, st, ar, si);
         else tlaunch(tm, KC_RECON, k_recon2<16>, nr, 128, st, ar, si);

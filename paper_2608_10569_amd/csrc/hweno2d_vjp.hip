@@ -72,7 +72,7 @@ __device__ __forceinline__ void mu_partial(double v, double* part, int lb) {
 // ---------------------------------------------------------------------------
 constexpr int AF = 64;
 
-template <int d>
+template <int d, bool VarMu>
 __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) {
     __shared__ double shs[2][3 * AF];     // speeds of the two sides
     __shared__ double shb[3 * AF];        // beta-bar partial sums
@@ -150,7 +150,13 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
     double Umb[4] = {0.0, 0.0, 0.0, 0.0}, Upb[4] = {0.0, 0.0, 0.0, 0.0};
     double smb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, spb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mub = 0.0, betab = 0.0;
-    const double mu = K.mu_ref;
+    // the viscosity at the point on each side: mu_ref, or mu(T) of that
+    // side's state, whose adjoint (mbm, mbp) is chained through T below
+    const double mum = VarMu ? point_mu(K, Um) : K.mu_ref;
+    const double mup = VarMu ? point_mu(K, Up) : K.mu_ref;
+    double mubm = 0.0, mubp = 0.0;
+    double& mbm = VarMu ? mubm : mub;
+    double& mbp = VarMu ? mubp : mub;
     if (valid) {
         double hf[4];
 #pragma unroll
@@ -160,15 +166,18 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
             Upb[c] -= 0.5 * beta * fb[c];
             betab -= 0.5 * fb[c] * (Up[c] - Um[c]);
         }
-        flux2_vjp<d>(K, Um, sm, mu, hf, Umb, smb, mub);
-        flux2_vjp<d>(K, Up, sp, mu, hf, Upb, spb, mub);
+        flux2_vjp<d>(K, Um, sm, mum, hf, Umb, smb, mbm);
+        flux2_vjp<d>(K, Up, sp, mup, hf, Upb, spb, mbp);
     }
     shb[threadIdx.x] = betab;
     __syncthreads();
     if (valid && arg % 3 == G) {
         const double bsum = shb[fl] + shb[AF + fl] + shb[2 * AF + fl];
-        if (arg < 3) speed2_vjp<d>(K, Um, sm, mu, bsum, Umb, smb, mub);
-        else speed2_vjp<d>(K, Up, sp, mu, bsum, Upb, spb, mub);
+        if (arg < 3) speed2_vjp<d>(K, Um, sm, mum, bsum, Umb, smb, mbm);
+        else speed2_vjp<d>(K, Up, sp, mup, bsum, Upb, spb, mbp);
+    }
+    if constexpr (VarMu) {
+        if (valid) mub = mubm * mu_T_vjp(K, Um, mubm, Umb) + mubp * mu_T_vjp(K, Up, mubp, Upb);
     }
     if (valid) {
         double* XB = d == 0 ? W.xfb : W.yfb;
@@ -192,6 +201,7 @@ __global__ __launch_bounds__(3 * AF) void k_adj_flux(Grid2 g, AdjIn A, AdjWs W) 
 // ---------------------------------------------------------------------------
 constexpr int AG = 32;
 
+template <bool VarMu>
 __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) {
     __shared__ double shv[6 * 9 * AG];       // forward volume gradients
     __shared__ double shvb[2][6 * 9 * AG];   // their adjoints from f and from g
@@ -256,8 +266,12 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
             }
 #pragma unroll
             for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * AG + cl];
-            if (s == 0) flux2_vjp<0>(K, Uq, sq, K.mu_ref, f, Uqb, sqb, mub);
-            else flux2_vjp<1>(K, Uq, sq, K.mu_ref, f, Uqb, sqb, mub);
+            const double muq = VarMu ? point_mu(K, Uq) : K.mu_ref;
+            double mubq = 0.0;
+            double& mb = VarMu ? mubq : mub;
+            if (s == 0) flux2_vjp<0>(K, Uq, sq, muq, f, Uqb, sqb, mb);
+            else flux2_vjp<1>(K, Uq, sq, muq, f, Uqb, sqb, mb);
+            if constexpr (VarMu) mub += mubq * mu_T_vjp(K, Uq, mubq, Uqb);
 #pragma unroll
             for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] = Uqb[c];
 #pragma unroll
@@ -961,9 +975,15 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     // weak-moment adjoint before it (1.5 % of a step adjoint on 256^2; the
     // other kernels showed no gain)
     W.rev = 1u << 5;
-    k_adj_flux<0><<<bx, 3 * AF, 0, st>>>(g, A, W);
-    k_adj_flux<1><<<by, 3 * AF, 0, st>>>(g, A, W);
-    k_adj_grad<<<bg, 6 * AG, 0, st>>>(g, A, W);
+    if (g.K.mu_exp != 0.0) {   // mu(T): the viscosity's dependence on the state too
+        k_adj_flux<0, true><<<bx, 3 * AF, 0, st>>>(g, A, W);
+        k_adj_flux<1, true><<<by, 3 * AF, 0, st>>>(g, A, W);
+        k_adj_grad<true><<<bg, 6 * AG, 0, st>>>(g, A, W);
+    } else {
+        k_adj_flux<0, false><<<bx, 3 * AF, 0, st>>>(g, A, W);
+        k_adj_flux<1, false><<<by, 3 * AF, 0, st>>>(g, A, W);
+        k_adj_grad<false><<<bg, 6 * AG, 0, st>>>(g, A, W);
+    }
     k_adj_rgather<<<nb2((long long)(g.NX - 4) * (g.NY - 4), 256), 256, 0, st>>>(g, W);
     k_adj_wmom<<<nb2((long long)(g.NX - 2) * (g.NY - 2), WM_CELLS), 6 * WM_CELLS, 0, st>>>(g, W);
     const unsigned brec = nb2((long long)(g.NX - 2) * (g.NY - 2), AC);

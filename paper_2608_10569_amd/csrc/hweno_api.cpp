@@ -1175,7 +1175,7 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
                                           const double* Vbar, double* Ubar, double* mu_bar) {
     GUARD_BEGIN
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty() ||
+    if (c->dim() != 2 || !c->solid_host.empty() ||
         c->i0().opt.gradients != 0)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
@@ -1207,7 +1207,7 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     GUARD_BEGIN
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
-    if (c->dim() != 2 || c->i0().phys.mu_exp != 0.0 || !c->solid_host.empty() ||
+    if (c->dim() != 2 || !c->solid_host.empty() ||
         c->i0().opt.gradients != 0)
         return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;

@@ -71,6 +71,37 @@ __device__ __forceinline__ void speed2_vjp(const Consts& K, const double* U, con
     }
 }
 
+// mu(T) = mu_ref (T / T_ref)^mu_exp, T = p / rho (eq. (3.1) with the power
+// law), at a point as the forward fluxes form it.
+__device__ __forceinline__ double point_mu(const Consts& K, const double* U) {
+#pragma clang fp contract(off)
+    const double r = U[0], m = U[1], n = U[2], E = U[3];
+    const double ir = rcp(r);
+    const double u = m * ir, v = n * ir;
+    const double p = K.gm1 * fma(-0.5, fma(m, u, n * v), E);
+    return viscosity<true>(K, r, p);
+}
+
+// Adjoint of the dependence of mu(T) on the state at a point: Ub += mub *
+// dmu/dU with dmu/dT = mu_exp mu / T and T = (gamma - 1)(E / rho - |u|^2 / 2);
+// returns dmu/dmu_ref = (T / T_ref)^mu_exp, which carries mub into the
+// adjoint of mu_ref.
+__device__ __forceinline__ double mu_T_vjp(const Consts& K, const double* U, double mub,
+                                           double* Ub) {
+    if (K.mu_exp == 0.0) return 1.0;
+    const double r = U[0], ir = 1.0 / r;
+    const double u = U[1] * ir, v = U[2] * ir;
+    const double q2 = u * u + v * v;
+    const double T = K.gm1 * (U[3] * ir - 0.5 * q2);
+    const double f = pow(T / K.T_ref, K.mu_exp);
+    const double gT = mub * K.mu_ref * f * K.mu_exp / T;   // mub * dmu/dT
+    Ub[0] += gT * (0.5 * K.gm1 * q2 - T) * ir;
+    Ub[1] -= gT * K.gm1 * u * ir;
+    Ub[2] -= gT * K.gm1 * v * ir;
+    Ub[3] += gT * K.gm1 * ir;
+    return f;
+}
+
 long long adj_mu_partials2(const Grid2& g);
 // mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar)
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,

@@ -34,21 +34,21 @@ def rule_dt(s, U):
     return s.rk_step(0.0)['dt']
 
 
-def step_dot_test(U, bc, extent, mu, seed, dt=None):
+def step_dot_test(U, bc, extent, mu, seed, dt=None, mu_exp=0.0):
     ny, nx = U.shape[2:]
-    s = hweno.Solver(nx, ny, extent=extent, bc=bc, mu_ref=mu)
+    s = hweno.Solver(nx, ny, extent=extent, bc=bc, mu_ref=mu, mu_exp=mu_exp)
     dt = dt or rule_dt(s, U)
     rng = np.random.default_rng([2608, 77, seed])
     scale = np.abs(U).reshape(3, 4, -1).max(axis=-1)[..., None, None]
     dU = rng.standard_normal(U.shape) * scale
     Wb = rng.standard_normal(U.shape)
-    sc = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu), Options(), bc=bc)
+    sc = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu, mu_exp=mu_exp), Options(), bc=bc)
     U3c, used, info = rk3_step(sc, U + 1j * H * dU, 0.0, dt)
     assert used == dt and info['restarts'] == 0
     lhs = np.sum(U3c.imag / H * Wb)
     Ub, mub = s.rk_step_vjp(to_dev(U), dt, to_dev(Wb))
     rhs = np.sum(dU * Ub.cpu().numpy())
-    sm = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu + 1j * H), Options(), bc=bc)
+    sm = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu + 1j * H, mu_exp=mu_exp), Options(), bc=bc)
     U3m, _, _ = rk3_step(sm, U.astype(complex), 0.0, dt)
     mref = np.sum(U3m.imag / H * Wb)
     return lhs, rhs, mref, mub, info
@@ -68,6 +68,16 @@ def test_step_vjp_walls():
     lhs, rhs, mref, mub, _ = step_dot_test(U, ('noslip', 'noslip', 'noslip', 'slip'),
                                            (0.0, 1.0, 0.0, 0.5), 1 / 200, 1)
     print('step walls: rel %.2e mu rel %.2e' % (rel(lhs, rhs), rel(mref, mub)))
+    assert rel(lhs, rhs) < 1e-10
+    assert rel(mref, mub) < 1e-10
+
+
+def test_step_vjp_mu_T():
+    """One RK step with mu = mu_ref (T / T_ref)^0.76 and walls."""
+    U = workloads.random_smooth_2d(12, 10, seed=24, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+    lhs, rhs, mref, mub, _ = step_dot_test(U, ('noslip', 'noslip', 'noslip', 'slip'),
+                                           (0.0, 1.0, 0.0, 0.5), 1 / 200, 3, mu_exp=0.76)
+    print('step mu(T): rel %.2e mu rel %.2e' % (rel(lhs, rhs), rel(mref, mub)))
     assert rel(lhs, rhs) < 1e-10
     assert rel(mref, mub) < 1e-10
 

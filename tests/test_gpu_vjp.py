@@ -28,17 +28,20 @@ def directions(U, seed):
     return dU, Rb, Vb
 
 
-def dot_test(U, bc, linear=False, extent=(0.0, 1.0, 0.0, 1.0), mu=0.01, seed=0):
+def dot_test(U, bc, linear=False, extent=(0.0, 1.0, 0.0, 1.0), mu=0.01, seed=0, mu_exp=0.0):
     ny, nx = U.shape[2:]
-    s = hweno.Solver(nx, ny, extent=extent, bc=bc, mu_ref=mu, linear_weights=int(linear))
-    sc = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu), Options(linear_weights=linear), bc=bc)
+    s = hweno.Solver(nx, ny, extent=extent, bc=bc, mu_ref=mu, mu_exp=mu_exp,
+                     linear_weights=int(linear))
+    sc = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu, mu_exp=mu_exp),
+                  Options(linear_weights=linear), bc=bc)
     dU, Rb, Vb = directions(U, seed)
     Fc, Vc, dd = sc.residual(U + 1j * H * dU)
     lhs = np.sum(Fc.imag / H * Rb) + np.sum((Vc.imag / H).reshape(8, ny, nx) * Vb)
     Ub, mub = s.residual_vjp(to_dev(U), to_dev(Rb), to_dev(Vb))
     rhs = np.sum(dU * Ub.cpu().numpy())
     # mu: complex step in mu_ref
-    sm = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu + 1j * H), Options(linear_weights=linear), bc=bc)
+    sm = Scheme2D(nx, ny, *extent, Physics(mu_ref=mu + 1j * H, mu_exp=mu_exp),
+                  Options(linear_weights=linear), bc=bc)
     Fm, _, _ = sm.residual(U.astype(complex))
     mu_ref = np.sum(Fm.imag / H * Rb)
     return lhs, rhs, mu_ref, mub, dd
@@ -64,6 +67,25 @@ def test_vjp_dot_product_walls(bc):
     U = workloads.random_smooth_2d(12, 10, seed=6, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
     lhs, rhs, mref, mub, _ = dot_test(U, bc, extent=(0.0, 1.0, 0.0, 0.5), mu=1 / 200)
     print('bc %s: rel %.2e mu rel %.2e' % (bc, rel(lhs, rhs), rel(mref, mub)))
+    assert rel(lhs, rhs) < 1e-10
+    assert rel(mref, mub) < 1e-10
+
+
+@pytest.mark.parametrize('case', ['periodic', 'walls'])
+def test_vjp_dot_product_mu_T(case):
+    """Temperature-dependent viscosity mu = mu_ref (T / T_ref)^0.76: the
+    adjoint carries the viscosity's dependence on the state at every face
+    and volume point, and mu-bar is the derivative in mu_ref of the whole
+    law."""
+    if case == 'periodic':
+        U = workloads.random_smooth_2d(13, 11, seed=15, noise=1e-3)
+        lhs, rhs, mref, mub, _ = dot_test(U, ('periodic',) * 4, mu=0.02, mu_exp=0.76)
+    else:
+        U = workloads.random_smooth_2d(12, 10, seed=16, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+        lhs, rhs, mref, mub, _ = dot_test(U, ('noslip', 'noslip', 'noslip', 'slip'),
+                                          extent=(0.0, 1.0, 0.0, 0.5), mu=1 / 200, mu_exp=0.76)
+    print('mu(T) %s: <J du, rb> %.15e  <du, J^T rb> %.15e  rel %.2e; mu %.6e vs %.6e rel %.2e'
+          % (case, lhs, rhs, rel(lhs, rhs), mref, mub, rel(mref, mub)))
     assert rel(lhs, rhs) < 1e-10
     assert rel(mref, mub) < 1e-10
 
