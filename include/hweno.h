@@ -199,6 +199,21 @@ HWENO_API hweno_status hweno_rk_step_inflow(hweno_ctx* ctx, double dt, hweno_dia
  * 1D context, another wall kind, no fluid cell). */
 HWENO_API hweno_status hweno_set_solid(hweno_ctx* ctx, const unsigned char* mask, int wall);
 
+/* Solid cells that hold a prescribed state instead of a mirror image
+ * (Example 5.10: the exact post-shock state imposed along part of the bottom
+ * of its channel, beside a reflective wall).  fixed: host array of ny x nx
+ * bytes, row-major, nonzero = such a cell, each solid in the mask of
+ * hweno_set_solid; copied before return.  state: host (rho, u, v, p).  Every
+ * such cell within 4 cells of the fluid is set before each residual to the
+ * conservative state with zero first moments, as the ghost cells of an
+ * inflow side are (Remark 4.1); they count as solid for the mirror search of
+ * the other solid cells and are never a mirror's source.  fixed = NULL makes
+ * every solid cell a mirror again; hweno_set_solid clears the setting.
+ * Errors: HWENO_E_INVAL (no mask, batch or 1D context, a fixed cell that is
+ * not solid, state NULL, rho or p not positive, a value not finite). */
+HWENO_API hweno_status hweno_set_solid_state(hweno_ctx* ctx, const unsigned char* fixed,
+                                             const double* state);
+
 /* Stream (hipStream_t) on which all later work of this context is ordered. */
 HWENO_API hweno_status hweno_set_stream(hweno_ctx* ctx, void* hip_stream);
 

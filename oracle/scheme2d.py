@@ -59,7 +59,8 @@ class Scheme2D:
     """
 
     def __init__(self, nx, ny, x0, x1, y0, y1, phys=None, opts=None,
-                 bc=('periodic',) * 4, inflow=None, solid=None, solid_wall='slip'):
+                 bc=('periodic',) * 4, inflow=None, solid=None, solid_wall='slip',
+                 fixed=None, fixed_state=None):
         self.nx, self.ny = nx, ny
         self.dx = (x1 - x0) / nx
         self.dy = (y1 - y0) / ny
@@ -68,8 +69,16 @@ class Scheme2D:
         self.bc = tuple(bc)
         self.inflow = inflow or {}
         self.rec = Hweno2D()
-        # masked domain (Examples 5.8, 5.10): solid cells of the grid
+        # masked domain (Examples 5.8, 5.10): solid cells of the grid; the
+        # solid cells of `fixed` hold the conservative state `fixed_state`
+        # (first moments zero) instead of a mirror image, as the ghost cells
+        # of a prescribed-state boundary do (Remark 4.1)
         self.solid = None if solid is None else np.asarray(solid, dtype=bool)
+        self.fixed = None if fixed is None else np.asarray(fixed, dtype=bool)
+        if self.fixed is not None:
+            assert self.solid is not None and not (self.fixed & ~self.solid).any()
+        self.fixed_state = None if fixed_state is None else np.asarray(fixed_state)
+        self.fixed_cells = []
         self.mirrors = [] if solid is None else self._mirror_map(solid_wall)
 
     # -- walls inside the grid (masked domains) ------------------------------
@@ -90,6 +99,9 @@ class Scheme2D:
                 win = S[max(j - HALO, 0):j + HALO + 1, max(i - HALO, 0):i + HALO + 1]
                 if win.all():
                     continue                      # deep inside the solid
+                if self.fixed is not None and self.fixed[j, i]:
+                    self.fixed_cells.append((j, i))
+                    continue
                 best = None
                 for dj, di, axis in ((0, 1, 0), (0, -1, 0), (1, 0, 1), (-1, 0, 1)):
                     k = 1
@@ -162,6 +174,9 @@ class Scheme2D:
         Ug[:, :, H:H + self.ny, H:H + self.nx] = U
         for (j, i), (js, is_), sg in self.mirrors:
             Ug[:, :, H + j, H + i] = sg * Ug[:, :, H + js, H + is_]
+        for j, i in self.fixed_cells:
+            Ug[0, :, H + j, H + i] = self.fixed_state
+            Ug[1:, :, H + j, H + i] = 0.0
         for side in (0, 1):
             self._fill(Ug, side, 0)
         for side in (0, 1):

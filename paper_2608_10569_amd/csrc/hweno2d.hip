@@ -185,7 +185,9 @@ __device__ __forceinline__ void x_ghost(const Grid2& g, const Side& sd, const do
 }
 
 // Walls inside the grid (masked domains): solid cell = mirror image of a fluid
-// cell across the nearest wall face, with the box walls' parities (Remark 4.1).
+// cell across the nearest wall face, with the box walls' parities (Remark 4.1);
+// a cell listed with source -1 holds the prescribed state with zero first
+// moments instead, as the ghost cells of an inflow side do.
 __global__ void k_solid2(const Grid2* gp, int sidx) {
     const Grid2& g = *gp;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,6 +195,15 @@ __global__ void k_solid2(const Grid2* gp, int sidx) {
     double* S = g.S[sidx];
     const long long N = g.ncell;
     const long long d = g.sdst[t], s = g.ssrc[t];
+    if (s < 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            S[c * N + d] = g.fixed_state[c];
+            S[(4 + c) * N + d] = 0.0;
+            S[(8 + c) * N + d] = 0.0;
+        }
+        return;
+    }
     const int dir = g.sdir[t];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {

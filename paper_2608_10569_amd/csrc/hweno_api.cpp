@@ -86,6 +86,9 @@ struct hweno_ctx {
     std::vector<unsigned char> solid_host;
     std::vector<int> sdst_host, ssrc_host, sdir_host;
     int solid_wall = 0;
+    // solid cells that hold a prescribed state (hweno_set_solid_state)
+    std::vector<unsigned char> fixed_host;
+    double fixed_cons[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned char* solid_dev = nullptr;
     int* sdst_dev = nullptr;
     int* ssrc_dev = nullptr;
@@ -425,6 +428,7 @@ hweno_status upload_solid(hweno_ctx* c) {
     g.sdst = g.ssrc = g.sdir = nullptr;
     g.nsolid = 0;
     g.solid_wall = c->solid_wall;
+    for (int k = 0; k < 4; ++k) g.fixed_state[k] = c->fixed_cons[k];
     if (c->solid_host.empty()) return HWENO_OK;
     TRY(dev(hipMemcpyAsync(c->solid_dev, c->solid_host.data(), c->solid_host.size(),
                            hipMemcpyHostToDevice, c->stream)));
@@ -761,8 +765,10 @@ namespace {
 // across the nearest wall face along +x, -x, +y, -y (ties in that order), of a
 // fluid cell; a mirror off the grid or in solid falls back to the first fluid
 // cell in that direction; a cell with fluid only diagonally is left as it is.
-void mirror_list(const unsigned char* m, int nx, int ny, int NX, std::vector<int>& dst,
-                 std::vector<int>& src, std::vector<int>& dir) {
+// A cell marked in `fixed` (may be null) is listed with source -1: it holds
+// the prescribed state instead.
+void mirror_list(const unsigned char* m, const unsigned char* fixed, int nx, int ny, int NX,
+                 std::vector<int>& dst, std::vector<int>& src, std::vector<int>& dir) {
     auto solid = [&](int j, int i) { return m[(size_t)j * nx + i] != 0; };
     auto in = [&](int j, int i) { return j >= 0 && j < ny && i >= 0 && i < nx; };
     auto ghosted = [&](int j, int i) { return (j + HALO) * NX + i + HALO; };
@@ -778,6 +784,12 @@ void mirror_list(const unsigned char* m, int nx, int ny, int NX, std::vector<int
                         break;
                     }
             if (!near) continue;
+            if (fixed && fixed[(size_t)j * nx + i]) {
+                dst.push_back(ghosted(j, i));
+                src.push_back(-1);
+                dir.push_back(0);
+                continue;
+            }
             int bk = 0, bd = -1;
             for (int d = 0; d < 4; ++d) {
                 int k = 1;
@@ -815,13 +827,51 @@ HWENO_API hweno_status hweno_set_solid(hweno_ctx* c, const unsigned char* mask, 
         bool fluid = false;
         for (auto v : m) fluid = fluid || v == 0;
         if (!fluid) return HWENO_E_INVAL;
-        mirror_list(m.data(), nx, ny, nx + 2 * HALO, dst, src, dir);
+        mirror_list(m.data(), nullptr, nx, ny, nx + 2 * HALO, dst, src, dir);
     }
+    c->fixed_host.clear();
     c->solid_host = std::move(m);
     c->sdst_host = std::move(dst);
     c->ssrc_host = std::move(src);
     c->sdir_host = std::move(dir);
     c->solid_wall = wall;
+    if (!c->ws) return HWENO_OK;
+    TRY(upload_solid(c));
+    return upload_grids(c);
+    GUARD_END
+}
+
+HWENO_API hweno_status hweno_set_solid_state(hweno_ctx* c, const unsigned char* fixed,
+                                             const double* state) {
+    GUARD_BEGIN
+    if (!c || c->batch || c->dim() != 2 || c->solid_host.empty()) return HWENO_E_INVAL;
+    const int nx = c->i0().grid.nx, ny = c->i0().grid.ny;
+    std::vector<unsigned char> f;
+    double cons[4] = {0.0, 0.0, 0.0, 0.0};
+    if (fixed) {
+        if (!state) return HWENO_E_INVAL;
+        const double r = state[0], u = state[1], v = state[2], p = state[3];
+        if (!(r > 0.0) || !(p > 0.0) || !std::isfinite(r) || !std::isfinite(u) ||
+            !std::isfinite(v) || !std::isfinite(p))
+            return HWENO_E_INVAL;
+        f.assign(fixed, fixed + (size_t)nx * ny);
+        for (size_t k = 0; k < f.size(); ++k) {
+            f[k] = f[k] ? 1 : 0;
+            if (f[k] && !c->solid_host[k]) return HWENO_E_INVAL;
+        }
+        cons[0] = r;
+        cons[1] = r * u;
+        cons[2] = r * v;
+        cons[3] = p / (c->i0().phys.gamma - 1.0) + 0.5 * r * (u * u + v * v);
+    }
+    std::vector<int> dst, src, dir;
+    mirror_list(c->solid_host.data(), fixed ? f.data() : nullptr, nx, ny, nx + 2 * HALO, dst,
+                src, dir);
+    c->fixed_host = std::move(f);
+    for (int k = 0; k < 4; ++k) c->fixed_cons[k] = cons[k];
+    c->sdst_host = std::move(dst);
+    c->ssrc_host = std::move(src);
+    c->sdir_host = std::move(dir);
     if (!c->ws) return HWENO_OK;
     TRY(upload_solid(c));
     return upload_grids(c);

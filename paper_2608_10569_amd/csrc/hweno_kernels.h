@@ -104,6 +104,7 @@ struct Grid2 {
     const HW_GLOBAL int* sdir;
     int nsolid;
     int solid_wall;
+    double fixed_state[4];   // conservative state of the solid cells listed with source -1
 };
 
 struct Grid1 {

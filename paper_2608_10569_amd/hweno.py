@@ -20,7 +20,7 @@ NOALLOC_BYTES = 256 << 20
 #: every symbol include/hweno.h declares
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_inflow_stages',
-           'hweno_rk_step_inflow', 'hweno_set_solid', 'hweno_set_stream',
+           'hweno_rk_step_inflow', 'hweno_set_solid', 'hweno_set_solid_state', 'hweno_set_stream',
            'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_residual_noalloc', 'hweno_rk_step', 'hweno_rk_step_source',
            'hweno_residual_vjp',
@@ -109,6 +109,7 @@ def lib():
         L.hweno_set_inflow_stages.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
         L.hweno_rk_step_inflow.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
         L.hweno_set_solid.argtypes = [vp, vp, ctypes.c_int]
+        L.hweno_set_solid_state.argtypes = [vp, vp, dp]
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
@@ -250,6 +251,20 @@ class Solver:
         if m.shape != (self.ny, self.nx):
             raise ValueError('mask of shape (ny, nx) expected')
         check(lib().hweno_set_solid(self._h, m.ctypes.data_as(ctypes.c_void_p), BC[wall]))
+
+    def set_solid_state(self, fixed, state=None):
+        """Solid cells (bool array (ny, nx), each solid in the mask) that hold
+        the primitive state (rho, u, v, p) instead of a mirror image; None
+        makes every solid cell a mirror again."""
+        import numpy as np
+        if fixed is None:
+            check(lib().hweno_set_solid_state(self._h, None, None))
+            return
+        f = np.ascontiguousarray(fixed, dtype=np.uint8)
+        if f.shape != (self.ny, self.nx):
+            raise ValueError('mask of shape (ny, nx) expected')
+        st = (ctypes.c_double * 4)(*[float(v) for v in state])
+        check(lib().hweno_set_solid_state(self._h, f.ctypes.data_as(ctypes.c_void_p), st))
 
     def rk_step_inflow(self, dt):
         """One step of fixed dt with the stage inflow profiles; returns diag."""

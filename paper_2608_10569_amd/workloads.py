@@ -250,6 +250,46 @@ class ShockMixingLayer:
         return project2d(lambda X, Y: self.prim(Y, 0.0), self.nx, self.ny, self.extent, self.gamma)
 
 
+class Mach10Reflection:
+    """Example 5.10 (gamma = 1.4): a Mach-10 shock at 60 degrees to a wall
+    reflects along it and diffracts round a step.  The domain is read as
+    [0,1]x[0,1] U [1,3]x[-1,1] (the text lists the second rectangle's
+    intervals in the order y, x), inside the grid of [0,3]x[-1,1], whose
+    cells with centres at x < 1, y < 0 are solid.  Post-shock state (8,
+    33/4 sin(pi/3), -33/4 cos(pi/3), 116.5) left of x = 1/6 + y/sqrt(3),
+    (1.4, 0, 0, 1) right of it.  Left side: inflow of the post-shock state;
+    right side and bottom: outflow; along y = 0 the solid cells with centres
+    at x < 1/6 hold the post-shock state, and the wall from x = 1/6 to 1 and
+    the step face {1} x [-1, 0] are reflective; the top follows the exact
+    shock, one state per boundary cell from its centre: post-shock for
+    x <= 1/6 + (1 + 20 t)/sqrt(3)."""
+
+    extent = (0.0, 3.0, -1.0, 1.0)
+    bc = ('inflow', 'outflow', 'outflow', 'inflow')
+    post = (8.0, 8.25 * np.sin(np.pi / 3.0), -8.25 * np.cos(np.pi / 3.0), 116.5)
+    pre = (1.4, 0.0, 0.0, 1.0)
+
+    def __init__(self, nx=480, ny=480, gamma=1.4):
+        self.nx, self.ny, self.gamma = nx, ny, gamma
+        self.xc = (np.arange(nx) + 0.5) * (3.0 / nx)
+        self.yc = -1.0 + (np.arange(ny) + 0.5) * (2.0 / ny)
+        X, Y = np.meshgrid(self.xc, self.yc)
+        self.solid = (X < 1.0) & (Y < 0.0)
+        self.fixed = self.solid & (X < 1.0 / 6.0)
+
+    def prim(self, X, Y):
+        left = X < 1.0 / 6.0 + Y / np.sqrt(3.0)
+        return tuple(np.where(left, a, b) for a, b in zip(self.post, self.pre))
+
+    def top(self, t):
+        """Top-side profile (nx, 4) of primitive states at time t."""
+        left = self.xc <= 1.0 / 6.0 + (1.0 + 20.0 * t) / np.sqrt(3.0)
+        return np.where(left[:, None], np.array(self.post)[None, :], np.array(self.pre)[None, :])
+
+    def initial(self):
+        return project2d(self.prim, self.nx, self.ny, self.extent, self.gamma)
+
+
 def random_smooth_2d(nx, ny, seed, gamma=1.4, extent=(0.0, 1.0, 0.0, 1.0), noise=1e-4):
     """Smooth random periodic state (4 Fourier modes per field, Mach < 0.5)
     with small cell-level noise on the moments, for parity tests."""

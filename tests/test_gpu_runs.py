@@ -314,3 +314,51 @@ def test_shock_mixing_layer_example_5_11():
           % (steps, t, rho.min(), rho.max(), up, down))
     assert abs(t - T) < 1e-9 and 0.3 < rho.min() and rho.max() < 2.8
     assert up < 0.08 and down > 2.5 * up
+
+
+def test_mach10_reflection_example_5_10():
+    """Example 5.10 on the paper's 480 x 480 grid (the domain read as [0,1]x[0,1]
+    U [1,3]x[-1,1] inside [0,3]x[-1,1]; Re = 1000) to T = 0.2: the step from
+    the paper's rule on the step's initial state and, when a stage is
+    inadmissible, the step restarted at half the size (the flow chart of
+    Sec. 4; the state is left unchanged by the rejected step), the top
+    boundary at each stage's time.  Every accepted stage is admissible, the
+    density stays within the paper's contour range (0 .. 25), and by T = 0.2
+    the shock reflected along the wall has passed the step corner and
+    diffracted into the lower part of the domain."""
+    m = workloads.Mach10Reflection(480, 480)
+    ph = dict(gamma=1.4, Pr=0.72, mu_ref=1e-3)
+    s = hweno.Solver(m.nx, m.ny, extent=m.extent, bc=m.bc, inflow={0: m.post, 3: m.post}, **ph)
+    s.set_solid(m.solid)
+    s.set_solid_state(m.fixed, m.post)
+    s.set_state(to_dev(m.initial()))
+    t, steps, T, h = 0.0, 0, 0.2, 2.0 / 480
+    pp = restarts = 0
+    while t < T - 1e-12:
+        _, _, d = s.residual(s.get_state()[0])
+        dt = min(0.6 * h / d['alpha_star'], 0.001 * h * h / ph['mu_ref'], T - t)
+        for _ in range(64):
+            s.set_inflow_stages(3, m.top(t), m.top(t + dt), m.top(t + 0.5 * dt))
+            try:
+                d = s.rk_step_inflow(dt)
+                break
+            except hweno.HwenoError as e:
+                if e.code != 4:                      # only an inadmissible stage restarts
+                    raise
+                dt *= 0.5
+                restarts += 1
+        assert d['min_rho'] > 0.0 and d['min_p'] > 0.0
+        pp += d['pp_cells']
+        t += dt
+        steps += 1
+    rho = s.get_state()[0][0, 0].cpu().numpy()
+    X, Y = np.meshgrid(m.xc, m.yc)
+    fl = ~m.solid
+    lower = fl & (Y < 0.0)
+    print('Example 5.10: %d steps (%d restarts) to T = %.3f, limiter cell-stages %d, density '
+          '%.3f .. %.3f; below y = 0: max %.3f, cells above 2 %d'
+          % (steps, restarts, t, pp, rho[fl].min(), rho[fl].max(), rho[lower].max(),
+             (rho[lower] > 2.0).sum()))
+    assert abs(t - T) < 1e-12
+    assert 0.0 < rho[fl].min() and rho[fl].max() < 25.0
+    assert rho[lower].max() > 5.0 and (rho[lower] > 2.0).sum() > 1000
