@@ -247,15 +247,18 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
     __syncthreads();
     const bool inter = valid && interior(g, j, i);
     double mub = 0.0;
-    if (inter && s < 2) {
-        // volume flux: vf = sum_q w_q f(U_q, s_q); vf-bar = F2-bar/dx (f), F3-bar/dy (g)
+    if (inter) {
+        // volume flux: vf = sum_q w_q f(U_q, s_q); vf-bar = F2-bar/dx (f), F3-bar/dy (g).
+        // The 18 point adjoints over the cell's 6 threads: direction dv = s / 3,
+        // points 3 (s % 3) .. 3 (s % 3) + 2
+        const int dv = s / 3, q0 = 3 * (s % 3);
         double fb[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            fb[c] = s == 0 ? rbar(A, g, 1, c, j, i) * K.idx : rbar(A, g, 2, c, j, i) * K.idy;
-        const double* V = s == 0 ? g.xv : g.yv;
-        double* VB = s == 0 ? W.xvb : W.yvb;
-        for (int q = 0; q < 9; ++q) {
+            fb[c] = dv == 0 ? rbar(A, g, 1, c, j, i) * K.idx : rbar(A, g, 2, c, j, i) * K.idy;
+        const double* V = dv == 0 ? g.xv : g.yv;
+        double* VB = dv == 0 ? W.xvb : W.yvb;
+        for (int q = q0; q < q0 + 3; ++q) {
             const double wq = gw(q / 3) * gw(q % 3);
             double Uq[4], sq[6], Uqb[4] = {0.0, 0.0, 0.0, 0.0}, sqb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             double f[4];
@@ -269,13 +272,13 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
             const double muq = VarMu ? point_mu(K, Uq) : K.mu_ref;
             double mubq = 0.0;
             double& mb = VarMu ? mubq : mub;
-            if (s == 0) flux2_vjp<0>(K, Uq, sq, muq, f, Uqb, sqb, mb);
+            if (dv == 0) flux2_vjp<0>(K, Uq, sq, muq, f, Uqb, sqb, mb);
             else flux2_vjp<1>(K, Uq, sq, muq, f, Uqb, sqb, mb);
             if constexpr (VarMu) mub += mubq * mu_T_vjp(K, Uq, mubq, Uqb);
 #pragma unroll
             for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] = Uqb[c];
 #pragma unroll
-            for (int z = 0; z < 6; ++z) shvb[s][(z * 9 + q) * AG + cl] = sqb[z];
+            for (int z = 0; z < 6; ++z) shvb[dv][(z * 9 + q) * AG + cl] = sqb[z];
         }
     }
     __syncthreads();
