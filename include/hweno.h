@@ -275,7 +275,7 @@ HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* ctx, double dt, const dou
                                             hweno_diag* diag);
 
 /* Reverse mode (vector-Jacobian product) of hweno_residual at the state U
- * (device, D1), 2D grids:
+ * (device, D1), single 1D or 2D grids:
  *   Ubar = (dR/dU)^T Rbar + (dVhat/dU)^T Vbar        (device, D1, overwritten)
  *   *mu_bar = (dR/dmu_ref) . Rbar                    (host double; NULL: skip)
  * With mu_exp != 0 the viscosity mu_ref (T/T_ref)^mu_exp is differentiated
@@ -287,15 +287,15 @@ HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* ctx, double dt, const dou
  * weights with derivative sign(x), 0 at 0); ties go to the lowest index.
  * Every sum is a fixed-order gather, so results are bitwise reproducible.
  * Uses the workspace (the forward intermediates are recomputed); with a
- * non-NULL mu_bar the call synchronises.  HWENO_E_INVAL for dim = 1.
- * Reverse-mode part of the differentiable rollout (the paper's
+ * non-NULL mu_bar the call synchronises.  Reverse-mode part of the
+ * differentiable rollout (the paper's
  * scheme of eq. (3.2); adjoint of its Sec. 3 residual).  HWENO_E_INVAL also
  * for a context with options.gradients = 1 (DR) or a solid mask. */
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar);
 
 /* Reverse mode of one SSP-RK3 step of eq. (2.12) taken with the fixed step
- * dt > 0 from the state U0 (device, D1), 2D grids (mu(T) as in
+ * dt > 0 from the state U0 (device, D1), single 1D or 2D grids (mu(T) as in
  * hweno_residual_vjp): with
  * U3 = step(U0) as hweno_rk_step computes it for that dt,
  *   U0bar = (dU3/dU0)^T U3bar              (device, D1, overwritten)
@@ -309,8 +309,9 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const
  * second and third stage keep theirs (three); the results are the same bits.
  * U3bar must not overlap U0.
  * Uses the workspace; leaves the context state alone; with a non-NULL
- * mu_bar the call synchronises.  HWENO_E_INVAL for dt <= 0 or dim = 1 (and,
- * as for hweno_residual_vjp, for DR contexts or a solid mask). */
+ * mu_bar the call synchronises.  HWENO_E_INVAL for dt <= 0 (and, as for
+ * hweno_residual_vjp, for DR contexts or a solid mask).  1D grids always
+ * recompute (five residual evaluations per call). */
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar);
 

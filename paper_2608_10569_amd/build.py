@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libhweno.so')
-SOURCES = ['hweno2d.hip', 'hweno1d.hip', 'hweno2d_vjp.hip', 'hweno_api.cpp']
+SOURCES = ['hweno2d.hip', 'hweno1d.hip', 'hweno2d_vjp.hip', 'hweno1d_vjp.hip', 'hweno_api.cpp']
 ARCH = os.environ.get('HWENO_ARCH', 'gfx950')
 
 

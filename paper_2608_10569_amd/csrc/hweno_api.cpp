@@ -52,10 +52,13 @@ struct hweno_ctx {
     hw::Reduce* red = nullptr;         // device, by instance id
     int cur = 0;                       // single 2D grid: current state is hg[0].S[cur]
     // 1D
-    double* S1[3] = {nullptr, nullptr, nullptr};   // ghosted states; S1[0] = current
+    // ghosted states; S1[0] = current, 1 and 2 the step's stages, 3 and 4
+    // the reverse mode's recomputed stages
+    double* S1[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hw::Grid1 g1{};
-    // reverse mode (single 2D grid)
+    // reverse mode (single 2D grid; 1D grid)
     hw::AdjWs adj{};
+    hw::AdjWs1 adj1{};
     // keep_stages (single 2D grid): residual intermediates of RK stages 2 and 3
     // in arrays of their own, described by stage[k] (host) / dstage + k
     // (device) and launched through blstage[k]
@@ -207,7 +210,7 @@ size_t layout(hweno_ctx* c, char* base) {
         g.nx = c->i0().grid.nx;
         g.NX = g.nx + 2 * HALO;
         const size_t m = (size_t)g.NX;
-        for (int k = 0; k < 3; ++k) c->S1[k] = take(6 * m);
+        for (int k = 0; k < 5; ++k) c->S1[k] = take(6 * m);
         g.pts = take(12 * m);
         g.wb = take(2 * m);
         g.vk = take(3 * m);
@@ -218,6 +221,21 @@ size_t layout(hweno_ctx* c, char* base) {
         g.vf = take(3 * m);
         c->red = reinterpret_cast<hw::Reduce*>(take_bytes(sizeof(hw::Reduce)));
         g.red = (HW_GLOBAL hw::Reduce*)c->red;
+        // reverse-mode workspace (the first three arrays zero-filled by every
+        // adjoint call, in one region)
+        hw::AdjWs1& A = c->adj1;
+        const size_t nm = m + (size_t)g.nx + 1;
+        A.ptsb = take(12 * m + 8 * m + nm);
+        A.grb = A.ptsb ? A.ptsb + 12 * m : nullptr;
+        A.mupart = A.ptsb ? A.grb + 8 * m : nullptr;
+        A.base = A.ptsb;
+        A.count = (long long)(20 * m + nm);
+        A.rbc = take(10 * m);
+        A.uc = take(15 * m);
+        A.ub = take(6 * m);
+        c->mu_dev = take(1);
+        c->X1 = take(6 * (size_t)g.nx);
+        c->X2 = take(6 * (size_t)g.nx);
         return off;
     }
     for (int p = 0; p < n; ++p) {
@@ -1225,10 +1243,22 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
                                           const double* Vbar, double* Ubar, double* mu_bar) {
     GUARD_BEGIN
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
-    if (c->dim() != 2 || !c->solid_host.empty() ||
-        c->i0().opt.gradients != 0)
-        return HWENO_E_INVAL;
+    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
+    if (c->dim() == 1) {   // the step's stage buffer 2 holds U (the state is kept)
+        TRY(dev(hw::launch_copy_in1(c->g1, U, c->S1[2], c->stream)));
+        TRY(reset(c));
+        TRY(ghost(c, 2));
+        TRY(residual(c, 2));
+        hw::AdjIn A{Rbar, Vbar, 1.0, 1.0};
+        TRY(dev(hw::launch_vjp1(c->g1, A, c->adj1, c->S1[2], Ubar, c->mu_dev, 0, c->stream)));
+        if (mu_bar) {
+            TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream)));
+            TRY(dev(hipStreamSynchronize(c->stream)));
+        }
+        return HWENO_OK;
+    }
     const hw::Grid2& g = g2(c);
     hw::BatchL full = c->bl;   // the adjoint kernels read all six face gradients
     full.full_grad = true;
@@ -1257,10 +1287,45 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     GUARD_BEGIN
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
-    if (c->dim() != 2 || !c->solid_host.empty() ||
-        c->i0().opt.gradients != 0)
-        return HWENO_E_INVAL;
+    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
+    if (c->dim() == 1) {
+        // U0, U1, U2 in stage buffers 2, 3, 4 (the state in buffer 0 is kept);
+        // every stage adjoint recomputes its residual's intermediates first
+        const long long na = 3LL * c->g1.nx, nall = 6LL * c->g1.nx;
+        const int ia = 2, ib = 3, ic = 4;
+        TRY(dev(hw::launch_copy_in1(c->g1, U0, c->S1[ia], c->stream)));
+        TRY(reset(c));
+        TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
+        TRY(ghost(c, ia));
+        TRY(residual(c, ia));
+        TRY(update(c, 1, ia, ia, ib, nullptr, nullptr));
+        TRY(ghost(c, ib));
+        TRY(residual(c, ib));
+        TRY(update(c, 2, ia, ib, ic, nullptr, nullptr));
+        auto vjp_at1 = [&](int si, const double* Rb, const double* Vb, double rs, double vs,
+                           double* out, int acc) {
+            TRY(reset(c));
+            TRY(ghost(c, si));
+            TRY(residual(c, si));
+            hw::AdjIn A{Rb, Vb, rs, vs};
+            return dev(hw::launch_vjp1(c->g1, A, c->adj1, c->S1[si], out, c->mu_dev, acc,
+                                       c->stream));
+        };
+        TRY(vjp_at1(ic, U3bar, U3bar + na, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
+        TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, na, c->stream)));           // U2bar
+        TRY(vjp_at1(ib, c->X2, c->X2 + na, 0.25 * dt, 0.25, c->X1, 1));
+        TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, na, c->stream)));                // U1bar
+        TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, nall, c->stream)));
+        TRY(vjp_at1(ia, c->X1, c->X2 + na, dt, 1.0, U0bar, 1));
+        TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, na, c->stream)));
+        if (mu_bar) {
+            TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream)));
+            TRY(dev(hipStreamSynchronize(c->stream)));
+        }
+        return HWENO_OK;
+    }
     const hw::Grid2& g = g2(c);
     const long long nint = (long long)g.nx * g.ny;
     const int ia = 1 - c->cur, ib = 2, ic = 3;   // U0, U1, U2 (the current state is kept)

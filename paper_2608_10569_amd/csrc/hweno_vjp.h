@@ -102,6 +102,58 @@ __device__ __forceinline__ double mu_T_vjp(const Consts& K, const double* U, dou
     return f;
 }
 
+// Adjoint workspace of a 1D grid (component-major over the ghosted cells).
+struct AdjWs1 {
+    double* base;       // start of the zero-filled region (ptsb .. mupart)
+    long long count;    // doubles in that region
+    double* ptsb;       // 12: adjoints of the limited LGL values (p*3 + c)
+    double* grb;        // 8: adjoints of the LGL gradients (p*2 + w)
+    double* mupart;     // NX + nx + 1: mu-adjoint partials of the faces, then of the cells
+    double* rbc;        // 10: weak-moment adjoints from the gradient stencil (w*5 + s)
+    double* uc;         // 15: state adjoints from the reconstruction stencil (s*3 + c)
+    double* ub;         // 6: gathered state adjoint
+};
+
+// Adjoint of the 1D LF speed speed1 (the branch of the forward point; ties
+// to |u| + c), accumulated into Ub, uxb, exb, mub.
+__device__ __forceinline__ void speed1_vjp(const Consts& K, const double* U, double ux, double ex,
+                                           double mu, double yb, double* Ub, double& uxb,
+                                           double& exb, double& mub) {
+    const double r = U[0], u = U[1] / r;
+    const double p = pressure1(K, r, U[1], U[2]);
+    const double e = p / (K.gm1 * r);
+    const double tau = (4.0 / 3.0) * mu * ux;
+    const double q = -K.gamma * mu * ex / K.Pr;
+    const double r2e = r * r * e;
+    const double root = sqrt(r * r * q * q + 2.0 * r2e * (tau - p) * (tau - p));
+    const double bpp = fabs(u) + (root + r * fabs(q)) / (2.0 * r2e);
+    const double ac = fabs(u) + sqrt(K.gamma * p / r);
+    if (ac >= bpp) adj::speed1_ac_vjp(K, U, sgn(u), yb, Ub);
+    else adj::speed1_bpp_vjp(K, U, ux, ex, mu, sgn(u), sgn(q), yb, Ub, uxb, exb, mub);
+}
+
+// mu(T) of a 1D point as flux1 and speed1 form it, and the adjoint of its
+// dependence on (rho, m, E) (T = (gamma - 1)(E / rho - u^2 / 2)); the return
+// value carries mub into the adjoint of mu_ref.
+__device__ __forceinline__ double point_mu1(const Consts& K, const double* U) {
+    return viscosity<true>(K, U[0], pressure1(K, U[0], U[1], U[2]));
+}
+__device__ __forceinline__ double mu_T_vjp1(const Consts& K, const double* U, double mub,
+                                            double* Ub) {
+    if (K.mu_exp == 0.0) return 1.0;
+    const double ir = 1.0 / U[0], u = U[1] * ir;
+    const double T = K.gm1 * (U[2] * ir - 0.5 * u * u);
+    const double f = pow(T / K.T_ref, K.mu_exp);
+    const double gT = mub * K.mu_ref * f * K.mu_exp / T;
+    Ub[0] += gT * (0.5 * K.gm1 * u * u - T) * ir;
+    Ub[1] -= gT * K.gm1 * u * ir;
+    Ub[2] += gT * K.gm1 * ir;
+    return f;
+}
+
+hipError_t launch_vjp1(const Grid1& g, const AdjIn& A, AdjWs1 W, const double* S, double* Ubar,
+                       double* mu_out, int mu_acc, hipStream_t st);
+
 long long adj_mu_partials2(const Grid2& g);
 // mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar)
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,

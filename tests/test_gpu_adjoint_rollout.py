@@ -121,7 +121,7 @@ def test_step_vjp_rejects_bad_arguments():
     s1 = hweno.Solver(16)
     U1 = to_dev(workloads.random_smooth_1d(16, seed=1))
     with pytest.raises(hweno.HwenoError):
-        s1.rk_step_vjp(U1, 1e-3, U1.clone())
+        s1.rk_step_vjp(U1, -1e-3, U1.clone())
 
 
 def test_rollout_checkpointing_is_exact():
