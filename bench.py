@@ -356,8 +356,12 @@ def bench_developed(nsteps, t_dev=0.3):
 
 
 def bench_adjoint(nsteps=200, every=20):
-    """Double shear layer: forward + checkpointed backward vs plain forward
-    (the stage intermediates kept for the step adjoints)."""
+    """Double shear layer: forward + checkpointed backward vs plain forward.
+    The backward recomputes each segment once, recording every step's stage
+    intermediates (``every`` recording slots in HBM), and runs the step
+    adjoints from the recordings; the same gradient from recomputing every
+    stage residual inside each step adjoint (stage intermediates of stages 2
+    and 3 kept) is timed too."""
     import numpy as np
     import torch
     from paper_2608_10569_amd import adjoint, hweno
@@ -376,28 +380,40 @@ def bench_adjoint(nsteps=200, every=20):
         s.rk_step(dt)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    def run(n_steps):
+        r = rho.clone().requires_grad_(True)
+        m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = adjoint.kinetic_energy(adjoint.rollout(s, adjoint.project_fields(r, u, v, f[3], gamma),
+                                                   m, dt, n_steps, every), s.dx, s.dy)
+        J.backward()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, J.item(), m.grad.item(), r.grad
     # untimed warm-up: one checkpoint segment forward and backward (first
-    # launches of the reverse-mode kernels, autograd set-up)
-    r = rho.clone().requires_grad_(True)
-    m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
-    adjoint.kinetic_energy(adjoint.rollout(s, adjoint.project_fields(r, u, v, f[3], gamma), m,
-                                           dt, every, every), s.dx, s.dy).backward()
-    r = rho.clone().requires_grad_(True)
-    m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J = adjoint.kinetic_energy(adjoint.rollout(s, adjoint.project_fields(r, u, v, f[3], gamma), m,
-                                               dt, nsteps, every), s.dx, s.dy)
-    J.backward()
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t0
+    # launches of the reverse-mode kernels, autograd set-up), without and
+    # with recordings
+    run(every)
+    s.set_record(every)
+    run(every)
+    t_rec, J_rec, g_rec, r_rec = run(nsteps)
+    rec_bytes = s._rec.numel()
+    s.set_record(0)
+    t_all, J, gmu, r_all = run(nsteps)
+    # the recorded steps run the full-layout kernels, whose residuals differ
+    # from the forward's by a unit in the last place in a few entries
+    diff = {'rho_grad': ((r_rec - r_all).abs().max() / r_all.abs().max()).item(),
+            'mu_grad': abs(g_rec - gmu) / abs(gmu), 'J': abs(J_rec - J) / abs(J)}
     cs = n * n * 3 * nsteps
     return {'workload': 'double shear layer 256^2, Re 1000, %d steps with dt frozen, checkpoints '
                         'every %d; d KE / d (rho, u, v node fields, mu)' % (nsteps, every),
-            'forward_seconds': t_fwd, 'forward_backward_seconds': t_all,
-            'ratio_to_forward': t_all / t_fwd, 'forward_value': cs / t_fwd,
-            'value': cs / t_all, 'unit': UNIT + ' (forward-equivalent, with gradient)',
-            'J': J.item(), 'dJ_dmu': m.grad.item()}
+            'forward_seconds': t_fwd, 'forward_backward_seconds': t_rec,
+            'ratio_to_forward': t_rec / t_fwd, 'forward_value': cs / t_fwd,
+            'value': cs / t_rec, 'unit': UNIT + ' (forward-equivalent, with gradient)',
+            'recording_bytes': rec_bytes,
+            'recompute_in_step_adjoints': {'forward_backward_seconds': t_all,
+                                           'ratio_to_forward': t_all / t_fwd},
+            'recorded_vs_recomputed_rel_diff': diff, 'J': J, 'dJ_dmu': gmu}
 
 
 def main():

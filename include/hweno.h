@@ -315,6 +315,43 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar);
 
+/* Recorded steps: the step adjoint from a recording instead of a
+ * recomputation (single 2D grids; HBM spent to skip the three stage
+ * residuals hweno_rk_step_vjp evaluates).  A recording buffer holds nslots
+ * slots; each keeps the three ghosted stage inputs of one RK step and the
+ * full intermediates of their residuals (966 doubles per ghosted cell, plus
+ * the slot descriptors).
+ * hweno_record_bytes: size of a buffer for nslots slots.
+ * hweno_set_record: device buffer (owned by the caller, at least
+ *   hweno_record_bytes long; HWENO_E_WORKSPACE if shorter) for nslots slots;
+ *   nslots = 0 removes it.  Every slot starts unrecorded.
+ * hweno_rk_step_record: one SSP-RK3 step of the fixed size dt > 0 from U0
+ *   (device, D1) into U3 (device, D1; may not overlap U0), recorded in slot
+ *   `slot`.  The step is not checked for admissibility: it is meant to
+ *   repeat a step the forward pass has already taken.  Leaves the context
+ *   state alone.  Its residuals run the full-layout kernels of the
+ *   reverse mode, whose roundings differ from the forward's in a few
+ *   entries: U3 agrees with hweno_rk_step's result to within a unit or so in
+ *   the last place.
+ * hweno_rk_step_vjp_recorded: U0bar = (dU3/dU0)^T U3bar of the step recorded
+ *   in `slot`: the same bits as hweno_rk_step_vjp from that step's U0 and
+ *   dt.  *mu_bar as hweno_rk_step_vjp (the call synchronises); mu_bar = NULL
+ *   adds this step's mu adjoint to a device-side running sum instead, with
+ *   no synchronisation (hweno_take_mu_bar reads and clears it; a call with
+ *   a non-NULL mu_bar restarts it).  HWENO_E_INVAL for an unrecorded slot.
+ * The recordings use the buffer until the next hweno_rk_step_record of the
+ * slot or hweno_set_record; HWENO_E_INVAL as for hweno_rk_step_vjp. */
+HWENO_API hweno_status hweno_record_bytes(const hweno_ctx* ctx, int nslots, size_t* bytes);
+HWENO_API hweno_status hweno_set_record(hweno_ctx* ctx, void* buffer, size_t bytes, int nslots);
+HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* ctx, int slot, const double* U0,
+                                            double dt, double* U3);
+HWENO_API hweno_status hweno_rk_step_vjp_recorded(hweno_ctx* ctx, int slot,
+                                                  const double* U3bar, double* U0bar,
+                                                  double* mu_bar);
+/* The running sum of mu adjoints of hweno_rk_step_vjp_recorded calls made
+ * with mu_bar = NULL (host double), which is then cleared.  Synchronises. */
+HWENO_API hweno_status hweno_take_mu_bar(hweno_ctx* ctx, double* mu_bar);
+
 /* Per-kernel-class GPU time, measured with HIP events while timing is
  * enabled.  A class of one kernel has the kernel record the events at the
  * start and end of its execution (hipExtLaunchKernel: the dispatch is not

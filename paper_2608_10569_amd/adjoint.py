@@ -82,9 +82,21 @@ class _Rollout(torch.autograd.Function):
         want_mu = ctx.needs_input_grad[1]
         g = gU.contiguous()
         mu_bar = 0.0
+        record = getattr(s, 'record_slots', 0) >= every
+        if record:
+            s.take_mu_bar()                      # clear the device-side sum
         for seg in reversed(range(len(cps))):
             start = seg * every
             stop = min(ctx.nsteps, start + every)
+            if record:
+                # recompute the segment once more, recording every step, then
+                # run the step adjoints from the recordings
+                U = cps[seg]
+                for k in range(stop - start):
+                    U = s.rk_step_record(k, U, dt)
+                for k in reversed(range(stop - start)):   # mu-bar summed on the device
+                    g, _ = s.rk_step_vjp_recorded(k, g, want_mu=False)
+                continue
             states = [cps[seg]]
             s.set_state(cps[seg])
             for _ in range(start, stop - 1):     # recompute the segment
@@ -94,13 +106,18 @@ class _Rollout(torch.autograd.Function):
                 g, mub = s.rk_step_vjp(U, dt, g, want_mu=want_mu)
                 if want_mu:
                     mu_bar += mub
+        if record and want_mu:
+            mu_bar = s.take_mu_bar()
         gmu = torch.tensor(mu_bar, dtype=torch.float64, device=g.device) if want_mu else None
         return g, gmu, None, None, None, None
 
 
 def rollout(solver, U0, mu, dt, nsteps, every=20):
     """U after ``nsteps`` fixed steps dt from U0, differentiable in U0 and mu;
-    the backward keeps one state per ``every`` steps and recomputes the rest."""
+    the backward keeps one state per ``every`` steps and recomputes the rest.
+    With at least ``every`` recording slots on the solver (``set_record``)
+    the recomputation records each step's stage intermediates and the step
+    adjoints run from them (the same bits, no second recomputation)."""
     if nsteps < 1 or every < 1:
         raise ValueError('nsteps and every must be positive')
     if mu is None:

@@ -68,6 +68,14 @@ struct hweno_ctx {
     double* mu_dev = nullptr;
     double* X1 = nullptr;              // interior stage cotangents (12 per cell)
     double* X2 = nullptr;
+    // recorded steps (single 2D grid, caller's buffer): per slot the three
+    // stage inputs and their residual intermediates, described by rec_desc
+    // (host) / rec_ddesc (device, 3 per slot); rec_dt > 0 once recorded
+    char* rec_base = nullptr;
+    int rec_slots = 0;
+    std::vector<hw::Grid2> rec_desc;
+    hw::Grid2* rec_ddesc = nullptr;
+    std::vector<double> rec_dt;
     double t = 0.0;
     bool has_state = false;
     bool state_checked = false;        // the current state passed the admissibility check
@@ -358,6 +366,59 @@ void drop_graphs(hweno_ctx* c) {
 }
 
 // Schedule order, block tables and device grid array (synchronous).
+// Carves a recording buffer into nslots slots, each the three ghosted stage
+// inputs of one RK step and the full-layout intermediates of its three stage
+// residuals, then the slots' device descriptors (3 per slot: the grid's own,
+// with S[0..2] the slot's stage inputs, S[3] the grid's scratch state, and
+// the intermediate arrays of that stage).  base == nullptr: size only.
+size_t record_layout(const hweno_ctx* c, char* base, int nslots, std::vector<hw::Grid2>* desc,
+                     hw::Grid2** ddesc) {
+    size_t off = 0;
+    auto take = [&](size_t nd) -> hw::gdouble* {
+        hw::gdouble* p = base ? (hw::gdouble*)(base + off) : nullptr;
+        off += up(nd * sizeof(double));
+        return p;
+    };
+    const hw::Grid2& g = c->hg[0];
+    const size_t m = (size_t)g.ncell;
+    if (desc) desc->assign(3 * (size_t)nslots, g);
+    for (int sl = 0; sl < nslots; ++sl) {
+        hw::gdouble* S[3];
+        for (int k = 0; k < 3; ++k) S[k] = take(12 * m);
+        for (int k = 0; k < 3; ++k) {
+            hw::Grid2 d = g;
+            for (int q = 0; q < 3; ++q) d.S[q] = S[q];
+            d.S[3] = g.S[3];
+            d.xf = take(24 * m);
+            d.yf = take(24 * m);
+            d.xv = take(36 * m);
+            d.yv = take(36 * m);
+            d.vc = take(2 * hw::VC_B * m);
+            d.wb = take(6 * m);
+            d.vk = take(8 * m);
+            d.rb = take(18 * m);
+            d.gf = take(72 * m);
+            d.vf = take(8 * m);
+            d.fx = take(8 * m);
+            d.fy = take(8 * m);
+            if (desc) (*desc)[3 * (size_t)sl + k] = d;
+        }
+    }
+    char* dd = base ? base + off : nullptr;
+    off += up(3 * (size_t)nslots * sizeof(hw::Grid2));
+    if (ddesc) *ddesc = reinterpret_cast<hw::Grid2*>(dd);
+    return off;
+}
+
+hweno_status upload_record(hweno_ctx* c) {
+    if (c->rec_slots <= 0) return HWENO_OK;
+    record_layout(c, c->rec_base, c->rec_slots, &c->rec_desc, &c->rec_ddesc);
+    TRY(dev(hipMemcpyAsync(c->rec_ddesc, c->rec_desc.data(),
+                           c->rec_desc.size() * sizeof(hw::Grid2), hipMemcpyHostToDevice,
+                           c->stream)));
+    return dev(hipStreamSynchronize(c->stream));
+}
+
 hweno_status upload_grids(hweno_ctx* c) {
     const int n = (int)c->hg.size();
     c->order.resize(n);
@@ -412,6 +473,7 @@ hweno_status upload_grids(hweno_ctx* c) {
             c->blstage[k].dg = c->dstage + k;
         }
     }
+    if (!c->batch) TRY(upload_record(c));
     drop_graphs(c);
     return HWENO_OK;
 }
@@ -1379,6 +1441,107 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
         TRY(dev(hipStreamSynchronize(c->stream)));
     }
     return HWENO_OK;
+    GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// Recorded steps: the step adjoint from a recording instead of a recomputation
+// ---------------------------------------------------------------------------
+HWENO_API hweno_status hweno_record_bytes(const hweno_ctx* c, int nslots, size_t* bytes) {
+    GUARD_BEGIN
+    if (!c || !bytes || c->batch || c->dim() != 2 || nslots < 0) return HWENO_E_INVAL;
+    *bytes = record_layout(c, nullptr, nslots, nullptr, nullptr);
+    return HWENO_OK;
+    GUARD_END
+}
+
+HWENO_API hweno_status hweno_set_record(hweno_ctx* c, void* buffer, size_t bytes, int nslots) {
+    GUARD_BEGIN
+    if (!c || c->batch || c->dim() != 2 || nslots < 0) return HWENO_E_INVAL;
+    if (nslots > 0 && !buffer) return HWENO_E_INVAL;
+    if (nslots > 0 && bytes < record_layout(c, nullptr, nslots, nullptr, nullptr))
+        return HWENO_E_WORKSPACE;
+    c->rec_base = nslots > 0 ? static_cast<char*>(buffer) : nullptr;
+    c->rec_slots = nslots;
+    c->rec_desc.clear();
+    c->rec_ddesc = nullptr;
+    c->rec_dt.assign((size_t)nslots, 0.0);
+    if (!c->ws || nslots == 0) return HWENO_OK;
+    return upload_record(c);
+    GUARD_END
+}
+
+HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* c, int slot, const double* U0, double dt,
+                                            double* U3) {
+    GUARD_BEGIN
+    if (!c || !U0 || !U3 || c->batch || c->dim() != 2 || !(dt > 0.0) || !std::isfinite(dt))
+        return HWENO_E_INVAL;
+    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (slot < 0 || slot >= c->rec_slots || c->rec_desc.empty()) return HWENO_E_INVAL;
+    const hw::Grid2* dd = c->rec_ddesc + 3 * (size_t)slot;
+    const hw::Grid2& d0 = c->rec_desc[3 * (size_t)slot];
+    hw::BatchL b[3];
+    for (int k = 0; k < 3; ++k) {
+        b[k] = c->bl;
+        b[k].dg = dd + k;
+        b[k].full_grad = true;   // the step adjoint reads all six face gradients
+    }
+    c->rec_dt[slot] = 0.0;
+    TRY(dev(hw::launch_copy_in2(d0, U0, d0.S[0], c->stream)));
+    TRY(reset(c));
+    TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
+    for (int k = 0; k < 3; ++k) {   // stage k + 1 from input S[k] into S[k + 1]
+        TRY(dev(hw::launch_ghost2(b[k], k, c->stream, c->tm())));
+        TRY(residual(c, k, &b[k]));
+        TRY(update(c, k + 1, 0, k, k + 1, nullptr, nullptr, nullptr, &b[k]));
+    }
+    TRY(dev(hw::launch_copy_out2(d0, d0.S[3], U3, c->stream)));
+    c->rec_dt[slot] = dt;
+    return HWENO_OK;
+    GUARD_END
+}
+
+HWENO_API hweno_status hweno_rk_step_vjp_recorded(hweno_ctx* c, int slot, const double* U3bar,
+                                                  double* U0bar, double* mu_bar) {
+    GUARD_BEGIN
+    if (!c || !U3bar || !U0bar || c->batch || c->dim() != 2) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    if (slot < 0 || slot >= c->rec_slots || c->rec_desc.empty() || !(c->rec_dt[slot] > 0.0))
+        return HWENO_E_INVAL;
+    const double dt = c->rec_dt[slot];
+    const hw::Grid2* d = &c->rec_desc[3 * (size_t)slot];
+    const long long nint = (long long)d[0].nx * d[0].ny;
+    // the stage adjoints in reverse, seeded as in hweno_rk_step_vjp
+    hw::AdjIn A3{U3bar, U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0};
+    // mu_bar NULL: this step's mu adjoint joins the device-side running sum
+    TRY(dev(hw::launch_vjp2(d[2], A3, c->adj, d[2].S[2], c->X2, c->mu_dev, mu_bar ? 0 : 1,
+                            c->stream)));
+    TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
+    hw::AdjIn A2{c->X2, c->X2 + 4 * nint, 0.25 * dt, 0.25};
+    TRY(dev(hw::launch_vjp2(d[1], A2, c->adj, d[1].S[1], c->X1, c->mu_dev, 1, c->stream)));
+    TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
+    TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
+    hw::AdjIn A1{c->X1, c->X2 + 4 * nint, dt, 1.0};
+    TRY(dev(hw::launch_vjp2(d[0], A1, c->adj, d[0].S[0], U0bar, c->mu_dev, 1, c->stream)));
+    TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
+    if (mu_bar) {
+        TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream)));
+        TRY(dev(hipStreamSynchronize(c->stream)));
+    }
+    return HWENO_OK;
+    GUARD_END
+}
+
+HWENO_API hweno_status hweno_take_mu_bar(hweno_ctx* c, double* mu_bar) {
+    GUARD_BEGIN
+    if (!c || !mu_bar || c->batch) return HWENO_E_INVAL;
+    if (!c->ws) return HWENO_E_WORKSPACE;
+    static const double zero = 0.0;
+    TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream)));
+    TRY(dev(hipMemcpyAsync(c->mu_dev, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream)));
+    return dev(hipStreamSynchronize(c->stream));
     GUARD_END
 }
 

@@ -21,6 +21,8 @@ NOALLOC_BYTES = 256 << 20
 EXPORTS = ('hweno_default_options', 'hweno_create', 'hweno_destroy', 'hweno_workspace_bytes',
            'hweno_set_workspace', 'hweno_set_inflow_profile', 'hweno_set_inflow_stages',
            'hweno_rk_step_inflow', 'hweno_set_solid', 'hweno_set_solid_state', 'hweno_set_stream',
+           'hweno_record_bytes', 'hweno_set_record', 'hweno_rk_step_record',
+           'hweno_rk_step_vjp_recorded', 'hweno_take_mu_bar',
            'hweno_set_state', 'hweno_get_state',
            'hweno_residual', 'hweno_residual_noalloc', 'hweno_rk_step', 'hweno_rk_step_source',
            'hweno_residual_vjp',
@@ -110,6 +112,11 @@ def lib():
         L.hweno_rk_step_inflow.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Diag)]
         L.hweno_set_solid.argtypes = [vp, vp, ctypes.c_int]
         L.hweno_set_solid_state.argtypes = [vp, vp, dp]
+        L.hweno_record_bytes.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.hweno_set_record.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
+        L.hweno_rk_step_record.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, vp]
+        L.hweno_rk_step_vjp_recorded.argtypes = [vp, ctypes.c_int, vp, vp, dp]
+        L.hweno_take_mu_bar.argtypes = [vp, dp]
         L.hweno_set_state.argtypes = [vp, vp, ctypes.c_double]
         L.hweno_get_state.argtypes = [vp, vp, dp]
         L.hweno_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Diag)]
@@ -207,6 +214,8 @@ class Solver:
         self.set_stream(torch.cuda.current_stream(self.device).cuda_stream)
         self.state_shape = (3, 4, ny, nx) if self.dim == 2 else (2, 3, nx)
         self.vhat_shape = (8, ny, nx) if self.dim == 2 else (3, nx)
+        self.record_slots = 0
+        self._rec = None
 
     def set_stream(self, stream):
         check(lib().hweno_set_stream(self._h, ctypes.c_void_p(stream)))
@@ -346,6 +355,48 @@ class Solver:
         mu = ctypes.c_double(0.0)
         check(lib().hweno_rk_step_vjp(self._h, _ptr(U0), float(dt), _ptr(U3bar), _ptr(U0b),
                                       ctypes.byref(mu) if want_mu else None))
+        return U0b, (mu.value if want_mu else None)
+
+    def set_record(self, nslots):
+        """Device buffer for ``nslots`` recorded steps (0 frees it)."""
+        import torch
+        self._rec = None
+        check(lib().hweno_set_record(self._h, None, 0, 0))
+        self.record_slots = 0
+        if nslots <= 0:
+            return
+        n = ctypes.c_size_t()
+        check(lib().hweno_record_bytes(self._h, int(nslots), ctypes.byref(n)))
+        self._rec = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        check(lib().hweno_set_record(self._h, _ptr(self._rec), n.value, int(nslots)))
+        self.record_slots = int(nslots)
+
+    def rk_step_record(self, slot, U0, dt):
+        """U3 of one fixed step dt from U0, recorded in ``slot`` for
+        rk_step_vjp_recorded (the context state is left alone)."""
+        import torch
+        self._dev(U0)
+        U3 = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        check(lib().hweno_rk_step_record(self._h, int(slot), _ptr(U0), float(dt), _ptr(U3)))
+        return U3
+
+    def take_mu_bar(self):
+        """Running sum of the mu adjoints of rk_step_vjp_recorded calls made
+        with want_mu=False (cleared by the call)."""
+        mu = ctypes.c_double(0.0)
+        check(lib().hweno_take_mu_bar(self._h, ctypes.byref(mu)))
+        return mu.value
+
+    def rk_step_vjp_recorded(self, slot, U3bar, want_mu=True):
+        """(U0bar, mu_bar) of the step recorded in ``slot``; with
+        want_mu=False this step's mu adjoint joins the device-side sum that
+        take_mu_bar returns (no synchronisation)."""
+        import torch
+        self._dev(U3bar)
+        U0b = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        mu = ctypes.c_double(0.0)
+        check(lib().hweno_rk_step_vjp_recorded(self._h, int(slot), _ptr(U3bar), _ptr(U0b),
+                                               ctypes.byref(mu) if want_mu else None))
         return U0b, (mu.value if want_mu else None)
 
     def rk_step(self, dt=0.0):

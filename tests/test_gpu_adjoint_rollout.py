@@ -141,6 +141,22 @@ def test_rollout_checkpointing_is_exact():
         grads.append((U.grad.clone(), mu.grad.item(), J.item()))
     for g in grads[1:]:
         assert torch.equal(g[0], grads[0][0]) and g[1] == grads[0][1] and g[2] == grads[0][2]
+    # the backward from recorded steps (three and seven slots): the recorded
+    # recomputation advances the states with the full-layout kernels of the
+    # reverse mode, whose residuals can differ from the compact ones in the
+    # last bit of a few entries, so the gradient agrees to rounding
+    for every in (3, 7):
+        s.set_record(every)
+        U = U0.clone().requires_grad_(True)
+        mu = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
+        J = adjoint.kinetic_energy(adjoint.rollout(s, U, mu, dt, nsteps, every), s.dx, s.dy)
+        J.backward()
+        e = ((U.grad - grads[0][0]).abs().max() / grads[0][0].abs().max()).item()
+        print('recorded rollout, %d slots: gradient rel %.2e, mu %.2e' % (
+            every, e, abs(mu.grad.item() - grads[0][1]) / abs(grads[0][1])))
+        assert J.item() == grads[0][2]
+        assert e < 1e-12 and abs(mu.grad.item() - grads[0][1]) <= 1e-12 * abs(grads[0][1])
+    s.set_record(0)
     U = U0.clone().requires_grad_(True)
     mu = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
     X = U
@@ -272,3 +288,33 @@ def test_double_shear_layer_full_size():
                                           rel(gmu, fdm)))
     assert min(res) < 1e-6
     assert rel(gmu, fdm) < 1e-6
+
+
+def test_recorded_step_equals_recomputed_step():
+    """A recorded step's adjoint equals hweno_rk_step_vjp's bit for bit (both
+    evaluate the stages with the full-layout kernels), and its result equals
+    hweno_rk_step's to the last bit of a few entries (walls, and mu(T));
+    refused slots."""
+    rng = np.random.default_rng([2608, 79])
+    for seed, mu_exp in ((31, 0.0), (32, 0.76)):
+        U = workloads.random_smooth_2d(20, 16, seed=seed, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+        s = hweno.Solver(20, 16, extent=(0.0, 1.0, 0.0, 0.5), mu_ref=1 / 200, mu_exp=mu_exp,
+                         bc=('noslip', 'noslip', 'noslip', 'slip'))
+        dt = rule_dt(s, U)
+        s.set_state(to_dev(U))
+        s.rk_step(dt)
+        U3ref = s.get_state()[0].clone()
+        s.set_record(2)
+        U3 = s.rk_step_record(1, to_dev(U), dt)
+        assert ((U3 - U3ref).abs() <= 4e-16 * U3ref.abs().amax(dim=(-2, -1), keepdim=True)).all()
+        Wb = to_dev(rng.standard_normal(U.shape))
+        a, ma = s.rk_step_vjp(to_dev(U), dt, Wb)
+        b, mb = s.rk_step_vjp_recorded(1, Wb)
+        assert torch.equal(a, b) and ma == mb
+        with pytest.raises(hweno.HwenoError):
+            s.rk_step_vjp_recorded(0, Wb)                 # not recorded
+        with pytest.raises(hweno.HwenoError):
+            s.rk_step_vjp_recorded(2, Wb)                 # no such slot
+        s.set_record(0)
+        with pytest.raises(hweno.HwenoError):
+            s.rk_step_record(0, to_dev(U), dt)
