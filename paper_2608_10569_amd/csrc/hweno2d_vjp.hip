@@ -35,6 +35,20 @@ __device__ __forceinline__ bool interior(const Grid2& g, int j, int i) {
     return j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
 }
 
+// Whether face f (0 left, 1 right, 2 bottom, 3 top) of cell (j, i) is one of
+// the faces k_adj_flux visits (the faces of the interior cells): its trace
+// and gradient adjoints are then assigned there, and later kernels add to
+// them; the other slots the later kernels assign (or read as zero), so the
+// adjoint workspace needs no clearing.
+__device__ __forceinline__ bool flux_face(const Grid2& g, int j, int i, int f) {
+    if (f < 2) {
+        if (j < HALO || j >= HALO + g.ny) return false;
+        return f == 0 ? (i >= HALO && i <= HALO + g.nx) : (i >= HALO - 1 && i <= HALO + g.nx - 1);
+    }
+    if (i < HALO || i >= HALO + g.nx) return false;
+    return f == 2 ? (j >= HALO && j <= HALO + g.ny) : (j >= HALO - 1 && j <= HALO + g.ny - 1);
+}
+
 // residual adjoint of interior cell (j, i): F1, F2, F3 component c
 __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, int c, int j, int i) {
     const long long nint = (long long)g.nx * g.ny;
@@ -285,7 +299,8 @@ __global__ __launch_bounds__(6 * AG) void k_adj_grad(Grid2 g, AdjIn A, AdjWs W) 
     // adjoint of this component's 21 point values
     double yb[21];
 #pragma unroll
-    for (int p = 0; p < 12; ++p) yb[p] = g_ld(W.gfb, (p * 6 + s) * N + cell);
+    for (int p = 0; p < 12; ++p)
+        yb[p] = flux_face(g, j, i, p / 3) ? g_ld(W.gfb, (p * 6 + s) * N + cell) : 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         yb[12 + q] = shvb[0][(s * 9 + q) * AG + cl] + shvb[1][(s * 9 + q) * AG + cl];
@@ -404,12 +419,22 @@ __global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
 #pragma unroll
             for (int w = 0; w < 3; ++w) wb[w] = 0.5 * gw(G) * (W0b[w] + gx(G) * W1b[w]);
             adj::prim2_vjp(U, wb, Ub);
+            const bool add = flux_face(g, j, i, dir * 2 + (hi ? 1 : 0));
 #pragma unroll
-            for (int c = 0; c < 4; ++c) FB[(p * 4 + c) * N + cell] += Ub[c];
+            for (int c = 0; c < 4; ++c) {
+                double& x = FB[(p * 4 + c) * N + cell];
+                x = add ? x + Ub[c] : Ub[c];
+            }
         }
-    } else if (in_ring2(g, j, i)) {
+    } else if (!in_ring2(g, j, i)) {
+        // no weak moments here: the volume-value adjoints are zero
+        double* VB = task == 4 ? W.xvb : W.yvb;
+        for (int q = 0; q < 36; ++q) VB[q * N + cell] = 0.0;
+    } else {
         // wbar adjoint of this cell's own weak moments, to its volume values
+        // (added to the volume-flux adjoints on interior cells)
         const int dir = task - 4;
+        const bool add = interior(g, j, i);
         const double* V = dir == 0 ? g.xv : g.yv;
         double* VB = dir == 0 ? W.xvb : W.yvb;
         double wbb[3];
@@ -425,7 +450,10 @@ __global__ __launch_bounds__(6 * WM_CELLS) void k_adj_wmom(Grid2 g, AdjWs W) {
             for (int w = 0; w < 3; ++w) wb[w] = wq * wbb[w];
             adj::prim2_vjp(U, wb, Ub);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) VB[(q * 4 + c) * N + cell] += Ub[c];
+            for (int c = 0; c < 4; ++c) {
+                double& x = VB[(q * 4 + c) * N + cell];
+                x = add ? x + Ub[c] : Ub[c];
+            }
         }
     }
 }
@@ -881,50 +909,46 @@ __device__ __forceinline__ int ghost_src(int kind, int side, int d, int n) {
     return kind == 0 ? HALO + d - 1 : (kind == 1 ? HALO + n - 1 : HALO + n - d);
 }
 
-__global__ void k_adj_ghost_y(Grid2 g, AdjWs W) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)g.ny * g.NX) return;
-    const int r = HALO + (int)(t / g.NX), i = (int)(t % g.NX);
+// Component q of the adjoint at cell (r, i) of an interior row once the y
+// sweep is undone: its own value plus the ghost rows copied from it.
+__device__ __forceinline__ double ghost_y_gather(const Grid2& g, const AdjWs& W, int q, int r,
+                                                 int i) {
     const long long N = g.ncell;
-    const long long dst = (long long)r * g.NX + i;
+    double v = W.ubb[q * N + (long long)r * g.NX + i];
     for (int side = 0; side < 2; ++side) {
         const Side& sd = g.side[2 + side];
         for (int d = 1; d <= HALO; ++d) {
             if (ghost_src(sd.kind, side, d, g.ny) != r) continue;
             const int gj = side == 0 ? HALO - d : HALO + g.ny - 1 + d;
-            const long long gc = (long long)gj * g.NX + i;
-#pragma unroll
-            for (int q = 0; q < 12; ++q) W.ubb[q * N + dst] += sd.sign[q] * W.ubb[q * N + gc];
+            v += sd.sign[q] * W.ubb[q * N + (long long)gj * g.NX + i];
         }
     }
+    return v;
 }
 
-__global__ void k_adj_ghost_x(Grid2 g, AdjWs W) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)g.ny * g.nx) return;
-    const int j = HALO + (int)(t / g.nx), c0 = HALO + (int)(t % g.nx);
-    const long long N = g.ncell;
-    const long long dst = (long long)j * g.NX + c0;
-    for (int side = 0; side < 2; ++side) {
-        const Side& sd = g.side[side];
-        for (int d = 1; d <= HALO; ++d) {
-            if (ghost_src(sd.kind, side, d, g.nx) != c0) continue;
-            const int gi = side == 0 ? HALO - d : HALO + g.nx - 1 + d;
-            const long long gc = (long long)j * g.NX + gi;
-#pragma unroll
-            for (int q = 0; q < 12; ++q) W.ubb[q * N + dst] += sd.sign[q] * W.ubb[q * N + gc];
-        }
-    }
-}
-
-__global__ void k_adj_out(Grid2 g, AdjWs W, double* __restrict__ Ubar) {
+// Both sweeps undone for interior cell (j, c0), component q, written to the
+// caller's interior array: the y sweep's gather at the cell, then the x
+// ghost columns copied from it, each with its own y sweep's gather (the
+// corner ghost cells reach the interior through the x-ghost columns).
+__global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
+                                const double* __restrict__ add, double add_a) {
     const long long nint = (long long)g.nx * g.ny;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nint * 12) return;
     const int q = (int)(t / nint);
     const long long r = t % nint;
-    const int jj = (int)(r / g.nx), ii = (int)(r % g.nx);
-    Ubar[t] = W.ubb[q * g.ncell + (long long)(jj + HALO) * g.NX + ii + HALO];
+    const int j = HALO + (int)(r / g.nx), c0 = HALO + (int)(r % g.nx);
+    double v = ghost_y_gather(g, W, q, j, c0);
+    for (int side = 0; side < 2; ++side) {
+        const Side& sd = g.side[side];
+        for (int d = 1; d <= HALO; ++d) {
+            if (ghost_src(sd.kind, side, d, g.nx) != c0) continue;
+            const int gi = side == 0 ? HALO - d : HALO + g.nx - 1 + d;
+            v += sd.sign[q] * ghost_y_gather(g, W, q, j, gi);
+        }
+    }
+    if (add && q < 4) v += add_a * add[t];
+    Ubar[t] = v;
 }
 
 __global__ void k_fill(double* p, long long n, double v) {
@@ -933,17 +957,19 @@ __global__ void k_fill(double* p, long long n, double v) {
 }
 
 // mu-bar = fixed-order sum of the block partials (added to *out if acc)
-__global__ void k_mu_sum(const double* part, int n, double* out, int acc) {
+__global__ __launch_bounds__(256) void k_mu_sum(const double* part, int n, double* out, int acc) {
     __shared__ double sh[256];
+    const int t = threadIdx.x;
     double s = 0.0;
-    for (int q = threadIdx.x; q < n; q += 256) s += part[q];
-    sh[threadIdx.x] = s;
+    for (int q = t; q < n; q += 256) s += part[q];
+    sh[t] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int q = 0; q < 256; ++q) tot += sh[q];
-        *out = acc ? *out + tot : tot;
+    // pairwise tree in a fixed order
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
     }
+    if (t == 0) *out = acc ? *out + sh[0] : sh[0];
 }
 
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, long long n) {
@@ -967,8 +993,8 @@ long long adj_mu_partials2(const Grid2& g) {
 }
 
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
-                       double* mu_out, int mu_acc, hipStream_t st) {
-    k_fill<<<1024, 256, 0, st>>>(W.base, W.count, 0.0);
+                       double* mu_out, int mu_acc, hipStream_t st, const double* add,
+                       double add_a) {
     const unsigned bx = nb2((long long)(g.nx + 1) * g.ny, AF);
     const unsigned by = nb2((long long)g.nx * (g.ny + 1), AF);
     const unsigned bg = nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
@@ -993,9 +1019,7 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     k_adj_recon_a<<<brec, 8 * AC, 0, st>>>(g, A, W, S);
     k_adj_recon_b<<<brec, 8 * AC, 0, st>>>(g, W, S);
     k_adj_ugather<<<nb2(g.ncell, 256), 256, 0, st>>>(g, W);
-    k_adj_ghost_y<<<nb2((long long)g.ny * g.NX, 256), 256, 0, st>>>(g, W);
-    k_adj_ghost_x<<<nb2((long long)g.ny * g.nx, 256), 256, 0, st>>>(g, W);
-    k_adj_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar);
+    k_adj_ghost_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar, add, add_a);
     k_mu_sum<<<1, 256, 0, st>>>(W.mupart, (int)(bx + by + bg), mu_out, mu_acc);
     return hipGetLastError();
 }

@@ -1413,28 +1413,28 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     // (launched through bi when they are formed first)
     auto vjp_at = [&](int si, const hw::Grid2& gi, const hw::BatchL* bi, bool form,
                       const double* Rb, const double* Vb, double rs, double vs, double* out,
-                      int acc) {
+                      int acc, const double* add, double add_a) {
         if (form) {
             TRY(reset(c));
             TRY(ghost(c, si));
             TRY(residual(c, si, bi));
         }
         hw::AdjIn A{Rb, Vb, rs, vs};
-        return dev(hw::launch_vjp2(gi, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream));
+        return dev(hw::launch_vjp2(gi, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream, add,
+                                   add_a));
     };
-    // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified moments)
+    // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified
+    // moments); the averages' direct path 2/3 U3bar joins the output (U2bar)
     TRY(vjp_at(ic, keep ? c->stage[1] : g, keep ? &full_st[1] : &full, true, U3bar,
-               U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0));
-    TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
-    // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar
+               U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0, U3bar, 2.0 / 3.0));
+    // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar, plus 1/4 U2bar direct (U1bar)
     TRY(vjp_at(ib, keep ? c->stage[0] : g, &full, !keep, c->X2, c->X2 + 4 * nint, 0.25 * dt,
-               0.25, c->X1, 1));
-    TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
+               0.25, c->X1, 1, c->X2, 0.25));
     // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
-    // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar
-    TRY(vjp_at(ia, g, &full, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1));
-    TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
+    // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar, plus
+    // B(U0)-bar's averages direct
+    TRY(vjp_at(ia, g, &full, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1, c->X2, 1.0));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));
@@ -1516,15 +1516,14 @@ HWENO_API hweno_status hweno_rk_step_vjp_recorded(hweno_ctx* c, int slot, const 
     hw::AdjIn A3{U3bar, U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0};
     // mu_bar NULL: this step's mu adjoint joins the device-side running sum
     TRY(dev(hw::launch_vjp2(d[2], A3, c->adj, d[2].S[2], c->X2, c->mu_dev, mu_bar ? 0 : 1,
-                            c->stream)));
-    TRY(dev(hw::launch_axpy(c->X2, U3bar, 2.0 / 3.0, 4 * nint, c->stream)));      // U2bar
+                            c->stream, U3bar, 2.0 / 3.0)));                         // U2bar
     hw::AdjIn A2{c->X2, c->X2 + 4 * nint, 0.25 * dt, 0.25};
-    TRY(dev(hw::launch_vjp2(d[1], A2, c->adj, d[1].S[1], c->X1, c->mu_dev, 1, c->stream)));
-    TRY(dev(hw::launch_axpy(c->X1, c->X2, 0.25, 4 * nint, c->stream)));           // U1bar
+    TRY(dev(hw::launch_vjp2(d[1], A2, c->adj, d[1].S[1], c->X1, c->mu_dev, 1, c->stream, c->X2,
+                            0.25)));                                                // U1bar
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     hw::AdjIn A1{c->X1, c->X2 + 4 * nint, dt, 1.0};
-    TRY(dev(hw::launch_vjp2(d[0], A1, c->adj, d[0].S[0], U0bar, c->mu_dev, 1, c->stream)));
-    TRY(dev(hw::launch_axpy(U0bar, c->X2, 1.0, 4 * nint, c->stream)));
+    TRY(dev(hw::launch_vjp2(d[0], A1, c->adj, d[0].S[0], U0bar, c->mu_dev, 1, c->stream, c->X2,
+                            1.0)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));

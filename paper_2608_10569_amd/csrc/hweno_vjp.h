@@ -155,9 +155,12 @@ hipError_t launch_vjp1(const Grid1& g, const AdjIn& A, AdjWs1 W, const double* S
                        double* mu_out, int mu_acc, hipStream_t st);
 
 long long adj_mu_partials2(const Grid2& g);
-// mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar)
+// mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar).
+// add != nullptr: add_a * add[t] joins the cell-average adjoints (the first
+// 4 nx ny entries of Ubar), as an axpy after the call would.
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
-                       double* mu_out, int mu_acc, hipStream_t st);
+                       double* mu_out, int mu_acc, hipStream_t st, const double* add = nullptr,
+                       double add_a = 0.0);
 // y[0:n] += a x[0:n]
 hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
 // y[0:n] = a u[0:n] + b y[0:n] + x[0:n]
