@@ -358,8 +358,10 @@ def bench_developed(nsteps, t_dev=0.3):
 def bench_adjoint(nsteps=200, every=20):
     """Double shear layer: forward + checkpointed backward vs plain forward.
     The backward recomputes each segment once, recording every step's stage
-    intermediates (``every`` recording slots in HBM), and runs the step
-    adjoints from the recordings; the same gradient from recomputing every
+    intermediates (two banks of ``every`` recording slots in HBM, the next
+    segment recorded on a second stream while the current one's adjoints
+    run), and runs the step adjoints from the recordings; the same gradient
+    from recomputing every
     stage residual inside each step adjoint (stage intermediates of stages 2
     and 3 kept) is timed too."""
     import numpy as np
@@ -394,8 +396,8 @@ def bench_adjoint(nsteps=200, every=20):
     # launches of the reverse-mode kernels, autograd set-up), without and
     # with recordings
     run(every)
-    s.set_record(every)
-    run(every)
+    s.set_record(2 * every)
+    run(2 * every)
     t_rec, J_rec, g_rec, r_rec = run(nsteps)
     rec_bytes = s._rec.numel()
     s.set_record(0)

@@ -84,19 +84,10 @@ class _Rollout(torch.autograd.Function):
         mu_bar = 0.0
         record = getattr(s, 'record_slots', 0) >= every
         if record:
-            s.take_mu_bar()                      # clear the device-side sum
+            return _Rollout._backward_recorded(ctx, cps, g, want_mu)
         for seg in reversed(range(len(cps))):
             start = seg * every
             stop = min(ctx.nsteps, start + every)
-            if record:
-                # recompute the segment once more, recording every step, then
-                # run the step adjoints from the recordings
-                U = cps[seg]
-                for k in range(stop - start):
-                    U = s.rk_step_record(k, U, dt)
-                for k in reversed(range(stop - start)):   # mu-bar summed on the device
-                    g, _ = s.rk_step_vjp_recorded(k, g, want_mu=False)
-                continue
             states = [cps[seg]]
             s.set_state(cps[seg])
             for _ in range(start, stop - 1):     # recompute the segment
@@ -106,9 +97,57 @@ class _Rollout(torch.autograd.Function):
                 g, mub = s.rk_step_vjp(U, dt, g, want_mu=want_mu)
                 if want_mu:
                     mu_bar += mub
-        if record and want_mu:
-            mu_bar = s.take_mu_bar()
         gmu = torch.tensor(mu_bar, dtype=torch.float64, device=g.device) if want_mu else None
+        return g, gmu, None, None, None, None
+
+    @staticmethod
+    def _backward_recorded(ctx, cps, g, want_mu):
+        """Each segment is recomputed once more with every step recorded, and
+        the step adjoints start from the recordings.  With two banks of
+        ``every`` slots the recording of the segment before runs on a second
+        stream while the current segment's adjoints run: bank seg % 2 holds
+        segment seg, and a bank is recorded again only after the adjoints
+        that read it (the second stream waits for everything the main
+        stream has queued)."""
+        s, dt, every, nsteps = ctx.solver, ctx.dt, ctx.every, ctx.nsteps
+        main = torch.cuda.current_stream(g.device)
+        overlap = s.record_slots >= 2 * every
+        side = torch.cuda.Stream(g.device) if overlap else main
+
+        def bank(seg):
+            return (seg % 2) * every if overlap else 0
+
+        def record(seg):
+            start = seg * every
+            stop = min(nsteps, start + every)
+            side.wait_stream(main)
+            try:
+                with torch.cuda.stream(side):
+                    s.set_stream(side.cuda_stream)
+                    U = cps[seg]
+                    for k in range(stop - start):
+                        U = s.rk_step_record(bank(seg) + k, U, dt)
+                    done = torch.cuda.Event()
+                    done.record(side)
+            finally:
+                s.set_stream(main.cuda_stream)
+            return done, stop - start
+
+        s.take_mu_bar()                          # clear the device-side sum
+        nseg = len(cps)
+        pending = record(nseg - 1)
+        for seg in reversed(range(nseg)):
+            done, n = pending
+            if overlap and seg > 0:
+                pending = record(seg - 1)
+            main.wait_event(done)
+            for k in reversed(range(n)):         # mu-bar summed on the device
+                g, _ = s.rk_step_vjp_recorded(bank(seg) + k, g, want_mu=False)
+            if not overlap and seg > 0:
+                pending = record(seg - 1)
+        gmu = None
+        if want_mu:
+            gmu = torch.tensor(s.take_mu_bar(), dtype=torch.float64, device=g.device)
         return g, gmu, None, None, None, None
 
 
@@ -117,7 +156,10 @@ def rollout(solver, U0, mu, dt, nsteps, every=20):
     the backward keeps one state per ``every`` steps and recomputes the rest.
     With at least ``every`` recording slots on the solver (``set_record``)
     the recomputation records each step's stage intermediates and the step
-    adjoints run from them (the same bits, no second recomputation)."""
+    adjoints run from them (no second recomputation; the same step adjoints
+    bit for bit); with ``2 every`` slots the recording of the next segment
+    overlaps the adjoints of the current one on a second stream (the same
+    bits as one bank)."""
     if nsteps < 1 or every < 1:
         raise ValueError('nsteps and every must be positive')
     if mu is None:

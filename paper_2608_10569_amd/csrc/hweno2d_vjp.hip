@@ -17,7 +17,8 @@
 //   k_adj_recon_a  forward recompute; limiter and back-transform adjoints
 //   k_adj_recon_b  scalar HWENO, eigen-system and projection adjoints
 //   k_adj_ugather  gather of the state adjoint from the 3x3 stencils
-//   k_adj_ghost_*  adjoint of the ghost fill (Remark 4.1)
+//   k_adj_ghost_out adjoint of the ghost fill (Remark 4.1), written to the output
+//   k_mu_sum       fixed-order sum of the mu-adjoint block partials
 
 #include "hweno_adj.h"
 #include "hweno_vjp.h"
@@ -949,11 +950,6 @@ __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
     }
     if (add && q < 4) v += add_a * add[t];
     Ubar[t] = v;
-}
-
-__global__ void k_fill(double* p, long long n, double v) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (long long q = t; q < n; q += (long long)gridDim.x * blockDim.x) p[q] = v;
 }
 
 // mu-bar = fixed-order sum of the block partials (added to *out if acc)

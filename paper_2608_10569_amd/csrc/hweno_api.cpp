@@ -268,19 +268,15 @@ size_t layout(hweno_ctx* c, char* base) {
         g.fy = take(8 * m);
     }
     if (!c->batch) {
-        // reverse-mode workspace (zero-filled at the start of every adjoint call)
+        // reverse-mode workspace: every slot an adjoint call reads is written
+        // earlier in the same call (no clearing)
         const size_t m = (size_t)c->hg[0].ncell;
         hw::AdjWs& A = c->adj;
-        const size_t first = off;
         A.xfb = take(24 * m);
         A.yfb = take(24 * m);
         A.xvb = take(36 * m);
         A.yvb = take(36 * m);
         A.gfb = take(72 * m);
-        // only the arrays above are accumulated into or read where no kernel
-        // writes them; every slot of the ones below has one writer before it is read
-        A.base = A.xfb;
-        A.count = (long long)((off - first) / sizeof(double));
         A.rbc = take(102 * m);
         A.rbb = take(18 * m);
         A.uc = take(136 * m);

@@ -15,8 +15,6 @@ struct AdjIn {
 
 // Adjoint workspace (component-major over the ghosted grid, like Grid2/Grid1).
 struct AdjWs {
-    double* base;       // start of the zero-filled region (xfb .. gfb)
-    long long count;    // doubles in that region
     double* xfb;        // 24 / 12: face-trace adjoints
     double* yfb;        // 24
     double* xvb;        // 36: volume-value adjoints
