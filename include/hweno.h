@@ -421,7 +421,12 @@ HWENO_API hweno_status hweno_batch_get_diag(hweno_ctx* ctx, int i, hweno_diag* o
 /* Work per block of the tunable kernels and the instance order of a launch. */
 typedef struct hweno_tiles {
     int recon;      /* cells per block of the characteristic reconstruction: 16 or 32 */
-    int grad;       /* cells per block of the gradient reconstruction: 32 or 64 */
+    int grad;       /* cells per block of the gradient reconstruction: 32 or 64; 0:
+                       the weak moments (eqs. 3.6-3.8) are formed inside the gradient
+                       kernel, per 16 x 4 tile of cells and the ring around it, in
+                       LDS instead of through HBM (same results; the reverse mode's
+                       forward launches keep the separate kernels, whose weak
+                       moments the adjoint reads) */
     int flux;       /* faces per block of the face-flux kernels: 64 or 128; 0: no
                        separate flux kernels -- the update kernel forms the fluxes
                        of each 32 x 8 tile of cells in LDS (same results) */
@@ -438,7 +443,8 @@ HWENO_API hweno_status hweno_set_tiles(hweno_ctx* ctx, const hweno_tiles* tiles)
 /* Autotuner: times `reps` residual evaluations (each with a stage update) of
  * the current state(s) for each candidate tile of every tunable kernel, keeps
  * the fastest per kernel (for the face fluxes: split or fused into the
- * update, by the time of fluxes plus update), then the faster block order
+ * update, by the time of fluxes plus update; for the weak moments and the
+ * gradients: split or fused, by the time of both), then the faster block order
  * and (batches) the faster instance order, and sets them; `chosen` may be
  * NULL.  Needs the state(s) set; leaves them unchanged.  Synchronises. */
 HWENO_API hweno_status hweno_autotune(hweno_ctx* ctx, int reps, hweno_tiles* chosen);

@@ -654,6 +654,7 @@ __global__ __launch_bounds__(8 * RC_CELLS) void k_recon2(Batch bt, int si) {
 // Primitives (u, v, e) of face point p of `cell` (one reciprocal of rho).
 __device__ __forceinline__ void prim3(const double* F, long long N, long long cell, int p,
                                       double* w) {
+#pragma clang fp contract(off)
     const double r = F[(p * 4 + 0) * N + cell];
     const double ir = rcp(r);
     const double u = F[(p * 4 + 1) * N + cell] * ir;
@@ -661,6 +662,45 @@ __device__ __forceinline__ void prim3(const double* F, long long N, long long ce
     w[0] = u;
     w[1] = v;
     w[2] = F[(p * 4 + 3) * N + cell] * ir - 0.5 * (u * u + v * v);
+}
+
+// Gauss average W0 = sum_G w_G h_G and first moment W1 = sum_G w_G x_G h_G of
+// the interface average h = (w- + w+)/2 of (u, v, e) over the face between
+// cell `lo` (its upper points 3..5) and cell `hi` (its lower points 0..2).
+// Mirror-symmetric forms: exchanging the outer points gives the same W0 and
+// the negated W1.  Contraction is fixed in the source, so every kernel that
+// forms the weak moments gets the same bits.
+__device__ __forceinline__ void face_wavg(const double* F, long long N, long long lo, long long hi,
+                                          double* W0, double* W1) {
+#pragma clang fp contract(off)
+    double h[3][3];   // [G][w]
+#pragma unroll
+    for (int G = 0; G < 3; ++G) {
+        double a[3], c[3];
+        prim3(F, N, lo, 3 + G, a);
+        prim3(F, N, hi, G, c);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) h[G][w] = 0.5 * (a[w] + c[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        W0[w] = fma(GW0, h[0][w] + h[2][w], GW1 * h[1][w]);
+        W1[w] = (GW0 * GS) * (h[2][w] - h[0][w]);
+    }
+}
+
+// The three weak moments (eqs. (3.6)-(3.8)) of d w / d x_l of a cell from the
+// face data of its lower and upper l-faces and its w-bar; ih = 1/dx_l.
+// m[0] = moment 0, m[1] = xi moment, m[2] = eta moment.
+__device__ __forceinline__ void cell_wmom(double W0lo, double W0hi, double W1lo, double W1hi,
+                                          double wbl, double ih, int l, double* m) {
+#pragma clang fp contract(off)
+    const double d0 = (W0hi - W0lo) * ih;                    // moment 0
+    const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
+    const double d1 = (W1hi - W1lo) * ih;                    // transverse moment
+    m[0] = d0;
+    m[1] = l ? d1 : dm;
+    m[2] = l ? dm : d1;
 }
 
 // Block = RB_TX x RB_TY cells of the region (rows and columns 2 .. N-3).
@@ -706,26 +746,16 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
         }
         const double* F = xd ? g.xf : g.yf;
         const long long lo = (long long)jlo * g.NX + ilo, hi = (long long)j * g.NX + i;
-        double h[3][3];   // [G][w]
-#pragma unroll
-        for (int G = 0; G < 3; ++G) {
-            double a[3], c[3];
-            prim3(F, N, lo, 3 + G, a);
-            prim3(F, N, hi, G, c);
-#pragma unroll
-            for (int w = 0; w < 3; ++w) h[G][w] = 0.5 * (a[w] + c[w]);
-        }
-        // mirror-symmetric forms (outer points exchanged: same W0, -W1)
+        double W0[3], W1[3];
+        face_wavg(F, N, lo, hi, W0, W1);
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
-            const double W0 = fma(GW0, h[0][w] + h[2][w], GW1 * h[1][w]);
-            const double W1 = (GW0 * GS) * (h[2][w] - h[0][w]);
             if (xd) {
-                hx[w][j - j0][i - i0] = W0;
-                hx[3 + w][j - j0][i - i0] = W1;
+                hx[w][j - j0][i - i0] = W0[w];
+                hx[3 + w][j - j0][i - i0] = W1[w];
             } else {
-                hy[w][j - j0][i - i0] = W0;
-                hy[3 + w][j - j0][i - i0] = W1;
+                hy[w][j - j0][i - i0] = W0[w];
+                hy[3 + w][j - j0][i - i0] = W1[w];
             }
         }
     }
@@ -743,23 +773,122 @@ __global__ __launch_bounds__(RB_TX * RB_TY) void k_rbar2(Batch bt) {
             const double W0hi = l ? hy[w][ty + 1][tx] : hx[w][ty][tx + 1];
             const double W1lo = l ? hy[3 + w][ty][tx] : hx[3 + w][ty][tx];
             const double W1hi = l ? hy[3 + w][ty + 1][tx] : hx[3 + w][ty][tx + 1];
-            const double wbl = g.wb[(l * 3 + w) * N + cell];
-            const double d0 = (W0hi - W0lo) * ih;                    // moment 0
-            const double dm = (0.5 * (W0hi + W0lo) - wbl) * ih;      // moment along l
-            const double d1 = (W1hi - W1lo) * ih;                    // transverse moment
+            double m[3];
+            cell_wmom(W0lo, W0hi, W1lo, W1hi, g.wb[(l * 3 + w) * N + cell], ih, l, m);
             double* R = g.rb + ((l * 3 + w) * 3) * N + cell;
-            R[0] = d0;
-            R[N] = l ? d1 : dm;       // xi moment
-            R[2 * N] = l ? dm : d1;   // eta moment
+            R[0] = m[0];
+            R[N] = m[1];       // xi moment
+            R[2 * N] = m[2];   // eta moment
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Gradient reconstruction (eq. (3.9)) on halo ring 1; block 32 cells x 6
-// (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also form
-// the volume-flux quadratures of eq. (3.2).
+// Gradient reconstruction (eq. (3.9)) on halo ring 1; block 32 or 64 cells
+// x 6 (thread s = 2*w + l reconstructs d w / d x_l).  Interior cells also
+// form the volume-flux quadratures of eq. (3.2).
 // ---------------------------------------------------------------------------
+// Gradient reconstruction of component s = 2 w + l of one cell from its 17
+// stencil data a (eq. (3.9)), the face gradients it stores, and on interior
+// cells the volume-flux quadrature of eq. (3.2).  The block has NC cells x 6
+// components (cell cl, component s); shv holds 6 x 9 x NC doubles of LDS.
+// Every thread of the block calls it (it holds barriers).
+template <int NC, bool VarMu, bool FULL>
+__device__ __forceinline__ void grad_body(const Grid2& g, double* shv, const double* a, int cl,
+                                          int s, bool valid, int j, int i) {
+    const Consts& K = g.K;
+    const long long N = g.ncell;
+    const long long cell = (long long)j * g.NX + i;
+    double C[15];
+    hweno2d(a, grad_consts(K), C);
+    double fo[12], vo[9];
+    eval_xface(C, fo);
+    eval_yface(C, fo + 6);
+    eval_vol(C, vo);
+    if constexpr (FULL) {
+        if (valid) {
+#pragma unroll
+            for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
+        }
+    } else {
+        // the face fluxes need three combinations of the six gradients per
+        // face point (stress_combos): the x-face points, then the y-face
+        // points, meet in LDS, and thread s forms outputs s, s + 6, s + 12 of
+        // the 18 of each half
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) shv[(s * 6 + q) * NC + cl] = fo[half * 6 + q];
+            __syncthreads();
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int o = s + 6 * r, q = o / 3, z = o % 3;
+                    double sq[6], dc[3];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) sq[c] = shv[(c * 6 + q) * NC + cl];
+                    if (half == 0) stress_combos<0>(sq, dc);
+                    else stress_combos<1>(sq, dc);
+                    g.gf[((half * 6 + q) * 3 + z) * N + cell] = dc[z];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
+    // volume-flux quadratures of interior cells: the reconstruction kernel
+    // left the Gauss sum of the convective flux and the velocities (and
+    // viscosities) at the points; the viscous part is summed here over the
+    // cell's 6 threads, 2 directions x 9 points, 3 points each (thread s:
+    // direction s / 3, points 3 (s % 3) .. 3 (s % 3) + 2), and the partial
+    // sums meet in LDS.  The point data are loaded before the barrier.
+    const bool dy = s >= 3;
+    const int q0 = 3 * (s % 3);
+    const double* VC = g.vc + (long long)(dy ? VC_B : 0) * N + cell;
+    double pu[3], pv[3], pm[3];
+    if (inter) {
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq) {
+            pu[qq] = VC[(4 + q0 + qq) * N];
+            pv[qq] = VC[(13 + q0 + qq) * N];
+            pm[qq] = VarMu ? VC[(22 + q0 + qq) * N] : K.mu_ref;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * NC + cl] = vo[q];
+    __syncthreads();
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (inter) {
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq) {
+            const int q = q0 + qq;
+            const double wq = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
+            double sq[6], f[3];
+#pragma unroll
+            for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * NC + cl];
+            visc2_dir(K, pu[qq], pv[qq], pm[qq], sq, dy, f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += wq * f[c];
+        }
+    }
+    __syncthreads();   // every read of the gradient values is done
+#pragma unroll
+    for (int c = 0; c < 3; ++c) shv[(s * 3 + c) * NC + cl] = acc[c];
+    __syncthreads();
+    if (inter && s < 2) {
+        const double* VS = g.vc + (long long)s * VC_B * N + cell;
+        g.vf[(s * 4) * N + cell] = VS[0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double t0 = shv[((3 * s + 0) * 3 + c) * NC + cl];
+            const double t1 = shv[((3 * s + 1) * 3 + c) * NC + cl];
+            const double t2 = shv[((3 * s + 2) * 3 + c) * NC + cl];
+            g.vf[(s * 4 + 1 + c) * N + cell] = VS[(1 + c) * N] + (t0 + t1 + t2);
+        }
+    }
+}
+
+
 template <int GR_CELLS, bool VarMu, bool FULL>
 __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
     __shared__ double shv[6 * 9 * GR_CELLS];
@@ -797,93 +926,129 @@ __global__ __launch_bounds__(6 * GR_CELLS) void k_grad2(Batch bt) {
         a[9 + e] = R1[nb];
         a[13 + e] = R2[nb];
     }
-    double C[15];
-    hweno2d(a, grad_consts(K), C);
-    double fo[12], vo[9];
-    eval_xface(C, fo);
-    eval_yface(C, fo + 6);
-    eval_vol(C, vo);
-    if constexpr (FULL) {
-        if (valid) {
-#pragma unroll
-            for (int p = 0; p < 12; ++p) g.gf[(p * 6 + s) * N + cell] = fo[p];
+    grad_body<GR_CELLS, VarMu, FULL>(g, shv, a, cl, s, valid, j, i);
+}
+
+// ---------------------------------------------------------------------------
+// Weak moments and gradient reconstruction in one kernel (HWENO-GR, face
+// gradients in the three combinations).  A block takes RG_TX x RG_TY cells of
+// the gradient region and forms the weak moments of those cells and of the
+// ring around them in LDS (the ring is formed again by the neighbouring
+// tiles): first the interface data of every face of the ring's cells, then
+// their 18 weak moments, then the gradient reconstruction reads its 3x3
+// stencils from LDS.  Same arithmetic as k_rbar2 followed by k_grad2, without
+// the weak moments' round trip through HBM.
+// ---------------------------------------------------------------------------
+constexpr int RG_TX = 16, RG_TY = 4, RG_CELLS = RG_TX * RG_TY;
+constexpr int RG_RX = RG_TX + 2, RG_RY = RG_TY + 2;                   // tile + ring
+constexpr int RG_NXF = RG_RY * (RG_RX + 1), RG_NYF = (RG_RY + 1) * RG_RX;   // faces
+constexpr int RG_LDS_A = 6 * (RG_NXF + RG_NYF) + 18 * RG_RY * RG_RX;
+constexpr int RG_LDS = RG_LDS_A > 54 * RG_CELLS ? RG_LDS_A : 54 * RG_CELLS;
+
+template <bool VarMu>
+__global__ __launch_bounds__(6 * RG_CELLS) void k_rgrad2(Batch bt) {
+    // phase 1: hx[6][RY][RX + 1] and hy[6][RY + 1][RX] (W0 for w = 0..2, then
+    // W1), rbs[18][RY][RX] (index (l * 3 + w) * 3 + moment); phase 2: the
+    // gradient body's exchange over the same memory
+    __shared__ double lds[RG_LDS];
+    double* const hx = lds;
+    double* const hy = hx + 6 * RG_NXF;
+    double* const rbs = hy + 6 * RG_NYF;
+    const Loc lc = locate(bt);
+    const Grid2& gsrc = bt.g[lc.p];   // arrays indexed at run time are read from here
+    if (!gsrc.st->active) return;
+    const Grid2 g = gsrc;
+    const long long N = g.ncell;
+    const int tiles_x = (g.NX - 6 + RG_TX - 1) / RG_TX;
+    const int i0 = 3 + (lc.b % tiles_x) * RG_TX;   // first cell of the tile
+    const int j0 = 3 + (lc.b / tiles_x) * RG_TY;
+    constexpr int NT = 6 * RG_CELLS;
+    // interface data of the faces of the ring's cells (j0 - 1 + r, i0 - 1 + c);
+    // cells of weak moments lie in rows and columns 2 .. N - 3
+    for (int t = threadIdx.x; t < RG_NXF + RG_NYF; t += NT) {
+        const bool xd = t < RG_NXF;
+        const int q = xd ? t : t - RG_NXF;
+        int r, c, i, j, ilo, jlo;
+        if (xd) {   // face i - 1/2 of row j
+            r = q / (RG_RX + 1);
+            c = q % (RG_RX + 1);
+            j = j0 - 1 + r;
+            i = i0 - 1 + c;
+            ilo = i - 1;
+            jlo = j;
+            if (j > g.NY - 3 || i > g.NX - 2) continue;
+        } else {    // face j - 1/2 of column i
+            r = q / RG_RX;
+            c = q % RG_RX;
+            j = j0 - 1 + r;
+            i = i0 - 1 + c;
+            ilo = i;
+            jlo = j - 1;
+            if (i > g.NX - 3 || j > g.NY - 2) continue;
         }
-    } else {
-        // the face fluxes need three combinations of the six gradients per
-        // face point (stress_combos): the x-face points, then the y-face
-        // points, meet in LDS, and thread s forms outputs s, s + 6, s + 12 of
-        // the 18 of each half
+        double W0[3], W1[3];
+        face_wavg(xd ? g.xf : g.yf, N, (long long)jlo * g.NX + ilo, (long long)j * g.NX + i, W0,
+                  W1);
+        double* H = xd ? hx : hy;
+        const int plane = xd ? RG_NXF : RG_NYF;
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) shv[(s * 6 + q) * GR_CELLS + cl] = fo[half * 6 + q];
-            __syncthreads();
-            if (valid) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int o = s + 6 * r, q = o / 3, z = o % 3;
-                    double sq[6], dc[3];
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) sq[c] = shv[(c * 6 + q) * GR_CELLS + cl];
-                    if (half == 0) stress_combos<0>(sq, dc);
-                    else stress_combos<1>(sq, dc);
-                    g.gf[((half * 6 + q) * 3 + z) * N + cell] = dc[z];
-                }
-            }
-            __syncthreads();
+        for (int w = 0; w < 3; ++w) {
+            H[w * plane + q] = W0[w];
+            H[(3 + w) * plane + q] = W1[w];
         }
     }
-    const bool inter = valid && j >= HALO && j < HALO + g.ny && i >= HALO && i < HALO + g.nx;
-    // volume-flux quadratures of interior cells: the reconstruction kernel
-    // left the Gauss sum of the convective flux and the velocities (and
-    // viscosities) at the points; the viscous part is summed here over the
-    // cell's 6 threads, 2 directions x 9 points, 3 points each (thread s:
-    // direction s / 3, points 3 (s % 3) .. 3 (s % 3) + 2), and the partial
-    // sums meet in LDS.  The point data are loaded before the barrier.
-    const bool dy = s >= 3;
-    const int q0 = 3 * (s % 3);
-    const double* VC = g.vc + (long long)(dy ? VC_B : 0) * N + cell;
-    double pu[3], pv[3], pm[3];
-    if (inter) {
-#pragma unroll
-        for (int qq = 0; qq < 3; ++qq) {
-            pu[qq] = VC[(4 + q0 + qq) * N];
-            pv[qq] = VC[(13 + q0 + qq) * N];
-            pm[qq] = VarMu ? VC[(22 + q0 + qq) * N] : K.mu_ref;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) shv[(s * 9 + q) * GR_CELLS + cl] = vo[q];
     __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (inter) {
-#pragma unroll
-        for (int qq = 0; qq < 3; ++qq) {
-            const int q = q0 + qq;
-            const double wq = (q / 3 == 1 ? GW1 : GW0) * (q % 3 == 1 ? GW1 : GW0);
-            double sq[6], f[3];
-#pragma unroll
-            for (int z = 0; z < 6; ++z) sq[z] = shv[(z * 9 + q) * GR_CELLS + cl];
-            visc2_dir(K, pu[qq], pv[qq], pm[qq], sq, dy, f);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += wq * f[c];
+    // weak moments of the ring's cells: one task per (cell, l, w)
+    for (int t = threadIdx.x; t < 6 * RG_RY * RG_RX; t += NT) {
+        const int lw = t / (RG_RY * RG_RX), rc = t % (RG_RY * RG_RX);
+        const int l = lw / 3, w = lw % 3;
+        const int r = rc / RG_RX, c = rc % RG_RX;
+        const int j = j0 - 1 + r, i = i0 - 1 + c;
+        if (j > g.NY - 3 || i > g.NX - 3) continue;
+        double W0lo, W0hi, W1lo, W1hi;
+        if (l == 0) {
+            const int f = r * (RG_RX + 1) + c;
+            W0lo = hx[w * RG_NXF + f];
+            W0hi = hx[w * RG_NXF + f + 1];
+            W1lo = hx[(3 + w) * RG_NXF + f];
+            W1hi = hx[(3 + w) * RG_NXF + f + 1];
+        } else {
+            const int f = r * RG_RX + c;
+            W0lo = hy[w * RG_NYF + f];
+            W0hi = hy[w * RG_NYF + f + RG_RX];
+            W1lo = hy[(3 + w) * RG_NYF + f];
+            W1hi = hy[(3 + w) * RG_NYF + f + RG_RX];
         }
-    }
-    __syncthreads();   // every read of the gradient values is done
+        double m[3];
+        cell_wmom(W0lo, W0hi, W1lo, W1hi, g.wb[(l * 3 + w) * N + (long long)j * g.NX + i],
+                  l ? g.K.idy : g.K.idx, l, m);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) shv[(s * 3 + c) * GR_CELLS + cl] = acc[c];
+        for (int k = 0; k < 3; ++k) rbs[(lw * 3 + k) * (RG_RY * RG_RX) + rc] = m[k];
+    }
     __syncthreads();
-    if (inter && s < 2) {
-        const double* VS = g.vc + (long long)s * VC_B * N + cell;
-        g.vf[(s * 4) * N + cell] = VS[0];
+    // gradient reconstruction: cell cl of the tile, component s = 2 w + l
+    const int cl = threadIdx.x % RG_CELLS;
+    const int s = threadIdx.x / RG_CELLS;
+    const int w = s >> 1, l = s & 1;
+    const int ty = cl / RG_TX, tx = cl % RG_TX;
+    const int j = j0 + ty, i = i0 + tx;
+    const bool valid = j <= g.NY - 4 && i <= g.NX - 4;
+    const double* R = rbs + (long long)((l * 3 + w) * 3) * (RG_RY * RG_RX);
+    double a[17];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double t0 = shv[((3 * s + 0) * 3 + c) * GR_CELLS + cl];
-            const double t1 = shv[((3 * s + 1) * 3 + c) * GR_CELLS + cl];
-            const double t2 = shv[((3 * s + 2) * 3 + c) * GR_CELLS + cl];
-            g.vf[(s * 4 + 1 + c) * N + cell] = VS[(1 + c) * N] + (t0 + t1 + t2);
-        }
+    for (int q = 0; q < 9; ++q) {
+        const int o = (ty + 1 + q / 3 - 1) * RG_RX + (tx + 1 + q % 3 - 1);
+        a[q] = valid ? R[o] : 0.0;
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = 2 * e + 1;
+        const int o = (ty + 1 + q / 3 - 1) * RG_RX + (tx + 1 + q % 3 - 1);
+        a[9 + e] = valid ? R[RG_RY * RG_RX + o] : 0.0;
+        a[13 + e] = valid ? R[2 * RG_RY * RG_RX + o] : 0.0;
+    }
+    __syncthreads();   // the weak moments are in registers; the exchange reuses the LDS
+    grad_body<RG_CELLS, VarMu, false>(g, lds, a, cl, s, valid, valid ? j : 3, valid ? i : 3);
 }
 
 // The two Gauss moments of a face flux that the assembly of eq. (3.2) takes
@@ -1436,7 +1601,15 @@ void batch_blocks(const Grid2* hg, int n, const Tiles& t, int* out) {
                            ((g.NY - 4 + RB_TY - 1) / RB_TY);
                     per = 1;
                     break;
-                case KB_GRAD: work = (long long)(g.NX - 6) * (g.NY - 6); per = t.grad; break;
+                case KB_GRAD:    // the split kernel (32 cells per block with the fused one chosen)
+                    work = (long long)(g.NX - 6) * (g.NY - 6);
+                    per = t.grad ? t.grad : 32;
+                    break;
+                case KB_RGRAD:   // tiles of RG_TX x RG_TY cells of the gradient region
+                    work = (long long)((g.NX - 6 + RG_TX - 1) / RG_TX) *
+                           ((g.NY - 6 + RG_TY - 1) / RG_TY);
+                    per = 1;
+                    break;
                 case KB_FLUX0:   // none when the update kernel forms the fluxes
                     work = t.flux ? (long long)(g.nx + 1) * g.ny : 0;
                     per = t.flux ? t.flux : 1;
@@ -1546,10 +1719,16 @@ hipError_t launch_residual2(const BatchL& b, int si, hipStream_t st, Timer* tm) 
         if (b.var_mu) tlaunch(tm, KC_RECON, k_recon2<32, false, true>, nr, 256, st, ar, si);
         else tlaunch(tm, KC_RECON, k_recon2<32>, nr, 256, st, ar, si);
     }
-    if (!b.dr) {   // HWENO-GR: weak-derivative moments, then their reconstruction
+    if (!b.dr && !b.full_grad && b.tiles.grad == 0) {
+        // HWENO-GR, weak moments formed inside the gradient kernel
+        const Batch ag = b.arg(KB_RGRAD);
+        if (b.var_mu) tlaunch(tm, KC_GRAD, k_rgrad2<true>, b.blocks(KB_RGRAD), 6 * RG_CELLS, st, ag);
+        else tlaunch(tm, KC_GRAD, k_rgrad2<false>, b.blocks(KB_RGRAD), 6 * RG_CELLS, st, ag);
+    } else if (!b.dr) {   // HWENO-GR: weak-derivative moments, then their reconstruction
         tlaunch(tm, KC_RBAR, k_rbar2, b.blocks(KB_RBAR), RB_TX * RB_TY, st, b.arg(KB_RBAR));
         const Batch ag = b.arg(KB_GRAD);
-        if (b.full_grad) {   // the reverse mode reads all six gradients
+        if (b.full_grad) {   // the reverse mode reads all six gradients (and the adjoint
+                             // the weak moments)
             if (b.tiles.grad == 64) {
                 if (b.var_mu) tlaunch(tm, KC_GRAD, k_grad2<64, true, true>, ng, 384, st, ag);
                 else tlaunch(tm, KC_GRAD, k_grad2<64, false, true>, ng, 384, st, ag);

@@ -1671,7 +1671,7 @@ HWENO_API hweno_status hweno_get_tiles(const hweno_ctx* c, hweno_tiles* t) {
 HWENO_API hweno_status hweno_set_tiles(hweno_ctx* c, const hweno_tiles* t) {
     GUARD_BEGIN
     if (!c || !t || c->dim() != 2) return HWENO_E_INVAL;
-    if ((t->recon != 16 && t->recon != 32) || (t->grad != 32 && t->grad != 64) ||
+    if ((t->recon != 16 && t->recon != 32) || (t->grad != 0 && t->grad != 32 && t->grad != 64) ||
         (t->flux != 0 && t->flux != 64 && t->flux != 128) || (t->order != 0 && t->order != 1) ||
         (t->xcd != 0 && t->xcd != 1))
         return HWENO_E_INVAL;
@@ -1731,8 +1731,9 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         c->timer.reset();
         return HWENO_OK;
     };
-    // candidate 2 differs in the flux path only: fused into the update
-    const hw::Tiles cand[3] = {{16, 32, 64, 1}, {32, 64, 128, 1}, {16, 32, 0, 1}};
+    // candidate 2 differs in the flux path (fused into the update) and in the
+    // gradient kernel (weak moments formed inside it)
+    const hw::Tiles cand[3] = {{16, 32, 64, 1}, {32, 64, 128, 1}, {16, 0, 0, 1}};
     double ms[3][hw::KC_COUNT];
     for (int q = 0; q < 3; ++q) {
         c->tiles = cand[q];
@@ -1745,7 +1746,12 @@ HWENO_API hweno_status hweno_autotune(hweno_ctx* c, int reps, hweno_tiles* chose
         fu[q] = ms[q][hw::KC_FLUX] + ms[q][hw::KC_UPDATE] + ms[q][hw::KC_FLUXUP];
     hw::Tiles best;
     best.recon = ms[0][hw::KC_RECON] <= ms[1][hw::KC_RECON] ? cand[0].recon : cand[1].recon;
-    best.grad = ms[0][hw::KC_GRAD] <= ms[1][hw::KC_GRAD] ? cand[0].grad : cand[1].grad;
+    // weak moments + gradients: the split kernels (32 or 64 cells) or the fused one
+    int gq = 0;
+    for (int q = 1; q < 3; ++q)
+        if (ms[q][hw::KC_RBAR] + ms[q][hw::KC_GRAD] < ms[gq][hw::KC_RBAR] + ms[gq][hw::KC_GRAD])
+            gq = q;
+    best.grad = cand[gq].grad;
     const int fq = fu[2] < std::min(fu[0], fu[1]) ? 2 : (fu[0] <= fu[1] ? 0 : 1);
     best.flux = cand[fq].flux;
     c->tiles = best;

@@ -204,7 +204,7 @@ inline void tend(Timer* t, hipStream_t st) { if (t) t->end(st); }
 // block of the instance in slot p (start[n] = the launch's block count).
 // ---------------------------------------------------------------------------
 enum { KB_GHOST = 0, KB_RECON, KB_RBAR, KB_GRAD, KB_FLUX0, KB_FLUX1, KB_CELLS,
-       KB_FLUXUP, KB_COUNT };
+       KB_FLUXUP, KB_RGRAD, KB_COUNT };
 
 struct Batch {
     const Grid2* g;
@@ -217,7 +217,8 @@ struct Batch {
 // Work per block of the tunable kernels (cells, cells, faces).
 struct Tiles {
     int recon = 32;   // 16 or 32
-    int grad = 32;    // 32 or 64
+    int grad = 32;    // 32 or 64; 0: weak moments formed in the gradient kernel
+                      // (tiles of 16 x 4 cells)
     int flux = 0;     // 64 or 128; 0: face fluxes formed inside the update kernel
     int xcd = 1;      // 1: each XCD takes a contiguous range of a launch's blocks
 };
@@ -238,7 +239,8 @@ struct BatchL {
     // most of their input just before them (reconstruction, gradients), so
     // their first blocks read what is still in L2 and the memory-side cache;
     // the next stage's reconstruction then again runs opposite to them.
-    unsigned rev = (1u << KB_RBAR) | (1u << KB_FLUX0) | (1u << KB_FLUX1) | (1u << KB_FLUXUP);
+    unsigned rev = (1u << KB_RBAR) | (1u << KB_FLUX0) | (1u << KB_FLUX1) | (1u << KB_FLUXUP) |
+                   (1u << KB_RGRAD);
     Batch arg(int k) const {
         return Batch{dg, dstart + k * (n + 1), n, tiles.xcd, (int)((rev >> k) & 1u)};
     }

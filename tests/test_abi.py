@@ -108,7 +108,8 @@ def test_tile_defaults_and_validation_without_device():
     base = t.as_dict()
     assert base == dict(recon=32, grad=32, flux=0, order=0, xcd=1)
     for change, code in ((dict(flux=64), 0), (dict(flux=128), 0), (dict(recon=16, grad=32), 0),
-                         (dict(order=1, xcd=0), 0), (dict(recon=64), 1), (dict(grad=16), 1),
+                         (dict(order=1, xcd=0), 0), (dict(grad=0), 0), (dict(recon=64), 1),
+                         (dict(grad=16), 1),
                          (dict(flux=32), 1), (dict(order=2), 1), (dict(xcd=2), 1)):
         v = dict(base, **change)
         tt = hweno.TilesC(v['recon'], v['grad'], v['flux'], v['order'], v['xcd'])

@@ -82,7 +82,8 @@ def test_batch_mixed_viscosity_laws_equal_single_grids():
     states = states[:3]
     probs[1] = dict(probs[1], mu_exp=0.7, T_ref=1.0 / 1.4)
     for tiles in (dict(recon=32, grad=64, flux=0, order=0, xcd=1),
-                  dict(recon=32, grad=32, flux=64, order=0, xcd=1)):
+                  dict(recon=32, grad=32, flux=64, order=0, xcd=1),
+                  dict(recon=32, grad=0, flux=0, order=0, xcd=1)):
         b = run_batch(probs, states, 4, tiles)
         for i, (p, U) in enumerate(zip(probs, states)):
             ref, t, steps, _ = single_run(p, U, 4)
@@ -95,7 +96,9 @@ def test_batch_mixed_viscosity_laws_equal_single_grids():
 @pytest.mark.parametrize('tiles', [dict(recon=16, grad=64, flux=128, order=1, xcd=1),
                                    dict(recon=32, grad=32, flux=64, order=1, xcd=0),
                                    dict(recon=16, grad=32, flux=128, order=0, xcd=0),
-                                   dict(recon=32, grad=64, flux=0, order=1, xcd=1)])
+                                   dict(recon=32, grad=64, flux=0, order=1, xcd=1),
+                                   dict(recon=16, grad=0, flux=0, order=1, xcd=1),
+                                   dict(recon=32, grad=0, flux=64, order=0, xcd=0)])
 def test_batch_tiles_do_not_change_results(tiles):
     probs, states = mixed_problems()
     a = run_batch(probs, states, 3)
@@ -114,7 +117,7 @@ def test_single_grid_tiles_and_autotune():
     s = hweno.Solver(30, 22, mu_ref=0.01)
     s.set_state(to_dev(U))
     chosen = s.autotune(reps=2)
-    assert chosen['recon'] in (16, 32) and chosen['grad'] in (32, 64)
+    assert chosen['recon'] in (16, 32) and chosen['grad'] in (0, 32, 64)
     assert chosen['flux'] in (0, 64, 128)
     assert chosen['xcd'] in (0, 1)
     assert torch.equal(s.get_state()[0], to_dev(U))          # the tuner leaves the state alone

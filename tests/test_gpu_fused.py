@@ -1,10 +1,13 @@
-"""Face fluxes formed inside the update kernel (tiles flux = 0: one kernel per
-tile of 32 x 8 cells keeps the fluxes of the tile's faces in LDS) against the
-split path (two face-flux kernels writing HBM, then the update kernel).  The
-tiles change no result, so the two paths must give the same bits: residual,
-modified moments, diagnostics and RK steps, on sizes whose last tile is
-ragged in x, in y or both, with walls, outflow, a masked domain, source
-moments and a strong shock where the positivity limiter acts."""
+"""Fused kernels against the split path: face fluxes formed inside the update
+kernel (tiles flux = 0: one kernel per tile of 32 x 8 cells keeps the fluxes
+of the tile's faces in LDS, against two face-flux kernels writing HBM, then
+the update kernel), and weak moments formed inside the gradient kernel
+(tiles grad = 0: per tile of 16 x 4 cells and its ring, in LDS, against the
+weak-moment kernel writing HBM, then the gradient kernel).  The tiles change
+no result, so the paths must give the same bits: residual, modified moments,
+diagnostics and RK steps, on sizes whose last tile is ragged in x, in y or
+both, with walls, outflow, a masked domain, source moments and a strong
+shock where the positivity limiter acts."""
 
 import numpy as np
 import pytest
@@ -16,32 +19,34 @@ from paper_2608_10569_amd import hweno, workloads  # noqa: E402
 pytestmark = pytest.mark.gpu
 DEV = 'cuda:0'
 SPLIT = dict(recon=16, grad=32, flux=64, order=0, xcd=1)
-FUSED = dict(recon=16, grad=32, flux=0, order=0, xcd=1)
+VARIANTS = {'flux': dict(SPLIT, flux=0), 'grad': dict(SPLIT, grad=0),
+            'both': dict(SPLIT, grad=0, flux=0)}
 
 
 def to_dev(U):
     return torch.from_numpy(np.ascontiguousarray(U)).to(DEV)
 
 
-def pair(nx, ny, **kw):
+def pair(nx, ny, variant='both', **kw):
     a = hweno.Solver(nx, ny, **kw)
     b = hweno.Solver(nx, ny, **kw)
     a.set_tiles(**SPLIT)
-    b.set_tiles(**FUSED)
-    assert b.tiles()['flux'] == 0
+    b.set_tiles(**VARIANTS[variant])
+    assert b.tiles() == VARIANTS[variant]
     return a, b
 
 
 DIAG_KEYS = ('alpha_star', 'beta_max', 'min_rho', 'min_p', 'pp_cells', 'dt')
 
 
+@pytest.mark.parametrize('variant', list(VARIANTS))
 @pytest.mark.parametrize('shape', [(4, 4), (32, 8), (33, 9), (37, 13), (64, 16), (100, 41)])
 @pytest.mark.parametrize('bc', [('periodic',) * 4, ('outflow', 'slip', 'noslip', 'outflow')])
-def test_fused_residual_same_bits(shape, bc):
+def test_fused_residual_same_bits(shape, bc, variant):
     nx, ny = shape
-    print('residual %dx%d %s' % (nx, ny, bc[0]), flush=True)
+    print('residual %dx%d %s %s' % (nx, ny, bc[0], variant), flush=True)
     U = to_dev(workloads.random_smooth_2d(nx, ny, seed=nx * 7 + ny, noise=1e-3))
-    a, b = pair(nx, ny, mu_ref=0.01, bc=bc)
+    a, b = pair(nx, ny, variant, mu_ref=0.01, bc=bc)
     Ra, Va, da = a.residual(U)
     Rb, Vb, db = b.residual(U)
     assert torch.equal(Ra, Rb) and torch.equal(Va, Vb)
