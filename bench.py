@@ -71,10 +71,10 @@ FLOPS = {'recon': 7049, 'grad': 3428, 'rbar': 414, 'flux': 560, 'update': 400,
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
 # and for the kernels as they are now: e.g. recon with 32-cell tiles reads
 # 53.0 MB and writes 436.8 MB per launch.
-TRAFFIC_BYTES = {('recon', 16): 485793001, ('recon', 32): 489850960,
-                 ('grad', 32): 452673258, ('grad', 64): 431288905,
-                 ('rbar', None): 317537487, ('update', None): 228200086,
-                 ('fluxup', None): 618917909}
+TRAFFIC_BYTES = {('recon', 16): 485727236, ('recon', 32): 483043051,
+                 ('grad', 32): 432885712, ('grad', 64): 431268299, ('grad', 0): 715273789,
+                 ('rbar', None): 315149506, ('update', None): 227677481,
+                 ('fluxup', None): 618245338}
 # Algorithmic HBM bytes per cell-stage of the whole path if every input were
 # read once and every output written once (stage average: 256 B residual
 # in/out + the RK bases of stages 2 and 3).
@@ -87,8 +87,9 @@ def pipeline_hbm(tiles, value):
     the rate they imply at the measured throughput."""
     if tiles.get('flux') != 0:   # split face-flux kernels have no entry in the table
         return None
-    parts = [('recon', tiles.get('recon')), ('rbar', None), ('grad', tiles.get('grad')),
-             ('fluxup', None)]
+    parts = [('recon', tiles.get('recon')), ('grad', tiles.get('grad')), ('fluxup', None)]
+    if tiles.get('grad') != 0:   # the fused gradient kernel forms the weak moments itself
+        parts.append(('rbar', None))
     if any(p not in TRAFFIC_BYTES for p in parts):
         return None
     per_cell = sum(TRAFFIC_BYTES[p] for p in parts) / (NX * NY)

@@ -939,6 +939,13 @@ __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
     const int q = (int)(t / nint);
     const long long r = t % nint;
     const int j = HALO + (int)(r / g.nx), c0 = HALO + (int)(r % g.nx);
+    // every ghost cell copies one of the HALO cells next to a side
+    if (c0 >= 2 * HALO && c0 < g.nx && j >= 2 * HALO && j < g.ny) {
+        double v = W.ubb[q * g.ncell + (long long)j * g.NX + c0];
+        if (add && q < 4) v += add_a * add[t];
+        Ubar[t] = v;
+        return;
+    }
     double v = ghost_y_gather(g, W, q, j, c0);
     for (int side = 0; side < 2; ++side) {
         const Side& sd = g.side[side];
@@ -956,8 +963,18 @@ __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
 __global__ __launch_bounds__(256) void k_mu_sum(const double* part, int n, double* out, int acc) {
     __shared__ double sh[256];
     const int t = threadIdx.x;
+    // each thread sums its partials q = t, t + 256, ... in order; the loads
+    // of eight of them are issued together
     double s = 0.0;
-    for (int q = t; q < n; q += 256) s += part[q];
+    int q = t;
+    for (; q + 7 * 256 < n; q += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[q + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < n; q += 256) s += part[q];
     sh[t] = s;
     __syncthreads();
     // pairwise tree in a fixed order
