@@ -289,8 +289,12 @@ HWENO_API hweno_status hweno_rk_step_source(hweno_ctx* ctx, double dt, const dou
  * Uses the workspace (the forward intermediates are recomputed); with a
  * non-NULL mu_bar the call synchronises.  Reverse-mode part of the
  * differentiable rollout (the paper's
- * scheme of eq. (3.2); adjoint of its Sec. 3 residual).  HWENO_E_INVAL also
- * for a context with options.gradients = 1 (DR) or a solid mask. */
+ * scheme of eq. (3.2); adjoint of its Sec. 3 residual).  Masked grids
+ * (hweno_set_solid): solid cells carry no residual, so Rbar and Vbar there
+ * are ignored; the adjoint of the mirror fill (Remark 4.1 applied inside the
+ * grid) sends the solid cells' share to their mirror sources, and Ubar is
+ * zero on every solid cell.  HWENO_E_INVAL also for a context with
+ * options.gradients = 1 (DR). */
 HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const double* Rbar,
                                           const double* Vbar, double* Ubar, double* mu_bar);
 
@@ -308,10 +312,17 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* ctx, const double* U, const
  * recomputed (five residual evaluations per call), with keep_stages = 1 the
  * second and third stage keep theirs (three); the results are the same bits.
  * U3bar must not overlap U0.
+ * Masked grids: each stage fills the solid cells next to the fluid from
+ * their mirror sources in place and leaves every solid cell at that filled
+ * input, so U3 there is the mirror image of the last stage input (fluid
+ * values, with the wall signs) and U3bar on solid cells flows back to those
+ * sources; a caller that takes solid cells as no data passes zeros there.
+ * U0bar is zero on the solid cells next to the fluid (their input values are
+ * overwritten).
  * Uses the workspace; leaves the context state alone; with a non-NULL
  * mu_bar the call synchronises.  HWENO_E_INVAL for dt <= 0 (and, as for
- * hweno_residual_vjp, for DR contexts or a solid mask).  1D grids always
- * recompute (five residual evaluations per call). */
+ * hweno_residual_vjp, for DR contexts).  1D grids always recompute (five
+ * residual evaluations per call). */
 HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, double dt,
                                          const double* U3bar, double* U0bar, double* mu_bar);
 
@@ -340,7 +351,8 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, doubl
  *   no synchronisation (hweno_take_mu_bar reads and clears it; a call with
  *   a non-NULL mu_bar restarts it).  HWENO_E_INVAL for an unrecorded slot.
  * The recordings use the buffer until the next hweno_rk_step_record of the
- * slot or hweno_set_record; HWENO_E_INVAL as for hweno_rk_step_vjp. */
+ * slot or hweno_set_record; HWENO_E_INVAL as for hweno_rk_step_vjp, and for
+ * masked grids (their steps are not recorded). */
 HWENO_API hweno_status hweno_record_bytes(const hweno_ctx* ctx, int nslots, size_t* bytes);
 HWENO_API hweno_status hweno_set_record(hweno_ctx* ctx, void* buffer, size_t bytes, int nslots);
 HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* ctx, int slot, const double* U0,

@@ -50,10 +50,17 @@ __device__ __forceinline__ bool flux_face(const Grid2& g, int j, int i, int f) {
     return f == 2 ? (j >= HALO && j <= HALO + g.ny) : (j >= HALO - 1 && j <= HALO + g.ny - 1);
 }
 
-// residual adjoint of interior cell (j, i): F1, F2, F3 component c
+// Solid cell of a masked grid (interior index t)
+__device__ __forceinline__ bool solid_cell(const Grid2& g, long long t) {
+    return g.solid && g.solid[t];
+}
+
+// residual adjoint of interior cell (j, i): F1, F2, F3 component c (zero on
+// the solid cells of a masked grid, which carry no residual)
 __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, int c, int j, int i) {
     const long long nint = (long long)g.nx * g.ny;
-    return A.rs * A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
+    const long long t = (long long)(j - HALO) * g.nx + (i - HALO);
+    return solid_cell(g, t) ? 0.0 : A.rs * A.Rb[(m * 4 + c) * nint + t];
 }
 
 // Logical index of this block: XCD-aware (each XCD takes a contiguous range
@@ -641,9 +648,9 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon_a(Grid2 g, AdjIn A, AdjWs 
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ub[6 + q] = valid ? VB[(q * 4 + k) * N + cell] : 0.0;
         const long long nint = (long long)g.nx * g.ny;
-        Ub[15] = (inter && A.Vb)
-                     ? A.vs * A.Vb[(b * 4 + k) * nint + (long long)(j - HALO) * g.nx + (i - HALO)]
-                     : 0.0;
+        const long long ti = (long long)(j - HALO) * g.nx + (i - HALO);
+        Ub[15] = (inter && A.Vb && !solid_cell(g, ti)) ? A.vs * A.Vb[(b * 4 + k) * nint + ti]
+                                                        : 0.0;
     }
     shr[bk * AC + cl] = th1b;
     shx[bk * AC + cl] = th2b;
@@ -932,17 +939,25 @@ __device__ __forceinline__ double ghost_y_gather(const Grid2& g, const AdjWs& W,
 // ghost columns copied from it, each with its own y sweep's gather (the
 // corner ghost cells reach the interior through the x-ghost columns).
 __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
-                                const double* __restrict__ add, double add_a) {
+                                const double* __restrict__ add, double add_a,
+                                const double* __restrict__ pass) {
     const long long nint = (long long)g.nx * g.ny;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nint * 12) return;
     const int q = (int)(t / nint);
     const long long r = t % nint;
     const int j = HALO + (int)(r / g.nx), c0 = HALO + (int)(r % g.nx);
+    // a stage's direct term: fluid cells (averages) or, on a masked grid,
+    // solid cells (every component: a stage leaves them at its filled input)
+    const bool sol = solid_cell(g, r);
     // every ghost cell copies one of the HALO cells next to a side
     if (c0 >= 2 * HALO && c0 < g.nx && j >= 2 * HALO && j < g.ny) {
         double v = W.ubb[q * g.ncell + (long long)j * g.NX + c0];
-        if (add && q < 4) v += add_a * add[t];
+        if (sol) {
+            if (pass) v += pass[t];
+        } else if (add && q < 4) {
+            v += add_a * add[t];
+        }
         Ubar[t] = v;
         return;
     }
@@ -955,8 +970,47 @@ __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
             v += sd.sign[q] * ghost_y_gather(g, W, q, j, gi);
         }
     }
-    if (add && q < 4) v += add_a * add[t];
+    if (sol) {
+        if (pass) v += pass[t];
+    } else if (add && q < 4) {
+        v += add_a * add[t];
+    }
     Ubar[t] = v;
+}
+
+// Adjoint of the mirror fill of a masked grid's solid cells (k_solid2):
+// each mirror source gathers sign * adjoint of the solid cells copied from it
+// (in the list's order), then every listed solid cell's adjoint is zero (its
+// value was overwritten).  Ubar in the interior layout.
+__global__ void k_adj_solid_gather(Grid2 g, AdjWs W, double* __restrict__ Ubar) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)W.nsrc * 12) return;
+    const int u = (int)(t / 12), q = (int)(t % 12);
+    const int m = q / 4, c = q % 4;
+    const long long nint = (long long)g.nx * g.ny;
+    auto interior = [&](int gi) -> long long {
+        return (long long)(gi / g.NX - HALO) * g.nx + (gi % g.NX - HALO);
+    };
+    const long long s = interior(W.ssrcu[u]);
+    double acc = Ubar[q * nint + s];
+    for (int k = W.sstart[u]; k < W.sstart[u + 1]; ++k) {
+        const int e = W.sord[k];
+        const int dir = g.sdir[e];
+        const bool vel = g.solid_wall == 4 ? (c == 1 || c == 2) : (c == 1 + dir);
+        const bool mom = m == 1 + dir;
+        const double sg = (vel != mom) ? -1.0 : 1.0;
+        acc += sg * Ubar[q * nint + interior(g.sdst[e])];
+    }
+    Ubar[q * nint + s] = acc;
+}
+
+__global__ void k_adj_solid_zero(Grid2 g, double* __restrict__ Ubar) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.nsolid * 12) return;
+    const int e = (int)(t / 12), q = (int)(t % 12);
+    const int gi = g.sdst[e];
+    const long long nint = (long long)g.nx * g.ny;
+    Ubar[q * nint + (long long)(gi / g.NX - HALO) * g.nx + (gi % g.NX - HALO)] = 0.0;
 }
 
 // mu-bar = fixed-order sum of the block partials (added to *out if acc)
@@ -1007,7 +1061,7 @@ long long adj_mu_partials2(const Grid2& g) {
 
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
                        double* mu_out, int mu_acc, hipStream_t st, const double* add,
-                       double add_a) {
+                       double add_a, const double* pass) {
     const unsigned bx = nb2((long long)(g.nx + 1) * g.ny, AF);
     const unsigned by = nb2((long long)g.nx * (g.ny + 1), AF);
     const unsigned bg = nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
@@ -1032,7 +1086,13 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     k_adj_recon_a<<<brec, 8 * AC, 0, st>>>(g, A, W, S);
     k_adj_recon_b<<<brec, 8 * AC, 0, st>>>(g, W, S);
     k_adj_ugather<<<nb2(g.ncell, 256), 256, 0, st>>>(g, W);
-    k_adj_ghost_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar, add, add_a);
+    k_adj_ghost_out<<<nb2((long long)g.nx * g.ny * 12, 256), 256, 0, st>>>(g, W, Ubar, add, add_a,
+                                                                            pass);
+    if (g.nsolid > 0) {   // masked grid: the mirror fill, undone
+        if (W.nsrc > 0)
+            k_adj_solid_gather<<<nb2((long long)W.nsrc * 12, 256), 256, 0, st>>>(g, W, Ubar);
+        k_adj_solid_zero<<<nb2((long long)g.nsolid * 12, 256), 256, 0, st>>>(g, Ubar);
+    }
     k_mu_sum<<<1, 256, 0, st>>>(W.mupart, (int)(bx + by + bg), mu_out, mu_acc);
     return hipGetLastError();
 }

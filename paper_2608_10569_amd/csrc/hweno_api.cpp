@@ -104,6 +104,10 @@ struct hweno_ctx {
     int* sdst_dev = nullptr;
     int* ssrc_dev = nullptr;
     int* sdir_dev = nullptr;
+    // the mirror list grouped by source, for the reverse mode (AdjWs::ssrcu ..)
+    int* ssrcu_dev = nullptr;
+    int* sstart_dev = nullptr;
+    int* sord_dev = nullptr;
     // allocation-free residual (hweno_residual_noalloc): the descriptors it
     // copies into the library's static scratch, kept here so that the copies
     // read host memory that outlives the call
@@ -298,6 +302,9 @@ size_t layout(hweno_ctx* c, char* base) {
         c->sdst_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
         c->ssrc_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
         c->sdir_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
+        c->ssrcu_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
+        c->sstart_dev = reinterpret_cast<int*>(take_bytes((nint + 1) * sizeof(int)));
+        c->sord_dev = reinterpret_cast<int*>(take_bytes(nint * sizeof(int)));
         if (c->i0().opt.keep_stages) {
             for (int k = 0; k < 2; ++k) {
                 hw::Grid2& st = c->stage[k];
@@ -505,6 +512,8 @@ hweno_status upload_solid(hweno_ctx* c) {
     g.nsolid = 0;
     g.solid_wall = c->solid_wall;
     for (int k = 0; k < 4; ++k) g.fixed_state[k] = c->fixed_cons[k];
+    c->adj.ssrcu = c->adj.sstart = c->adj.sord = nullptr;
+    c->adj.nsrc = 0;
     if (c->solid_host.empty()) return HWENO_OK;
     TRY(dev(hipMemcpyAsync(c->solid_dev, c->solid_host.data(), c->solid_host.size(),
                            hipMemcpyHostToDevice, c->stream)));
@@ -522,6 +531,33 @@ hweno_status upload_solid(hweno_ctx* c) {
     g.ssrc = (const HW_GLOBAL int*)c->ssrc_dev;
     g.sdir = (const HW_GLOBAL int*)c->sdir_dev;
     g.nsolid = (int)n;
+    // the reverse mode gathers by mirror source: the entries with a source,
+    // grouped by it (ascending source, then list order)
+    std::vector<int> ord;
+    for (size_t e = 0; e < n; ++e)
+        if (c->ssrc_host[e] >= 0) ord.push_back((int)e);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return c->ssrc_host[a] < c->ssrc_host[b]; });
+    std::vector<int> srcu, start;
+    for (size_t k = 0; k < ord.size(); ++k) {
+        if (k == 0 || c->ssrc_host[ord[k]] != c->ssrc_host[ord[k - 1]]) {
+            srcu.push_back(c->ssrc_host[ord[k]]);
+            start.push_back((int)k);
+        }
+    }
+    start.push_back((int)ord.size());
+    if (!srcu.empty() && c->ssrcu_dev) {
+        TRY(dev(hipMemcpyAsync(c->ssrcu_dev, srcu.data(), srcu.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+        TRY(dev(hipMemcpyAsync(c->sstart_dev, start.data(), start.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+        TRY(dev(hipMemcpyAsync(c->sord_dev, ord.data(), ord.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream)));
+        c->adj.ssrcu = c->ssrcu_dev;
+        c->adj.sstart = c->sstart_dev;
+        c->adj.sord = c->sord_dev;
+        c->adj.nsrc = (int)srcu.size();
+    }
     return dev(hipStreamSynchronize(c->stream));
 }
 
@@ -1301,7 +1337,7 @@ HWENO_API hweno_status hweno_residual_vjp(hweno_ctx* c, const double* U, const d
                                           const double* Vbar, double* Ubar, double* mu_bar) {
     GUARD_BEGIN
     if (!c || !U || !Rbar || !Ubar || c->batch) return HWENO_E_INVAL;
-    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
+    if (c->i0().opt.gradients != 0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (c->dim() == 1) {   // the step's stage buffer 2 holds U (the state is kept)
         TRY(dev(hw::launch_copy_in1(c->g1, U, c->S1[2], c->stream)));
@@ -1345,7 +1381,7 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     GUARD_BEGIN
     if (!c || !U0 || !U3bar || !U0bar || !(dt > 0.0) || !std::isfinite(dt) || c->batch)
         return HWENO_E_INVAL;
-    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
+    if (c->i0().opt.gradients != 0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (c->dim() == 1) {
         // U0, U1, U2 in stage buffers 2, 3, 4 (the state in buffer 0 is kept);
@@ -1409,7 +1445,7 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
     // (launched through bi when they are formed first)
     auto vjp_at = [&](int si, const hw::Grid2& gi, const hw::BatchL* bi, bool form,
                       const double* Rb, const double* Vb, double rs, double vs, double* out,
-                      int acc, const double* add, double add_a) {
+                      int acc, const double* add, double add_a, const double* pass) {
         if (form) {
             TRY(reset(c));
             TRY(ghost(c, si));
@@ -1417,20 +1453,23 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* c, const double* U0, double 
         }
         hw::AdjIn A{Rb, Vb, rs, vs};
         return dev(hw::launch_vjp2(gi, A, c->adj, g.S[si], out, c->mu_dev, acc, c->stream, add,
-                                   add_a));
+                                   add_a, pass));
     };
     // stage 3: seeds 2/3 dt U3bar (residual) and 2/3 U3bar (modified
     // moments); the averages' direct path 2/3 U3bar joins the output (U2bar)
+    // (a masked grid's solid cells pass each stage's output adjoint through)
     TRY(vjp_at(ic, keep ? c->stage[1] : g, keep ? &full_st[1] : &full, true, U3bar,
-               U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0, U3bar, 2.0 / 3.0));
+               U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0, c->X2, 0, U3bar, 2.0 / 3.0,
+               U3bar));
     // stage 2: seeds 1/4 dt U2bar and 1/4 U2bar, plus 1/4 U2bar direct (U1bar)
     TRY(vjp_at(ib, keep ? c->stage[0] : g, &full, !keep, c->X2, c->X2 + 4 * nint, 0.25 * dt,
-               0.25, c->X1, 1, c->X2, 0.25));
+               0.25, c->X1, 1, c->X2, 0.25, c->X2));
     // B(U0)-bar = 1/3 U3bar + 3/4 U2bar + U1bar (into X2)
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     // stage 1: residual seed dt U1bar, modified-moment seed B(U0)-bar, plus
     // B(U0)-bar's averages direct
-    TRY(vjp_at(ia, g, &full, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1, c->X2, 1.0));
+    TRY(vjp_at(ia, g, &full, !keep, c->X1, c->X2 + 4 * nint, dt, 1.0, U0bar, 1, c->X2, 1.0,
+               c->X1));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));

@@ -28,6 +28,13 @@ struct AdjWs {
     double* rlim;       // 4: the limiter's share of the cell-average adjoint
     double* ubb;        // 12 / 6: gathered state adjoint (ghosted)
     double* mupart;     // block partials of the mu adjoint
+    // masked grids: the mirror list grouped by source (fluid cells that are
+    // the mirror source of a listed solid cell, ghosted index; the listed
+    // entries of source u are sord[sstart[u] .. sstart[u + 1]), ascending)
+    const int* ssrcu;
+    const int* sstart;
+    const int* sord;
+    int nsrc;
     int mu_off1, mu_off2;
     unsigned rev;       // bit k: adjoint kernel k takes its blocks last first (per XCD)
 };
@@ -155,10 +162,14 @@ hipError_t launch_vjp1(const Grid1& g, const AdjIn& A, AdjWs1 W, const double* S
 long long adj_mu_partials2(const Grid2& g);
 // mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar).
 // add != nullptr: add_a * add[t] joins the cell-average adjoints (the first
-// 4 nx ny entries of Ubar), as an axpy after the call would.
+// 4 nx ny entries of Ubar) of the fluid cells, as an axpy after the call would.
+// Masked grids: the residual adjoint of solid cells is taken as zero (they
+// carry no residual), pass != nullptr adds pass[t] to every component of the
+// solid cells (a stage leaves them at its filled input), and the adjoint of
+// the mirror fill of the solid cells ends the call.
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
                        double* mu_out, int mu_acc, hipStream_t st, const double* add = nullptr,
-                       double add_a = 0.0);
+                       double add_a = 0.0, const double* pass = nullptr);
 // y[0:n] += a x[0:n]
 hipError_t launch_axpy(double* y, const double* x, double a, long long n, hipStream_t st);
 // y[0:n] = a u[0:n] + b y[0:n] + x[0:n]
