@@ -351,8 +351,8 @@ HWENO_API hweno_status hweno_rk_step_vjp(hweno_ctx* ctx, const double* U0, doubl
  *   no synchronisation (hweno_take_mu_bar reads and clears it; a call with
  *   a non-NULL mu_bar restarts it).  HWENO_E_INVAL for an unrecorded slot.
  * The recordings use the buffer until the next hweno_rk_step_record of the
- * slot or hweno_set_record; HWENO_E_INVAL as for hweno_rk_step_vjp, and for
- * masked grids (their steps are not recorded). */
+ * slot or hweno_set_record; HWENO_E_INVAL as for hweno_rk_step_vjp.  Masked
+ * grids as in hweno_rk_step_vjp. */
 HWENO_API hweno_status hweno_record_bytes(const hweno_ctx* ctx, int nslots, size_t* bytes);
 HWENO_API hweno_status hweno_set_record(hweno_ctx* ctx, void* buffer, size_t bytes, int nslots);
 HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* ctx, int slot, const double* U0,

@@ -1511,7 +1511,7 @@ HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* c, int slot, const double
     GUARD_BEGIN
     if (!c || !U0 || !U3 || c->batch || c->dim() != 2 || !(dt > 0.0) || !std::isfinite(dt))
         return HWENO_E_INVAL;
-    if (!c->solid_host.empty() || c->i0().opt.gradients != 0) return HWENO_E_INVAL;
+    if (c->i0().opt.gradients != 0) return HWENO_E_INVAL;
     if (!c->ws) return HWENO_E_WORKSPACE;
     if (slot < 0 || slot >= c->rec_slots || c->rec_desc.empty()) return HWENO_E_INVAL;
     const hw::Grid2* dd = c->rec_ddesc + 3 * (size_t)slot;
@@ -1526,7 +1526,10 @@ HWENO_API hweno_status hweno_rk_step_record(hweno_ctx* c, int slot, const double
     TRY(dev(hw::launch_copy_in2(d0, U0, d0.S[0], c->stream)));
     TRY(reset(c));
     TRY(dev(hw::launch_set_dt(c->red, dt, c->stream)));
+    const int nsolid = (int)c->sdst_host.size();
     for (int k = 0; k < 3; ++k) {   // stage k + 1 from input S[k] into S[k + 1]
+        // walls inside the grid first (the slot's stage input, in place)
+        if (nsolid) TRY(dev(hw::launch_solid2(dd + k, nsolid, k, c->stream)));
         TRY(dev(hw::launch_ghost2(b[k], k, c->stream, c->tm())));
         TRY(residual(c, k, &b[k]));
         TRY(update(c, k + 1, 0, k, k + 1, nullptr, nullptr, nullptr, &b[k]));
@@ -1550,15 +1553,16 @@ HWENO_API hweno_status hweno_rk_step_vjp_recorded(hweno_ctx* c, int slot, const 
     // the stage adjoints in reverse, seeded as in hweno_rk_step_vjp
     hw::AdjIn A3{U3bar, U3bar + 4 * nint, (2.0 / 3.0) * dt, 2.0 / 3.0};
     // mu_bar NULL: this step's mu adjoint joins the device-side running sum
+    // (a masked grid's solid cells pass each stage's output adjoint through)
     TRY(dev(hw::launch_vjp2(d[2], A3, c->adj, d[2].S[2], c->X2, c->mu_dev, mu_bar ? 0 : 1,
-                            c->stream, U3bar, 2.0 / 3.0)));                         // U2bar
+                            c->stream, U3bar, 2.0 / 3.0, U3bar)));                  // U2bar
     hw::AdjIn A2{c->X2, c->X2 + 4 * nint, 0.25 * dt, 0.25};
     TRY(dev(hw::launch_vjp2(d[1], A2, c->adj, d[1].S[1], c->X1, c->mu_dev, 1, c->stream, c->X2,
-                            0.25)));                                                // U1bar
+                            0.25, c->X2)));                                         // U1bar
     TRY(dev(hw::launch_lin3(c->X2, U3bar, 1.0 / 3.0, 0.75, c->X1, 12 * nint, c->stream)));
     hw::AdjIn A1{c->X1, c->X2 + 4 * nint, dt, 1.0};
     TRY(dev(hw::launch_vjp2(d[0], A1, c->adj, d[0].S[0], U0bar, c->mu_dev, 1, c->stream, c->X2,
-                            1.0)));
+                            1.0, c->X1)));
     if (mu_bar) {
         TRY(dev(hipMemcpyAsync(mu_bar, c->mu_dev, sizeof(double), hipMemcpyDeviceToHost,
                                c->stream)));
