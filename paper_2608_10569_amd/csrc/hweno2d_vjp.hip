@@ -55,12 +55,11 @@ __device__ __forceinline__ bool solid_cell(const Grid2& g, long long t) {
     return g.solid && g.solid[t];
 }
 
-// residual adjoint of interior cell (j, i): F1, F2, F3 component c (zero on
-// the solid cells of a masked grid, which carry no residual)
+// residual adjoint of interior cell (j, i): F1, F2, F3 component c (on a
+// masked grid the seeds come with the solid cells' zeroed, k_mask_seeds)
 __device__ __forceinline__ double rbar(const AdjIn& A, const Grid2& g, int m, int c, int j, int i) {
     const long long nint = (long long)g.nx * g.ny;
-    const long long t = (long long)(j - HALO) * g.nx + (i - HALO);
-    return solid_cell(g, t) ? 0.0 : A.rs * A.Rb[(m * 4 + c) * nint + t];
+    return A.rs * A.Rb[(m * 4 + c) * nint + (long long)(j - HALO) * g.nx + (i - HALO)];
 }
 
 // Logical index of this block: XCD-aware (each XCD takes a contiguous range
@@ -648,9 +647,9 @@ __global__ __launch_bounds__(8 * AC) void k_adj_recon_a(Grid2 g, AdjIn A, AdjWs 
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ub[6 + q] = valid ? VB[(q * 4 + k) * N + cell] : 0.0;
         const long long nint = (long long)g.nx * g.ny;
-        const long long ti = (long long)(j - HALO) * g.nx + (i - HALO);
-        Ub[15] = (inter && A.Vb && !solid_cell(g, ti)) ? A.vs * A.Vb[(b * 4 + k) * nint + ti]
-                                                        : 0.0;
+        Ub[15] = (inter && A.Vb)
+                     ? A.vs * A.Vb[(b * 4 + k) * nint + (long long)(j - HALO) * g.nx + (i - HALO)]
+                     : 0.0;
     }
     shr[bk * AC + cl] = th1b;
     shx[bk * AC + cl] = th2b;
@@ -978,6 +977,21 @@ __global__ void k_adj_ghost_out(Grid2 g, AdjWs W, double* __restrict__ Ubar,
     Ubar[t] = v;
 }
 
+// Seeds of a masked grid with the solid cells' entries zeroed (solid cells
+// carry no residual and no modified moments): the residual seed into rbm (12
+// per cell), the modified-moment seed (if any) into vbm (8 per cell).
+__global__ void k_mask_seeds(Grid2 g, AdjWs W, const double* __restrict__ Rb,
+                             const double* __restrict__ Vb) {
+    const long long nint = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nint * 20) return;
+    const int q = (int)(t / nint);
+    const long long r = t % nint;
+    const bool sol = g.solid[r] != 0;
+    if (q < 12) W.rbm[t] = sol ? 0.0 : Rb[t];
+    else if (Vb) W.vbm[t - 12 * nint] = sol ? 0.0 : Vb[t - 12 * nint];
+}
+
 // Adjoint of the mirror fill of a masked grid's solid cells (k_solid2):
 // each mirror source gathers sign * adjoint of the solid cells copied from it
 // (in the list's order), then every listed solid cell's adjoint is zero (its
@@ -1059,7 +1073,7 @@ long long adj_mu_partials2(const Grid2& g) {
            nb2((long long)(g.NX - 6) * (g.NY - 6), AG);
 }
 
-hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
+hipError_t launch_vjp2(const Grid2& g, const AdjIn& A0, AdjWs W, const double* S, double* Ubar,
                        double* mu_out, int mu_acc, hipStream_t st, const double* add,
                        double add_a, const double* pass) {
     const unsigned bx = nb2((long long)(g.nx + 1) * g.ny, AF);
@@ -1071,6 +1085,12 @@ hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S,
     // weak-moment adjoint before it (1.5 % of a step adjoint on 256^2; the
     // other kernels showed no gain)
     W.rev = 1u << 5;
+    AdjIn A = A0;
+    if (g.solid) {   // masked grid: the solid cells' seeds zeroed once, for every kernel
+        k_mask_seeds<<<nb2((long long)g.nx * g.ny * 20, 256), 256, 0, st>>>(g, W, A0.Rb, A0.Vb);
+        A.Rb = W.rbm;
+        A.Vb = A0.Vb ? W.vbm : nullptr;
+    }
     if (g.K.mu_exp != 0.0) {   // mu(T): the viscosity's dependence on the state too
         k_adj_flux<0, true><<<bx, 3 * AF, 0, st>>>(g, A, W);
         k_adj_flux<1, true><<<by, 3 * AF, 0, st>>>(g, A, W);

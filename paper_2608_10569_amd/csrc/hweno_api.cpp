@@ -293,6 +293,8 @@ size_t layout(hweno_ctx* c, char* base) {
         const size_t nint = (size_t)c->hg[0].nx * c->hg[0].ny;
         c->X1 = take(12 * nint);
         c->X2 = take(12 * nint);
+        A.rbm = take(12 * nint);
+        A.vbm = take(8 * nint);
         for (int sd = 0; sd < 4; ++sd) {
             const size_t len = (size_t)(sd < 2 ? c->hg[0].ny : c->hg[0].nx);
             c->prof_dev[sd] = take(4 * len);

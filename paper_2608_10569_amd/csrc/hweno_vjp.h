@@ -28,6 +28,8 @@ struct AdjWs {
     double* rlim;       // 4: the limiter's share of the cell-average adjoint
     double* ubb;        // 12 / 6: gathered state adjoint (ghosted)
     double* mupart;     // block partials of the mu adjoint
+    double* rbm;        // 12 / cell (interior): a masked grid's residual seed, solid cells zeroed
+    double* vbm;        // 8 / cell (interior): its modified-moment seed likewise
     // masked grids: the mirror list grouped by source (fluid cells that are
     // the mirror source of a listed solid cell, ghosted index; the listed
     // entries of source u are sord[sstart[u] .. sstart[u + 1]), ascending)
@@ -163,8 +165,8 @@ long long adj_mu_partials2(const Grid2& g);
 // mu_acc = 0: *mu_out = mu-bar; 1: *mu_out += mu-bar (device scalar).
 // add != nullptr: add_a * add[t] joins the cell-average adjoints (the first
 // 4 nx ny entries of Ubar) of the fluid cells, as an axpy after the call would.
-// Masked grids: the residual adjoint of solid cells is taken as zero (they
-// carry no residual), pass != nullptr adds pass[t] to every component of the
+// Masked grids: the seeds of solid cells are taken as zero (they carry no
+// residual), pass != nullptr adds pass[t] to every component of the
 // solid cells (a stage leaves them at its filled input), and the adjoint of
 // the mirror fill of the solid cells ends the call.
 hipError_t launch_vjp2(const Grid2& g, const AdjIn& A, AdjWs W, const double* S, double* Ubar,
