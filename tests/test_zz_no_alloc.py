@@ -39,6 +39,8 @@ def _cases():
         ('2d walls 40x24', dict(nx=40, ny=24, extent=(0.0, 1.0, 0.0, 0.5), mu_ref=1 / 200,
                                 Pr=0.73, bc=['noslip', 'noslip', 'noslip', 'slip']),
          workloads.viscous_shock_tube_2d(40, 24, seed=1, amp=0.05)),
+        ('2d 36x20 tiles: weak moments inside the gradient kernel, fluxes split',
+         dict(nx=36, ny=20, mu_ref=0.01), workloads.random_smooth_2d(36, 20, seed=8)),
         ('2d trough 16x16 (limiter active)', dict(nx=16, ny=16, mu_ref=1e-3),
          _trough(workloads.random_smooth_2d(16, 16, seed=3))),
         ('2d DR 30x20 (comparison scheme)', dict(nx=30, ny=20, mu_ref=0.01, gradients='DR'),
@@ -57,6 +59,8 @@ def test_noalloc_residual_equals_workspace_residual():
     for name, kw, U in _cases():
         print('case', name, flush=True)
         s = hweno.Solver(device=dev, **kw)
+        if 'tiles' in name:
+            s.set_tiles(recon=16, grad=0, flux=64)
         Ut = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
         R0, V0, d0 = s.residual(Ut)
         R1, V1, d1 = _noalloc(s, Ut)
