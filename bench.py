@@ -260,18 +260,21 @@ def bench_batched(nsteps, sequential=True):
         b.set_state(i, U)
     tiles = b.autotune(reps=3)
     b.run(nsteps)                       # records and instantiates the graph
-    for i, U in enumerate(states):      # timed run from the initial states
-        b.set_state(i, U)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.run(nsteps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    runs = []
+    for _ in range(3):                  # timed runs from the initial states; the median
+        for i, U in enumerate(states):
+            b.set_state(i, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(nsteps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    el = sorted(runs)[1]
     out = {'workload': '64 periodic 2D grids from {64,128,256,512}^2, Re log-uniform [1e2,1e4], '
                        '8 random-phase Fourier modes amplitude 0.3, %d SSP-RK3 steps each, one graph '
                        'launch' % nsteps,
            'instances': len(inst), 'cells': cells, 'steps': nsteps, 'seconds': el,
-           'value': cells * 3 * nsteps / el, 'unit': UNIT, 'tiles': tiles,
+           'seconds_runs': runs, 'value': cells * 3 * nsteps / el, 'unit': UNIT, 'tiles': tiles,
            'restarts': sum(b.diag(i)['restarts'] for i in range(len(inst)))}
     del b
     torch.cuda.empty_cache()
@@ -375,14 +378,17 @@ def bench_adjoint(nsteps=200, every=20):
     U0 = adjoint.project_fields(rho, u, v, f[3], gamma)
     s.set_state(U0)
     dt = s.rk_step(0.0)['dt']
-    # plain forward: the same fixed-step steps through rk_step
-    s.set_state(U0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        s.rk_step(dt)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
+    # plain forward: the same fixed-step steps through rk_step (median of three)
+    fwd = []
+    for _ in range(3):
+        s.set_state(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            s.rk_step(dt)
+        torch.cuda.synchronize()
+        fwd.append(time.perf_counter() - t0)
+    t_fwd = sorted(fwd)[1]
     def run(n_steps):
         r = rho.clone().requires_grad_(True)
         m = torch.tensor(mu, dtype=torch.float64, device=rho.device, requires_grad=True)
@@ -399,7 +405,9 @@ def bench_adjoint(nsteps=200, every=20):
     run(every)
     s.set_record(2 * every)
     run(2 * every)
-    t_rec, J_rec, g_rec, r_rec = run(nsteps)
+    recs = [run(nsteps) for _ in range(3)]          # the median of three
+    t_runs = [r[0] for r in recs]
+    t_rec, J_rec, g_rec, r_rec = sorted(recs, key=lambda r: r[0])[1]
     rec_bytes = s._rec.numel()
     s.set_record(0)
     t_all, J, gmu, r_all = run(nsteps)
@@ -410,7 +418,9 @@ def bench_adjoint(nsteps=200, every=20):
     cs = n * n * 3 * nsteps
     return {'workload': 'double shear layer 256^2, Re 1000, %d steps with dt frozen, checkpoints '
                         'every %d; d KE / d (rho, u, v node fields, mu)' % (nsteps, every),
-            'forward_seconds': t_fwd, 'forward_backward_seconds': t_rec,
+            'forward_seconds': t_fwd, 'forward_seconds_runs': fwd,
+            'forward_backward_seconds': t_rec,
+            'forward_backward_seconds_runs': t_runs,
             'ratio_to_forward': t_rec / t_fwd, 'forward_value': cs / t_fwd,
             'value': cs / t_rec, 'unit': UNIT + ' (forward-equivalent, with gradient)',
             'recording_bytes': rec_bytes,
