@@ -70,7 +70,7 @@ FLOPS = {'recon': 7049, 'grad': 3428, 'rbar': 414, 'flux': 560, 'update': 400,
 # dispatch) scaled by the factors a 1 GiB device copy gives in the same process
 # (FETCH x 2.0, WRITE x 1.0), per kernel class and tile variant, on this grid
 # and for the kernels as they are now: e.g. recon with 32-cell tiles reads
-# 53.0 MB and writes 436.8 MB per launch.
+# 50.9 MB and writes 432.1 MB per launch.
 TRAFFIC_BYTES = {('recon', 16): 485727236, ('recon', 32): 483043051,
                  ('grad', 32): 432885712, ('grad', 64): 431268299, ('grad', 0): 715273789,
                  ('rbar', None): 315149506, ('update', None): 227677481,
