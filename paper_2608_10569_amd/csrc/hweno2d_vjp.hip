@@ -73,15 +73,20 @@ __device__ __forceinline__ int lblock(const AdjWs& W, int k) {
     return xcd_block((int)blockIdx.x, (int)gridDim.x, (W.rev >> k) & 1u);
 }
 
-// fixed-order block sum of the mu adjoint: one partial per (logical) block
+// fixed-order block sum of the mu adjoint: one partial per (logical) block;
+// a butterfly within each wavefront, then the wavefronts' sums in order
 template <int NT>
 __device__ __forceinline__ void mu_partial(double v, double* part, int lb) {
-    __shared__ double sh[NT];
-    sh[threadIdx.x] = v;
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    __shared__ double sh[NT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int t = 0; t < NT; ++t) s += sh[t];
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s += sh[w];
         part[lb] = s;
     }
 }
