@@ -417,7 +417,11 @@ HWENO_API hweno_status hweno_batch_get_state(hweno_ctx* ctx, int i, double* U, d
 
 /* Advances every instance by nsteps accepted SSP-RK3 steps (fewer if its
  * t_final is reached).  One graph launch covers the run; instances that needed
- * restarts finish with extra single-step launches.  Checks the input states
+ * restarts finish with extra single-step launches.  With two or more
+ * instances the graph holds two concurrent chains, each advancing a group of
+ * instances (consecutive in the schedule order, about equal cells), so one
+ * group's reconstruction runs beside the other's memory-bound kernels; each
+ * instance's results do not depend on the grouping.  Checks the input states
  * first (HWENO_E_NONFINITE for an instance with a bad cell; it is not
  * advanced).  An instance that exhausts max_halvings stops at its last
  * accepted state and the call returns HWENO_E_INADMISSIBLE after the others

@@ -44,6 +44,13 @@ struct hweno_ctx {
     hw::Grid2* dg = nullptr;
     int* dstart = nullptr;
     std::vector<int> hstart;
+    // batches of two or more instances: two groups of consecutive slots with
+    // about equal cells, recorded as two concurrent chains of the run's graph
+    // (one group's reconstruction beside the other's memory-bound kernels)
+    int ngroups = 1;
+    int* dstart_g[2] = {nullptr, nullptr};
+    std::vector<int> hstart_g[2];
+    hw::BatchL blg[2];
     hw::Tiles tiles;
     int order_mode = 0;                // 0: as given, 1: largest first
     hw::BatchL bl;
@@ -85,6 +92,7 @@ struct hweno_ctx {
     int gsteps = 0;
     hipGraphExec_t gexec1 = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream the graphs are recorded on
+    hipStream_t cap_stream2 = nullptr; // the second group's chain while recording
     hw::Timer timer;
     // single 2D grid: inflow profiles (conservative, 4 per boundary cell) and
     // their workspace copies
@@ -330,6 +338,9 @@ size_t layout(hweno_ctx* c, char* base) {
     c->dst = reinterpret_cast<hw::InstState*>(take_bytes(n * sizeof(hw::InstState)));
     c->dg = reinterpret_cast<hw::Grid2*>(take_bytes(n * sizeof(hw::Grid2)));
     c->dstart = reinterpret_cast<int*>(take_bytes(hw::KB_COUNT * (n + 1) * sizeof(int)));
+    if (c->batch)
+        for (int k = 0; k < 2; ++k)
+            c->dstart_g[k] = reinterpret_cast<int*>(take_bytes(hw::KB_COUNT * (n + 1) * sizeof(int)));
     for (int p = 0; p < n; ++p) {
         c->hg[p].red = (HW_GLOBAL hw::Reduce*)(c->red ? c->red + p : nullptr);
         c->hg[p].st = (HW_GLOBAL hw::InstState*)(c->dst ? c->dst + p : nullptr);
@@ -370,7 +381,6 @@ void drop_graphs(hweno_ctx* c) {
     c->gsteps = 0;
 }
 
-// Schedule order, block tables and device grid array (synchronous).
 // Carves a recording buffer into nslots slots, each the three ghosted stage
 // inputs of one RK step and the full-layout intermediates of its three stage
 // residuals, then the slots' device descriptors (3 per slot: the grid's own,
@@ -424,6 +434,7 @@ hweno_status upload_record(hweno_ctx* c) {
     return dev(hipStreamSynchronize(c->stream));
 }
 
+// Schedule order, block tables and device grid array (synchronous).
 hweno_status upload_grids(hweno_ctx* c) {
     const int n = (int)c->hg.size();
     c->order.resize(n);
@@ -450,6 +461,41 @@ hweno_status upload_grids(hweno_ctx* c) {
     c->bl.var_mu = false;
     for (const Inst& in : c->in) c->bl.var_mu = c->bl.var_mu || in.phys.mu_exp != 0.0;
     c->bl.dr = c->i0().opt.gradients != 0;   // the same for every instance (checked)
+    c->ngroups = 1;
+    if (c->batch && n >= 2 && c->dstart_g[0]) {
+        // split the slots where the two groups' cells are closest to equal
+        long long tot = 0, pre = 0;
+        for (const hw::Grid2& gg : slots) tot += gg.ncell;
+        int h = 1;
+        long long best = -1;
+        for (int k = 1; k < n; ++k) {
+            pre += slots[k - 1].ncell;
+            const long long d = pre * 2 > tot ? pre * 2 - tot : tot - pre * 2;
+            if (best < 0 || d < best) {
+                best = d;
+                h = k;
+            }
+        }
+        for (int q = 0; q < 2; ++q) {
+            const int off = q ? h : 0, ng = q ? n - h : h;
+            c->hstart_g[q].assign(hw::KB_COUNT * (ng + 1), 0);
+            hw::batch_blocks(slots.data() + off, ng, c->tiles, c->hstart_g[q].data());
+            TRY(dev(hipMemcpyAsync(c->dstart_g[q], c->hstart_g[q].data(),
+                                   c->hstart_g[q].size() * sizeof(int), hipMemcpyHostToDevice,
+                                   c->stream)));
+            hw::BatchL& b = c->blg[q];
+            b = c->bl;
+            b.dg = c->dg + off;
+            b.dstart = c->dstart_g[q];
+            b.hstart = c->hstart_g[q].data();
+            b.n = ng;
+            b.var_mu = false;
+            for (int k = off; k < off + ng; ++k)
+                b.var_mu = b.var_mu || c->in[c->order[k]].phys.mu_exp != 0.0;
+        }
+        TRY(dev(hipStreamSynchronize(c->stream)));
+        c->ngroups = 2;
+    }
     if (!c->batch && c->dstage) {
         // descriptors of the stage intermediates: the grid's own, with the
         // intermediate arrays of set k
@@ -698,9 +744,7 @@ hweno_ctx* make_ctx(int n, const hweno_grid* grids, const hweno_physics* phys,
 
 // One step of every active instance of a batch (eq. (2.12) with the step rule
 // on the device); recorded into a graph by hweno_batch_run.
-hweno_status batch_step(hweno_ctx* c) {
-    const hw::BatchL& b = c->bl;
-    hipStream_t st = c->stream;
+hweno_status batch_step(const hw::BatchL& b, hipStream_t st) {
     TRY(dev(hw::launch_reset2(b, st)));
     TRY(dev(hw::launch_ghost2(b, 0, st, nullptr)));
     TRY(dev(hw::launch_residual2(b, 0, st, nullptr)));
@@ -729,7 +773,27 @@ hweno_status capture(hweno_ctx* c, int nsteps, hipGraphExec_t* out) {
         c->stream = user;
         return s;
     }
-    for (int k = 0; k < nsteps && s == HWENO_OK; ++k) s = batch_step(c);
+    if (c->ngroups == 2) {
+        // the second group's chain on a second stream, forked from and
+        // joined back into the capturing stream
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (!c->cap_stream2)
+            s = dev(hipStreamCreateWithFlags(&c->cap_stream2, hipStreamNonBlocking));
+        if (s == HWENO_OK) s = dev(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        if (s == HWENO_OK) s = dev(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        if (s == HWENO_OK) s = dev(hipEventRecord(fork, c->stream));
+        if (s == HWENO_OK) s = dev(hipStreamWaitEvent(c->cap_stream2, fork, 0));
+        for (int k = 0; k < nsteps && s == HWENO_OK; ++k) {
+            s = batch_step(c->blg[0], c->stream);
+            if (s == HWENO_OK) s = batch_step(c->blg[1], c->cap_stream2);
+        }
+        if (s == HWENO_OK) s = dev(hipEventRecord(join, c->cap_stream2));
+        if (s == HWENO_OK) s = dev(hipStreamWaitEvent(c->stream, join, 0));
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    } else {
+        for (int k = 0; k < nsteps && s == HWENO_OK; ++k) s = batch_step(c->bl, c->stream);
+    }
     const hipError_t e = hipStreamEndCapture(c->stream, &graph);
     c->stream = user;
     if (s != HWENO_OK) {
@@ -802,6 +866,7 @@ HWENO_API hweno_status hweno_destroy(hweno_ctx* c) {
     if (!c) return HWENO_E_INVAL;
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->cap_stream2) (void)hipStreamDestroy(c->cap_stream2);
     c->timer.destroy();
     delete c;
     return HWENO_OK;
