@@ -1,8 +1,9 @@
 """GPU against the oracle on the workloads' own configurations: a batch of
 mixed instances (sizes, viscosities, boundary kinds) after three steps, one
 step of the full 1000 x 500 viscous shock tube on sampled windows (walls,
-corners, the diaphragm), and long prefixes of the N = 2000 Riemann problems
-with the paper's time-step rule."""
+corners, the diaphragm), one step of the full 64-instance batch on sampled
+windows of one instance per size, and long prefixes of the N = 2000 Riemann
+problems with the paper's time-step rule."""
 
 import numpy as np
 import pytest
@@ -217,6 +218,57 @@ def test_c3_full_size_step_matches_oracle_on_windows():
         print('window rows %d-%d cols %d-%d: max rel err per field %.2e (window-max scale '
               '%.2e)' % (j0, j1, i0, i1, e, field_rel_err(Ug[:, :, j0:j1, i0:i1], Uo)))
         worst = max(worst, e)
+    assert worst < 1e-12
+
+
+def test_c4_full_batch_step_matches_oracle_on_windows():
+    """The 64-instance batch of the benchmark (periodic grids of 64^2 to
+    512^2, Re from 1e2 to 1e4, random Fourier velocity fields) in the launch
+    configuration it times (autotuned tiles, one graph launch of two
+    concurrent chains): one step of every instance with its own paper-rule
+    step; sampled instances of each size against the oracle's step on
+    windows at a corner (the periodic wrap in both directions), an edge and
+    the interior.  The grids are periodic, so each window is compared after
+    rolling both states to put it at the centre (the windowed oracle step
+    grows its boxes without wrapping).  Errors are taken relative to the
+    largest cell average of the same component: the density is nearly
+    uniform, so its scaled moments are 1e-6 of it and carry the rounding of
+    differences of O(1) averages (the oracle's own step moves them by 6e-10
+    of their size under a 1e-15 perturbation of the state)."""
+    inst = workloads.batched_periodic_2d()
+    probs = [dict(nx=n, ny=n, mu_ref=1.0 / Re) for n, Re, _ in inst]
+    b = hweno.Batch(probs)
+    for i, (_, _, U) in enumerate(inst):
+        b.set_state(i, to_dev(U))
+    b.autotune(reps=2)
+    for i, (_, _, U) in enumerate(inst):
+        b.set_state(i, to_dev(U))
+    b.run(1)
+    picks = {}
+    for i, (n, _, _) in enumerate(inst):
+        picks.setdefault(n, i)
+    worst = 0.0
+    for n, i in sorted(picks.items()):
+        _, Re, U = inst[i]
+        d = b.diag(i)
+        Ug, tg = b.get_state(i)
+        Ug = Ug.cpu().numpy()
+        assert d['steps'] == 1 and d['restarts'] == 0 and tg == d['dt']
+        sc = Scheme2D(n, n, 0.0, 1.0, 0.0, 1.0, Physics(mu_ref=1.0 / Re), Options(),
+                      bc=('periodic',) * 4)
+        windows = [(0, 8, 0, 8), (n - 8, n, n - 8, n), (0, 8, n // 2 - 4, n // 2 + 4),
+                   (n // 2 - 4, n // 2 + 4, n // 3, n // 3 + 8)]
+        scale = np.tile(np.abs(Ug[0]).reshape(4, -1).max(axis=1), 3)
+        for w in windows:
+            j0, j1, i0, i1 = w
+            sh = (n // 2 - j0, n // 2 - i0)
+            Ur, Gr = np.roll(U, sh, axis=(2, 3)), np.roll(Ug, sh, axis=(2, 3))
+            c = (n // 2, n // 2 + j1 - j0, n // 2, n // 2 + i1 - i0)
+            Uo = oracle_step_windows(sc, Ur, d['dt'], [c])[0]
+            diff = np.abs(Gr[:, :, c[0]:c[1], c[2]:c[3]] - Uo).reshape(12, -1).max(axis=1)
+            worst = max(worst, float(np.max(diff / scale)))
+        print('instance %d (%d^2, Re %.0f, dt %.3e): worst window rel err %.2e'
+              % (i, n, Re, d['dt'], worst), flush=True)
     assert worst < 1e-12
 
 
