@@ -1,7 +1,8 @@
 """GPU against the oracle on the workloads' own configurations: a batch of
 mixed instances (sizes, viscosities, boundary kinds) after three steps, one
-step of the full 1000 x 500 viscous shock tube on sampled windows (walls,
-corners, the diaphragm), one step of the full 64-instance batch on sampled
+step and the residual of the full 1000 x 500 viscous shock tube on sampled
+windows (walls, corners, the diaphragm; at t = 0 and from the developed
+t = 0.3 state), one step of the full 64-instance batch on sampled
 windows of one instance per size, and long prefixes of the N = 2000 Riemann
 problems with the paper's time-step rule."""
 
@@ -218,7 +219,75 @@ def test_c3_full_size_step_matches_oracle_on_windows():
         print('window rows %d-%d cols %d-%d: max rel err per field %.2e (window-max scale '
               '%.2e)' % (j0, j1, i0, i1, e, field_rel_err(Ug[:, :, j0:j1, i0:i1], Uo)))
         worst = max(worst, e)
-    assert worst < 1e-12
+    # the step takes the viscous bound (dt = 2e-7) and moves the state
+    # little: the residual itself on the same windows, per field relative to
+    # its largest value over the grid
+    R, V, _ = s.residual(to_dev(U))
+    R, V = R.cpu().numpy(), V.cpu().numpy()
+    rs = np.abs(R).reshape(12, -1).max(axis=1)
+    vs = np.abs(V).reshape(8, -1).max(axis=1)
+    worst_r = 0.0
+    for w in windows:
+        F, Vo = _residual_box(sc, U, w)
+        j0, j1, i0, i1 = w
+        dr = np.abs(R[:, :, j0:j1, i0:i1] - F).reshape(12, -1).max(axis=1) / rs
+        dv = np.abs(V.reshape(8, ny, nx)[:, j0:j1, i0:i1] - Vo.reshape(8, j1 - j0, i1 - i0))
+        worst_r = max(worst_r, float(dr.max()), float((dv.reshape(8, -1).max(axis=1) / vs).max()))
+    print('residual on the windows: worst rel err %.2e' % worst_r)
+    assert worst < 1e-12 and worst_r < 1e-11
+
+
+def test_c3_developed_state_step_matches_oracle_on_windows():
+    """The 1000 x 500 shock tube advanced on the GPU to t = 0.3 as the
+    benchmark prepares it (viscous step bound off, CFL 0.3), with shock,
+    contact and wall layers present: one more paper-rule step on the GPU
+    equals the oracle's step from the same state on windows along the bottom
+    wall and at mid-height across the waves, and at the corners."""
+    nx, ny = 1000, 500
+    kw = dict(gamma=1.4, Pr=0.73, mu_ref=1.0 / 200)
+    bc = ('noslip', 'noslip', 'noslip', 'slip')
+    ext = (0.0, 1.0, 0.0, 0.5)
+    s = hweno.Solver(nx, ny, extent=ext, bc=bc, cfl=0.3, b_visc=0.0, t_final=0.3, **kw)
+    s.set_state(to_dev(workloads.viscous_shock_tube_2d(nx, ny)))
+    steps = 0
+    while s.rk_step(0.0)['dt'] > 0.0:
+        steps += 1
+    U0, t0 = s.get_state()
+    s = hweno.Solver(nx, ny, extent=ext, bc=bc, cfl=0.3, t_final=1.0, **kw)
+    s.set_state(U0, t0)
+    d = s.rk_step(0.0)
+    G = s.get_state()[0].cpu().numpy()
+    U = U0.cpu().numpy()
+    assert d['restarts'] == 0
+    sc = Scheme2D(nx, ny, *ext, Physics(**kw), Options(cfl=0.3), bc=bc)
+    windows = [(0, 10, 0, 10), (0, 10, 990, 1000), (490, 500, 0, 10), (490, 500, 990, 1000)]
+    windows += [(0, 10, c, c + 10) for c in range(100, 1000, 100)]
+    windows += [(245, 255, c, c + 10) for c in range(50, 1000, 100)]
+    res = oracle_step_windows(sc, U, d['dt'], windows)
+    scale = np.abs(G).reshape(12, -1).max(axis=1)
+    worst = 0.0
+    for w, Uo in zip(windows, res):
+        j0, j1, i0, i1 = w
+        diff = np.abs(G[:, :, j0:j1, i0:i1] - Uo).reshape(12, -1).max(axis=1)
+        worst = max(worst, float(np.max(diff / scale)))
+    # the paper's rule takes the viscous bound here (dt = 2e-7), so the step
+    # moves the state little: the residual itself, per field relative to its
+    # largest value over the grid, on the same windows
+    R, V, _ = s.residual(U0)
+    R, V = R.cpu().numpy(), V.cpu().numpy()
+    rs = np.abs(R).reshape(12, -1).max(axis=1)
+    vs = np.abs(V).reshape(8, -1).max(axis=1)
+    worst_r = 0.0
+    for w in windows:
+        F, Vo = _residual_box(sc, U, w)
+        j0, j1, i0, i1 = w
+        dr = np.abs(R[:, :, j0:j1, i0:i1] - F).reshape(12, -1).max(axis=1) / rs
+        dv = np.abs(V.reshape(8, ny, nx)[:, j0:j1, i0:i1] - Vo.reshape(8, j1 - j0, i1 - i0))
+        worst_r = max(worst_r, float(dr.max()), float((dv.reshape(8, -1).max(axis=1) / vs).max()))
+    print('developed state after %d steps (t = %.4f), dt %.3e, limiter cell-stages %d: worst '
+          'window rel err %.2e (state), %.2e (residual)'
+          % (steps, t0, d['dt'], d['pp_cells'], worst, worst_r))
+    assert worst < 1e-11 and worst_r < 1e-11
 
 
 def test_c4_full_batch_step_matches_oracle_on_windows():
