@@ -81,6 +81,28 @@ def test_residual2d_periodic(mode, shape):
     assert d['pp_cells'] == do['pp_cells']
 
 
+def test_inviscid_limit_residual_and_step():
+    """mu = 0 (the Euler limit): no viscous fluxes and no viscous step bound;
+    the residual, the modified moments and one paper-rule step (Delta t from
+    the wave speed alone) against the oracle, with walls."""
+    nx, ny = 30, 22
+    U = workloads.random_smooth_2d(nx, ny, seed=14, noise=1e-3, extent=(0.0, 1.0, 0.0, 0.5))
+    ext = (0.0, 1.0, 0.0, 0.5)
+    s = hweno.Solver(nx, ny, extent=ext, mu_ref=0.0, bc=BCS_WALL)
+    sc = Scheme2D(nx, ny, *ext, Physics(mu_ref=0.0), Options(), bc=BCS_WALL)
+    R, V, d = s.residual(to_dev(U))
+    Ro, Vo, do = sc.residual(U)
+    eR = rel_err(fields2d(R.cpu().numpy()), fields2d(Ro))
+    eV = rel_err(fields2d(V.cpu().numpy()), fields2d(Vo.reshape(8, ny, nx)))
+    s.set_state(to_dev(U))
+    dg = s.rk_step(0.0)
+    Uo, dto, _ = rk.rk3_step(sc, U, 0.0)
+    eS = rel_err(fields2d(s.get_state()[0].cpu().numpy()), fields2d(Uo))
+    print('mu = 0: residual %.2e, V %.2e, step %.2e, dt %.6e vs %.6e' % (eR, eV, eS, dg['dt'], dto))
+    assert eR < 1e-11 and eV < 1e-12 and eS < 1e-12
+    assert abs(dg['dt'] - dto) < 1e-13 * dto
+
+
 @pytest.mark.parametrize('bc', [BCS_WALL, ('outflow', 'slip', 'slip', 'outflow')])
 def test_residual2d_walls_and_outflow(bc):
     nx, ny = 24, 14
