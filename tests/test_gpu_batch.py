@@ -218,3 +218,24 @@ def test_c4_batch_sampled_instances():
         got, tb = b.get_state(i)
         print('C4 instance %d (%d^2, Re %.0f): equal %s' % (i, sizes[i], inst[i][1], torch.equal(got, ref)))
         assert tb == t and torch.equal(got, ref)
+
+
+def test_full_batch_two_chains_equal_single_grids():
+    """The benchmark's 64-instance batch (two concurrent chains in its graph)
+    over 50 steps: one instance of each size, and the last instance of each
+    chain, equal the same problems advanced alone, bit for bit."""
+    inst = workloads.batched_periodic_2d()
+    probs = [dict(nx=n, ny=n, mu_ref=1.0 / Re) for n, Re, _ in inst]
+    b = hweno.Batch(probs)
+    for i, (_, _, U) in enumerate(inst):
+        b.set_state(i, to_dev(U))
+    b.run(50)
+    picks = {}
+    for i, (n, _, _) in enumerate(inst):
+        picks.setdefault(n, i)
+    for i in sorted(set(picks.values()) | {len(inst) // 2 - 1, len(inst) - 1}):
+        ref, t, steps, _ = single_run(probs[i], inst[i][2], 50)
+        got, tb = b.get_state(i)
+        print('instance %d (%d^2): t %.6e vs %.6e, equal %s'
+              % (i, inst[i][0], tb, t, torch.equal(got, ref)), flush=True)
+        assert b.diag(i)['steps'] == 50 and tb == t and torch.equal(got, ref)
