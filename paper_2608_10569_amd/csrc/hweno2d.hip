@@ -9,14 +9,17 @@
 //                      moments (eqs. (3.6)-(3.8))      [halo ring 2]
 //   grad             : gradient HWENO (eq. (3.9)) at 12 face + 9 volume points,
 //                      volume-flux quadratures         [halo ring 1]
+//   rgrad            : rbar + grad in one kernel per tile of cells, the weak
+//                      moments of the tile and its ring kept in LDS (a tile
+//                      choice)
 //   flux_x, flux_y   : PP Lax-Friedrichs fluxes at face Gauss points (eq. (3.3))
 //   update           : assembly of eq. (3.2) and the stage combination of the
 //                      SSP-RK3 scheme with modified moments (eq. (2.12))
 //   fluxup           : flux_x + flux_y + update in one kernel per tile of
 //                      cells, the face fluxes kept in LDS (a tile choice)
 //
-// Every intermediate lives in HBM, laid out component-major over the ghosted
-// grid so that consecutive lanes touch consecutive cells.
+// Every other intermediate lives in HBM, laid out component-major over the
+// ghosted grid so that consecutive lanes touch consecutive cells.
 
 #include <hip/hip_ext.h>
 
